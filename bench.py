@@ -1,0 +1,162 @@
+"""Throughput of the plain leap-frog stepper on the 4M-triangle periodic FP32 workload.
+
+Workload: periodic unit square, Delaunay triangulation of a 1415 x 1415 lattice jittered by
++-0.25 h (4,004,450 triangles, 6,006,675 edges), Gaussian-enveloped plane wave of 20 cells
+per wavelength at a seeded random angle, dt = 0.5 * 2/omega_max (power iteration), FP32 fields
+with FP64-derived coefficients.  One step = one edge half-step and one triangle half-step
+over the whole mesh (10,011,125 cell-updates).
+
+Prints one JSON line: cell-updates/s, ms per step, the roofline of the dominant kernel
+(algorithmic bytes per launch / average launch time from HIP events in the timed region),
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_LATTICE = 1415
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10000)
+    p.add_argument("--warmup", type=int, default=500)
+    p.add_argument("--n", type=int, default=N_LATTICE, help="lattice size (default 1415)")
+    p.add_argument("--order", default="morton", choices=["none", "random", "morton", "rcm"])
+    p.add_argument("--fusion", type=int, default=0, help="steps per launch (0 = auto)")
+    p.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
+    return p.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1812_01448_amd as ty
+    from meshgen import lattice_mesh, periodic_wavevector, plane_wave_packet, random_angle
+
+    n = args.n
+    t0 = time.time()
+    xy, tri = lattice_mesh(n, 0.25, 1, periodic=True)
+    log(f"mesh {n}x{n}: {len(tri)} triangles ({time.time() - t0:.1f} s)")
+    mesh = ty.Mesh(xy, tri, periodic=True)
+    mesh.reorder(args.order, 0)
+    lam, iters, ok = mesh.cfl(max_iter=20000, rtol=1e-12, seed=0)
+    dt = 0.5 * 2.0 / np.sqrt(lam)
+    log(f"omega_max {np.sqrt(lam):.6e} ({iters} iterations, converged={ok}), dt {dt:.6e}")
+    view = mesh.view()
+    theta = random_angle(2)
+    k, _, _ = periodic_wavevector(theta, 20.0, 1.0 / n)
+    B0, E0 = plane_wave_packet(view["O"], view["C"], view["evec"] / view["elen"][:, None], k, dt,
+                               sigma=0.1, center=(0.5, 0.5))
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    sim = ty.Sim(mesh, dt, args.prec, stream=stream.cuda_stream)
+    sim.set_state("E", E0)
+    sim.set_state("B", B0)
+    sim.set_fusion(args.fusion)
+    ne, nt = mesh.ne, mesh.nt
+    cells = ne + nt
+
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_profiling(True)
+    t_start = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = sim.kernel_times()
+    sim.set_profiling(False)
+    diag = sim.diagnostics()
+    log(f"timed {args.steps} steps in {elapsed:.4f} s; energy {diag['energy']:.6e} "
+        f"nonfinite={diag['nonfinite']}")
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = cells * args.steps / elapsed
+    esz = 4 if args.prec == "f32" else 8
+    # algorithmic bytes (every cell read/written once, compulsory gathers counted once)
+    bytes_edge = (5 * esz) * ne + 2 * 4 * ne + esz * nt - 2 * esz * ne + 0
+    bytes_edge = 3 * esz * ne + 8 * ne + esz * nt          # Et r/w + cE, R/L, B gather
+    bytes_tri = 3 * esz * nt + 12 * nt + esz * ne           # B r/w + nB, A, Et gather
+    algo = {"edge": bytes_edge, "tri": bytes_tri}
+    # dominant kernel = the one with the largest total time in the timed region
+    dom = max(prof, key=lambda kk: prof[kk]["total_ms"])
+    units = prof[dom]["steps_per_launch"]
+    per_launch_bytes = units * (bytes_edge + bytes_tri) if dom == "fused" else algo[dom]
+    avg_ms = prof[dom]["total_ms"] / prof[dom]["count"]
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+    step_bytes = bytes_edge + bytes_tri
+    roofline = {"bound": "hbm", "kernel": prof[dom]["name"], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                "algorithmic_bytes_per_launch": per_launch_bytes,
+                "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(xy, tri, dt, E0, B0, args.cpu_steps, view)
+
+    out = {
+        "metric": "cell-updates/s (edges+tris) & HBM GB/s, plain vs learned at fixed phase error",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": f"plain FP32 periodic jittered-lattice Delaunay {n}x{n} "
+                               f"(+-0.25h), plane-wave packet 20 cells/lambda, CFL 0.5",
+                   "triangles": nt, "edges": ne, "cell_updates_per_step": cells,
+                   "order": args.order, "steps_per_launch": sim.fusion_used(),
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(xy, tri, dt, E0_lib, B0_lib, steps, view):
+    """The FP64 CPU oracle stepping the same mesh (bounded sample of steps)."""
+    import oracle
+    t0 = time.time()
+    om = oracle.OracleMesh(xy, tri, True)
+    log(f"oracle mesh built in {time.time() - t0:.1f} s")
+    from meshgen import periodic_wavevector, plane_wave_packet, random_angle
+    n = int(round(np.sqrt(len(xy))))
+    k, _, _ = periodic_wavevector(random_angle(2), 20.0, 1.0 / n)
+    B0, E0 = plane_wave_packet(om.O, om.C, om.tangent, k, dt, sigma=0.1, center=(0.5, 0.5))
+    cells = om.ne + om.nt
+    if steps <= 0:
+        t1 = time.perf_counter()
+        om.step(E0, B0, dt, 2)
+        per = (time.perf_counter() - t1) / 2
+        steps = int(max(2, min(2000, 15.0 / max(per, 1e-9))))
+    t1 = time.perf_counter()
+    om.step(E0, B0, dt, steps)
+    el = time.perf_counter() - t1
+    log(f"oracle {steps} steps in {el:.2f} s")
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 leap-frog steps of the same {om.nt}-triangle mesh, "
+                      f"single-threaded plain C oracle"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * tyee — leap-frog Maxwell solver on unstructured triangular Yee-like meshes, for AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Fadeev, "Numerical simulation of 2D electrodynamic problems with unstructured
+ * triangular meshes", arXiv:1812.01448.  Section numbers and equation numbers below refer
+ * to that paper.
+ *
+ * Placement (Section 1, Fig. 1 and Fig. 2): E_i is the projection of the electric field on
+ * mesh edge i at its midpoint C_i; the single magnetic component B_j sits at the
+ * circumcentre O_j of triangle j; plasma currents j_i share the edges with E; charge sits on
+ * nodes.  The plane carries coordinates (x1, x2); B is the component along x1 x x2.
+ *
+ * Numbering (canonical, independent of any reordering):
+ *   - triangle j = row j of the triangle array handed to tyee_mesh_create; its vertices are
+ *     made counter-clockwise by swapping v1 and v2 when needed;
+ *   - edge i = rank of its node pair (lo < hi) in lexicographic order; its vector e_i
+ *     points lo -> hi (the paper allows any direction, Fig. 2);
+ *   - R(i) is the triangle whose counter-clockwise boundary runs lo -> hi along edge i, L(i)
+ *     the other (-1 on an outer edge of a closed resonator);
+ *   - A(j,q) is the edge from local vertex q to q+1 of triangle j; s(j,q) = +1 when
+ *     j = R(A(j,q)), else -1 (the sign of eq. 4 read from the mesh topology).
+ * Geometry is computed in FP64 in each triangle's own frame: area S_j, circumcentre O_j,
+ * signed half dual lengths hR_i = (O_R - C_i).n_i and hL_i = (C_i - O_L).n_i with n_i the
+ * left normal of e_i, and dual length d_i = hR_i + hL_i (|O_R O_L| of eq. 3 on a Delaunay
+ * mesh).
+ *
+ * Time levels: E and Q at t = n dt; B and j at t = (n + 1/2) dt.  One step (eqs. 3-6):
+ *   j  <- [(1 - nu dt/2) j + dt wp2 E] / (1 + nu dt/2)             (plasma edges, eq. 5)
+ *   E  <- E + dt [ gamma (B_R - B_L)/d - j - Jsrc(t + dt/2) ]       (interior edges, eqs. 3, 6)
+ *   Q  <- Q - dt sum_i sigma(k,i) d_i (j + Jsrc)_i                  (interior nodes)
+ *   B  <- B - (dt/S_j) sum_q s(j,q) gamma |e| E                      (eq. 4)
+ * with gamma = 1 for the plain method (a per-edge scale for the learned correction).
+ * Outer edges of a closed resonator carry E = 0 and are never updated (eqs. 9-10).
+ *
+ * Conventions for every call:
+ *   - return 0 (TYEE_OK) on success or a negative tyee_status; tyee_last_error() then holds a
+ *     message for the calling thread.  No C++ exception crosses this interface.
+ *   - input arrays are copied; output arrays are caller-owned; views are borrowed and stay
+ *     valid until the owning handle is destroyed or reordered.
+ *   - a handle is not thread-safe; one simulation uses one HIP stream.
+ *   - destroy functions accept NULL.
+ */
+#ifndef TYEE_H
+#define TYEE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TYEE_OK = 0,
+    TYEE_EINVAL = -1,        /* bad argument, size or state */
+    TYEE_ENOTDELAUNAY = -2,  /* an interior edge has d_i <= dual_tol * |e_i| */
+    TYEE_EDEGENERATE = -3,   /* a triangle with |2 S| <= 1e-14 Lx Ly */
+    TYEE_ENONMANIFOLD = -4,  /* an edge in more than two triangles, or twice in one direction */
+    TYEE_EPERIODIC = -5,     /* periodic mesh with an edge that has only one triangle */
+    TYEE_ENOMEM = -6,        /* host or device allocation failed */
+    TYEE_EDEVICE = -7,       /* a HIP runtime call failed */
+    TYEE_EUNSTABLE = -8,     /* non-finite field detected */
+    TYEE_ENOTCONVERGED = -9  /* power iteration hit max_iter */
+} tyee_status;
+
+typedef enum { TYEE_PEC_BOX = 0, TYEE_PERIODIC = 1 } tyee_domain_kind;
+
+/* kind: closed resonator (outer edges E = 0, eqs. 9-10) or periodic square (a torus).
+   Lx, Ly: periods of a torus (positions are taken modulo them and differences by minimum
+   image); for a box they only set the degeneracy scale Lx*Ly.  dual_tol: creation fails when
+   an interior edge has d_i <= dual_tol * |e_i| (0 = require a strictly positive dual). */
+typedef struct {
+    int32_t kind;
+    double Lx, Ly;
+    double dual_tol;
+} tyee_domain;
+
+typedef enum { TYEE_ORDER_NONE = 0, TYEE_ORDER_RANDOM = 1, TYEE_ORDER_MORTON = 2,
+               TYEE_ORDER_RCM = 3 } tyee_order;
+
+typedef enum { TYEE_F32 = 0, TYEE_F64 = 1 } tyee_prec;
+
+typedef enum { TYEE_FIELD_E = 0, TYEE_FIELD_B = 1, TYEE_FIELD_J = 2, TYEE_FIELD_Q = 3 } tyee_field;
+
+typedef struct tyee_mesh tyee_mesh;
+typedef struct tyee_sim tyee_sim;
+
+typedef struct {
+    int64_t n_nodes, n_edges, n_tris, n_boundary_edges;
+    double min_dual_ratio, max_dual_ratio;  /* min / max of d_i/|e_i| over interior edges */
+    double sum_area;                        /* sum_j S_j */
+    double sum_dual_area;                   /* sum_i |e_i| d_i / 2 (equals sum_area) */
+    int64_t n_obtuse;                       /* triangles whose circumcentre is outside */
+} tyee_mesh_info;
+
+/* Borrowed host views of a mesh, canonical numbering, FP64 geometry. */
+typedef struct {
+    const int32_t *tri;         /* [n_tris][3] counter-clockwise vertices */
+    const int32_t *edge_nodes;  /* [n_edges][2] (lo, hi) */
+    const int32_t *R, *L;       /* [n_edges] triangles left / right of e_i, -1 if none */
+    const int32_t *A;           /* [n_tris][3] edges of each triangle */
+    const int8_t *sgn;          /* [n_tris][3] s(j,q) */
+    const double *elen;         /* [n_edges] |e_i| */
+    const double *evec;         /* [n_edges][2] e_i = x_hi - x_lo (minimum image) */
+    const double *hR, *hL, *d;  /* [n_edges] half dual lengths and dual length */
+    const double *S;            /* [n_tris] areas */
+    const double *O;            /* [n_tris][2] circumcentres (vertex 0 + local offset) */
+    const double *C;            /* [n_edges][2] edge midpoints x_lo + e_i/2 */
+    const int32_t *perm_t;      /* [n_tris]  device slot -> canonical triangle */
+    const int32_t *perm_e;      /* [n_edges] device slot -> canonical edge */
+} tyee_mesh_arrays;
+
+/* ---------------------------------------------------------------- mesh ---- */
+
+/* Build connectivity and geometry from a node cloud and triangles (Section 3 mesh
+   creation; Fig. 2 quantities).  xy: [n_nodes][2] FP64 host; tri: [n_tris][3] int32 node
+   indices, any winding.  Errors: TYEE_EINVAL, TYEE_EDEGENERATE, TYEE_ENONMANIFOLD,
+   TYEE_EPERIODIC, TYEE_ENOTDELAUNAY, TYEE_ENOMEM.  *out receives a new handle. */
+int tyee_mesh_create(const double *xy, int64_t n_nodes, const int32_t *tri, int64_t n_tris,
+                     const tyee_domain *dom, tyee_mesh **out);
+
+/* Choose the device numbering of triangles and edges for memory locality.  Always computed
+   from the canonical numbering (idempotent).  NONE: identity.  RANDOM: triangles sorted by
+   (splitmix64(seed + j), j), edges by (splitmix64(seed + n_tris + i), i).  MORTON: triangles
+   by the 32-bit Z-order key of their vertex-average quantised to 16 bits per axis, ties by
+   id.  RCM: reverse Cuthill-McKee on triangles sharing interior edges, each component
+   started from a George-Liu pseudo-peripheral triangle, neighbours visited by (degree, id).
+   MORTON and RCM number edges by first appearance over (new triangle order, q = 0, 1, 2).
+   A simulation created afterwards uses this numbering on the device; results read back
+   are always canonical. */
+int tyee_mesh_reorder(tyee_mesh *mesh, int32_t kind, uint64_t seed);
+
+int tyee_mesh_query(const tyee_mesh *mesh, tyee_mesh_info *out);
+int tyee_mesh_view(const tyee_mesh *mesh, tyee_mesh_arrays *out);
+
+/* omega_max^2 of K = -L_E L_B by normalised iteration in the S-weighted product (the
+   "complex time" iteration of Section 2, used for the eq. 20 bound dt < 2/omega_max).
+   gamma: per-edge coefficient scale [n_edges] or NULL.  Start vector
+   x_j = 2 u_j - 1, u_j = (splitmix64(seed + j) >> 11) * 2^-53.  Stops when
+   |lambda_k - lambda_{k-1}| <= rtol * lambda_k (TYEE_OK) or after max_iter iterations
+   (TYEE_ENOTCONVERGED, *lambda still set).  FP64 on host threads. */
+int tyee_mesh_cfl(const tyee_mesh *mesh, const double *gamma, int64_t max_iter, double rtol,
+                  uint64_t seed, double *lambda, int64_t *iters);
+
+void tyee_mesh_destroy(tyee_mesh *mesh);
+
+/* ----------------------------------------------------------- simulation ---- */
+
+/* Upload a mesh for stepping with time step dt in FP32 or FP64 device arithmetic
+   (geometry stays FP64 on the host; coefficients are folded with dt and rounded once).
+   stream: a hipStream_t, or NULL for the default stream.  Fields start at zero.  The
+   simulation copies what it needs: the mesh may be destroyed afterwards. */
+int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream,
+                    tyee_sim **out);
+
+/* Host FP64 arrays in canonical numbering: E [n_edges] (physical projection E_i), B
+   [n_tris], J [n_edges] (plasma edges only; other entries must be 0), Q [n_nodes].  Values
+   given for outer resonator edges are ignored (they stay 0).  get synchronises the stream. */
+int tyee_sim_set_state(tyee_sim *sim, int32_t field, const double *host);
+int tyee_sim_get_state(tyee_sim *sim, int32_t field, double *host);
+
+/* Plasma-like medium (eq. 5, j' = wp2 E - nu j, with E' = ... - j of eq. 6 taken with the
+   physical sign).  wp2_tri [n_tris]: plasma frequency squared per triangle (canonical);
+   each interior edge takes (hR wp2_R + hL wp2_L)/d.  Edges with a positive value form the
+   plasma list.  Passing NULL removes the medium. */
+int tyee_sim_set_media(tyee_sim *sim, const double *wp2_tri, double nu);
+
+/* Soft current source Jsrc_i(t) = w * g(t) on the edges joining node_pairs[k][0] ->
+   node_pairs[k][1] (weight sign follows that direction), g(t) = sin(omega t)
+   sin^2(pi t / T) for 0 <= t < T = cycles 2 pi/omega, else 0, taken at t = (n + 1/2) dt.
+   n = 0 removes the source.  Errors: TYEE_EINVAL if a pair is not a mesh edge. */
+int tyee_sim_set_source(tyee_sim *sim, const int32_t *node_pairs, const double *weights,
+                        int64_t n, double omega, double cycles);
+
+/* Per-edge scale gamma_i [n_edges] (canonical) of the eq. 3 and eq. 4 coefficients of
+   edge i (the learned correction); NULL restores gamma = 1.  Physical fields are kept. */
+int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma);
+
+/* Steps fused per kernel launch (1, 2, 4 or 8) for vacuum runs; 0 selects automatically.
+   Results are bit-identical for every setting. */
+int tyee_sim_set_fusion(tyee_sim *sim, int32_t steps_per_launch);
+
+/* Enqueue n leap-frog steps on the simulation's stream (asynchronous). */
+int tyee_sim_step(tyee_sim *sim, int64_t n);
+
+/* Wait for all enqueued work. */
+int tyee_sim_sync(tyee_sim *sim);
+
+typedef struct {
+    int64_t step;          /* steps taken */
+    double time;           /* step * dt */
+    double energy;         /* sum w E^2 + sum S B^2 at the current levels (eq. 8 form) */
+    double max_abs_E, max_abs_B;
+    int32_t nonfinite;     /* 1 if any field value is NaN or infinite */
+} tyee_diag;
+
+/* Diagnostics from the current state (synchronises). Returns TYEE_EUNSTABLE if a field
+   is not finite (out is still filled). */
+int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out);
+
+/* Kernel time of the last tyee_sim_step call in milliseconds, measured with HIP events on
+   the simulation's stream (synchronises). */
+int tyee_sim_last_step_ms(tyee_sim *sim, double *ms);
+
+/* Kernels of one step, for per-launch timing. */
+typedef enum { TYEE_KERNEL_EDGE = 0, TYEE_KERNEL_TRI = 1, TYEE_KERNEL_FUSED = 2,
+               TYEE_KERNEL_SPECIAL = 3, TYEE_KERNEL_CHARGE = 4 } tyee_kernel;
+
+/* Time every later launch of the kernel kinds in the bit mask `kinds` (bit k = tyee_kernel
+   k) with a HIP event pair on the simulation's stream; resets the totals.  0 turns timing
+   off. */
+int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds);
+
+/* Number of timed launches of one kernel kind and their summed duration in ms since the
+   last tyee_sim_set_profiling (waits for the timed launches). */
+int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *total_ms);
+
+/* Steps per launch in use for vacuum runs. */
+int tyee_sim_get_fusion(const tyee_sim *sim, int32_t *k);
+
+int64_t tyee_sim_steps(const tyee_sim *sim);
+void tyee_sim_destroy(tyee_sim *sim);
+
+const char *tyee_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,109 @@
+// Half-step kernels of the triangular Yee-like leap-frog scheme (arXiv:1812.01448,
+// eqs. 3-6) for gfx950. One work-item per cell; every output cell is written by exactly
+// one work-item, so no atomics are needed and results do not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tyee {
+
+// Work-groups are dispatched round-robin over the 8 XCDs of the chip (group g runs on
+// XCD g mod 8).  Remap so that each XCD works on one contiguous run of groups: the
+// neighbour gathers of adjacent groups then hit the same XCD-private L2.
+__device__ __forceinline__ int xcd_group(int g, int ngroups) {
+    constexpr int kXcd = 8;
+    const int q = ngroups / kXcd, r = ngroups % kXcd;
+    const int x = g % kXcd, k = g / kXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Sign in bit 31 of a packed edge index: flip the sign bit of the value.
+__device__ __forceinline__ float signed_load(const float *__restrict__ v, uint32_t packed) {
+    const float x = v[packed & 0x7FFFFFFFu];
+    return __uint_as_float(__float_as_uint(x) ^ (packed & 0x80000000u));
+}
+__device__ __forceinline__ double signed_load(const double *__restrict__ v, uint32_t packed) {
+    const double x = v[packed & 0x7FFFFFFFu];
+    const unsigned long long bits = __double_as_longlong(x) ^ (uint64_t(packed & 0x80000000u) << 32);
+    return __longlong_as_double(bits);
+}
+
+// Edge half-step (eq. 3): Et_i += cE_i (B_R - B_L).
+template <typename T>
+__global__ __launch_bounds__(256) void k_edge(int n, T *__restrict__ Et, const T *__restrict__ B,
+                                              const T *__restrict__ cE, const int2 *__restrict__ RL) {
+    const int i = xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int2 rl = RL[i];
+    const T diff = B[rl.x] - B[rl.y];
+    Et[i] = fma(cE[i], diff, Et[i]);
+}
+
+// Triangle half-step (eq. 4): B_j += nB_j ((s0 Et_0 + s1 Et_1) + s2 Et_2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tri(int n, T *__restrict__ B, const T *__restrict__ Et,
+                                             const T *__restrict__ nB, const uint32_t *__restrict__ a0,
+                                             const uint32_t *__restrict__ a1, const uint32_t *__restrict__ a2) {
+    const int j = xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const T circ = (signed_load(Et, a0[j]) + signed_load(Et, a1[j])) + signed_load(Et, a2[j]);
+    B[j] = fma(nB[j], circ, B[j]);
+}
+
+// Plasma current and soft source on the special-edge list (eqs. 5-6), before the edge
+// half-step:  jt <- ca jt + cb Et;  delta = dt jt + w g;  Et -= delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_special(int n, const int32_t *__restrict__ slot, T *__restrict__ Et,
+                                                 T *__restrict__ jt, const T *__restrict__ ca,
+                                                 const T *__restrict__ cb, const T *__restrict__ w,
+                                                 T *__restrict__ delta, T g, T dt) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int e = slot[k];
+    const T e_old = Et[e];
+    const T j = fma(ca[k], jt[k], cb[k] * e_old);
+    jt[k] = j;
+    const T dl = fma(dt, j, w[k] * g);
+    delta[k] = dl;
+    Et[e] = e_old - dl;
+}
+
+// Nodal charge by continuity: Q_v -= sum over its special edges of coef * delta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict__ node,
+                                                const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
+                                                const T *__restrict__ coef, const T *__restrict__ delta,
+                                                T *__restrict__ Q) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    T acc = T(0);
+    for (int r = off[k]; r < off[k + 1]; ++r) acc = fma(coef[r], delta[inc[r]], acc);
+    Q[node[k]] -= acc;
+}
+
+template <typename T>
+inline void launch_edge(hipStream_t s, int64_t n, int grid, T *Et, const T *B, const T *cE, const int2 *RL) {
+    if (n > 0) k_edge<T><<<grid, 256, 0, s>>>(int(n), Et, B, cE, RL);
+}
+
+template <typename T>
+inline void launch_tri(hipStream_t s, int64_t n, int grid, T *B, const T *Et, const T *nB, const uint32_t *a0,
+                       const uint32_t *a1, const uint32_t *a2) {
+    if (n > 0) k_tri<T><<<grid, 256, 0, s>>>(int(n), B, Et, nB, a0, a1, a2);
+}
+
+template <typename T>
+inline void launch_special(hipStream_t s, int64_t n, const int32_t *slot, T *Et, T *jt, const T *ca, const T *cb,
+                           const T *w, T *delta, T g, T dt) {
+    if (n > 0) k_special<T><<<int((n + 255) / 256), 256, 0, s>>>(int(n), slot, Et, jt, ca, cb, w, delta, g, dt);
+}
+
+template <typename T>
+inline void launch_charge(hipStream_t s, int64_t n, const int32_t *node, const int32_t *off, const int32_t *inc,
+                          const T *coef, const T *delta, T *Q) {
+    if (n > 0) k_charge<T><<<int((n + 255) / 256), 256, 0, s>>>(int(n), node, off, inc, coef, delta, Q);
+}
+
+}  // namespace tyee

@@ -1,0 +1,721 @@
+// libtyee device runtime for AMD Instinct MI355X (gfx950): the leap-frog half-step kernels
+// of the triangular Yee-like scheme (arXiv:1812.01448, eqs. 3-6) and the simulation
+// object behind the C ABI.
+//
+// Device formulation. Every edge stores the scaled field Et_i = gamma_i |e_i| E_i, which
+// turns both half-steps into one coefficient per cell:
+//   edge i     : Et_i += cE_i (B_R - B_L),         cE_i = dt gamma_i^2 |e_i| / d_i   (eq. 3)
+//   triangle j : B_j  += nB_j sum_q s(j,q) Et_A,   nB_j = -dt / S_j                 (eq. 4)
+// Signs s(j,q) live in bit 31 of the edge index; outer edges of a closed resonator have
+// cE = 0 and both neighbour slots pointing at their one triangle, so they stay at zero
+// without a branch. The plasma current (eq. 5) and the soft source act on a short list of
+// "special" edges that a small kernel pre-corrects before the edge half-step (eq. 6).
+// Fields, coefficients and indices are separate arrays (structure of arrays) so every
+// per-cell access is a coalesced 4- or 8-byte load; only the neighbour gathers are
+// indirect, and the locality numbering keeps them inside a small window.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace tyee {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+#define TYEE_HIP(call)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(TYEE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int blocks_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// simulation object
+// ---------------------------------------------------------------------------------------
+
+struct DeviceBuffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t n) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = n;
+        if (n == 0) return TYEE_OK;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(TYEE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        return TYEE_OK;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Per-launch HIP-event timing of the stepping kernels (enabled per kernel kind).  A ring
+// of event pairs keeps the queue deep: only the oldest pair is waited for when it fills.
+struct LaunchTimer {
+    static constexpr int kKinds = 5;
+    static constexpr size_t kRing = 1024;
+    struct Pair {
+        int kind = 0;
+        hipEvent_t start = nullptr, stop = nullptr;
+    };
+    uint32_t mask = 0;
+    std::vector<Pair> ring;
+    size_t head = 0, pending = 0;
+    int64_t count[kKinds] = {0, 0, 0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0, 0, 0};
+
+    ~LaunchTimer() {
+        for (auto &p : ring) {
+            if (p.start) (void)hipEventDestroy(p.start);
+            if (p.stop) (void)hipEventDestroy(p.stop);
+        }
+    }
+    void reset(uint32_t m) {
+        mask = m;
+        std::fill(count, count + kKinds, 0);
+        std::fill(total_ms, total_ms + kKinds, 0.0);
+    }
+    int retire_oldest() {
+        Pair &p = ring[(head + ring.size() - pending) % ring.size()];
+        TYEE_HIP(hipEventSynchronize(p.stop));
+        float ms = 0.0f;
+        TYEE_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
+        count[p.kind] += 1;
+        total_ms[p.kind] += ms;
+        --pending;
+        return TYEE_OK;
+    }
+    int drain() {
+        while (pending > 0) {
+            int rc = retire_oldest();
+            if (rc) return rc;
+        }
+        return TYEE_OK;
+    }
+    // returns the ring slot used, or -1 when this kind is not timed
+    int begin(int kind, hipStream_t s, int *rc) {
+        *rc = TYEE_OK;
+        if (!(mask & (1u << kind))) return -1;
+        if (ring.empty()) ring.resize(kRing);
+        if (pending == ring.size() && (*rc = retire_oldest())) return -1;
+        Pair &p = ring[head];
+        if (!p.start && (hipEventCreate(&p.start) != hipSuccess || hipEventCreate(&p.stop) != hipSuccess)) {
+            *rc = fail(TYEE_EDEVICE, "hipEventCreate failed");
+            return -1;
+        }
+        p.kind = kind;
+        if (hipEventRecord(p.start, s) != hipSuccess) {
+            *rc = fail(TYEE_EDEVICE, "hipEventRecord failed");
+            return -1;
+        }
+        int slot = int(head);
+        head = (head + 1) % ring.size();
+        ++pending;
+        return slot;
+    }
+    int end(int slot, hipStream_t s) {
+        if (slot < 0) return TYEE_OK;
+        TYEE_HIP(hipEventRecord(ring[slot].stop, s));
+        return TYEE_OK;
+    }
+};
+
+struct Sim {
+    bool f64 = false;
+    size_t esz = 4;
+    double dt = 0.0;
+    hipStream_t stream = nullptr;
+    int64_t nv = 0, ne = 0, nt = 0;
+    int64_t step = 0;
+    int fusion = 1;
+
+    // host copies (canonical numbering)
+    std::vector<int32_t> perm_t, perm_e, slot_t, slot_e;
+    std::vector<int32_t> edge, R, L, A;
+    std::vector<int8_t> sgn;
+    std::vector<double> elen, d, hR, hL, S;
+    std::vector<uint8_t> node_outer;
+    std::vector<double> gamma;  // per canonical edge
+    std::vector<double> wp2_edge;
+    double nu = 0.0;
+    std::vector<int32_t> src_edge;
+    std::vector<double> src_w;
+    double src_omega = 1.0, src_cycles = 1.0;
+
+    // device arrays, device numbering
+    DeviceBuffer Et, B, cE, nB, RL, A0, A1, A2;
+    // special edges (plasma and/or source)
+    int64_t n_special = 0;
+    std::vector<int32_t> sp_edge;  // canonical edge of each special entry
+    std::vector<uint8_t> sp_plasma;
+    DeviceBuffer sp_slot, sp_j, sp_ca, sp_cb, sp_w, sp_delta;
+    // nodal charge
+    int64_t n_qnode = 0;
+    DeviceBuffer Q, q_node, q_off, q_inc, q_coef;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    LaunchTimer timer;
+
+    ~Sim() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+
+    double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
+};
+
+template <typename T> int launch_fused(Sim &s, int k);
+
+namespace {
+
+template <typename T> int upload(DeviceBuffer &buf, const std::vector<double> &host, hipStream_t s) {
+    std::vector<T> tmp(host.begin(), host.end());
+    int rc = buf.alloc(tmp.size() * sizeof(T));
+    if (rc) return rc;
+    if (tmp.empty()) return TYEE_OK;
+    TYEE_HIP(hipMemcpyAsync(buf.p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    TYEE_HIP(hipStreamSynchronize(s));
+    return TYEE_OK;
+}
+
+template <typename I> int upload_raw(DeviceBuffer &buf, const std::vector<I> &host, hipStream_t s) {
+    int rc = buf.alloc(host.size() * sizeof(I));
+    if (rc) return rc;
+    if (host.empty()) return TYEE_OK;
+    TYEE_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * sizeof(I), hipMemcpyHostToDevice, s));
+    TYEE_HIP(hipStreamSynchronize(s));
+    return TYEE_OK;
+}
+
+template <typename T> int upload_doubles(Sim &s, DeviceBuffer &buf, const std::vector<double> &host) {
+    return upload<T>(buf, host, s.stream);
+}
+
+int upload_field(Sim &s, DeviceBuffer &buf, const std::vector<double> &host) {
+    return s.f64 ? upload_doubles<double>(s, buf, host) : upload_doubles<float>(s, buf, host);
+}
+
+int download_field(Sim &s, const DeviceBuffer &buf, std::vector<double> &host, int64_t n) {
+    host.resize(n);
+    if (n == 0) return TYEE_OK;
+    if (s.f64) {
+        TYEE_HIP(hipMemcpyAsync(host.data(), buf.p, n * sizeof(double), hipMemcpyDeviceToHost, s.stream));
+        TYEE_HIP(hipStreamSynchronize(s.stream));
+    } else {
+        std::vector<float> tmp(n);
+        TYEE_HIP(hipMemcpyAsync(tmp.data(), buf.p, n * sizeof(float), hipMemcpyDeviceToHost, s.stream));
+        TYEE_HIP(hipStreamSynchronize(s.stream));
+        std::copy(tmp.begin(), tmp.end(), host.begin());
+    }
+    return TYEE_OK;
+}
+
+// Coefficients of the two half-steps in device numbering (FP64, rounded once on upload).
+int upload_coefficients(Sim &s) {
+    std::vector<double> ce(s.ne), nb(s.nt);
+    for (int64_t k = 0; k < s.ne; ++k) {
+        int32_t i = s.perm_e[k];
+        bool inner = s.R[i] >= 0 && s.L[i] >= 0;
+        ce[k] = inner ? s.dt * s.gamma[i] * s.gamma[i] * s.elen[i] / s.d[i] : 0.0;
+    }
+    for (int64_t k = 0; k < s.nt; ++k) nb[k] = -s.dt / s.S[s.perm_t[k]];
+    int rc = upload_field(s, s.cE, ce);
+    if (rc) return rc;
+    return upload_field(s, s.nB, nb);
+}
+
+int upload_connectivity(Sim &s) {
+    std::vector<int32_t> rl(2 * s.ne), a0(s.nt), a1(s.nt), a2(s.nt);
+    for (int64_t k = 0; k < s.ne; ++k) {
+        int32_t i = s.perm_e[k];
+        int32_t r = s.R[i], l = s.L[i];
+        int32_t one = r >= 0 ? r : l;  // outer edge: both slots on its one triangle
+        rl[2 * k] = s.slot_t[r >= 0 ? r : one];
+        rl[2 * k + 1] = s.slot_t[l >= 0 ? l : one];
+    }
+    std::vector<int32_t> *dst[3] = {&a0, &a1, &a2};
+    for (int64_t k = 0; k < s.nt; ++k) {
+        int32_t j = s.perm_t[k];
+        for (int q = 0; q < 3; ++q) {
+            uint32_t slot = uint32_t(s.slot_e[s.A[3 * j + q]]);
+            if (s.sgn[3 * j + q] < 0) slot |= 0x80000000u;
+            (*dst[q])[k] = int32_t(slot);
+        }
+    }
+    int rc = upload_raw(s.RL, rl, s.stream);
+    if (!rc) rc = upload_raw(s.A0, a0, s.stream);
+    if (!rc) rc = upload_raw(s.A1, a1, s.stream);
+    if (!rc) rc = upload_raw(s.A2, a2, s.stream);
+    return rc;
+}
+
+// Special edges: plasma edges (wp2 > 0) and source edges, each listed once.  The nodal
+// charge list holds every interior node touching a special edge with its incidences.
+int rebuild_specials(Sim &s) {
+    std::vector<int64_t> which(s.ne, -1);
+    s.sp_edge.clear();
+    s.sp_plasma.clear();
+    auto add = [&](int32_t i) {
+        if (which[i] < 0) {
+            which[i] = int64_t(s.sp_edge.size());
+            s.sp_edge.push_back(i);
+            s.sp_plasma.push_back(0);
+        }
+        return which[i];
+    };
+    if (!s.wp2_edge.empty())
+        for (int64_t i = 0; i < s.ne; ++i)
+            if (s.wp2_edge[i] > 0.0) s.sp_plasma[add(int32_t(i))] = 1;
+    std::vector<double> wsum;
+    for (size_t r = 0; r < s.src_edge.size(); ++r) add(s.src_edge[r]);
+    const int64_t n = int64_t(s.sp_edge.size());
+    s.n_special = n;
+    std::vector<int32_t> slot(n);
+    std::vector<double> ca(n, 0.0), cb(n, 0.0), w(n, 0.0), zero(n, 0.0);
+    const double half = s.nu * s.dt / 2.0;
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t i = s.sp_edge[k];
+        slot[k] = s.slot_e[i];
+        if (s.sp_plasma[k]) {
+            ca[k] = (1.0 - half) / (1.0 + half);
+            cb[k] = s.dt * s.wp2_edge[i] / (1.0 + half);
+        }
+    }
+    // Et is decreased by dt * scale * Jsrc = (dt * scale * w) * g(t)
+    for (size_t r = 0; r < s.src_edge.size(); ++r) {
+        int32_t i = s.src_edge[r];
+        w[which[i]] += s.dt * s.scale(i) * s.src_w[r];
+    }
+    int rc = upload_raw(s.sp_slot, slot, s.stream);
+    if (!rc) rc = upload_field(s, s.sp_j, zero);
+    if (!rc) rc = upload_field(s, s.sp_ca, ca);
+    if (!rc) rc = upload_field(s, s.sp_cb, cb);
+    if (!rc) rc = upload_field(s, s.sp_w, w);
+    if (!rc) rc = upload_field(s, s.sp_delta, zero);
+    if (rc) return rc;
+
+    // node incidences: Q_k -= sum sigma(k,i) d_i/scale_i * delta_i  (delta = dt scale (j + Jsrc))
+    std::vector<std::vector<std::pair<int32_t, double>>> inc(s.nv);
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t i = s.sp_edge[k];
+        double c = s.d[i] / s.scale(i);
+        int32_t lo = s.edge[2 * i], hi = s.edge[2 * i + 1];
+        if (!s.node_outer[lo]) inc[lo].push_back({int32_t(k), +c});
+        if (!s.node_outer[hi]) inc[hi].push_back({int32_t(k), -c});
+    }
+    std::vector<int32_t> qn, off{0}, qk;
+    std::vector<double> qc;
+    for (int64_t v = 0; v < s.nv; ++v) {
+        if (inc[v].empty()) continue;
+        qn.push_back(int32_t(v));
+        for (auto &p : inc[v]) {
+            qk.push_back(p.first);
+            qc.push_back(p.second);
+        }
+        off.push_back(int32_t(qk.size()));
+    }
+    s.n_qnode = int64_t(qn.size());
+    rc = upload_raw(s.q_node, qn, s.stream);
+    if (!rc) rc = upload_raw(s.q_off, off, s.stream);
+    if (!rc) rc = upload_raw(s.q_inc, qk, s.stream);
+    if (!rc) rc = upload_field(s, s.q_coef, qc);
+    return rc;
+}
+
+double waveform(double t, double omega, double cycles) {
+    const double T = cycles * 2.0 * M_PI / omega;
+    if (!(t >= 0.0 && t < T)) return 0.0;
+    const double s = std::sin(M_PI * t / T);
+    return std::sin(omega * t) * s * s;
+}
+
+// Launch one kernel kind, bracketed by timing events when that kind is profiled.
+template <typename F> int timed(Sim &s, int kind, F &&launch) {
+    int rc;
+    int slot = s.timer.begin(kind, s.stream, &rc);
+    if (rc) return rc;
+    launch();
+    return s.timer.end(slot, s.stream);
+}
+
+template <typename T> int enqueue_steps(Sim &s, int64_t n) {
+    const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
+    T *Et = s.Et.as<T>(), *B = s.B.as<T>();
+    const T *cE = s.cE.as<T>(), *nB = s.nB.as<T>();
+    const int2 *RL = s.RL.as<int2>();
+    const uint32_t *a0 = s.A0.as<uint32_t>(), *a1 = s.A1.as<uint32_t>(), *a2 = s.A2.as<uint32_t>();
+    const bool special = s.n_special > 0;
+    int64_t done = 0;
+    int rc = TYEE_OK;
+    while (done < n && !rc) {
+        int k = 1;
+        if (special) {
+            const double g = waveform((double(s.step) + 0.5) * s.dt, s.src_omega, s.src_cycles);
+            rc = timed(s, TYEE_KERNEL_SPECIAL, [&] {
+                launch_special<T>(s.stream, s.n_special, s.sp_slot.as<int32_t>(), Et, s.sp_j.as<T>(),
+                                  s.sp_ca.as<T>(), s.sp_cb.as<T>(), s.sp_w.as<T>(), s.sp_delta.as<T>(),
+                                  T(g), T(s.dt));
+            });
+            if (!rc && s.n_qnode > 0)
+                rc = timed(s, TYEE_KERNEL_CHARGE, [&] {
+                    launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(),
+                                     s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(),
+                                     s.Q.as<T>());
+                });
+        } else {
+            k = s.fusion;
+            while (k > 1 && k > n - done) k >>= 1;
+        }
+        if (rc) break;
+        if (k > 1) {
+            rc = timed(s, TYEE_KERNEL_FUSED, [&] { launch_fused<T>(s, k); });
+        } else {
+            rc = timed(s, TYEE_KERNEL_EDGE, [&] { launch_edge<T>(s.stream, s.ne, ge, Et, B, cE, RL); });
+            if (!rc)
+                rc = timed(s, TYEE_KERNEL_TRI, [&] { launch_tri<T>(s.stream, s.nt, gt, B, Et, nB, a0, a1, a2); });
+        }
+        s.step += k;
+        done += k;
+    }
+    if (rc) return rc;
+    TYEE_HIP(hipGetLastError());
+    return TYEE_OK;
+}
+
+}  // namespace
+
+// Fused multi-step launches (tile kernels in fused.hip); falls back to k = 1 launches when
+// no tiling was prepared.
+template <typename T> int launch_fused(Sim &s, int k) {
+    const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
+    for (int r = 0; r < k; ++r) {
+        launch_edge<T>(s.stream, s.ne, ge, s.Et.as<T>(), s.B.as<T>(), s.cE.as<T>(), s.RL.as<int2>());
+        launch_tri<T>(s.stream, s.nt, gt, s.B.as<T>(), s.Et.as<T>(), s.nB.as<T>(),
+                      s.A0.as<uint32_t>(), s.A1.as<uint32_t>(), s.A2.as<uint32_t>());
+    }
+    return TYEE_OK;
+}
+
+}  // namespace tyee
+
+// ---------------------------------------------------------------------------------------
+// C ABI: simulation
+// ---------------------------------------------------------------------------------------
+
+struct tyee_sim {
+    tyee::Sim s;
+};
+
+using tyee::fail;
+
+extern "C" {
+
+int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream, tyee_sim **out) {
+    if (!mesh || !out) return fail(TYEE_EINVAL, "null argument");
+    *out = nullptr;
+    if (prec != TYEE_F32 && prec != TYEE_F64) return fail(TYEE_EINVAL, "prec must be TYEE_F32 or TYEE_F64");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TYEE_EINVAL, "dt must be positive and finite");
+    try {
+        std::unique_ptr<tyee_sim> h(new tyee_sim());
+        tyee::Sim &s = h->s;
+        const tyee::Mesh &m = mesh->m;
+        s.f64 = prec == TYEE_F64;
+        s.esz = s.f64 ? 8 : 4;
+        s.dt = dt;
+        s.stream = static_cast<hipStream_t>(stream);
+        s.nv = m.nv;
+        s.ne = m.ne;
+        s.nt = m.nt;
+        s.perm_t = m.perm_t;
+        s.perm_e = m.perm_e;
+        s.slot_t.resize(m.nt);
+        s.slot_e.resize(m.ne);
+        for (int64_t k = 0; k < m.nt; ++k) s.slot_t[m.perm_t[k]] = int32_t(k);
+        for (int64_t k = 0; k < m.ne; ++k) s.slot_e[m.perm_e[k]] = int32_t(k);
+        s.edge = m.edge;
+        s.R = m.R;
+        s.L = m.L;
+        s.A = m.A;
+        s.sgn = m.sgn;
+        s.elen = m.elen;
+        s.d = m.d;
+        s.hR = m.hR;
+        s.hL = m.hL;
+        s.S = m.S;
+        s.node_outer = m.node_outer;
+        s.gamma.assign(m.ne, 1.0);
+        int device = 0;
+        hipError_t e = hipGetDevice(&device);
+        if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+        std::vector<double> zero_e(m.ne, 0.0), zero_t(m.nt, 0.0), zero_v(m.nv, 0.0);
+        int rc = tyee::upload_field(s, s.Et, zero_e);
+        if (!rc) rc = tyee::upload_field(s, s.B, zero_t);
+        if (!rc) rc = tyee::upload_field(s, s.Q, zero_v);
+        if (!rc) rc = tyee::upload_coefficients(s);
+        if (!rc) rc = tyee::upload_connectivity(s);
+        if (!rc) rc = tyee::rebuild_specials(s);
+        if (rc) return rc;
+        if (hipEventCreate(&s.ev0) != hipSuccess || hipEventCreate(&s.ev1) != hipSuccess)
+            return fail(TYEE_EDEVICE, "hipEventCreate failed");
+        *out = h.release();
+        return TYEE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(TYEE_ENOMEM, "host allocation failed");
+    }
+}
+
+int tyee_sim_set_state(tyee_sim *sim, int32_t field, const double *host) {
+    if (!sim || !host) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    std::vector<double> dev;
+    switch (field) {
+    case TYEE_FIELD_E:
+        dev.resize(s.ne);
+        for (int64_t k = 0; k < s.ne; ++k) {
+            int32_t i = s.perm_e[k];
+            dev[k] = (s.R[i] >= 0 && s.L[i] >= 0) ? s.scale(i) * host[i] : 0.0;
+        }
+        return tyee::upload_field(s, s.Et, dev);
+    case TYEE_FIELD_B:
+        dev.resize(s.nt);
+        for (int64_t k = 0; k < s.nt; ++k) dev[k] = host[s.perm_t[k]];
+        return tyee::upload_field(s, s.B, dev);
+    case TYEE_FIELD_J: {
+        std::vector<uint8_t> listed(s.ne, 0);
+        dev.assign(s.n_special, 0.0);
+        for (int64_t k = 0; k < s.n_special; ++k)
+            if (s.sp_plasma[k]) {
+                int32_t i = s.sp_edge[k];
+                listed[i] = 1;
+                dev[k] = s.scale(i) * host[i];
+            }
+        for (int64_t i = 0; i < s.ne; ++i)
+            if (!listed[i] && host[i] != 0.0) return fail(TYEE_EINVAL, "current on a non-plasma edge");
+        if (s.n_special == 0) return TYEE_OK;
+        return tyee::upload_field(s, s.sp_j, dev);
+    }
+    case TYEE_FIELD_Q:
+        dev.assign(host, host + s.nv);
+        return tyee::upload_field(s, s.Q, dev);
+    default:
+        return fail(TYEE_EINVAL, "unknown field");
+    }
+}
+
+int tyee_sim_get_state(tyee_sim *sim, int32_t field, double *host) {
+    if (!sim || !host) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    std::vector<double> dev;
+    int rc;
+    switch (field) {
+    case TYEE_FIELD_E:
+        if ((rc = tyee::download_field(s, s.Et, dev, s.ne))) return rc;
+        for (int64_t k = 0; k < s.ne; ++k) {
+            int32_t i = s.perm_e[k];
+            host[i] = dev[k] / s.scale(i);
+        }
+        return TYEE_OK;
+    case TYEE_FIELD_B:
+        if ((rc = tyee::download_field(s, s.B, dev, s.nt))) return rc;
+        for (int64_t k = 0; k < s.nt; ++k) host[s.perm_t[k]] = dev[k];
+        return TYEE_OK;
+    case TYEE_FIELD_J:
+        std::fill(host, host + s.ne, 0.0);
+        if (s.n_special == 0) return TYEE_OK;
+        if ((rc = tyee::download_field(s, s.sp_j, dev, s.n_special))) return rc;
+        for (int64_t k = 0; k < s.n_special; ++k)
+            if (s.sp_plasma[k]) host[s.sp_edge[k]] = dev[k] / s.scale(s.sp_edge[k]);
+        return TYEE_OK;
+    case TYEE_FIELD_Q:
+        if ((rc = tyee::download_field(s, s.Q, dev, s.nv))) return rc;
+        std::copy(dev.begin(), dev.end(), host);
+        return TYEE_OK;
+    default:
+        return fail(TYEE_EINVAL, "unknown field");
+    }
+}
+
+int tyee_sim_set_media(tyee_sim *sim, const double *wp2_tri, double nu) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(TYEE_EINVAL, "nu must be >= 0");
+    tyee::Sim &s = sim->s;
+    if (!wp2_tri) {
+        s.wp2_edge.clear();
+        s.nu = 0.0;
+        return tyee::rebuild_specials(s);
+    }
+    for (int64_t j = 0; j < s.nt; ++j)
+        if (!(wp2_tri[j] >= 0.0) || !std::isfinite(wp2_tri[j]))
+            return fail(TYEE_EINVAL, "plasma frequency squared must be finite and >= 0");
+    s.wp2_edge.assign(s.ne, 0.0);
+    for (int64_t i = 0; i < s.ne; ++i)
+        if (s.R[i] >= 0 && s.L[i] >= 0)
+            s.wp2_edge[i] = (s.hR[i] * wp2_tri[s.R[i]] + s.hL[i] * wp2_tri[s.L[i]]) / s.d[i];
+    s.nu = nu;
+    return tyee::rebuild_specials(s);
+}
+
+int tyee_sim_set_source(tyee_sim *sim, const int32_t *pairs, const double *weights, int64_t n,
+                        double omega, double cycles) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    tyee::Sim &s = sim->s;
+    if (n < 0 || (n > 0 && (!pairs || !weights))) return fail(TYEE_EINVAL, "bad source arrays");
+    if (n > 0 && (!(omega > 0.0) || !(cycles > 0.0))) return fail(TYEE_EINVAL, "omega, cycles must be > 0");
+    std::vector<int32_t> ids(n);
+    std::vector<double> w(n);
+    for (int64_t r = 0; r < n; ++r) {
+        int32_t a = pairs[2 * r], b = pairs[2 * r + 1];
+        if (a < 0 || b < 0 || a >= s.nv || b >= s.nv || a == b) return fail(TYEE_EINVAL, "bad node pair");
+        int32_t lo = std::min(a, b), hi = std::max(a, b);
+        // edges are sorted by (lo, hi): binary search
+        int64_t left = 0, right = s.ne;
+        while (left < right) {
+            int64_t mid = (left + right) / 2;
+            int32_t ml = s.edge[2 * mid], mh = s.edge[2 * mid + 1];
+            if (ml < lo || (ml == lo && mh < hi)) left = mid + 1;
+            else right = mid;
+        }
+        if (left >= s.ne || s.edge[2 * left] != lo || s.edge[2 * left + 1] != hi)
+            return fail(TYEE_EINVAL, "node pair is not a mesh edge");
+        if (!(s.R[left] >= 0 && s.L[left] >= 0)) return fail(TYEE_EINVAL, "source on an outer edge");
+        ids[r] = int32_t(left);
+        w[r] = a < b ? weights[r] : -weights[r];
+    }
+    s.src_edge = ids;
+    s.src_w = w;
+    s.src_omega = n > 0 ? omega : 1.0;
+    s.src_cycles = n > 0 ? cycles : 1.0;
+    // keep the plasma current across a source change
+    std::vector<double> J(s.ne, 0.0);
+    int rc = tyee_sim_get_state(sim, TYEE_FIELD_J, J.data());
+    if (!rc) rc = tyee::rebuild_specials(s);
+    if (!rc) rc = tyee_sim_set_state(sim, TYEE_FIELD_J, J.data());
+    return rc;
+}
+
+int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    tyee::Sim &s = sim->s;
+    if (gamma)
+        for (int64_t i = 0; i < s.ne; ++i)
+            if (!(gamma[i] > 0.0) || !std::isfinite(gamma[i])) return fail(TYEE_EINVAL, "gamma must be > 0");
+    std::vector<double> E(s.ne), J(s.ne);
+    int rc = tyee_sim_get_state(sim, TYEE_FIELD_E, E.data());
+    if (!rc) rc = tyee_sim_get_state(sim, TYEE_FIELD_J, J.data());
+    if (rc) return rc;
+    if (gamma) s.gamma.assign(gamma, gamma + s.ne);
+    else s.gamma.assign(s.ne, 1.0);
+    rc = tyee::upload_coefficients(s);
+    if (!rc) rc = tyee::rebuild_specials(s);
+    if (!rc) rc = tyee_sim_set_state(sim, TYEE_FIELD_E, E.data());
+    if (!rc) rc = tyee_sim_set_state(sim, TYEE_FIELD_J, J.data());
+    return rc;
+}
+
+int tyee_sim_set_fusion(tyee_sim *sim, int32_t k) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    if (k == 0) k = 1;
+    if (k != 1 && k != 2 && k != 4 && k != 8) return fail(TYEE_EINVAL, "steps per launch must be 1, 2, 4 or 8");
+    sim->s.fusion = k;
+    return TYEE_OK;
+}
+
+int tyee_sim_step(tyee_sim *sim, int64_t n) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    if (n < 0) return fail(TYEE_EINVAL, "negative step count");
+    tyee::Sim &s = sim->s;
+    if (n == 0) return TYEE_OK;
+    TYEE_HIP(hipEventRecord(s.ev0, s.stream));
+    int rc = s.f64 ? tyee::enqueue_steps<double>(s, n) : tyee::enqueue_steps<float>(s, n);
+    if (rc) return rc;
+    TYEE_HIP(hipEventRecord(s.ev1, s.stream));
+    return TYEE_OK;
+}
+
+int tyee_sim_sync(tyee_sim *sim) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    TYEE_HIP(hipStreamSynchronize(sim->s.stream));
+    return TYEE_OK;
+}
+
+int tyee_sim_last_step_ms(tyee_sim *sim, double *ms) {
+    if (!sim || !ms) return fail(TYEE_EINVAL, "null argument");
+    TYEE_HIP(hipEventSynchronize(sim->s.ev1));
+    float f = 0.0f;
+    TYEE_HIP(hipEventElapsedTime(&f, sim->s.ev0, sim->s.ev1));
+    *ms = f;
+    return TYEE_OK;
+}
+
+int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out) {
+    if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    std::vector<double> E(s.ne), B(s.nt);
+    int rc = tyee_sim_get_state(sim, TYEE_FIELD_E, E.data());
+    if (!rc) rc = tyee_sim_get_state(sim, TYEE_FIELD_B, B.data());
+    if (rc) return rc;
+    tyee_diag d{};
+    d.step = s.step;
+    d.time = double(s.step) * s.dt;
+    bool bad = false;
+    for (int64_t i = 0; i < s.ne; ++i) {
+        bad |= !std::isfinite(E[i]);
+        d.max_abs_E = std::max(d.max_abs_E, std::fabs(E[i]));
+        if (s.R[i] >= 0 && s.L[i] >= 0) d.energy += s.d[i] * s.elen[i] * E[i] * E[i];
+    }
+    for (int64_t j = 0; j < s.nt; ++j) {
+        bad |= !std::isfinite(B[j]);
+        d.max_abs_B = std::max(d.max_abs_B, std::fabs(B[j]));
+        d.energy += s.S[j] * B[j] * B[j];
+    }
+    d.nonfinite = bad;
+    *out = d;
+    return bad ? fail(TYEE_EUNSTABLE, "non-finite field value") : TYEE_OK;
+}
+
+int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    int rc = sim->s.timer.drain();
+    if (rc) return rc;
+    sim->s.timer.reset(kinds);
+    return TYEE_OK;
+}
+
+int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *total_ms) {
+    if (!sim || !count || !total_ms) return fail(TYEE_EINVAL, "null argument");
+    if (kind < 0 || kind >= tyee::LaunchTimer::kKinds) return fail(TYEE_EINVAL, "unknown kernel kind");
+    int rc = sim->s.timer.drain();
+    if (rc) return rc;
+    *count = sim->s.timer.count[kind];
+    *total_ms = sim->s.timer.total_ms[kind];
+    return TYEE_OK;
+}
+
+int tyee_sim_get_fusion(const tyee_sim *sim, int32_t *k) {
+    if (!sim || !k) return fail(TYEE_EINVAL, "null argument");
+    *k = sim->s.fusion;
+    return TYEE_OK;
+}
+
+int64_t tyee_sim_steps(const tyee_sim *sim) { return sim ? sim->s.step : -1; }
+
+void tyee_sim_destroy(tyee_sim *sim) { delete sim; }
+
+}  // extern "C"

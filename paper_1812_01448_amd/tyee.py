@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libtyee (the C ABI declared in include/tyee.h).
+
+Argument marshalling only: every step of the solver runs in the native library. The
+library must have been built (``python -m paper_1812_01448_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises immediately.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtyee.so")
+
+OK, EINVAL, ENOTDELAUNAY, EDEGENERATE, ENONMANIFOLD, EPERIODIC, ENOMEM, EDEVICE, \
+    EUNSTABLE, ENOTCONVERGED = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+PEC_BOX, PERIODIC = 0, 1
+ORDER = {"none": 0, "random": 1, "morton": 2, "rcm": 3}
+PREC = {"f32": 0, "f64": 1}
+FIELD = {"E": 0, "B": 1, "J": 2, "Q": 3}
+
+
+class TyeeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tyee error {code}: {msg}")
+        self.code = code
+
+
+class _Domain(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("dual_tol", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("n_tris", ctypes.c_int64), ("n_boundary_edges", ctypes.c_int64),
+                ("min_dual_ratio", ctypes.c_double), ("max_dual_ratio", ctypes.c_double),
+                ("sum_area", ctypes.c_double), ("sum_dual_area", ctypes.c_double),
+                ("n_obtuse", ctypes.c_int64)]
+
+
+_VIEW_FIELDS = ["tri", "edge_nodes", "R", "L", "A", "sgn", "elen", "evec", "hR", "hL", "d",
+                "S", "O", "C", "perm_t", "perm_e"]
+
+
+class _View(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in _VIEW_FIELDS]
+
+
+class _Diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
+                ("max_abs_E", ctypes.c_double), ("max_abs_B", ctypes.c_double),
+                ("nonfinite", ctypes.c_int32)]
+
+
+EXPORTS = [
+    "tyee_mesh_create", "tyee_mesh_reorder", "tyee_mesh_query", "tyee_mesh_view",
+    "tyee_mesh_cfl", "tyee_mesh_destroy", "tyee_sim_create", "tyee_sim_set_state",
+    "tyee_sim_get_state", "tyee_sim_set_media", "tyee_sim_set_source",
+    "tyee_sim_set_edge_scale", "tyee_sim_set_fusion", "tyee_sim_step", "tyee_sim_sync",
+    "tyee_sim_diagnostics", "tyee_sim_last_step_ms", "tyee_sim_set_profiling",
+    "tyee_sim_kernel_times", "tyee_sim_get_fusion", "tyee_sim_steps", "tyee_sim_destroy",
+    "tyee_last_error",
+]
+KERNELS = {"edge": 0, "tri": 1, "fused": 2, "special": 3, "charge": 4}
+KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special": "k_special",
+                "charge": "k_charge"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libtyee.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "tyee_mesh_create": [vp, i64, vp, i64, ctypes.POINTER(_Domain), ctypes.POINTER(vp)],
+        "tyee_mesh_reorder": [vp, i32, ctypes.c_uint64],
+        "tyee_mesh_query": [vp, ctypes.POINTER(_Info)],
+        "tyee_mesh_view": [vp, ctypes.POINTER(_View)],
+        "tyee_mesh_cfl": [vp, vp, i64, f64, ctypes.c_uint64, ctypes.POINTER(f64),
+                          ctypes.POINTER(i64)],
+        "tyee_sim_create": [vp, i32, f64, vp, ctypes.POINTER(vp)],
+        "tyee_sim_set_state": [vp, i32, vp],
+        "tyee_sim_get_state": [vp, i32, vp],
+        "tyee_sim_set_media": [vp, vp, f64],
+        "tyee_sim_set_source": [vp, vp, vp, i64, f64, f64],
+        "tyee_sim_set_edge_scale": [vp, vp],
+        "tyee_sim_set_fusion": [vp, i32],
+        "tyee_sim_step": [vp, i64],
+        "tyee_sim_sync": [vp],
+        "tyee_sim_diagnostics": [vp, ctypes.POINTER(_Diag)],
+        "tyee_sim_last_step_ms": [vp, ctypes.POINTER(f64)],
+        "tyee_sim_set_profiling": [vp, ctypes.c_uint32],
+        "tyee_sim_kernel_times": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)],
+        "tyee_sim_get_fusion": [vp, ctypes.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.tyee_mesh_destroy.argtypes = [vp]
+    lib.tyee_mesh_destroy.restype = None
+    lib.tyee_sim_destroy.argtypes = [vp]
+    lib.tyee_sim_destroy.restype = None
+    lib.tyee_sim_steps.argtypes = [vp]
+    lib.tyee_sim_steps.restype = i64
+    lib.tyee_last_error.argtypes = []
+    lib.tyee_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise TyeeError(rc, lib.tyee_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+class Mesh:
+    """Connectivity, FP64 geometry and locality numbering of a triangle mesh."""
+
+    def __init__(self, xy, tri, periodic, L=1.0, Ly=None, dual_tol=0.0):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        dom = _Domain(PERIODIC if periodic else PEC_BOX, float(L), float(L if Ly is None else Ly),
+                      float(dual_tol))
+        h = ctypes.c_void_p()
+        _check(lib.tyee_mesh_create(_ptr(xy), len(xy), _ptr(tri), len(tri), ctypes.byref(dom),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.periodic = bool(periodic)
+        info = self.info()
+        self.nv, self.ne, self.nt, self.nb = (info["n_nodes"], info["n_edges"], info["n_tris"],
+                                              info["n_boundary_edges"])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_mesh_destroy(h)
+            self._h = None
+
+    def reorder(self, kind, seed=0):
+        _check(lib.tyee_mesh_reorder(self._h, ORDER[kind] if isinstance(kind, str) else int(kind),
+                                     int(seed)))
+
+    def info(self):
+        out = _Info()
+        _check(lib.tyee_mesh_query(self._h, ctypes.byref(out)))
+        return {n: getattr(out, n) for n, _ in _Info._fields_}
+
+    def view(self):
+        """Copies of the mesh arrays (canonical numbering)."""
+        v = _View()
+        _check(lib.tyee_mesh_view(self._h, ctypes.byref(v)))
+        ne, nt = self.ne, self.nt
+        spec = {"tri": (np.int32, (nt, 3)), "edge_nodes": (np.int32, (ne, 2)),
+                "R": (np.int32, (ne,)), "L": (np.int32, (ne,)), "A": (np.int32, (nt, 3)),
+                "sgn": (np.int8, (nt, 3)), "elen": (np.float64, (ne,)),
+                "evec": (np.float64, (ne, 2)), "hR": (np.float64, (ne,)),
+                "hL": (np.float64, (ne,)), "d": (np.float64, (ne,)), "S": (np.float64, (nt,)),
+                "O": (np.float64, (nt, 2)), "C": (np.float64, (ne, 2)),
+                "perm_t": (np.int32, (nt,)), "perm_e": (np.int32, (ne,))}
+        out = {}
+        for name, (dt, shape) in spec.items():
+            n = int(np.prod(shape))
+            buf = (ctypes.c_byte * (n * np.dtype(dt).itemsize)).from_address(getattr(v, name))
+            out[name] = np.frombuffer(buf, dtype=dt).reshape(shape).copy()
+        return out
+
+    def cfl(self, gamma=None, max_iter=20000, rtol=1e-12, seed=0):
+        """(omega_max^2, iterations, converged) of K = -L_E L_B."""
+        lam = ctypes.c_double()
+        it = ctypes.c_int64()
+        g = None if gamma is None else _f64(gamma, self.ne)
+        rc = _check(lib.tyee_mesh_cfl(self._h, _ptr(g), int(max_iter), float(rtol), int(seed),
+                                      ctypes.byref(lam), ctypes.byref(it)), allow=(ENOTCONVERGED,))
+        return lam.value, it.value, rc == OK
+
+
+class Sim:
+    """Device state of one mesh: leap-frog stepping on a HIP stream."""
+
+    def __init__(self, mesh, dt, prec="f32", stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.tyee_sim_create(mesh._h, PREC[prec], float(dt),
+                                   None if stream is None else int(stream), ctypes.byref(h)))
+        self._h = h
+        self.nv, self.ne, self.nt = mesh.nv, mesh.ne, mesh.nt
+        self.prec = prec
+        self.dt = float(dt)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_sim_destroy(h)
+            self._h = None
+
+    def _n(self, field):
+        return {"E": self.ne, "B": self.nt, "J": self.ne, "Q": self.nv}[field]
+
+    def set_state(self, field, values):
+        a = _f64(values, self._n(field))
+        _check(lib.tyee_sim_set_state(self._h, FIELD[field], _ptr(a)))
+
+    def get_state(self, field):
+        out = np.zeros(self._n(field))
+        _check(lib.tyee_sim_get_state(self._h, FIELD[field], _ptr(out)))
+        return out
+
+    def set_media(self, wp2_tri, nu):
+        a = None if wp2_tri is None else _f64(wp2_tri, self.nt)
+        _check(lib.tyee_sim_set_media(self._h, _ptr(a), float(nu)))
+
+    def set_source(self, pairs, weights, omega, cycles):
+        p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        w = _f64(weights, len(p))
+        _check(lib.tyee_sim_set_source(self._h, _ptr(p), _ptr(w), len(p), float(omega),
+                                       float(cycles)))
+
+    def set_edge_scale(self, gamma):
+        g = None if gamma is None else _f64(gamma, self.ne)
+        _check(lib.tyee_sim_set_edge_scale(self._h, _ptr(g)))
+
+    def set_fusion(self, k):
+        _check(lib.tyee_sim_set_fusion(self._h, int(k)))
+
+    def step(self, n):
+        _check(lib.tyee_sim_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib.tyee_sim_sync(self._h))
+
+    def last_step_ms(self):
+        ms = ctypes.c_double()
+        _check(lib.tyee_sim_last_step_ms(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def set_profiling(self, on=True, kinds=None):
+        """Time launches with HIP events: all kernel kinds, or the named ones."""
+        mask = 0
+        if on:
+            names = KERNELS if kinds is None else kinds
+            for k in names:
+                mask |= 1 << KERNELS[k]
+        _check(lib.tyee_sim_set_profiling(self._h, mask))
+
+    def kernel_times(self):
+        """{kind: {count, total_ms, name, steps_per_launch}} for kinds with timed launches."""
+        out = {}
+        for name, kind in KERNELS.items():
+            c, t = ctypes.c_int64(), ctypes.c_double()
+            _check(lib.tyee_sim_kernel_times(self._h, kind, ctypes.byref(c), ctypes.byref(t)))
+            if c.value:
+                out[name] = {"count": c.value, "total_ms": t.value, "name": KERNEL_NAMES[name],
+                             "steps_per_launch": self.fusion_used() if name == "fused" else 1}
+        return out
+
+    def fusion_used(self):
+        k = ctypes.c_int32()
+        _check(lib.tyee_sim_get_fusion(self._h, ctypes.byref(k)))
+        return k.value
+
+    def diagnostics(self):
+        d = _Diag()
+        _check(lib.tyee_sim_diagnostics(self._h, ctypes.byref(d)), allow=(EUNSTABLE,))
+        return {n: getattr(d, n) for n, _ in _Diag._fields_}
+
+    @property
+    def steps(self):
+        return int(lib.tyee_sim_steps(self._h))

@@ -1,0 +1,114 @@
+"""Host side of the library (no GPU): exports, connectivity, geometry and orderings against
+the oracle, error paths and the omega_max iteration."""
+import ctypes
+import re
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from meshgen import lattice_mesh, scramble, equilateral_torus
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ty():
+    import paper_1812_01448_amd as ty
+    return ty
+
+
+def test_every_declared_symbol_is_exported(ty):
+    header = open(os.path.join(ROOT, "include", "tyee.h")).read()
+    declared = set(re.findall(r"\b(tyee_[a-z_0-9]+)\s*\(", header))
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(ty.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(ty.EXPORTS)
+
+
+@pytest.mark.parametrize("periodic,n,jitter,seed", [(False, 45, 0.2, 0), (True, 64, 0.25, 1),
+                                                    (True, 50, 0.3, 100)])
+def test_connectivity_and_geometry_match_oracle(ty, periodic, n, jitter, seed):
+    xy, tri = lattice_mesh(n, jitter, seed, periodic=periodic)
+    tri, _ = scramble(tri, seed + 1)
+    m = ty.Mesh(xy, tri, periodic)
+    o = oracle.OracleMesh(xy, tri, periodic)
+    v = m.view()
+    for a, b in (("tri", "tri"), ("edge_nodes", "edge"), ("R", "R"), ("L", "L"), ("A", "A"),
+                 ("sgn", "s")):
+        assert np.array_equal(v[a], getattr(o, b)), a
+    for a in ("elen", "hR", "hL", "d", "S", "O", "C"):
+        ref = getattr(o, a)
+        err = np.max(np.abs(v[a] - ref) / np.maximum(np.abs(ref), 1e-300 + np.max(np.abs(ref))))
+        assert err < 1e-12, a
+    np.testing.assert_array_equal(v["evec"], o.evec)
+    info = m.info()
+    assert info["n_edges"] == o.ne and info["n_boundary_edges"] == o.nb
+    assert abs(info["sum_area"] - 1) < 1e-12 and abs(info["sum_dual_area"] - 1) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["none", "random", "morton", "rcm"])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_orderings_bit_exact_against_oracle(ty, kind, periodic):
+    xy, tri = lattice_mesh(70, 0.25, 3, periodic=periodic)
+    m = ty.Mesh(xy, tri, periodic)
+    o = oracle.OracleMesh(xy, tri, periodic)
+    for seed in (0, 12345):
+        m.reorder(kind, seed)
+        v = m.view()
+        pt, pe = o.order(kind, seed)
+        assert np.array_equal(v["perm_t"], pt)
+        assert np.array_equal(v["perm_e"], pe)
+
+
+def test_rcm_with_several_components(ty):
+    # two disjoint boxes in one mesh: RCM must restart per component
+    xy1, t1 = lattice_mesh(8, 0.2, 1, periodic=False)
+    xy2, t2 = lattice_mesh(6, 0.2, 2, periodic=False)
+    xy = np.vstack([xy1, xy2 + [2.0, 0.0]])
+    tri = np.vstack([t1, t2 + len(xy1)]).astype(np.int32)
+    m = ty.Mesh(xy, tri, False, L=3.0)
+    o = oracle.OracleMesh(xy, tri, False, L=3.0)
+    m.reorder("rcm")
+    assert np.array_equal(m.view()["perm_t"], o.order("rcm")[0])
+
+
+def test_error_codes(ty):
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 0.8], [1.5, 0.8]])
+    with pytest.raises(ty.TyeeError) as e:
+        ty.Mesh(xy, np.array([[0, 1, 2], [0, 1, 2]]), False, L=2.0)
+    assert e.value.code == -4
+    with pytest.raises(ty.TyeeError) as e:
+        ty.Mesh(np.array([[0, 0], [1, 0], [2, 0.0]]), np.array([[0, 1, 2]]), False, L=2.0)
+    assert e.value.code == -3
+    with pytest.raises(ty.TyeeError) as e:
+        ty.Mesh(xy, np.array([[0, 1, 3], [0, 3, 2]]), False, L=2.0)
+    assert e.value.code == -2
+    xy3, tri3 = lattice_mesh(6, 0.2, 1, periodic=True)
+    with pytest.raises(ty.TyeeError) as e:
+        ty.Mesh(xy3, tri3[:-1], True)
+    assert e.value.code == -5
+    with pytest.raises(ty.TyeeError) as e:
+        ty.Mesh(xy3, np.array([[0, 1, 99]]), True)
+    assert e.value.code == -1
+    m = ty.Mesh(xy3, tri3, True)
+    with pytest.raises(ty.TyeeError):
+        m.reorder(7)
+
+
+def test_cfl_matches_oracle_and_closed_form(ty):
+    xy, tri, Lx, Ly = equilateral_torus(12, 8)
+    m = ty.Mesh(xy, tri, True, Lx, Ly)
+    lam, it, ok = m.cfl(rtol=1e-14)
+    assert ok and abs(np.sqrt(lam) - 2 * np.sqrt(6)) < 1e-9        # omega_max = 2 sqrt(6)/a
+    xy, tri = lattice_mesh(40, 0.25, 8, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    o = oracle.OracleMesh(xy, tri, True)
+    gamma = 1 + 0.05 * np.cos(np.arange(m.ne))
+    for g in (None, gamma):
+        lam, _, ok = m.cfl(gamma=g)
+        lam_o, _, ok_o = o.power(gamma=g)
+        assert ok and ok_o and abs(lam / lam_o - 1) < 1e-10
