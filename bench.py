@@ -32,7 +32,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=500)
     p.add_argument("--n", type=int, default=N_LATTICE, help="lattice size (default 1415)")
     p.add_argument("--order", default="morton", choices=["none", "random", "morton", "rcm"])
-    p.add_argument("--fusion", type=int, default=0, help="steps per launch (0 = auto)")
+    p.add_argument("--fusion", type=int, default=0, help="steps per launch (0 = library default)")
+    p.add_argument("--tile", type=int, default=0, help="fused tile size in triangles (0 = default)")
     p.add_argument("--prec", default="f32", choices=["f32", "f64"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
@@ -74,14 +75,17 @@ def main():
     sim = ty.Sim(mesh, dt, args.prec, stream=stream.cuda_stream)
     sim.set_state("E", E0)
     sim.set_state("B", B0)
-    sim.set_fusion(args.fusion)
+    sim.set_fusion(args.fusion, args.tile)
     ne, nt = mesh.ne, mesh.nt
     cells = ne + nt
 
     sim.step(args.warmup)
     sim.sync()
+    fuse = sim.fusion_info()
+    K = fuse["steps_per_launch"]
     torch.cuda.synchronize()
-    sim.set_profiling(True)
+    # HIP events bracket every launch of the dominant kernel inside the timed region
+    sim.set_profiling(True, kinds=["fused"] if K > 1 else ["edge", "tri"])
     t_start = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
@@ -96,7 +100,6 @@ def main():
     value = cells * args.steps / elapsed
     esz = 4 if args.prec == "f32" else 8
     # algorithmic bytes (every cell read/written once, compulsory gathers counted once)
-    bytes_edge = (5 * esz) * ne + 2 * 4 * ne + esz * nt - 2 * esz * ne + 0
     bytes_edge = 3 * esz * ne + 8 * ne + esz * nt          # Et r/w + cE, R/L, B gather
     bytes_tri = 3 * esz * nt + 12 * nt + esz * ne           # B r/w + nB, A, Et gather
     algo = {"edge": bytes_edge, "tri": bytes_tri}
@@ -112,6 +115,14 @@ def main():
                 "traffic": None, "avg_launch_ms": round(avg_ms, 5),
                 "algorithmic_bytes_per_launch": per_launch_bytes,
                 "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)}
+    if K > 1:
+        # bytes the fused kernel actually moves per launch (tile cells with halos, once)
+        moved = (fuse["local_tris"] * (esz + esz + 8 + 4) + fuse["local_edges"] * (esz + esz + 4 + 4)
+                 + (nt + ne) * esz)
+        roofline["moved_bytes_per_launch"] = moved
+        roofline["moved_GBs"] = round(moved / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["halo_ratio_tris"] = round(fuse["local_tris"] / nt, 3)
+        roofline["halo_ratio_edges"] = round(fuse["local_edges"] / ne, 3)
 
     cpu = None
     if not args.no_cpu:
@@ -125,7 +136,7 @@ def main():
         "config": {"workload": f"plain FP32 periodic jittered-lattice Delaunay {n}x{n} "
                                f"(+-0.25h), plane-wave packet 20 cells/lambda, CFL 0.5",
                    "triangles": nt, "edges": ne, "cell_updates_per_step": cells,
-                   "order": args.order, "steps_per_launch": sim.fusion_used(),
+                   "order": args.order, "steps_per_launch": K, "tile_tris": fuse["tile"],
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -176,9 +176,13 @@ int tyee_sim_set_source(tyee_sim *sim, const int32_t *node_pairs, const double *
    edge i (the learned correction); NULL restores gamma = 1.  Physical fields are kept. */
 int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma);
 
-/* Steps fused per kernel launch (1, 2, 4 or 8) for vacuum runs; 0 selects automatically.
-   Results are bit-identical for every setting. */
-int tyee_sim_set_fusion(tyee_sim *sim, int32_t steps_per_launch);
+/* Temporal fusion for vacuum runs: advance steps_per_launch (1, 2, 4 or 8; 0 = 4) steps in
+   one launch.  The device numbering is cut into tiles of tile_tris consecutive triangles
+   (0 = a default for the depth; else 256..8192); each work-group loads its tile with
+   steps_per_launch rings of neighbours into LDS, advances them, and writes its own cells to
+   the other of two field buffers.  Results are bit-identical for every setting.  A mesh
+   whose tiles exceed the kernel's capacity falls back to one launch per half-step. */
+int tyee_sim_set_fusion(tyee_sim *sim, int32_t steps_per_launch, int32_t tile_tris);
 
 /* Enqueue n leap-frog steps on the simulation's stream (asynchronous). */
 int tyee_sim_step(tyee_sim *sim, int64_t n);
@@ -215,8 +219,10 @@ int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds);
    last tyee_sim_set_profiling (waits for the timed launches). */
 int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *total_ms);
 
-/* Steps per launch in use for vacuum runs. */
-int tyee_sim_get_fusion(const tyee_sim *sim, int32_t *k);
+/* Fusion in use: out = {steps per launch, tile size in triangles, number of tiles, local
+   triangles summed over tiles, local edges summed over tiles}; the last four are 0 until
+   the first fused launch has built the tiles. */
+int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]);
 
 int64_t tyee_sim_steps(const tyee_sim *sim);
 void tyee_sim_destroy(tyee_sim *sim);

@@ -23,165 +23,11 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "sim.hpp"
 
 namespace tyee {
 
-namespace {
 
-constexpr int kBlock = 256;
-
-#define TYEE_HIP(call)                                                                     \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(TYEE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-int blocks_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
-
-}  // namespace
-
-// ---------------------------------------------------------------------------------------
-// simulation object
-// ---------------------------------------------------------------------------------------
-
-struct DeviceBuffer {
-    void *p = nullptr;
-    size_t bytes = 0;
-    ~DeviceBuffer() {
-        if (p) (void)hipFree(p);
-    }
-    int alloc(size_t n) {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = n;
-        if (n == 0) return TYEE_OK;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return fail(TYEE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        return TYEE_OK;
-    }
-    template <typename T> T *as() const { return static_cast<T *>(p); }
-};
-
-// Per-launch HIP-event timing of the stepping kernels (enabled per kernel kind).  A ring
-// of event pairs keeps the queue deep: only the oldest pair is waited for when it fills.
-struct LaunchTimer {
-    static constexpr int kKinds = 5;
-    static constexpr size_t kRing = 1024;
-    struct Pair {
-        int kind = 0;
-        hipEvent_t start = nullptr, stop = nullptr;
-    };
-    uint32_t mask = 0;
-    std::vector<Pair> ring;
-    size_t head = 0, pending = 0;
-    int64_t count[kKinds] = {0, 0, 0, 0, 0};
-    double total_ms[kKinds] = {0, 0, 0, 0, 0};
-
-    ~LaunchTimer() {
-        for (auto &p : ring) {
-            if (p.start) (void)hipEventDestroy(p.start);
-            if (p.stop) (void)hipEventDestroy(p.stop);
-        }
-    }
-    void reset(uint32_t m) {
-        mask = m;
-        std::fill(count, count + kKinds, 0);
-        std::fill(total_ms, total_ms + kKinds, 0.0);
-    }
-    int retire_oldest() {
-        Pair &p = ring[(head + ring.size() - pending) % ring.size()];
-        TYEE_HIP(hipEventSynchronize(p.stop));
-        float ms = 0.0f;
-        TYEE_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
-        count[p.kind] += 1;
-        total_ms[p.kind] += ms;
-        --pending;
-        return TYEE_OK;
-    }
-    int drain() {
-        while (pending > 0) {
-            int rc = retire_oldest();
-            if (rc) return rc;
-        }
-        return TYEE_OK;
-    }
-    // returns the ring slot used, or -1 when this kind is not timed
-    int begin(int kind, hipStream_t s, int *rc) {
-        *rc = TYEE_OK;
-        if (!(mask & (1u << kind))) return -1;
-        if (ring.empty()) ring.resize(kRing);
-        if (pending == ring.size() && (*rc = retire_oldest())) return -1;
-        Pair &p = ring[head];
-        if (!p.start && (hipEventCreate(&p.start) != hipSuccess || hipEventCreate(&p.stop) != hipSuccess)) {
-            *rc = fail(TYEE_EDEVICE, "hipEventCreate failed");
-            return -1;
-        }
-        p.kind = kind;
-        if (hipEventRecord(p.start, s) != hipSuccess) {
-            *rc = fail(TYEE_EDEVICE, "hipEventRecord failed");
-            return -1;
-        }
-        int slot = int(head);
-        head = (head + 1) % ring.size();
-        ++pending;
-        return slot;
-    }
-    int end(int slot, hipStream_t s) {
-        if (slot < 0) return TYEE_OK;
-        TYEE_HIP(hipEventRecord(ring[slot].stop, s));
-        return TYEE_OK;
-    }
-};
-
-struct Sim {
-    bool f64 = false;
-    size_t esz = 4;
-    double dt = 0.0;
-    hipStream_t stream = nullptr;
-    int64_t nv = 0, ne = 0, nt = 0;
-    int64_t step = 0;
-    int fusion = 1;
-
-    // host copies (canonical numbering)
-    std::vector<int32_t> perm_t, perm_e, slot_t, slot_e;
-    std::vector<int32_t> edge, R, L, A;
-    std::vector<int8_t> sgn;
-    std::vector<double> elen, d, hR, hL, S;
-    std::vector<uint8_t> node_outer;
-    std::vector<double> gamma;  // per canonical edge
-    std::vector<double> wp2_edge;
-    double nu = 0.0;
-    std::vector<int32_t> src_edge;
-    std::vector<double> src_w;
-    double src_omega = 1.0, src_cycles = 1.0;
-
-    // device arrays, device numbering
-    DeviceBuffer Et, B, cE, nB, RL, A0, A1, A2;
-    // special edges (plasma and/or source)
-    int64_t n_special = 0;
-    std::vector<int32_t> sp_edge;  // canonical edge of each special entry
-    std::vector<uint8_t> sp_plasma;
-    DeviceBuffer sp_slot, sp_j, sp_ca, sp_cb, sp_w, sp_delta;
-    // nodal charge
-    int64_t n_qnode = 0;
-    DeviceBuffer Q, q_node, q_off, q_inc, q_coef;
-
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    LaunchTimer timer;
-
-    ~Sim() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-    }
-
-    double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
-};
-
-template <typename T> int launch_fused(Sim &s, int k);
 
 namespace {
 
@@ -236,9 +82,12 @@ int upload_coefficients(Sim &s) {
         ce[k] = inner ? s.dt * s.gamma[i] * s.gamma[i] * s.elen[i] / s.d[i] : 0.0;
     }
     for (int64_t k = 0; k < s.nt; ++k) nb[k] = -s.dt / s.S[s.perm_t[k]];
+    s.ce_dev = ce;
+    s.nb_dev = nb;
     int rc = upload_field(s, s.cE, ce);
-    if (rc) return rc;
-    return upload_field(s, s.nB, nb);
+    if (!rc) rc = upload_field(s, s.nB, nb);
+    if (!rc && s.tiling) rc = refresh_tiling_coefficients(s);
+    return rc;
 }
 
 int upload_connectivity(Sim &s) {
@@ -351,13 +200,13 @@ template <typename F> int timed(Sim &s, int kind, F &&launch) {
     int rc;
     int slot = s.timer.begin(kind, s.stream, &rc);
     if (rc) return rc;
-    launch();
+    rc = launch();
+    if (rc) return rc;
     return s.timer.end(slot, s.stream);
 }
 
 template <typename T> int enqueue_steps(Sim &s, int64_t n) {
     const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
-    T *Et = s.Et.as<T>(), *B = s.B.as<T>();
     const T *cE = s.cE.as<T>(), *nB = s.nB.as<T>();
     const int2 *RL = s.RL.as<int2>();
     const uint32_t *a0 = s.A0.as<uint32_t>(), *a1 = s.A1.as<uint32_t>(), *a2 = s.A2.as<uint32_t>();
@@ -365,6 +214,7 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
     int64_t done = 0;
     int rc = TYEE_OK;
     while (done < n && !rc) {
+        T *Et = s.Et().as<T>(), *B = s.B().as<T>();
         int k = 1;
         if (special) {
             const double g = waveform((double(s.step) + 0.5) * s.dt, s.src_omega, s.src_cycles);
@@ -372,24 +222,41 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
                 launch_special<T>(s.stream, s.n_special, s.sp_slot.as<int32_t>(), Et, s.sp_j.as<T>(),
                                   s.sp_ca.as<T>(), s.sp_cb.as<T>(), s.sp_w.as<T>(), s.sp_delta.as<T>(),
                                   T(g), T(s.dt));
+                return TYEE_OK;
             });
             if (!rc && s.n_qnode > 0)
                 rc = timed(s, TYEE_KERNEL_CHARGE, [&] {
                     launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(),
                                      s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(),
                                      s.Q.as<T>());
+                    return TYEE_OK;
                 });
         } else {
             k = s.fusion;
-            while (k > 1 && k > n - done) k >>= 1;
+            if (k > n - done) k = 1;  // the remainder runs as single steps
         }
         if (rc) break;
+        if (k > 1 && (!s.tiling || s.tiling->K != k)) {
+            rc = build_tiling(s, k, s.tile_tris);
+            if (rc == TYEE_EINVAL) {  // this mesh does not tile at that depth: plain launches
+                clear_error();
+                rc = TYEE_OK;
+                k = 1;
+            }
+            if (rc) break;
+        }
         if (k > 1) {
-            rc = timed(s, TYEE_KERNEL_FUSED, [&] { launch_fused<T>(s, k); });
+            rc = timed(s, TYEE_KERNEL_FUSED, [&] { return launch_fused<T>(s, k); });
         } else {
-            rc = timed(s, TYEE_KERNEL_EDGE, [&] { launch_edge<T>(s.stream, s.ne, ge, Et, B, cE, RL); });
+            rc = timed(s, TYEE_KERNEL_EDGE, [&] {
+                launch_edge<T>(s.stream, s.ne, ge, Et, B, cE, RL);
+                return TYEE_OK;
+            });
             if (!rc)
-                rc = timed(s, TYEE_KERNEL_TRI, [&] { launch_tri<T>(s.stream, s.nt, gt, B, Et, nB, a0, a1, a2); });
+                rc = timed(s, TYEE_KERNEL_TRI, [&] {
+                    launch_tri<T>(s.stream, s.nt, gt, B, Et, nB, a0, a1, a2);
+                    return TYEE_OK;
+                });
         }
         s.step += k;
         done += k;
@@ -401,16 +268,9 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
 
 }  // namespace
 
-// Fused multi-step launches (tile kernels in fused.hip); falls back to k = 1 launches when
-// no tiling was prepared.
-template <typename T> int launch_fused(Sim &s, int k) {
-    const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
-    for (int r = 0; r < k; ++r) {
-        launch_edge<T>(s.stream, s.ne, ge, s.Et.as<T>(), s.B.as<T>(), s.cE.as<T>(), s.RL.as<int2>());
-        launch_tri<T>(s.stream, s.nt, gt, s.B.as<T>(), s.Et.as<T>(), s.nB.as<T>(),
-                      s.A0.as<uint32_t>(), s.A1.as<uint32_t>(), s.A2.as<uint32_t>());
-    }
-    return TYEE_OK;
+Sim::~Sim() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
 }
 
 }  // namespace tyee
@@ -465,8 +325,11 @@ int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream
         hipError_t e = hipGetDevice(&device);
         if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
         std::vector<double> zero_e(m.ne, 0.0), zero_t(m.nt, 0.0), zero_v(m.nv, 0.0);
-        int rc = tyee::upload_field(s, s.Et, zero_e);
-        if (!rc) rc = tyee::upload_field(s, s.B, zero_t);
+        int rc = TYEE_OK;
+        for (int b = 0; b < 2 && !rc; ++b) {
+            rc = tyee::upload_field(s, s.Et_buf[b], zero_e);
+            if (!rc) rc = tyee::upload_field(s, s.B_buf[b], zero_t);
+        }
         if (!rc) rc = tyee::upload_field(s, s.Q, zero_v);
         if (!rc) rc = tyee::upload_coefficients(s);
         if (!rc) rc = tyee::upload_connectivity(s);
@@ -492,11 +355,11 @@ int tyee_sim_set_state(tyee_sim *sim, int32_t field, const double *host) {
             int32_t i = s.perm_e[k];
             dev[k] = (s.R[i] >= 0 && s.L[i] >= 0) ? s.scale(i) * host[i] : 0.0;
         }
-        return tyee::upload_field(s, s.Et, dev);
+        return tyee::upload_field(s, s.Et(), dev);
     case TYEE_FIELD_B:
         dev.resize(s.nt);
         for (int64_t k = 0; k < s.nt; ++k) dev[k] = host[s.perm_t[k]];
-        return tyee::upload_field(s, s.B, dev);
+        return tyee::upload_field(s, s.B(), dev);
     case TYEE_FIELD_J: {
         std::vector<uint8_t> listed(s.ne, 0);
         dev.assign(s.n_special, 0.0);
@@ -526,14 +389,14 @@ int tyee_sim_get_state(tyee_sim *sim, int32_t field, double *host) {
     int rc;
     switch (field) {
     case TYEE_FIELD_E:
-        if ((rc = tyee::download_field(s, s.Et, dev, s.ne))) return rc;
+        if ((rc = tyee::download_field(s, s.Et(), dev, s.ne))) return rc;
         for (int64_t k = 0; k < s.ne; ++k) {
             int32_t i = s.perm_e[k];
             host[i] = dev[k] / s.scale(i);
         }
         return TYEE_OK;
     case TYEE_FIELD_B:
-        if ((rc = tyee::download_field(s, s.B, dev, s.nt))) return rc;
+        if ((rc = tyee::download_field(s, s.B(), dev, s.nt))) return rc;
         for (int64_t k = 0; k < s.nt; ++k) host[s.perm_t[k]] = dev[k];
         return TYEE_OK;
     case TYEE_FIELD_J:
@@ -629,11 +492,16 @@ int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma) {
     return rc;
 }
 
-int tyee_sim_set_fusion(tyee_sim *sim, int32_t k) {
+int tyee_sim_set_fusion(tyee_sim *sim, int32_t k, int32_t tile_tris) {
     if (!sim) return fail(TYEE_EINVAL, "null sim");
-    if (k == 0) k = 1;
+    if (k == 0) k = 4;
     if (k != 1 && k != 2 && k != 4 && k != 8) return fail(TYEE_EINVAL, "steps per launch must be 1, 2, 4 or 8");
-    sim->s.fusion = k;
+    if (tile_tris != 0 && (tile_tris < 256 || tile_tris > 8192))
+        return fail(TYEE_EINVAL, "tile size must be 0 or in [256, 8192] triangles");
+    tyee::Sim &s = sim->s;
+    if (s.tile_tris != tile_tris) s.tiling.reset();
+    s.fusion = k;
+    s.tile_tris = tile_tris;
     return TYEE_OK;
 }
 
@@ -708,9 +576,15 @@ int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *t
     return TYEE_OK;
 }
 
-int tyee_sim_get_fusion(const tyee_sim *sim, int32_t *k) {
-    if (!sim || !k) return fail(TYEE_EINVAL, "null argument");
-    *k = sim->s.fusion;
+int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]) {
+    if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
+    const tyee::Sim &s = sim->s;
+    out[0] = s.fusion;
+    const bool built = s.tiling && s.tiling->K == s.fusion;
+    out[1] = built ? s.tiling->tile : 0;
+    out[2] = built ? s.tiling->ntiles : 0;
+    out[3] = built ? s.tiling->sumT : 0;
+    out[4] = built ? s.tiling->sumE : 0;
     return TYEE_OK;
 }
 

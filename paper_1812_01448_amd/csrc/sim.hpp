@@ -1,0 +1,193 @@
+// Simulation object shared by the runtime (sim.hip) and the fused tile kernels (fused.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+#define TYEE_HIP(call)                                                                           \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return ::tyee::fail(TYEE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace tyee {
+
+constexpr int kBlock = 256;
+inline int blocks_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------------------------------
+// simulation object
+// ---------------------------------------------------------------------------------------
+
+struct DeviceBuffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t n) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = n;
+        if (n == 0) return TYEE_OK;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(TYEE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        return TYEE_OK;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Per-launch HIP-event timing of the stepping kernels (enabled per kernel kind).  A ring
+// of event pairs keeps the queue deep: only the oldest pair is waited for when it fills.
+struct LaunchTimer {
+    static constexpr int kKinds = 5;
+    static constexpr size_t kRing = 1024;
+    struct Pair {
+        int kind = 0;
+        hipEvent_t start = nullptr, stop = nullptr;
+    };
+    uint32_t mask = 0;
+    std::vector<Pair> ring;
+    size_t head = 0, pending = 0;
+    int64_t count[kKinds] = {0, 0, 0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0, 0, 0};
+
+    ~LaunchTimer() {
+        for (auto &p : ring) {
+            if (p.start) (void)hipEventDestroy(p.start);
+            if (p.stop) (void)hipEventDestroy(p.stop);
+        }
+    }
+    void reset(uint32_t m) {
+        mask = m;
+        std::fill(count, count + kKinds, 0);
+        std::fill(total_ms, total_ms + kKinds, 0.0);
+    }
+    int retire_oldest() {
+        Pair &p = ring[(head + ring.size() - pending) % ring.size()];
+        TYEE_HIP(hipEventSynchronize(p.stop));
+        float ms = 0.0f;
+        TYEE_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
+        count[p.kind] += 1;
+        total_ms[p.kind] += ms;
+        --pending;
+        return TYEE_OK;
+    }
+    int drain() {
+        while (pending > 0) {
+            int rc = retire_oldest();
+            if (rc) return rc;
+        }
+        return TYEE_OK;
+    }
+    // returns the ring slot used, or -1 when this kind is not timed
+    int begin(int kind, hipStream_t s, int *rc) {
+        *rc = TYEE_OK;
+        if (!(mask & (1u << kind))) return -1;
+        if (ring.empty()) ring.resize(kRing);
+        if (pending == ring.size() && (*rc = retire_oldest())) return -1;
+        Pair &p = ring[head];
+        if (!p.start && (hipEventCreate(&p.start) != hipSuccess || hipEventCreate(&p.stop) != hipSuccess)) {
+            *rc = fail(TYEE_EDEVICE, "hipEventCreate failed");
+            return -1;
+        }
+        p.kind = kind;
+        if (hipEventRecord(p.start, s) != hipSuccess) {
+            *rc = fail(TYEE_EDEVICE, "hipEventRecord failed");
+            return -1;
+        }
+        int slot = int(head);
+        head = (head + 1) % ring.size();
+        ++pending;
+        return slot;
+    }
+    int end(int slot, hipStream_t s) {
+        if (slot < 0) return TYEE_OK;
+        TYEE_HIP(hipEventRecord(ring[slot].stop, s));
+        return TYEE_OK;
+    }
+};
+
+struct Tiling;
+
+struct Sim {
+    bool f64 = false;
+    size_t esz = 4;
+    double dt = 0.0;
+    hipStream_t stream = nullptr;
+    int64_t nv = 0, ne = 0, nt = 0;
+    int64_t step = 0;
+    int fusion = 1;
+    int tile_tris = 0;                         // 0 = default tile size for the fusion depth
+    int cur = 0;                               // which of the two field buffers is current
+    std::vector<double> ce_dev, nb_dev;        // half-step coefficients in device numbering
+    std::unique_ptr<struct Tiling> tiling;
+
+    // host copies (canonical numbering)
+    std::vector<int32_t> perm_t, perm_e, slot_t, slot_e;
+    std::vector<int32_t> edge, R, L, A;
+    std::vector<int8_t> sgn;
+    std::vector<double> elen, d, hR, hL, S;
+    std::vector<uint8_t> node_outer;
+    std::vector<double> gamma;  // per canonical edge
+    std::vector<double> wp2_edge;
+    double nu = 0.0;
+    std::vector<int32_t> src_edge;
+    std::vector<double> src_w;
+    double src_omega = 1.0, src_cycles = 1.0;
+
+    // device arrays, device numbering
+    DeviceBuffer Et_buf[2], B_buf[2], cE, nB, RL, A0, A1, A2;
+    DeviceBuffer &Et() { return Et_buf[cur]; }
+    DeviceBuffer &B() { return B_buf[cur]; }
+    // special edges (plasma and/or source)
+    int64_t n_special = 0;
+    std::vector<int32_t> sp_edge;  // canonical edge of each special entry
+    std::vector<uint8_t> sp_plasma;
+    DeviceBuffer sp_slot, sp_j, sp_ca, sp_cb, sp_w, sp_delta;
+    // nodal charge
+    int64_t n_qnode = 0;
+    DeviceBuffer Q, q_node, q_off, q_inc, q_coef;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    LaunchTimer timer;
+
+    ~Sim();
+
+    double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
+};
+
+
+// Temporal tiling for the fused K-step kernel (built by fused.hip).
+struct TileInfo {
+    int32_t n_core;      // core triangles are local [0, n_core)
+    int32_t n_own;       // owned edges are local [0, n_own)
+    int32_t tri_off;     // offset of this tile in the packed triangle arrays
+    int32_t edge_off;    // offset of this tile in the packed edge arrays
+    int32_t cntT[9];     // local triangles with ring level <= m
+    int32_t cntE[9];     // local edges with level <= m
+};
+
+struct Tiling {
+    int K = 0, tile = 0, threads = 0, rt = 0, re = 0;
+    int64_t ntiles = 0, maxT = 0, maxE = 0, sumT = 0, sumE = 0;
+    DeviceBuffer info, tl_glob, tl_coef, tl_i0, tl_i1, el_glob, el_coef, el_idx;
+    std::vector<int32_t> h_tl_glob, h_el_glob;  // local cell -> device slot (for coefficient refresh)
+};
+
+int build_tiling(Sim &s, int K, int tile_tris);
+int refresh_tiling_coefficients(Sim &s);
+template <typename T> int launch_fused(Sim &s, int k);
+
+}  // namespace tyee

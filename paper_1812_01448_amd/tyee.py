@@ -85,14 +85,14 @@ def _load():
         "tyee_sim_set_media": [vp, vp, f64],
         "tyee_sim_set_source": [vp, vp, vp, i64, f64, f64],
         "tyee_sim_set_edge_scale": [vp, vp],
-        "tyee_sim_set_fusion": [vp, i32],
+        "tyee_sim_set_fusion": [vp, i32, i32],
         "tyee_sim_step": [vp, i64],
         "tyee_sim_sync": [vp],
         "tyee_sim_diagnostics": [vp, ctypes.POINTER(_Diag)],
         "tyee_sim_last_step_ms": [vp, ctypes.POINTER(f64)],
         "tyee_sim_set_profiling": [vp, ctypes.c_uint32],
         "tyee_sim_kernel_times": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)],
-        "tyee_sim_get_fusion": [vp, ctypes.POINTER(i32)],
+        "tyee_sim_get_fusion": [vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -234,8 +234,9 @@ class Sim:
         g = None if gamma is None else _f64(gamma, self.ne)
         _check(lib.tyee_sim_set_edge_scale(self._h, _ptr(g)))
 
-    def set_fusion(self, k):
-        _check(lib.tyee_sim_set_fusion(self._h, int(k)))
+    def set_fusion(self, k, tile=0):
+        """Steps per launch (1, 2, 4, 8; 0 = default) and tile size in triangles (0 = default)."""
+        _check(lib.tyee_sim_set_fusion(self._h, int(k), int(tile)))
 
     def step(self, n):
         _check(lib.tyee_sim_step(self._h, int(n)))
@@ -268,10 +269,14 @@ class Sim:
                              "steps_per_launch": self.fusion_used() if name == "fused" else 1}
         return out
 
+    def fusion_info(self):
+        out = np.zeros(5, np.int64)
+        _check(lib.tyee_sim_get_fusion(self._h, _ptr(out)))
+        return dict(zip(["steps_per_launch", "tile", "tiles", "local_tris", "local_edges"],
+                        (int(v) for v in out)))
+
     def fusion_used(self):
-        k = ctypes.c_int32()
-        _check(lib.tyee_sim_get_fusion(self._h, ctypes.byref(k)))
-        return k.value
+        return self.fusion_info()["steps_per_launch"]
 
     def diagnostics(self):
         d = _Diag()

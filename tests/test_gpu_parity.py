@@ -34,7 +34,7 @@ def _pair(xy, tri, periodic):
 
 
 def run_gpu(ty, xy, tri, periodic, dt, E0_fn, steps, prec, order="none", seed=0, fusion=1,
-            media=None, source=None, gamma=None, chunks=1):
+            media=None, source=None, gamma=None, chunks=1, tile=0):
     m = ty.Mesh(xy, tri, periodic)
     m.reorder(order, seed)
     view = m.view()
@@ -48,9 +48,9 @@ def run_gpu(ty, xy, tri, periodic, dt, E0_fn, steps, prec, order="none", seed=0,
         sim.set_source(*source)
     sim.set_state("E", E0)
     sim.set_state("B", B0)
-    sim.set_fusion(fusion)
+    sim.set_fusion(fusion, tile)
     for c in range(chunks):
-        sim.step(steps // chunks)
+        sim.step(steps // chunks + (steps % chunks if c == chunks - 1 else 0))
     out = {f: sim.get_state(f) for f in ("E", "B", "J", "Q")}
     return out, view
 
@@ -147,14 +147,31 @@ def test_edge_scale_fp64(ty):
     assert rel_l2(got["E"], ref["E"]) < 1e-12 and rel_l2(got["B"], ref["B"]) < 1e-12
 
 
-@pytest.mark.parametrize("fusion", [2, 4, 8])
-def test_fusion_depth_bit_identical(ty, fusion):
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("fusion,tile", [(2, 0), (4, 0), (8, 0), (4, 512), (8, 1024), (2, 256)])
+def test_fusion_depth_bit_identical(ty, fusion, tile, prec):
     n = 64
-    _note(f"case: torus{n} fp32 fusion={fusion} bit-exactness")
+    _note(f"case: torus{n} {prec} fusion={fusion} tile={tile} bit-exactness")
     xy, tri = lattice_mesh(n, 0.25, 7, periodic=True)
     om = oracle.OracleMesh(xy, tri, True)
     dt = 0.5 * 2 / np.sqrt(om.power()[0])
     fn = lambda side: packet_state(side, dt, n)
-    base, _ = run_gpu(ty, xy, tri, True, dt, fn, 37, "f32", order="morton", fusion=1)
-    got, _ = run_gpu(ty, xy, tri, True, dt, fn, 37, "f32", order="morton", fusion=fusion)
+    base, _ = run_gpu(ty, xy, tri, True, dt, fn, 37, prec, order="morton", fusion=1)
+    got, _ = run_gpu(ty, xy, tri, True, dt, fn, 37, prec, order="morton", fusion=fusion,
+                     tile=tile)
     assert np.array_equal(got["E"], base["E"]) and np.array_equal(got["B"], base["B"])
+
+
+@pytest.mark.parametrize("order", ["none", "random", "rcm"])
+def test_fusion_any_numbering_and_closed_box(ty, order):
+    n = 40
+    _note(f"case: cavity{n} fp64 fusion=4 order={order}")
+    xy, tri = lattice_mesh(n, 0.2, 3, periodic=False)
+    om = oracle.OracleMesh(xy, tri, False)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    ref = om.step(*cavity_state(om), dt, 203)
+    base, _ = run_gpu(ty, xy, tri, False, dt, cavity_state, 203, "f64", order=order, fusion=1)
+    got, _ = run_gpu(ty, xy, tri, False, dt, cavity_state, 203, "f64", order=order, fusion=4,
+                     tile=512, chunks=7)
+    assert np.array_equal(got["E"], base["E"]) and np.array_equal(got["B"], base["B"])
+    assert rel_l2(got["E"], ref["E"]) < 1e-12 and rel_l2(got["B"], ref["B"]) < 1e-12
