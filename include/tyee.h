@@ -134,7 +134,7 @@ int tyee_mesh_query(const tyee_mesh *mesh, tyee_mesh_info *out);
 int tyee_mesh_view(const tyee_mesh *mesh, tyee_mesh_arrays *out);
 
 /* omega_max^2 of K = -L_E L_B by normalised iteration in the S-weighted product (the
-   "complex time" iteration of Section 2, used for the eq. 20 bound dt < 2/omega_max).
+   imaginary-time iteration of Section 2, used for the eq. 20 bound dt < 2/omega_max).
    gamma: per-edge coefficient scale [n_edges] or NULL.  Start vector
    x_j = 2 u_j - 1, u_j = (splitmix64(seed + j) >> 11) * 2^-53.  Stops when
    |lambda_k - lambda_{k-1}| <= rtol * lambda_k (TYEE_OK) or after max_iter iterations

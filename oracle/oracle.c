@@ -390,7 +390,7 @@ int orc_step(const orc_mesh *m, const orc_params *p, int64_t n0, int64_t nsteps,
 }
 
 /* ------------------------------------------------------------------------- */
-/* diagnostics (eqs. 7-10, divergence of P:69 as flux through the Voronoi cell)  */
+/* diagnostics (eqs. 7-10; div E as the flux through the Voronoi cell, Section 1)  */
 /* ------------------------------------------------------------------------- */
 
 /* W_h = sum_i w_i E_i^2 + sum_j S_j Bold_j Bnew_j, w_i = d_i |e_i| (metric (7)); with
@@ -415,7 +415,7 @@ void orc_div(const orc_mesh *m, const double *E, double *out)
 }
 
 /* ------------------------------------------------------------------------- */
-/* largest eigenvalue of K = -L_E L_B by normalised iteration, S-weighted  */
+/* largest eigenvalue of K = -L_E L_B by normalised iteration (Section 2), S-weighted */
 /* ------------------------------------------------------------------------- */
 
 static void apply_K(const orc_mesh *m, const double *gamma, const double *x, double *y)

@@ -3,7 +3,7 @@
 Hand-derived tiny meshes, mesh identities (Euler characteristic, area sums, circumcentre
 equidistance), the skew-adjointness of M in metric (7) (eqs. 7-10), the exact spectrum of the
 equilateral mesh (the honeycomb dual), PEC cavity eigenfrequencies, the exact leap-frog time
-phase and the stability threshold of eq. 20, conservation of div E and of the discrete
+phase and the stability threshold of eq. 20, conservation of div E (Section 1) and of the discrete
 energy, and closed-form Drude oscillation/decay.
 """
 import numpy as np
