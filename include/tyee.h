@@ -193,14 +193,36 @@ int tyee_sim_sync(tyee_sim *sim);
 typedef struct {
     int64_t step;          /* steps taken */
     double time;           /* step * dt */
-    double energy;         /* sum w E^2 + sum S B^2 at the current levels (eq. 8 form) */
+    double energy;         /* W = sum w E^2 + sum S B^2 at the current levels (eq. 8 with the
+                              signed dual length, w = d |e|) */
+    double energy_h;       /* W_h = sum w E^n^2 + sum S B^{n-1/2} B^{n+1/2}: the quantity the
+                              leap-frog scheme conserves exactly in vacuum (eqs. 7-10);
+                              B^{n-1/2} is rebuilt on the host as B^{n+1/2} - dt L_E E^n */
     double max_abs_E, max_abs_B;
     int32_t nonfinite;     /* 1 if any field value is NaN or infinite */
 } tyee_diag;
 
-/* Diagnostics from the current state (synchronises). Returns TYEE_EUNSTABLE if a field
-   is not finite (out is still filled). */
+/* Diagnostics from the current state, computed on the host in FP64 (synchronises).
+   Returns TYEE_EUNSTABLE if a field is not finite (out is still filled). */
 int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out);
+
+/* Discrete Gauss residual per node (canonical, FP64 host): out_k = (D E)_k - Q_k with
+   (D E)_k = sum_i sigma(k,i) d_i E_i, sigma = +1 when e_i leaves node k (the flux of E
+   through the dual cell of node k, Section 1).  In vacuum D E is conserved on interior
+   nodes; with plasma or a source, D E - Q is.  out: [n_nodes]. */
+int tyee_sim_gauss(tyee_sim *sim, double *out);
+
+/* Probe: record field values at canonical ids (edges for E and J, triangles for B, nodes for
+   Q) after every step whose count is a multiple of `every`, up to max_samples samples (later
+   samples are dropped).  Fused launches are split so that every sampling step is a launch
+   boundary.  *probe receives its id. */
+int tyee_sim_add_probe(tyee_sim *sim, int32_t field, const int32_t *ids, int64_t n, int64_t every,
+                       int64_t max_samples, int32_t *probe);
+
+/* Copy the recorded samples of a probe: out [capacity][n] row-major (physical values),
+   *n_samples receives the number recorded (synchronises). */
+int tyee_sim_read_probe(tyee_sim *sim, int32_t probe, double *out, int64_t capacity,
+                        int64_t *n_samples);
 
 /* Kernel time of the last tyee_sim_step call in milliseconds, measured with HIP events on
    the simulation's stream (synchronises). */

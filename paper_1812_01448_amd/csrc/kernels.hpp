@@ -83,6 +83,14 @@ __global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict
     Q[node[k]] -= acc;
 }
 
+// Probe: copy field values at the listed device slots into one row of the sample buffer.
+template <typename T>
+__global__ __launch_bounds__(256) void k_probe(int n, const int32_t *__restrict__ slot, const T *__restrict__ src,
+                                               T *__restrict__ dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[slot[k]];
+}
+
 template <typename T>
 inline void launch_edge(hipStream_t s, int64_t n, int grid, T *Et, const T *B, const T *cE, const int2 *RL) {
     if (n > 0) k_edge<T><<<grid, 256, 0, s>>>(int(n), Et, B, cE, RL);

@@ -180,6 +180,12 @@ int rebuild_specials(Sim &s) {
         }
         off.push_back(int32_t(qk.size()));
     }
+    for (auto &pp : s.probes) {
+        if (pp->field != TYEE_FIELD_J) continue;
+        std::vector<int32_t> sl(pp->n, 0);
+        for (int64_t r = 0; r < pp->n; ++r) sl[r] = which[pp->ids[r]] >= 0 ? int32_t(which[pp->ids[r]]) : 0;
+        if ((rc = upload_raw(pp->slots, sl, s.stream))) return rc;
+    }
     s.n_qnode = int64_t(qn.size());
     rc = upload_raw(s.q_node, qn, s.stream);
     if (!rc) rc = upload_raw(s.q_off, off, s.stream);
@@ -203,6 +209,36 @@ template <typename F> int timed(Sim &s, int kind, F &&launch) {
     rc = launch();
     if (rc) return rc;
     return s.timer.end(slot, s.stream);
+}
+
+// Device array and slot list a probe reads from.
+template <typename T> const T *probe_source(Sim &s, const Probe &p) {
+    switch (p.field) {
+    case TYEE_FIELD_E: return s.Et().as<T>();
+    case TYEE_FIELD_B: return s.B().as<T>();
+    case TYEE_FIELD_J: return s.sp_j.as<T>();
+    default: return s.Q.as<T>();
+    }
+}
+
+template <typename T> int sample_probes(Sim &s) {
+    for (auto &pp : s.probes) {
+        Probe &p = *pp;
+        if (s.step % p.every != 0 || p.taken >= p.capacity) continue;
+        k_probe<T><<<int((p.n + 255) / 256), 256, 0, s.stream>>>(int(p.n), p.slots.as<int32_t>(),
+                                                                 probe_source<T>(s, p),
+                                                                 p.samples.as<T>() + p.taken * p.n);
+        ++p.taken;
+    }
+    return TYEE_OK;
+}
+
+// Largest step count from s.step that does not cross a probe's sampling step.
+int64_t steps_to_next_sample(const Sim &s) {
+    int64_t best = INT64_MAX;
+    for (auto &p : s.probes)
+        if (p->taken < p->capacity) best = std::min(best, p->every - s.step % p->every);
+    return best;
 }
 
 template <typename T> int enqueue_steps(Sim &s, int64_t n) {
@@ -233,7 +269,7 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
                 });
         } else {
             k = s.fusion;
-            if (k > n - done) k = 1;  // the remainder runs as single steps
+            if (k > n - done || k > steps_to_next_sample(s)) k = 1;  // remainder: single steps
         }
         if (rc) break;
         if (k > 1 && (!s.tiling || s.tiling->K != k)) {
@@ -260,6 +296,7 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
         }
         s.step += k;
         done += k;
+        if (!rc && !s.probes.empty()) rc = sample_probes<T>(s);
     }
     if (rc) return rc;
     TYEE_HIP(hipGetLastError());
@@ -542,11 +579,23 @@ int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out) {
     tyee_diag d{};
     d.step = s.step;
     d.time = double(s.step) * s.dt;
+    // B^{n-1/2} = B^{n+1/2} + (dt/S) sum_q s gamma |e| E^n  (undo the last triangle half-step)
+    for (int64_t j = 0; j < s.nt; ++j) {
+        double circ = 0.0;
+        for (int q = 0; q < 3; ++q) {
+            const int32_t i = s.A[3 * j + q];
+            circ += double(s.sgn[3 * j + q]) * s.scale(i) * E[i];
+        }
+        d.energy_h += s.S[j] * (B[j] + s.dt / s.S[j] * circ) * B[j];
+    }
     bool bad = false;
     for (int64_t i = 0; i < s.ne; ++i) {
         bad |= !std::isfinite(E[i]);
         d.max_abs_E = std::max(d.max_abs_E, std::fabs(E[i]));
-        if (s.R[i] >= 0 && s.L[i] >= 0) d.energy += s.d[i] * s.elen[i] * E[i] * E[i];
+        if (s.R[i] >= 0 && s.L[i] >= 0) {
+            d.energy += s.d[i] * s.elen[i] * E[i] * E[i];
+            d.energy_h += s.d[i] * s.elen[i] * E[i] * E[i];
+        }
     }
     for (int64_t j = 0; j < s.nt; ++j) {
         bad |= !std::isfinite(B[j]);
@@ -585,6 +634,79 @@ int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]) {
     out[2] = built ? s.tiling->ntiles : 0;
     out[3] = built ? s.tiling->sumT : 0;
     out[4] = built ? s.tiling->sumE : 0;
+    return TYEE_OK;
+}
+
+int tyee_sim_gauss(tyee_sim *sim, double *out) {
+    if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    std::vector<double> E(s.ne), Q(s.nv);
+    int rc = tyee_sim_get_state(sim, TYEE_FIELD_E, E.data());
+    if (!rc) rc = tyee_sim_get_state(sim, TYEE_FIELD_Q, Q.data());
+    if (rc) return rc;
+    std::fill(out, out + s.nv, 0.0);
+    for (int64_t i = 0; i < s.ne; ++i) {
+        out[s.edge[2 * i]] += s.d[i] * E[i];
+        out[s.edge[2 * i + 1]] -= s.d[i] * E[i];
+    }
+    for (int64_t v = 0; v < s.nv; ++v) out[v] -= Q[v];
+    return TYEE_OK;
+}
+
+int tyee_sim_add_probe(tyee_sim *sim, int32_t field, const int32_t *ids, int64_t n, int64_t every,
+                       int64_t max_samples, int32_t *probe) {
+    if (!sim || !ids || !probe) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    if (n <= 0 || every <= 0 || max_samples <= 0) return fail(TYEE_EINVAL, "n, every, max_samples must be > 0");
+    const int64_t limit = field == TYEE_FIELD_B ? s.nt : field == TYEE_FIELD_Q ? s.nv : s.ne;
+    if (field < TYEE_FIELD_E || field > TYEE_FIELD_Q) return fail(TYEE_EINVAL, "unknown field");
+    auto p = std::make_unique<tyee::Probe>();
+    p->field = field;
+    p->n = n;
+    p->every = every;
+    p->capacity = max_samples;
+    p->ids.assign(ids, ids + n);
+    std::vector<int32_t> sl(n);
+    std::vector<int64_t> which(field == TYEE_FIELD_J ? s.ne : 0, -1);
+    for (int64_t k = 0; k < s.n_special && field == TYEE_FIELD_J; ++k)
+        if (s.sp_plasma[k]) which[s.sp_edge[k]] = k;
+    for (int64_t r = 0; r < n; ++r) {
+        const int32_t id = ids[r];
+        if (id < 0 || id >= limit) return fail(TYEE_EINVAL, "probe id out of range");
+        switch (field) {
+        case TYEE_FIELD_E: sl[r] = s.slot_e[id]; break;
+        case TYEE_FIELD_B: sl[r] = s.slot_t[id]; break;
+        case TYEE_FIELD_J:
+            if (which[id] < 0) return fail(TYEE_EINVAL, "current probe on a non-plasma edge");
+            sl[r] = int32_t(which[id]);
+            break;
+        default: sl[r] = id;
+        }
+    }
+    int rc = tyee::upload_raw(p->slots, sl, s.stream);
+    if (!rc) rc = p->samples.alloc(size_t(n) * size_t(max_samples) * s.esz);
+    if (rc) return rc;
+    *probe = int32_t(s.probes.size());
+    s.probes.push_back(std::move(p));
+    return TYEE_OK;
+}
+
+int tyee_sim_read_probe(tyee_sim *sim, int32_t probe, double *out, int64_t capacity, int64_t *n_samples) {
+    if (!sim || !out || !n_samples) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    if (probe < 0 || probe >= int32_t(s.probes.size())) return fail(TYEE_EINVAL, "unknown probe");
+    tyee::Probe &p = *s.probes[probe];
+    const int64_t m = std::min(capacity, p.taken);
+    std::vector<double> raw;
+    int rc = tyee::download_field(s, p.samples, raw, m * p.n);
+    if (rc) return rc;
+    for (int64_t t = 0; t < m; ++t)
+        for (int64_t r = 0; r < p.n; ++r) {
+            double v = raw[t * p.n + r];
+            if (p.field == TYEE_FIELD_E || p.field == TYEE_FIELD_J) v /= s.scale(p.ids[r]);
+            out[t * p.n + r] = v;
+        }
+    *n_samples = p.taken;
     return TYEE_OK;
 }
 

@@ -121,6 +121,14 @@ struct LaunchTimer {
 
 struct Tiling;
 
+struct Probe {
+    int32_t field = 0;
+    int64_t n = 0, every = 1, capacity = 0, taken = 0;
+    std::vector<int32_t> ids;     // canonical ids
+    DeviceBuffer slots;           // device slots (special-list index for J)
+    DeviceBuffer samples;         // [capacity][n] raw device values
+};
+
 struct Sim {
     bool f64 = false;
     size_t esz = 4;
@@ -162,6 +170,7 @@ struct Sim {
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     LaunchTimer timer;
+    std::vector<std::unique_ptr<Probe>> probes;
 
     ~Sim();
 

@@ -49,8 +49,8 @@ class _View(ctypes.Structure):
 
 class _Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
-                ("max_abs_E", ctypes.c_double), ("max_abs_B", ctypes.c_double),
-                ("nonfinite", ctypes.c_int32)]
+                ("energy_h", ctypes.c_double), ("max_abs_E", ctypes.c_double),
+                ("max_abs_B", ctypes.c_double), ("nonfinite", ctypes.c_int32)]
 
 
 EXPORTS = [
@@ -60,7 +60,7 @@ EXPORTS = [
     "tyee_sim_set_edge_scale", "tyee_sim_set_fusion", "tyee_sim_step", "tyee_sim_sync",
     "tyee_sim_diagnostics", "tyee_sim_last_step_ms", "tyee_sim_set_profiling",
     "tyee_sim_kernel_times", "tyee_sim_get_fusion", "tyee_sim_steps", "tyee_sim_destroy",
-    "tyee_last_error",
+    "tyee_sim_gauss", "tyee_sim_add_probe", "tyee_sim_read_probe", "tyee_last_error",
 ]
 KERNELS = {"edge": 0, "tri": 1, "fused": 2, "special": 3, "charge": 4}
 KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special": "k_special",
@@ -93,6 +93,9 @@ def _load():
         "tyee_sim_set_profiling": [vp, ctypes.c_uint32],
         "tyee_sim_kernel_times": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)],
         "tyee_sim_get_fusion": [vp, vp],
+        "tyee_sim_gauss": [vp, vp],
+        "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
+        "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -277,6 +280,28 @@ class Sim:
 
     def fusion_used(self):
         return self.fusion_info()["steps_per_launch"]
+
+    def gauss(self):
+        """(D E)_k - Q_k per node (canonical)."""
+        out = np.zeros(self.nv)
+        _check(lib.tyee_sim_gauss(self._h, _ptr(out)))
+        return out
+
+    def add_probe(self, field, ids, every, max_samples):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        pid = ctypes.c_int32()
+        _check(lib.tyee_sim_add_probe(self._h, FIELD[field], _ptr(ids), len(ids), int(every),
+                                      int(max_samples), ctypes.byref(pid)))
+        self._probe_sizes = getattr(self, "_probe_sizes", {})
+        self._probe_sizes[pid.value] = (len(ids), int(max_samples))
+        return pid.value
+
+    def read_probe(self, pid):
+        n, cap = self._probe_sizes[pid]
+        out = np.zeros((cap, n))
+        got = ctypes.c_int64()
+        _check(lib.tyee_sim_read_probe(self._h, int(pid), _ptr(out), cap, ctypes.byref(got)))
+        return out[:min(cap, got.value)]
 
     def diagnostics(self):
         d = _Diag()
