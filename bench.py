@@ -37,6 +37,10 @@ def parse():
     p.add_argument("--prec", default="f32", choices=["f32", "f64"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
+    p.add_argument("--workload", default="torus1415", choices=["torus1415", "batch256"],
+                   help="torus1415 (the reported line) or batch256 (256 uneven meshes)")
+    p.add_argument("--graph", type=int, default=8, help="fused launches per HIP graph (0 = eager)")
+    p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (for counter calibration)")
     return p.parse_args()
@@ -94,6 +98,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.workload == "batch256":
+        bench_batch(args)
+        return
 
     import torch
     import paper_1812_01448_amd as ty
@@ -120,6 +127,7 @@ def main():
     sim.set_state("E", E0)
     sim.set_state("B", B0)
     sim.set_fusion(args.fusion, args.tile)
+    sim.set_graph(args.graph)
     ne, nt = mesh.ne, mesh.nt
     cells = ne + nt
 
@@ -128,8 +136,10 @@ def main():
     fuse = sim.fusion_info()
     K = fuse["steps_per_launch"]
     torch.cuda.synchronize()
-    # HIP events bracket every launch of the dominant kernel inside the timed region
-    sim.set_profiling(True, kinds=["fused"] if K > 1 else ["edge", "tri"])
+    # HIP events bracket every launch of the dominant kernel inside the timed region (every
+    # graph replay when the fused launches run from a captured graph)
+    use_graph = args.graph > 0 and K > 1
+    sim.set_profiling(True, kinds=["graph"] if use_graph else (["fused"] if K > 1 else ["edge", "tri"]))
     t_start = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
@@ -149,12 +159,15 @@ def main():
     algo = {"edge": bytes_edge, "tri": bytes_tri}
     # dominant kernel = the one with the largest total time in the timed region
     dom = max(prof, key=lambda kk: prof[kk]["total_ms"])
-    units = prof[dom]["steps_per_launch"]
-    per_launch_bytes = units * (bytes_edge + bytes_tri) if dom == "fused" else algo[dom]
-    avg_ms = prof[dom]["total_ms"] / prof[dom]["count"]
+    launches = prof[dom]["count"] * (args.graph if dom == "graph" else 1)
+    per_launch_bytes = K * (bytes_edge + bytes_tri) if dom in ("fused", "graph") else algo[dom]
+    avg_ms = prof[dom]["total_ms"] / launches
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     step_bytes = bytes_edge + bytes_tri
-    roofline = {"bound": "hbm", "kernel": prof[dom]["name"], "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": "k_fused" if dom in ("fused", "graph") else prof[dom]["name"],
+                "timed_with": "HIP events per graph replay of %d launches" % args.graph
+                if dom == "graph" else "HIP events per launch",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "avg_launch_ms": round(avg_ms, 5),
                 "algorithmic_bytes_per_launch": per_launch_bytes,
@@ -167,7 +180,7 @@ def main():
         roofline["moved_GBs"] = round(moved / (avg_ms * 1e-3) / 1e9, 1)
         roofline["halo_ratio_tris"] = round(fuse["local_tris"] / nt, 3)
         roofline["halo_ratio_edges"] = round(fuse["local_edges"] / ne, 3)
-        roofline["traffic"] = measured_traffic(prof[dom]["name"], {
+        roofline["traffic"] = measured_traffic("k_fused", {
             "triangles": nt, "steps_per_launch": K, "tile_tris": fuse["tile"], "prec": args.prec,
             "order": args.order})
 
@@ -184,9 +197,93 @@ def main():
                                f"(+-0.25h), plane-wave packet 20 cells/lambda, CFL 0.5",
                    "triangles": nt, "edges": ne, "cell_updates_per_step": cells,
                    "order": args.order, "steps_per_launch": K, "tile_tris": fuse["tile"],
+                   "graph_launches": args.graph if K > 1 else 0,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """256 independent periodic meshes, triangle counts log-uniform in [5k, 500k]."""
+    import torch
+    import paper_1812_01448_amd as ty
+    from meshgen import lattice_mesh, periodic_wavevector, plane_wave_packet
+    from meshgen.workloads import batch_lattice_sizes
+
+    sizes = batch_lattice_sizes(256, seed=4)
+    rng = np.random.default_rng(5)
+    meshes, dts, init = [], [], []
+    t0 = time.time()
+    for k, n in enumerate(sizes):
+        xy, tri = lattice_mesh(int(n), 0.25, 1000 + k, periodic=True)
+        m = ty.Mesh(xy, tri, True)
+        m.reorder(args.order)
+        lam, _, _ = m.cfl()
+        dt = 0.5 * 2 / np.sqrt(lam)
+        v = m.view()
+        kv, _, _ = periodic_wavevector(rng.uniform(0, 2 * np.pi), rng.uniform(8, 32), 1.0 / n)
+        B0, E0 = plane_wave_packet(v["O"], v["C"], v["evec"] / v["elen"][:, None], kv, dt,
+                                   sigma=0.1)
+        meshes.append(m)
+        dts.append(dt)
+        init.append((E0, B0))
+    log(f"batch of {len(sizes)} meshes built in {time.time() - t0:.1f} s")
+    torch.cuda.init()
+    batch = ty.Batch(meshes, dts, args.prec, stream=torch.cuda.current_stream().cuda_stream)
+    for k, (E0, B0) in enumerate(init):
+        batch.set_state(k, "E", E0)
+        batch.set_state(k, "B", B0)
+    info = batch.info()
+    tuned = None
+    if args.tune:
+        batch.set_graph(args.graph)
+        tuned = batch.tune(32)
+        best = min(tuned, key=lambda r: r["ms_per_step"])
+        log(f"tuned: {best}")
+    else:
+        batch.set_fusion(args.fusion, args.tile)
+        batch.set_graph(args.graph)
+    sim = batch.sim()
+    batch.step(args.warmup)
+    batch.sync()
+    fuse = sim.fusion_info()
+    K = fuse["steps_per_launch"]
+    torch.cuda.synchronize()
+    sim.set_profiling(True, kinds=["graph"] if args.graph and K > 1 else (
+        ["fused"] if K > 1 else ["edge", "tri"]))
+    t1 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = sim.kernel_times()
+    sim.set_profiling(False)
+    cells = info["triangles"] + info["edges"]
+    esz = 4 if args.prec == "f32" else 8
+    step_bytes = (3 * esz + 8) * info["edges"] + esz * info["triangles"] + \
+                 (3 * esz + 12) * info["triangles"] + esz * info["edges"]
+    dom = max(prof, key=lambda kk: prof[kk]["total_ms"])
+    launches = prof[dom]["count"] * (args.graph if dom == "graph" else 1)
+    avg_ms = prof[dom]["total_ms"] / launches
+    per_launch = step_bytes * (K if dom in ("graph", "fused") else 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "cell-updates/s (edges+tris), batched plain method",
+        "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "256 periodic jittered-lattice Delaunay meshes, triangle counts "
+                               "log-uniform in [5k, 500k], per-mesh dt and plane wave",
+                   "members": info["members"], "triangles": info["triangles"],
+                   "edges": info["edges"], "steps_per_launch": K, "tile_tris": fuse["tile"],
+                   "graph_launches": args.graph, "order": args.order if not tuned else "tuned"},
+        "roofline": {"bound": "hbm", "kernel": "k_fused" if K > 1 else prof[dom]["name"],
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": per_launch, "traffic": None},
+        "tune": tuned,
     }
     print(json.dumps(out), flush=True)
 

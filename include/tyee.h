@@ -148,8 +148,9 @@ void tyee_mesh_destroy(tyee_mesh *mesh);
 
 /* Upload a mesh for stepping with time step dt in FP32 or FP64 device arithmetic
    (geometry stays FP64 on the host; coefficients are folded with dt and rounded once).
-   stream: a hipStream_t, or NULL for the default stream.  Fields start at zero.  The
-   simulation copies what it needs: the mesh may be destroyed afterwards. */
+   stream: a hipStream_t, or NULL to let the library create a stream of its own (the legacy
+   default stream cannot be captured into graphs).  Fields start at zero.  The simulation
+   copies what it needs: the mesh may be destroyed afterwards. */
 int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream,
                     tyee_sim **out);
 
@@ -228,9 +229,15 @@ int tyee_sim_read_probe(tyee_sim *sim, int32_t probe, double *out, int64_t capac
    the simulation's stream (synchronises). */
 int tyee_sim_last_step_ms(tyee_sim *sim, double *ms);
 
-/* Kernels of one step, for per-launch timing. */
+/* Replay fused launches from a captured HIP graph, `launches` (an even number, 0 = off) per
+   graph, for vacuum runs; the graph is captured on first use and again after any change of
+   fusion, tiling or coefficients.  Stepping with per-launch timing of TYEE_KERNEL_FUSED
+   enabled launches eagerly instead. */
+int tyee_sim_set_graph(tyee_sim *sim, int32_t launches);
+
+/* Kernels of one step, for per-launch timing; TYEE_KERNEL_GRAPH times whole graph replays. */
 typedef enum { TYEE_KERNEL_EDGE = 0, TYEE_KERNEL_TRI = 1, TYEE_KERNEL_FUSED = 2,
-               TYEE_KERNEL_SPECIAL = 3, TYEE_KERNEL_CHARGE = 4 } tyee_kernel;
+               TYEE_KERNEL_SPECIAL = 3, TYEE_KERNEL_CHARGE = 4, TYEE_KERNEL_GRAPH = 5 } tyee_kernel;
 
 /* Time every later launch of the kernel kinds in the bit mask `kinds` (bit k = tyee_kernel
    k) with a HIP event pair on the simulation's stream; resets the totals.  0 turns timing
@@ -248,6 +255,54 @@ int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]);
 
 int64_t tyee_sim_steps(const tyee_sim *sim);
 void tyee_sim_destroy(tyee_sim *sim);
+
+/* ---------------------------------------------------------------- batch ---- */
+
+typedef struct tyee_batch tyee_batch;
+
+/* Step many independent meshes together (vacuum).  The members are copied and stored as one
+   disjoint union: their cells are concatenated in the device numbering (each member keeps
+   its own locality order inside its range) and member k's time step dt[k] is folded into
+   its cells' coefficients, so one launch advances every member.  Each member's fields are
+   bit-identical to a standalone simulation with the same dt, numbering and precision.
+   meshes: [n_meshes] handles (may be destroyed afterwards); stream as for
+   tyee_sim_create.  Fields start at zero. */
+int tyee_batch_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
+                      int32_t prec, void *stream, tyee_batch **out);
+
+/* Member k's E [n_edges_k] or B [n_tris_k] in the member's own canonical numbering. */
+int tyee_batch_set_state(tyee_batch *b, int64_t k, int32_t field, const double *host);
+int tyee_batch_get_state(tyee_batch *b, int64_t k, int32_t field, double *host);
+
+/* Renumber every member (as tyee_mesh_reorder); fields are kept. */
+int tyee_batch_reorder(tyee_batch *b, int32_t kind, uint64_t seed);
+int tyee_batch_set_fusion(tyee_batch *b, int32_t steps_per_launch, int32_t tile_tris);
+int tyee_batch_set_graph(tyee_batch *b, int32_t launches);
+int tyee_batch_step(tyee_batch *b, int64_t n);
+int tyee_batch_sync(tyee_batch *b);
+
+/* out = {members, triangles, edges, nodes} of the union. */
+int tyee_batch_info(const tyee_batch *b, int64_t out[4]);
+
+/* Borrowed handle of the union's simulation (profiling, fusion info, diagnostics); valid
+   until the next reorder, tune or destroy of the batch. */
+int tyee_batch_sim(tyee_batch *b, tyee_sim **sim);
+
+typedef struct {
+    int32_t order;             /* tyee_order */
+    int32_t steps_per_launch;  /* 1, 2, 4 or 8 */
+    int32_t tile_tris;         /* 0 for one launch per half-step */
+    double ms_per_step;        /* HIP-event time of the trial divided by its steps */
+} tyee_tune_result;
+
+/* Autotune: time about steps_per_trial steps for every ordering (Morton, RCM) x steps per
+   launch (1, 2, 4, 8) x tile size (1024, 2048, 3072, 4096), keep the fastest setting and
+   restore the fields and step count.  results: [capacity] trial records (may be NULL when
+   capacity is 0); *n_results receives the number of trials. */
+int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results,
+                    int64_t capacity, int64_t *n_results);
+
+void tyee_batch_destroy(tyee_batch *b);
 
 const char *tyee_last_error(void);
 

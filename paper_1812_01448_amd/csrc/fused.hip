@@ -348,6 +348,7 @@ int build_tiling(Sim &s, int K, int tile_tris) {
         if (!rc) rc = upload_vec(s, tg->el_idx, eidx);
         if (rc) return rc;
         s.tiling = std::move(tg);
+        s.graph_dirty = true;
         return refresh_tiling_coefficients(s);
     }
 }

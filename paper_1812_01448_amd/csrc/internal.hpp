@@ -43,6 +43,9 @@ int reorder_mesh(Mesh &m, int32_t kind, uint64_t seed);
 int power_iteration(const Mesh &m, const double *gamma, int64_t max_iter, double rtol,
                     uint64_t seed, double *lambda, int64_t *iters);
 uint64_t splitmix64(uint64_t x);
+// Disjoint union of meshes: node, edge and triangle ids of part p are offset by the totals
+// of parts 0..p-1, and so are their device numberings (each part keeps its own order).
+int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out);
 uint32_t morton_key(uint32_t qx, uint32_t qz);
 
 // Run fn(begin, end) over [0, n) on the host's hardware threads in fixed contiguous

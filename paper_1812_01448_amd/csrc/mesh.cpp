@@ -403,6 +403,52 @@ int reorder_mesh(Mesh &m, int32_t kind, uint64_t seed) {
     return TYEE_OK;
 }
 
+int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out) {
+    if (parts.empty()) return fail(TYEE_EINVAL, "no meshes to merge");
+    out = Mesh();
+    int64_t nv = 0, ne = 0, nt = 0;
+    for (const Mesh *p : parts) {
+        nv += p->nv;
+        ne += p->ne;
+        nt += p->nt;
+    }
+    if (nv > INT32_MAX || 3 * nt > INT32_MAX) return fail(TYEE_EINVAL, "batch too large for int32 ids");
+    out.periodic = parts[0]->periodic;
+    out.Lx = parts[0]->Lx;
+    out.Ly = parts[0]->Ly;
+    out.order_kind = parts[0]->order_kind;
+    int32_t ov = 0, oe = 0, ot = 0;
+    auto shift = [](int32_t v, int32_t off) { return v >= 0 ? v + off : v; };
+    for (const Mesh *p : parts) {
+        out.xy.insert(out.xy.end(), p->xy.begin(), p->xy.end());
+        for (int32_t v : p->tri) out.tri.push_back(v + ov);
+        for (int32_t v : p->edge) out.edge.push_back(v + ov);
+        for (int32_t v : p->R) out.R.push_back(shift(v, ot));
+        for (int32_t v : p->L) out.L.push_back(shift(v, ot));
+        for (int32_t v : p->A) out.A.push_back(v + oe);
+        out.sgn.insert(out.sgn.end(), p->sgn.begin(), p->sgn.end());
+        out.evec.insert(out.evec.end(), p->evec.begin(), p->evec.end());
+        out.elen.insert(out.elen.end(), p->elen.begin(), p->elen.end());
+        out.hR.insert(out.hR.end(), p->hR.begin(), p->hR.end());
+        out.hL.insert(out.hL.end(), p->hL.begin(), p->hL.end());
+        out.d.insert(out.d.end(), p->d.begin(), p->d.end());
+        out.S.insert(out.S.end(), p->S.begin(), p->S.end());
+        out.O.insert(out.O.end(), p->O.begin(), p->O.end());
+        out.C.insert(out.C.end(), p->C.begin(), p->C.end());
+        out.node_outer.insert(out.node_outer.end(), p->node_outer.begin(), p->node_outer.end());
+        for (int32_t v : p->perm_t) out.perm_t.push_back(v + ot);
+        for (int32_t v : p->perm_e) out.perm_e.push_back(v + oe);
+        out.nb += p->nb;
+        ov += int32_t(p->nv);
+        oe += int32_t(p->ne);
+        ot += int32_t(p->nt);
+    }
+    out.nv = nv;
+    out.ne = ne;
+    out.nt = nt;
+    return TYEE_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // omega_max^2 by normalised iteration on K = -L_E L_B in the S-weighted product
 // ---------------------------------------------------------------------------------------

@@ -79,9 +79,10 @@ int upload_coefficients(Sim &s) {
     for (int64_t k = 0; k < s.ne; ++k) {
         int32_t i = s.perm_e[k];
         bool inner = s.R[i] >= 0 && s.L[i] >= 0;
-        ce[k] = inner ? s.dt * s.gamma[i] * s.gamma[i] * s.elen[i] / s.d[i] : 0.0;
+        ce[k] = inner ? s.dt_edge[i] * s.gamma[i] * s.gamma[i] * s.elen[i] / s.d[i] : 0.0;
     }
-    for (int64_t k = 0; k < s.nt; ++k) nb[k] = -s.dt / s.S[s.perm_t[k]];
+    for (int64_t k = 0; k < s.nt; ++k) nb[k] = -s.dt_tri[s.perm_t[k]] / s.S[s.perm_t[k]];
+    s.graph_dirty = true;
     s.ce_dev = ce;
     s.nb_dev = nb;
     int rc = upload_field(s, s.cE, ce);
@@ -241,6 +242,37 @@ int64_t steps_to_next_sample(const Sim &s) {
     return best;
 }
 
+// Replay `graph_launches` fused launches captured in a HIP graph (captured on first use and
+// whenever the tiling, coefficients or buffers changed).  An even launch count returns the
+// field buffers to the same parity, so one graph serves every replay.
+template <typename T> int replay_graph(Sim &s, int k) {
+    if (s.graph_dirty || !s.graph || s.graph_K != k || s.graph_cur != s.cur) {
+        if (s.graph) {
+            (void)hipGraphExecDestroy(s.graph);
+            s.graph = nullptr;
+        }
+        const int cur0 = s.cur;
+        TYEE_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+        int rc = TYEE_OK;
+        for (int g = 0; g < s.graph_launches && !rc; ++g) rc = launch_fused<T>(s, k);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s.stream, &graph);
+        s.cur = cur0;
+        if (rc) return rc;
+        if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&s.graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        s.graph_dirty = false;
+        s.graph_K = k;
+        s.graph_cur = s.cur;
+    }
+    return timed(s, TYEE_KERNEL_GRAPH, [&]() -> int {
+        TYEE_HIP(hipGraphLaunch(s.graph, s.stream));
+        return TYEE_OK;
+    });
+}
+
 template <typename T> int enqueue_steps(Sim &s, int64_t n) {
     const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
     const T *cE = s.cE.as<T>(), *nB = s.nB.as<T>();
@@ -272,11 +304,33 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
             if (k > n - done || k > steps_to_next_sample(s)) k = 1;  // remainder: single steps
         }
         if (rc) break;
+        if (k > 1 && s.graph_launches > 0 && k == s.fusion && !s.timer_wants_kernels()) {
+            const int64_t span = int64_t(k) * s.graph_launches;
+            if (n - done >= span && steps_to_next_sample(s) >= span) {
+                if (!s.tiling || s.tiling->K != k) {
+                    rc = build_tiling(s, k, s.tile_tris);
+                    if (rc == TYEE_EINVAL) {  // this mesh does not tile at that depth
+                        clear_error();
+                        s.fusion = 1;
+                        rc = TYEE_OK;
+                        continue;
+                    }
+                    if (rc) break;
+                }
+                rc = replay_graph<T>(s, k);
+                if (rc) break;
+                s.step += span;
+                done += span;
+                if (!s.probes.empty()) rc = sample_probes<T>(s);
+                continue;
+            }
+        }
         if (k > 1 && (!s.tiling || s.tiling->K != k)) {
             rc = build_tiling(s, k, s.tile_tris);
             if (rc == TYEE_EINVAL) {  // this mesh does not tile at that depth: plain launches
                 clear_error();
                 rc = TYEE_OK;
+                s.fusion = 1;
                 k = 1;
             }
             if (rc) break;
@@ -306,8 +360,69 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
 }  // namespace
 
 Sim::~Sim() {
+    if (graph) (void)hipGraphExecDestroy(graph);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    probes.clear();
+    tiling.reset();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+// Set up a simulation of mesh m: copies of the host arrays it needs, zero fields, packed
+// coefficients and connectivity on the device.  dt_tri / dt_edge: time step per canonical
+// triangle / edge.
+int init_sim(Sim &s, const Mesh &m, int32_t prec, const std::vector<double> &dt_tri,
+             const std::vector<double> &dt_edge, void *stream) {
+    s.f64 = prec == TYEE_F64;
+    s.esz = s.f64 ? 8 : 4;
+    s.dt = dt_tri.empty() ? 0.0 : dt_tri[0];
+    s.dt_tri = dt_tri;
+    s.dt_edge = dt_edge;
+    s.nv = m.nv;
+    s.ne = m.ne;
+    s.nt = m.nt;
+    s.perm_t = m.perm_t;
+    s.perm_e = m.perm_e;
+    s.slot_t.resize(m.nt);
+    s.slot_e.resize(m.ne);
+    for (int64_t k = 0; k < m.nt; ++k) s.slot_t[m.perm_t[k]] = int32_t(k);
+    for (int64_t k = 0; k < m.ne; ++k) s.slot_e[m.perm_e[k]] = int32_t(k);
+    s.edge = m.edge;
+    s.R = m.R;
+    s.L = m.L;
+    s.A = m.A;
+    s.sgn = m.sgn;
+    s.elen = m.elen;
+    s.d = m.d;
+    s.hR = m.hR;
+    s.hL = m.hL;
+    s.S = m.S;
+    s.node_outer = m.node_outer;
+    s.gamma.assign(m.ne, 1.0);
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+    if (stream) {
+        s.stream = static_cast<hipStream_t>(stream);
+    } else {
+        // graphs cannot be captured on the legacy default stream: use a stream of our own
+        TYEE_HIP(hipStreamCreate(&s.stream));
+        s.own_stream = true;
+    }
+    std::vector<double> zero_e(m.ne, 0.0), zero_t(m.nt, 0.0), zero_v(m.nv, 0.0);
+    int rc = TYEE_OK;
+    for (int b = 0; b < 2 && !rc; ++b) {
+        rc = upload_field(s, s.Et_buf[b], zero_e);
+        if (!rc) rc = upload_field(s, s.B_buf[b], zero_t);
+    }
+    if (!rc) rc = upload_field(s, s.Q, zero_v);
+    if (!rc) rc = upload_coefficients(s);
+    if (!rc) rc = upload_connectivity(s);
+    if (!rc) rc = rebuild_specials(s);
+    if (rc) return rc;
+    if (hipEventCreate(&s.ev0) != hipSuccess || hipEventCreate(&s.ev1) != hipSuccess)
+        return fail(TYEE_EDEVICE, "hipEventCreate failed");
+    return TYEE_OK;
 }
 
 }  // namespace tyee
@@ -316,9 +431,6 @@ Sim::~Sim() {
 // C ABI: simulation
 // ---------------------------------------------------------------------------------------
 
-struct tyee_sim {
-    tyee::Sim s;
-};
 
 using tyee::fail;
 
@@ -331,49 +443,10 @@ int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(TYEE_EINVAL, "dt must be positive and finite");
     try {
         std::unique_ptr<tyee_sim> h(new tyee_sim());
-        tyee::Sim &s = h->s;
         const tyee::Mesh &m = mesh->m;
-        s.f64 = prec == TYEE_F64;
-        s.esz = s.f64 ? 8 : 4;
-        s.dt = dt;
-        s.stream = static_cast<hipStream_t>(stream);
-        s.nv = m.nv;
-        s.ne = m.ne;
-        s.nt = m.nt;
-        s.perm_t = m.perm_t;
-        s.perm_e = m.perm_e;
-        s.slot_t.resize(m.nt);
-        s.slot_e.resize(m.ne);
-        for (int64_t k = 0; k < m.nt; ++k) s.slot_t[m.perm_t[k]] = int32_t(k);
-        for (int64_t k = 0; k < m.ne; ++k) s.slot_e[m.perm_e[k]] = int32_t(k);
-        s.edge = m.edge;
-        s.R = m.R;
-        s.L = m.L;
-        s.A = m.A;
-        s.sgn = m.sgn;
-        s.elen = m.elen;
-        s.d = m.d;
-        s.hR = m.hR;
-        s.hL = m.hL;
-        s.S = m.S;
-        s.node_outer = m.node_outer;
-        s.gamma.assign(m.ne, 1.0);
-        int device = 0;
-        hipError_t e = hipGetDevice(&device);
-        if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
-        std::vector<double> zero_e(m.ne, 0.0), zero_t(m.nt, 0.0), zero_v(m.nv, 0.0);
-        int rc = TYEE_OK;
-        for (int b = 0; b < 2 && !rc; ++b) {
-            rc = tyee::upload_field(s, s.Et_buf[b], zero_e);
-            if (!rc) rc = tyee::upload_field(s, s.B_buf[b], zero_t);
-        }
-        if (!rc) rc = tyee::upload_field(s, s.Q, zero_v);
-        if (!rc) rc = tyee::upload_coefficients(s);
-        if (!rc) rc = tyee::upload_connectivity(s);
-        if (!rc) rc = tyee::rebuild_specials(s);
+        int rc = tyee::init_sim(h->s, m, prec, std::vector<double>(m.nt, dt), std::vector<double>(m.ne, dt),
+                                stream);
         if (rc) return rc;
-        if (hipEventCreate(&s.ev0) != hipSuccess || hipEventCreate(&s.ev1) != hipSuccess)
-            return fail(TYEE_EDEVICE, "hipEventCreate failed");
         *out = h.release();
         return TYEE_OK;
     } catch (const std::bad_alloc &) {
@@ -539,6 +612,16 @@ int tyee_sim_set_fusion(tyee_sim *sim, int32_t k, int32_t tile_tris) {
     if (s.tile_tris != tile_tris) s.tiling.reset();
     s.fusion = k;
     s.tile_tris = tile_tris;
+    s.graph_dirty = true;
+    return TYEE_OK;
+}
+
+int tyee_sim_set_graph(tyee_sim *sim, int32_t launches) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    if (launches < 0 || launches % 2 || launches > 1024)
+        return fail(TYEE_EINVAL, "launches per graph must be 0 or an even number up to 1024");
+    sim->s.graph_launches = launches;
+    sim->s.graph_dirty = true;
     return TYEE_OK;
 }
 
@@ -586,7 +669,7 @@ int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out) {
             const int32_t i = s.A[3 * j + q];
             circ += double(s.sgn[3 * j + q]) * s.scale(i) * E[i];
         }
-        d.energy_h += s.S[j] * (B[j] + s.dt / s.S[j] * circ) * B[j];
+        d.energy_h += s.S[j] * (B[j] + s.dt_tri[j] / s.S[j] * circ) * B[j];
     }
     bool bad = false;
     for (int64_t i = 0; i < s.ne; ++i) {

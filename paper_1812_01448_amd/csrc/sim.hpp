@@ -33,7 +33,10 @@ struct DeviceBuffer {
     ~DeviceBuffer() {
         if (p) (void)hipFree(p);
     }
+    // (Re)allocate n bytes; an existing buffer of the same size is kept, so device
+    // addresses captured in a graph stay valid across state uploads.
     int alloc(size_t n) {
+        if (p && bytes == n) return TYEE_OK;
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = n;
@@ -51,7 +54,7 @@ struct DeviceBuffer {
 // Per-launch HIP-event timing of the stepping kernels (enabled per kernel kind).  A ring
 // of event pairs keeps the queue deep: only the oldest pair is waited for when it fills.
 struct LaunchTimer {
-    static constexpr int kKinds = 5;
+    static constexpr int kKinds = 6;
     static constexpr size_t kRing = 1024;
     struct Pair {
         int kind = 0;
@@ -60,8 +63,8 @@ struct LaunchTimer {
     uint32_t mask = 0;
     std::vector<Pair> ring;
     size_t head = 0, pending = 0;
-    int64_t count[kKinds] = {0, 0, 0, 0, 0};
-    double total_ms[kKinds] = {0, 0, 0, 0, 0};
+    int64_t count[kKinds] = {0, 0, 0, 0, 0, 0};
+    double total_ms[kKinds] = {0, 0, 0, 0, 0, 0};
 
     ~LaunchTimer() {
         for (auto &p : ring) {
@@ -132,8 +135,14 @@ struct Probe {
 struct Sim {
     bool f64 = false;
     size_t esz = 4;
-    double dt = 0.0;
+    double dt = 0.0;                           // time step (of the first mesh in a batch)
+    std::vector<double> dt_tri, dt_edge;       // per canonical cell (batches mix meshes)
     hipStream_t stream = nullptr;
+    bool own_stream = false;                   // created by the library (caller passed NULL)
+    int graph_launches = 0;                    // fused launches per captured graph (0 = eager)
+    hipGraphExec_t graph = nullptr;
+    bool graph_dirty = true;
+    int graph_K = 0, graph_cur = -1;
     int64_t nv = 0, ne = 0, nt = 0;
     int64_t step = 0;
     int fusion = 1;
@@ -175,6 +184,8 @@ struct Sim {
     ~Sim();
 
     double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
+    // per-launch timing of fused kernels needs eager launches
+    bool timer_wants_kernels() const { return (timer.mask & (1u << TYEE_KERNEL_FUSED)) != 0; }
 };
 
 
@@ -196,7 +207,13 @@ struct Tiling {
 };
 
 int build_tiling(Sim &s, int K, int tile_tris);
+int init_sim(Sim &s, const Mesh &m, int32_t prec, const std::vector<double> &dt_tri,
+             const std::vector<double> &dt_edge, void *stream);
 int refresh_tiling_coefficients(Sim &s);
 template <typename T> int launch_fused(Sim &s, int k);
 
 }  // namespace tyee
+
+struct tyee_sim {
+    tyee::Sim s;
+};

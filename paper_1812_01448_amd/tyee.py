@@ -47,6 +47,11 @@ class _View(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in _VIEW_FIELDS]
 
 
+class _Tune(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
+                ("tile_tris", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+
+
 class _Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
                 ("energy_h", ctypes.c_double), ("max_abs_E", ctypes.c_double),
@@ -60,11 +65,15 @@ EXPORTS = [
     "tyee_sim_set_edge_scale", "tyee_sim_set_fusion", "tyee_sim_step", "tyee_sim_sync",
     "tyee_sim_diagnostics", "tyee_sim_last_step_ms", "tyee_sim_set_profiling",
     "tyee_sim_kernel_times", "tyee_sim_get_fusion", "tyee_sim_steps", "tyee_sim_destroy",
-    "tyee_sim_gauss", "tyee_sim_add_probe", "tyee_sim_read_probe", "tyee_last_error",
+    "tyee_sim_gauss", "tyee_sim_add_probe", "tyee_sim_read_probe", "tyee_sim_set_graph",
+    "tyee_batch_create", "tyee_batch_set_state", "tyee_batch_get_state", "tyee_batch_reorder",
+    "tyee_batch_set_fusion", "tyee_batch_set_graph", "tyee_batch_step", "tyee_batch_sync",
+    "tyee_batch_info", "tyee_batch_sim", "tyee_batch_tune", "tyee_batch_destroy",
+    "tyee_last_error",
 ]
-KERNELS = {"edge": 0, "tri": 1, "fused": 2, "special": 3, "charge": 4}
+KERNELS = {"edge": 0, "tri": 1, "fused": 2, "special": 3, "charge": 4, "graph": 5}
 KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special": "k_special",
-                "charge": "k_charge"}
+                "charge": "k_charge", "graph": "graph of k_fused"}
 
 
 def _load():
@@ -94,6 +103,18 @@ def _load():
         "tyee_sim_kernel_times": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)],
         "tyee_sim_get_fusion": [vp, vp],
         "tyee_sim_gauss": [vp, vp],
+        "tyee_sim_set_graph": [vp, i32],
+        "tyee_batch_create": [vp, vp, i64, i32, vp, ctypes.POINTER(vp)],
+        "tyee_batch_set_state": [vp, i64, i32, vp],
+        "tyee_batch_get_state": [vp, i64, i32, vp],
+        "tyee_batch_reorder": [vp, i32, ctypes.c_uint64],
+        "tyee_batch_set_fusion": [vp, i32, i32],
+        "tyee_batch_set_graph": [vp, i32],
+        "tyee_batch_step": [vp, i64],
+        "tyee_batch_sync": [vp],
+        "tyee_batch_info": [vp, vp],
+        "tyee_batch_sim": [vp, ctypes.POINTER(vp)],
+        "tyee_batch_tune": [vp, i64, vp, i64, ctypes.POINTER(i64)],
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
     }
@@ -105,6 +126,8 @@ def _load():
     lib.tyee_mesh_destroy.restype = None
     lib.tyee_sim_destroy.argtypes = [vp]
     lib.tyee_sim_destroy.restype = None
+    lib.tyee_batch_destroy.argtypes = [vp]
+    lib.tyee_batch_destroy.restype = None
     lib.tyee_sim_steps.argtypes = [vp]
     lib.tyee_sim_steps.restype = i64
     lib.tyee_last_error.argtypes = []
@@ -272,6 +295,11 @@ class Sim:
                              "steps_per_launch": self.fusion_used() if name == "fused" else 1}
         return out
 
+    def set_graph(self, launches):
+        """Fused launches per captured HIP graph (even; 0 = eager launches)."""
+        _check(lib.tyee_sim_set_graph(self._h, int(launches)))
+        self.graph_launches = int(launches)
+
     def fusion_info(self):
         out = np.zeros(5, np.int64)
         _check(lib.tyee_sim_get_fusion(self._h, _ptr(out)))
@@ -311,3 +339,80 @@ class Sim:
     @property
     def steps(self):
         return int(lib.tyee_sim_steps(self._h))
+
+
+class _BorrowedSim(Sim):
+    """Sim view of a batch's union (not owned: never destroyed from Python)."""
+
+    def __init__(self, handle, nv, ne, nt, prec):
+        self._h = handle
+        self.nv, self.ne, self.nt, self.prec = nv, ne, nt, prec
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """Many independent meshes stepped together in one union (see tyee_batch_create)."""
+
+    def __init__(self, meshes, dts, prec="f32", stream=None):
+        arr = (ctypes.c_void_p * len(meshes))(*[m._h.value for m in meshes])
+        dt = _f64(dts, len(meshes))
+        h = ctypes.c_void_p()
+        _check(lib.tyee_batch_create(arr, _ptr(dt), len(meshes), PREC[prec],
+                                     None if stream is None else int(stream), ctypes.byref(h)))
+        self._h = h
+        self.prec = prec
+        self.sizes = [(m.nv, m.ne, m.nt) for m in meshes]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_batch_destroy(h)
+            self._h = None
+
+    def info(self):
+        out = np.zeros(4, np.int64)
+        _check(lib.tyee_batch_info(self._h, _ptr(out)))
+        return dict(zip(["members", "triangles", "edges", "nodes"], (int(v) for v in out)))
+
+    def sim(self):
+        h = ctypes.c_void_p()
+        _check(lib.tyee_batch_sim(self._h, ctypes.byref(h)))
+        i = self.info()
+        return _BorrowedSim(h, i["nodes"], i["edges"], i["triangles"], self.prec)
+
+    def set_state(self, k, field, values):
+        n = self.sizes[k][1] if field == "E" else self.sizes[k][2]
+        a = _f64(values, n)
+        _check(lib.tyee_batch_set_state(self._h, int(k), FIELD[field], _ptr(a)))
+
+    def get_state(self, k, field):
+        out = np.zeros(self.sizes[k][1] if field == "E" else self.sizes[k][2])
+        _check(lib.tyee_batch_get_state(self._h, int(k), FIELD[field], _ptr(out)))
+        return out
+
+    def reorder(self, kind, seed=0):
+        _check(lib.tyee_batch_reorder(self._h, ORDER[kind], int(seed)))
+
+    def set_fusion(self, k, tile=0):
+        _check(lib.tyee_batch_set_fusion(self._h, int(k), int(tile)))
+
+    def set_graph(self, launches):
+        _check(lib.tyee_batch_set_graph(self._h, int(launches)))
+
+    def step(self, n):
+        _check(lib.tyee_batch_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib.tyee_batch_sync(self._h))
+
+    def tune(self, steps_per_trial=64):
+        cap = 64
+        res = (_Tune * cap)()
+        n = ctypes.c_int64()
+        _check(lib.tyee_batch_tune(self._h, int(steps_per_trial), res, cap, ctypes.byref(n)))
+        names = {v: k for k, v in ORDER.items()}
+        return [{"order": names[r.order], "steps_per_launch": r.steps_per_launch,
+                 "tile_tris": r.tile_tris, "ms_per_step": r.ms_per_step}
+                for r in res[:min(cap, n.value)]]
