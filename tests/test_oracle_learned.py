@@ -1,0 +1,119 @@
+"""Pins of the learned-correction oracle: closed forms on the equilateral mesh, geometric
+identities of the features, finite-difference checks of both analytic gradients, and the
+exact leap-frog phase of an eigenmode measured by the time-stepped phase error."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as L
+from meshgen import lattice_mesh, equilateral_torus, scramble
+
+SQ3 = np.sqrt(3.0)
+
+
+@pytest.fixture(scope="module")
+def eq_mesh():
+    xy, tri, Lx, Ly = equilateral_torus(12, 8, a=1.0)
+    return oracle.OracleMesh(xy, tri, True, Lx, Ly)
+
+
+@pytest.fixture(scope="module")
+def jit_mesh():
+    xy, tri = lattice_mesh(24, 0.3, 3, periodic=True)
+    return oracle.OracleMesh(xy, tri, True)
+
+
+def test_features_closed_form_on_equilateral_mesh(eq_mesh):
+    f = L.features(eq_mesh)
+    expect = [1 / SQ3, np.pi / 3, np.pi / 3, 1 / SQ3, 1 / SQ3, 0.0, 1 / np.sqrt(SQ3 / 4), 0.0]
+    np.testing.assert_allclose(f, np.tile(expect, (eq_mesh.ne, 1)), atol=1e-12)
+
+
+def test_features_geometry_and_symmetry(jit_mesh):
+    f = L.features(jit_mesh)
+    # d/|e| = (cot a_R + cot a_L)/2: the half dual length is (|e|/2) cot(opposite angle)
+    np.testing.assert_allclose(f[:, 0], (1 / np.tan(f[:, 1]) + 1 / np.tan(f[:, 2])) / 2,
+                               rtol=1e-9)
+    m = jit_mesh
+    assert np.all(f[:, 1] <= f[:, 2]) and np.all(f[:, 3] <= f[:, 4])
+    assert np.all((f[:, 3] >= 1 / SQ3 - 1e-12))           # circumradius >= side / sqrt(3)
+    # winding and row order of the input do not change any edge's features
+    st, _ = scramble(m.tri, 4)
+    m2 = oracle.OracleMesh(m.xy, st, True)
+    np.testing.assert_allclose(L.features(m2), f, rtol=1e-10, atol=1e-12)
+
+
+def _theta(seed, scale=0.5):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-scale, scale, L.N_PARAMS)
+
+
+def test_mlp_identity_init_and_fd_gradient(jit_mesh):
+    f = L.features(jit_mesh)[:200]
+    mu, sd = f.mean(0), f.std(0) + 1e-3
+    th = _theta(1)
+    p0 = th.copy()
+    p0[-(L.H2 + 1):] = 0.0                                 # w3 = b3 = 0
+    assert np.all(L.mlp_forward(p0, f, mu, sd) == 1.0)
+    rng = np.random.default_rng(2)
+    up = rng.standard_normal(len(f))
+    grad = L.mlp_param_grad(th, f, mu, sd, up)
+    h = 1e-6
+    for idx in list(range(0, L.N_PARAMS, 97)) + [L.N_PARAMS - 1]:
+        tp, tm = th.copy(), th.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        fd = (np.dot(up, L.mlp_forward(tp, f, mu, sd)) - np.dot(up, L.mlp_forward(tm, f, mu, sd))) / (2 * h)
+        assert abs(fd - grad[idx]) < 1e-7 * max(1.0, abs(fd)), idx
+    g = L.mlp_forward(th, f, mu, sd)
+    assert np.all((g > 0.9) & (g < 1.1))
+
+
+def test_rq_closed_form_on_equilateral_mesh(eq_mesh):
+    m = eq_mesh
+    delta = np.array([[0.0, -1 / SQ3], [0.5, 1 / (2 * SQ3)], [-0.5, 1 / (2 * SQ3)]])
+    dt = 0.1
+    for m1, m2 in ((1, 0), (2, 1), (3, 2), (0, 1)):
+        k = 2 * np.pi * np.array([m1 / m.Lx, m2 / m.Ly])
+        w2 = 4.0 * (3.0 - np.sum(np.cos(delta @ k)))
+        expect = 2 / dt * np.arcsin(np.sqrt(w2) * dt / 2) / np.hypot(*k) - 1
+        assert abs(L.rq_phase_error(m, None, dt, k) - expect) < 1e-12
+
+
+def test_rq_loss_gradient_fd(jit_mesh):
+    m = jit_mesh
+    rng = np.random.default_rng(3)
+    gamma = 1 + 0.05 * rng.standard_normal(m.ne)
+    dt = 0.5 * 2 / np.sqrt(m.power()[0])
+    waves = [2 * np.pi * np.array(v, float) for v in ((1, 0), (2, 3), (-1, 4))]
+    loss, grad = L.rq_loss_grad(m, gamma, dt, waves)
+    assert loss > 0
+    h = 1e-6
+    for i in rng.choice(m.ne, 12, replace=False):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[i] += h
+        gm[i] -= h
+        fd = (L.rq_loss_grad(m, gp, dt, waves)[0] - L.rq_loss_grad(m, gm, dt, waves)[0]) / (2 * h)
+        assert abs(fd - grad[i]) < 1e-6 * max(abs(fd), 1e-12) + 1e-14
+    # scaling every coefficient by c scales omega_RQ by c (before the leap-frog asin)
+    k = waves[0]
+    kn = np.hypot(*k)
+    e1 = L.rq_phase_error(m, None, dt, k)
+    e2 = L.rq_phase_error(m, np.full(m.ne, 1.01), dt, k)
+    s1 = np.sin((1 + e1) * kn * dt / 2)             # omega_RQ dt / 2 of the plain operator
+    assert abs((1 + e2) - 2 / dt * np.arcsin(1.01 * s1) / kn) < 1e-12
+
+
+def test_timestepped_phase_error_of_an_eigenmode(eq_mesh):
+    # k along x on the equilateral torus: exp(i k.O) is an exact eigenvector of K with
+    # omega = (4/a) sin(k a / 4); leap-frog then advances its phase by theta per step with
+    # sin(theta/2) = omega dt / 2.
+    m = eq_mesh
+    dt = 0.5 * 2 / (2 * np.sqrt(6))
+    for m1 in (1, 2):
+        k = np.array([2 * np.pi * m1 / m.Lx, 0.0])
+        om_ex = 4 * np.sin(k[0] / 4)
+        expect = 2 / dt * np.arcsin(om_ex * dt / 2) / k[0] - 1
+        got = L.timestepped_phase_error(m, None, dt, k, 400, samples=200)
+        assert abs(got - expect) < 2e-3 * abs(expect) + 1e-5
+        assert abs(L.rq_phase_error(m, None, dt, k) - expect) < 1e-12
