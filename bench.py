@@ -37,8 +37,15 @@ def parse():
     p.add_argument("--prec", default="f32", choices=["f32", "f64"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
-    p.add_argument("--workload", default="torus1415", choices=["torus1415", "batch256"],
-                   help="torus1415 (the reported line) or batch256 (256 uneven meshes)")
+    p.add_argument("--workload", default="torus1415", choices=["torus1415", "batch256", "learned"],
+                   help="torus1415 (the reported line), batch256 (256 uneven meshes) or "
+                        "learned (train and evaluate the learned edge scale)")
+    p.add_argument("--train-meshes", type=int, default=64)
+    p.add_argument("--train-n", type=int, default=316)
+    p.add_argument("--eval-meshes", type=int, default=16)
+    p.add_argument("--eval-n", type=int, default=707)
+    p.add_argument("--iters", type=int, default=400)
+    p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--graph", type=int, default=8, help="fused launches per HIP graph (0 = eager)")
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
     p.add_argument("--copy-calibration", action="store_true",
@@ -100,6 +107,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch256":
         bench_batch(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
 
     import torch
@@ -284,6 +294,140 @@ def bench_batch(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
                      "algorithmic_bytes_per_launch": per_launch, "traffic": None},
         "tune": tuned,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _waves(n, cells, angles):
+    from meshgen import periodic_wavevector
+    return np.array([periodic_wavevector(a, r, 1.0 / n)[0] for r in cells for a in angles])
+
+
+def _resolution_to_reach(r_grid, err, target):
+    """Coarsest resolution r* with err(r) <= target for every r in [r*, 10] (linear
+    interpolation between grid points)."""
+    r_grid, err = np.asarray(r_grid, float), np.asarray(err, float)
+    i10 = int(np.argmin(np.abs(r_grid - 10.0)))
+    if err[i10] > target:                       # worse than plain at 10: scan finer grids
+        for i in range(i10 + 1, len(r_grid)):
+            if err[i] <= target:
+                a, b = r_grid[i - 1], r_grid[i]
+                return a + (b - a) * (err[i - 1] - target) / (err[i - 1] - err[i])
+        return float(r_grid[-1])
+    for i in range(i10, 0, -1):
+        if err[i - 1] > target:
+            a, b = r_grid[i - 1], r_grid[i]
+            return b - (b - a) * (target - err[i]) / (err[i - 1] - err[i])
+    return float(r_grid[0])
+
+
+def bench_learned(args):
+    """Train the learned edge scale on the GPU and evaluate it on held-out meshes."""
+    import torch
+    import paper_1812_01448_amd as ty
+    from meshgen import lattice_mesh
+
+    angles = np.arange(12) * np.pi / 12
+    r_grid = [4, 5, 6, 7, 8, 9, 10, 12, 14]
+    stream = None
+    torch.cuda.init()
+    t0 = time.time()
+    train = []
+    for k in range(args.train_meshes):
+        xy, tri = lattice_mesh(args.train_n, 0.3, 100 + k, periodic=True)
+        m = ty.Mesh(xy, tri, True)
+        lam, _, _ = m.cfl()
+        train.append((m, 0.5 * 2 / np.sqrt(lam)))
+    W = _waves(args.train_n, (8, 10, 16, 32), angles)
+    log(f"{len(train)} training meshes ({train[0][0].nt} triangles) in {time.time() - t0:.1f} s")
+    learner = ty.Learner([m for m, _ in train], [d for _, d in train],
+                         np.stack([W] * len(train)), stream=stream)
+    learner.init(seed=0)
+    loss0, _, _ = learner.loss_grad(want_grad=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = learner.train(args.iters, args.lr)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    loss1, _, _ = learner.loss_grad(want_grad=False)
+    theta = learner.params()
+    log(f"trained {args.iters} Adam steps in {train_s:.2f} s: loss {loss0:.4e} -> {loss1:.4e}")
+    # constant-scale ablation: best single gamma for every edge on the training set
+    best_c, best_l = 1.0, loss0
+    for c in np.arange(0.990, 1.0201, 0.0005):
+        th = np.zeros_like(theta)
+        th[-1] = np.arctanh((c - 1.0) / 0.1)
+        learner.set_params(th)
+        lc, _, _ = learner.loss_grad(want_grad=False)
+        if lc < best_l:
+            best_c, best_l = float(c), lc
+    learner.set_params(theta)
+    log(f"best constant scale {best_c:.4f} (loss {best_l:.4e})")
+
+    rows = []
+    for k in range(args.eval_meshes):
+        xy, tri = lattice_mesh(args.eval_n, 0.3, 200 + k, periodic=True)
+        m = ty.Mesh(xy, tri, True)
+        gam = learner.gamma(m)
+        w10 = _waves(args.eval_n, (10,), angles)
+        gate = m.gate(gam, w10)
+        const = np.full(m.ne, best_c)
+        gate_c = m.gate(const, w10)
+        row = {"triangles": m.nt, "accepted": bool(gate["accepted"]),
+               "dt_ratio": gate["dt_learned"] / gate["dt_plain"],
+               "dt_ratio_const": gate_c["dt_learned"] / gate_c["dt_plain"]}
+        curves = {}
+        for name, g, dt in (("plain", None, gate["dt_plain"]),
+                            ("learned", gam if gate["accepted"] else None,
+                             gate["dt_learned"] if gate["accepted"] else gate["dt_plain"]),
+                            ("const", const, gate_c["dt_learned"])):
+            e = m.phase_error_rq(dt, _waves(args.eval_n, r_grid, angles), gamma=g)
+            curves[name] = np.abs(e).reshape(len(r_grid), len(angles)).mean(1)
+        target = curves["plain"][r_grid.index(10)]
+        for name in ("learned", "const"):
+            rs = _resolution_to_reach(r_grid, curves[name], target)
+            dtr = row["dt_ratio"] if name == "learned" else row["dt_ratio_const"]
+            if name == "learned" and not gate["accepted"]:
+                rs, dtr = 10.0, 1.0
+            row[f"r_star_{name}"] = rs
+            row[f"cost_ratio_{name}"] = (10.0 / rs) ** 3 * dtr
+            row[f"err10_{name}"] = float(curves[name][r_grid.index(10)])
+        row["err10_plain"] = float(target)
+        if k < 2:   # time-stepped check of the 10-cells/lambda error at two angles
+            ts = []
+            for a in (0, 3):
+                kv = w10[a]
+                nsteps = int(min(200000, max(2000, 3.0 / (np.hypot(*kv) * gate["dt_plain"]))))
+                ep = m.phase_error_timestepped(gate["dt_plain"], kv, nsteps, samples=20)
+                el = m.phase_error_timestepped(gate["dt_learned"], kv, nsteps, samples=20, gamma=gam)
+                ts.append({"angle_deg": float(np.degrees(angles[a])), "steps": nsteps,
+                           "plain": ep, "learned": el})
+            row["timestepped"] = ts
+        rows.append(row)
+        log(f"eval {k}: accepted {row['accepted']} err10 plain {row['err10_plain']:.4e} "
+            f"learned {row['err10_learned']:.4e} cost ratio {row['cost_ratio_learned']:.3f} "
+            f"(const {row['cost_ratio_const']:.3f})")
+    ratio = float(np.mean([r["cost_ratio_learned"] for r in rows]))
+    out = {
+        "metric": "cell-updates to reach the plain method's phase error at 10 cells/lambda, "
+                  "plain / learned",
+        "value": ratio, "unit": "x", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "learned edge scale: %d training meshes of %d triangles, %d "
+                               "held-out meshes of %d triangles, jitter 0.3"
+                               % (len(train), train[0][0].nt, len(rows), rows[0]["triangles"]),
+                   "waves_train": "12 angles x (8, 10, 16, 32) cells/lambda",
+                   "iters": args.iters, "lr": args.lr},
+        "train": {"loss_initial": loss0, "loss_final": loss1, "seconds": train_s,
+                  "ms_per_iter": 1e3 * train_s / max(1, args.iters),
+                  "loss_history_every_50": [float(h) for h in hist[::50]]},
+        "accepted": int(sum(r["accepted"] for r in rows)),
+        "err10_plain": float(np.mean([r["err10_plain"] for r in rows])),
+        "err10_learned": float(np.mean([r["err10_learned"] for r in rows])),
+        "cost_ratio_const": float(np.mean([r["cost_ratio_const"] for r in rows])),
+        "best_constant_scale": best_c,
+        "dt_ratio": float(np.mean([r["dt_ratio"] for r in rows])),
+        "per_mesh": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -256,6 +256,84 @@ int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]);
 int64_t tyee_sim_steps(const tyee_sim *sim);
 void tyee_sim_destroy(tyee_sim *sim);
 
+/* ------------------------------------------------------ learned correction ---- */
+
+/* Eight geometry features per edge (canonical order), FP64: out [n_edges][8] =
+   { d/|e|; min and max of the angles opposite the edge in R and L; min and max of
+     circumradius / shortest side of R and L; |hR - hL|/d (how far the edge midpoint is from
+     the segment O_R O_L, the off-centring that degrades eq. 3); |e|/sqrt(mean triangle
+     area); |S_R - S_L|/(S_R + S_L) }.  All are unchanged by swapping R and L or reversing the
+   edge (Fig. 2 allows either direction).  Outer edges repeat their one triangle. */
+int tyee_mesh_features(const tyee_mesh *mesh, double *out);
+
+/* Phase-velocity error of plane waves exp(i k.O) from the Rayleigh quotient of
+   K_gamma = -L_E L_B with edge scale gamma (NULL = 1), with the leap-frog correction:
+   omega_RQ^2 = sum_i gamma_i^2 (|e_i|/d_i) |exp(i k.O_R) - exp(i k.O_L)|^2 / sum_j S_j,
+   omega = (2/dt) asin(omega_RQ dt/2), out[w] = omega/|k| - 1 (the dispersion of Section 2,
+   measured per wave).  waves: [n_waves][2] wavevectors, integer-periodic on a torus.
+   Host FP64. */
+int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double dt,
+                             const double *waves, int64_t n_waves, double *out);
+
+/* Time-stepped phase error of one plane wave: two simulations (real and imaginary parts of
+   B = exp(i (k.O - |k| dt/2)), E = exp(i k.C) (t . (n x k^))) are advanced nsteps on the GPU
+   in `samples` chunks; the phase of the overlap z = sum w E conj(E0) + sum S B conj(B0)
+   (metric (7)) is unwrapped and fitted by least squares, *eps = slope/|k| - 1. */
+int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double *gamma, double dt,
+                                 int32_t prec, double kx, double kz, int64_t nsteps,
+                                 int64_t samples, void *stream, double *eps);
+
+typedef struct tyee_learner tyee_learner;
+
+/* Training set and model on the device.  Model: gamma_i = 1 + 0.1 tanh(w3 . tanh(W2
+   tanh(W1 x_i + b1) + b2) + b3), x_i = (f_i - mu)/sd the normalised features of edge i;
+   1,377 parameters in the order W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3.
+   Loss: mean over meshes and waves of the squared Rayleigh-quotient phase error (as in
+   tyee_mesh_phase_error_rq, interior edges).  meshes: periodic training meshes; dt [n_meshes];
+   waves [n_meshes][n_waves][2] (n_waves <= 64).  mu and sd default to the mean and
+   standard deviation (+1e-6) of the training features.  Parameters start at zero (gamma = 1). */
+int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
+                        const double *waves, int64_t n_waves, void *stream, tyee_learner **out);
+
+/* Glorot-uniform W1, W2 from splitmix64(seed + ...), zero biases and output layer (so the
+   initial model is gamma = 1); resets the optimiser. */
+int tyee_learner_init(tyee_learner *l, uint64_t seed);
+int tyee_learner_set_params(tyee_learner *l, const double *theta);
+int tyee_learner_get_params(tyee_learner *l, double *theta);
+
+/* Set (when mu_in and sd_in are given) and/or read the feature normalisation [8] each. */
+int tyee_learner_normaliser(tyee_learner *l, const double *mu_in, const double *sd_in,
+                            double *mu_out, double *sd_out);
+
+/* Loss, its gradient [1377] (NULL to skip) and the per-(mesh, wave) phase errors
+   [n_meshes][n_waves] (NULL to skip) for the current parameters, all computed on the GPU. */
+int tyee_learner_loss_grad(tyee_learner *l, double *loss, double *grad, double *errors);
+
+/* iters Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on the GPU;
+   loss_history [iters] receives the loss before each step (NULL to skip). */
+int tyee_learner_train(tyee_learner *l, int64_t iters, double lr, double *loss_history);
+
+/* gamma [n_edges] of any mesh under the current model (1 on outer edges), computed by the
+   GPU forward kernel. */
+int tyee_learner_gamma(tyee_learner *l, const tyee_mesh *mesh, double *gamma);
+void tyee_learner_destroy(tyee_learner *l);
+
+typedef struct {
+    int32_t accepted;      /* converged and err_learned < err_plain */
+    int32_t converged;     /* both power iterations converged */
+    double omega_plain, omega_learned;  /* omega_max without and with gamma */
+    double dt_plain, dt_learned;        /* cfl * 2 / omega_max */
+    double err_plain, err_learned;      /* mean |RQ phase error| over the held-out waves,
+                                           each at its own dt */
+} tyee_gate_result;
+
+/* Per-mesh acceptance of a learned scale: omega_max with and without gamma by power
+   iteration (the eq. 20 bound fixes dt = cfl * 2/omega_max for each), then the mean
+   absolute phase error over held-out waves [n_waves][2].  Callers use gamma and
+   dt_learned only when accepted, else the plain coefficients and dt_plain. */
+int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
+              double cfl, tyee_gate_result *out);
+
 /* ---------------------------------------------------------------- batch ---- */
 
 typedef struct tyee_batch tyee_batch;

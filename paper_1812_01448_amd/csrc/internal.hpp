@@ -46,11 +46,21 @@ uint64_t splitmix64(uint64_t x);
 // Disjoint union of meshes: node, edge and triangle ids of part p are offset by the totals
 // of parts 0..p-1, and so are their device numberings (each part keeps its own order).
 int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out);
+// Eight geometry features per edge for the learned coefficient scale (see tyee_mesh_features).
+constexpr int kFeatures = 8;
+void edge_features(const Mesh &m, std::vector<double> &out);
+// Minimum-image O_R - O_L per edge (0 on outer edges).
+void dual_vectors(const Mesh &m, std::vector<double> &out);
+// Plane-wave phase error from the Rayleigh quotient of K_gamma (host FP64).
+double rq_phase_error(const Mesh &m, const double *gamma, double dt, double kx, double kz);
+void rq_phase_errors(const Mesh &m, const double *gamma, double dt, const double *waves, int64_t n_waves,
+                     double *out);
 uint32_t morton_key(uint32_t qx, uint32_t qz);
 
-// Run fn(begin, end) over [0, n) on the host's hardware threads in fixed contiguous
+// Run fn(begin, end) over [0, n) on the host's hardware threads in 256 fixed contiguous
 // chunks (results never depend on the thread count when fn writes disjoint outputs).
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
+// `work` (default n) is the total cost in element units; small jobs run on the caller.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t work = -1);
 
 }  // namespace tyee
 

@@ -28,9 +28,9 @@ int fail(int code, const std::string &msg) {
 }
 void clear_error() { g_last_error.clear(); }
 
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn) {
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t work) {
     const int64_t chunks = 256;
-    if (n < 65536) {
+    if ((work < 0 ? n : work) < 65536) {
         for (int64_t c = 0; c < chunks; ++c) fn(n * c / chunks, n * (c + 1) / chunks);
         return;
     }
@@ -403,6 +403,95 @@ int reorder_mesh(Mesh &m, int32_t kind, uint64_t seed) {
     return TYEE_OK;
 }
 
+void dual_vectors(const Mesh &m, std::vector<double> &out) {
+    out.assign(2 * m.ne, 0.0);
+    for (int64_t i = 0; i < m.ne; ++i) {
+        if (!m.interior(i)) continue;
+        out[2 * i] = min_image(m.O[2 * m.R[i]] - m.O[2 * m.L[i]], m.Lx, m.periodic);
+        out[2 * i + 1] = min_image(m.O[2 * m.R[i] + 1] - m.O[2 * m.L[i] + 1], m.Ly, m.periodic);
+    }
+}
+
+void edge_features(const Mesh &m, std::vector<double> &out) {
+    const int64_t nt = m.nt, ne = m.ne;
+    // per triangle: the angle opposite each local side, and circumradius / shortest side
+    std::vector<double> opp(3 * nt), rho(nt);
+    double mean_area = 0.0;
+    for (int64_t j = 0; j < nt; ++j) mean_area += m.S[j];
+    mean_area /= double(nt);
+    for (int64_t j = 0; j < nt; ++j) {
+        const int32_t *v = &m.tri[3 * j];
+        double P[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        for (int q = 1; q < 3; ++q) {
+            P[q][0] = min_image(m.xy[2 * v[q]] - m.xy[2 * v[0]], m.Lx, m.periodic);
+            P[q][1] = min_image(m.xy[2 * v[q] + 1] - m.xy[2 * v[0] + 1], m.Ly, m.periodic);
+        }
+        double shortest = INFINITY;
+        for (int q = 0; q < 3; ++q) {
+            const double *a = P[q], *b = P[(q + 1) % 3], *w = P[(q + 2) % 3];
+            shortest = std::min(shortest, std::hypot(b[0] - a[0], b[1] - a[1]));
+            const double ux = a[0] - w[0], uz = a[1] - w[1], vx = b[0] - w[0], vz = b[1] - w[1];
+            opp[3 * j + q] = std::atan2(std::fabs(ux * vz - uz * vx), ux * vx + uz * vz);
+        }
+        const double ox = min_image(m.O[2 * j] - m.xy[2 * v[0]], m.Lx, m.periodic);
+        const double oz = min_image(m.O[2 * j + 1] - m.xy[2 * v[0] + 1], m.Ly, m.periodic);
+        rho[j] = std::hypot(ox, oz) / shortest;
+    }
+    std::vector<double> angR(ne, 0.0), angL(ne, 0.0);
+    for (int64_t k = 0; k < 3 * nt; ++k) (m.sgn[k] > 0 ? angR : angL)[m.A[k]] = opp[k];
+    out.assign(size_t(kFeatures) * ne, 0.0);
+    for (int64_t i = 0; i < ne; ++i) {
+        const int32_t r = m.R[i] >= 0 ? m.R[i] : m.L[i], l = m.L[i] >= 0 ? m.L[i] : m.R[i];
+        const double ar = m.R[i] >= 0 ? angR[i] : angL[i], al = m.L[i] >= 0 ? angL[i] : angR[i];
+        double *f = &out[size_t(kFeatures) * i];
+        f[0] = m.d[i] / m.elen[i];
+        f[1] = std::min(ar, al);
+        f[2] = std::max(ar, al);
+        f[3] = std::min(rho[r], rho[l]);
+        f[4] = std::max(rho[r], rho[l]);
+        f[5] = std::fabs(m.hR[i] - m.hL[i]) / m.d[i];
+        f[6] = m.elen[i] / std::sqrt(mean_area);
+        f[7] = std::fabs(m.S[r] - m.S[l]) / (m.S[r] + m.S[l]);
+    }
+}
+
+void rq_phase_errors(const Mesh &m, const double *gamma, double dt, const double *waves, int64_t n_waves,
+                     double *out) {
+    double area = 0.0;
+    for (int64_t j = 0; j < m.nt; ++j) area += m.S[j];
+    std::vector<double> dv;
+    dual_vectors(m, dv);
+    const int64_t chunks = 256;
+    std::vector<double> part(size_t(chunks) * n_waves, 0.0);
+    parallel_for(chunks, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            double *acc = &part[size_t(c) * n_waves];
+            for (int64_t i = m.ne * c / chunks; i < m.ne * (c + 1) / chunks; ++i) {
+                if (!m.interior(i)) continue;
+                const double g = gamma ? gamma[i] : 1.0;
+                const double base = g * g * (m.elen[i] / m.d[i]) * 4.0;
+                for (int64_t w = 0; w < n_waves; ++w) {
+                    const double s = std::sin(0.5 * (waves[2 * w] * dv[2 * i] + waves[2 * w + 1] * dv[2 * i + 1]));
+                    acc[w] += base * s * s;
+                }
+            }
+        }
+    }, m.ne * n_waves);
+    for (int64_t w = 0; w < n_waves; ++w) {
+        double sum = 0.0;
+        for (int64_t c = 0; c < chunks; ++c) sum += part[size_t(c) * n_waves + w];
+        const double om = std::sqrt(sum / area);
+        out[w] = 2.0 / dt * std::asin(om * dt / 2.0) / std::hypot(waves[2 * w], waves[2 * w + 1]) - 1.0;
+    }
+}
+
+double rq_phase_error(const Mesh &m, const double *gamma, double dt, double kx, double kz) {
+    const double k[2] = {kx, kz};
+    double out = 0.0;
+    rq_phase_errors(m, gamma, dt, k, 1, &out);
+    return out;
+}
+
 int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out) {
     if (parts.empty()) return fail(TYEE_EINVAL, "no meshes to merge");
     out = Mesh();
@@ -494,7 +583,7 @@ int power_iteration(const Mesh &m, const double *gamma, int64_t max_iter, double
                 part[3 * c + 1] = sxx;
                 part[3 * c + 2] = syy;
             }
-        });
+        }, nt);
         double sxy = 0.0, sxx = 0.0, syy = 0.0;
         for (int64_t c = 0; c < chunks; ++c) {
             sxy += part[3 * c];
@@ -617,6 +706,56 @@ int tyee_mesh_cfl(const tyee_mesh *mesh, const double *gamma, int64_t max_iter, 
     } catch (const std::bad_alloc &) {
         return tyee::fail(TYEE_ENOMEM, "host allocation failed");
     }
+}
+
+int tyee_mesh_features(const tyee_mesh *mesh, double *out) {
+    if (!mesh || !out) return tyee::fail(TYEE_EINVAL, "null argument");
+    std::vector<double> f;
+    tyee::edge_features(mesh->m, f);
+    std::copy(f.begin(), f.end(), out);
+    return TYEE_OK;
+}
+
+int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double dt, const double *waves,
+                             int64_t n_waves, double *out) {
+    if (!mesh || !waves || !out || n_waves <= 0 || !(dt > 0.0)) return tyee::fail(TYEE_EINVAL, "bad arguments");
+    for (int64_t w = 0; w < n_waves; ++w)
+        if (waves[2 * w] == 0.0 && waves[2 * w + 1] == 0.0) return tyee::fail(TYEE_EINVAL, "zero wavevector");
+    tyee::rq_phase_errors(mesh->m, gamma, dt, waves, n_waves, out);
+    return TYEE_OK;
+}
+
+int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves, double cfl,
+              tyee_gate_result *out) {
+    if (!mesh || !gamma || !waves || !out || n_waves <= 0 || !(cfl > 0.0 && cfl < 1.0))
+        return tyee::fail(TYEE_EINVAL, "bad gate arguments");
+    const tyee::Mesh &m = mesh->m;
+    for (int64_t i = 0; i < m.ne; ++i)
+        if (!(gamma[i] > 0.0) || !std::isfinite(gamma[i])) return tyee::fail(TYEE_EINVAL, "gamma must be > 0");
+    tyee_gate_result r{};
+    double lp = 0.0, lg = 0.0;
+    int64_t ip = 0, ig = 0;
+    const int rp = tyee::power_iteration(m, nullptr, 20000, 1e-12, 0, &lp, &ip);
+    const int rg = tyee::power_iteration(m, gamma, 20000, 1e-12, 0, &lg, &ig);
+    if ((rp && rp != TYEE_ENOTCONVERGED) || (rg && rg != TYEE_ENOTCONVERGED)) return rp ? rp : rg;
+    tyee::clear_error();
+    r.converged = rp == TYEE_OK && rg == TYEE_OK;
+    r.omega_plain = std::sqrt(lp);
+    r.omega_learned = std::sqrt(lg);
+    r.dt_plain = cfl * 2.0 / r.omega_plain;
+    r.dt_learned = cfl * 2.0 / r.omega_learned;
+    std::vector<double> ep(n_waves), el(n_waves);
+    tyee::rq_phase_errors(m, nullptr, r.dt_plain, waves, n_waves, ep.data());
+    tyee::rq_phase_errors(m, gamma, r.dt_learned, waves, n_waves, el.data());
+    for (int64_t w = 0; w < n_waves; ++w) {
+        r.err_plain += std::fabs(ep[w]);
+        r.err_learned += std::fabs(el[w]);
+    }
+    r.err_plain /= double(n_waves);
+    r.err_learned /= double(n_waves);
+    r.accepted = r.converged && r.err_learned < r.err_plain;
+    *out = r;
+    return TYEE_OK;
 }
 
 void tyee_mesh_destroy(tyee_mesh *mesh) { delete mesh; }

@@ -52,6 +52,13 @@ class _Tune(ctypes.Structure):
                 ("tile_tris", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
+class _Gate(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("omega_plain", ctypes.c_double), ("omega_learned", ctypes.c_double),
+                ("dt_plain", ctypes.c_double), ("dt_learned", ctypes.c_double),
+                ("err_plain", ctypes.c_double), ("err_learned", ctypes.c_double)]
+
+
 class _Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
                 ("energy_h", ctypes.c_double), ("max_abs_E", ctypes.c_double),
@@ -69,8 +76,13 @@ EXPORTS = [
     "tyee_batch_create", "tyee_batch_set_state", "tyee_batch_get_state", "tyee_batch_reorder",
     "tyee_batch_set_fusion", "tyee_batch_set_graph", "tyee_batch_step", "tyee_batch_sync",
     "tyee_batch_info", "tyee_batch_sim", "tyee_batch_tune", "tyee_batch_destroy",
+    "tyee_mesh_features", "tyee_mesh_phase_error_rq", "tyee_phase_error_timestepped",
+    "tyee_learner_create", "tyee_learner_init", "tyee_learner_set_params",
+    "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
+    "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
     "tyee_last_error",
 ]
+N_PARAMS = 1377
 KERNELS = {"edge": 0, "tri": 1, "fused": 2, "special": 3, "charge": 4, "graph": 5}
 KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special": "k_special",
                 "charge": "k_charge", "graph": "graph of k_fused"}
@@ -115,6 +127,19 @@ def _load():
         "tyee_batch_info": [vp, vp],
         "tyee_batch_sim": [vp, ctypes.POINTER(vp)],
         "tyee_batch_tune": [vp, i64, vp, i64, ctypes.POINTER(i64)],
+        "tyee_mesh_features": [vp, vp],
+        "tyee_mesh_phase_error_rq": [vp, vp, f64, vp, i64, vp],
+        "tyee_phase_error_timestepped": [vp, vp, f64, i32, f64, f64, i64, i64, vp,
+                                         ctypes.POINTER(f64)],
+        "tyee_learner_create": [vp, vp, i64, vp, i64, vp, ctypes.POINTER(vp)],
+        "tyee_learner_init": [vp, ctypes.c_uint64],
+        "tyee_learner_set_params": [vp, vp],
+        "tyee_learner_get_params": [vp, vp],
+        "tyee_learner_normaliser": [vp, vp, vp, vp, vp],
+        "tyee_learner_loss_grad": [vp, ctypes.POINTER(f64), vp, vp],
+        "tyee_learner_train": [vp, i64, f64, vp],
+        "tyee_learner_gamma": [vp, vp, vp],
+        "tyee_gate": [vp, vp, vp, i64, f64, ctypes.POINTER(_Gate)],
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
     }
@@ -126,6 +151,8 @@ def _load():
     lib.tyee_mesh_destroy.restype = None
     lib.tyee_sim_destroy.argtypes = [vp]
     lib.tyee_sim_destroy.restype = None
+    lib.tyee_learner_destroy.argtypes = [vp]
+    lib.tyee_learner_destroy.restype = None
     lib.tyee_batch_destroy.argtypes = [vp]
     lib.tyee_batch_destroy.restype = None
     lib.tyee_sim_steps.argtypes = [vp]
@@ -205,6 +232,35 @@ class Mesh:
             buf = (ctypes.c_byte * (n * np.dtype(dt).itemsize)).from_address(getattr(v, name))
             out[name] = np.frombuffer(buf, dtype=dt).reshape(shape).copy()
         return out
+
+    def features(self):
+        out = np.zeros((self.ne, 8))
+        _check(lib.tyee_mesh_features(self._h, _ptr(out)))
+        return out
+
+    def phase_error_rq(self, dt, waves, gamma=None):
+        w = np.ascontiguousarray(waves, np.float64).reshape(-1, 2)
+        g = None if gamma is None else _f64(gamma, self.ne)
+        out = np.zeros(len(w))
+        _check(lib.tyee_mesh_phase_error_rq(self._h, _ptr(g), float(dt), _ptr(w), len(w), _ptr(out)))
+        return out
+
+    def phase_error_timestepped(self, dt, k, nsteps, samples=20, gamma=None, prec="f64",
+                                stream=None):
+        g = None if gamma is None else _f64(gamma, self.ne)
+        e = ctypes.c_double()
+        _check(lib.tyee_phase_error_timestepped(self._h, _ptr(g), float(dt), PREC[prec],
+                                                float(k[0]), float(k[1]), int(nsteps),
+                                                int(samples), None if stream is None else
+                                                int(stream), ctypes.byref(e)))
+        return e.value
+
+    def gate(self, gamma, waves, cfl=0.5):
+        g = _f64(gamma, self.ne)
+        w = np.ascontiguousarray(waves, np.float64).reshape(-1, 2)
+        r = _Gate()
+        _check(lib.tyee_gate(self._h, _ptr(g), _ptr(w), len(w), float(cfl), ctypes.byref(r)))
+        return {n: getattr(r, n) for n, _ in _Gate._fields_}
 
     def cfl(self, gamma=None, max_iter=20000, rtol=1e-12, seed=0):
         """(omega_max^2, iterations, converged) of K = -L_E L_B."""
@@ -416,3 +472,61 @@ class Batch:
         return [{"order": names[r.order], "steps_per_launch": r.steps_per_launch,
                  "tile_tris": r.tile_tris, "ms_per_step": r.ms_per_step}
                 for r in res[:min(cap, n.value)]]
+
+
+class Learner:
+    """Training set + MLP of the learned edge scale on the device (tyee_learner_*)."""
+
+    def __init__(self, meshes, dts, waves, stream=None):
+        arr = (ctypes.c_void_p * len(meshes))(*[m._h.value for m in meshes])
+        dt = _f64(dts, len(meshes))
+        w = np.ascontiguousarray(waves, np.float64)
+        if w.ndim != 3 or w.shape[0] != len(meshes) or w.shape[2] != 2:
+            raise ValueError("waves must have shape [n_meshes, n_waves, 2]")
+        h = ctypes.c_void_p()
+        _check(lib.tyee_learner_create(arr, _ptr(dt), len(meshes), _ptr(w), w.shape[1],
+                                       None if stream is None else int(stream), ctypes.byref(h)))
+        self._h = h
+        self.n_meshes, self.n_waves = len(meshes), w.shape[1]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_learner_destroy(h)
+            self._h = None
+
+    def init(self, seed=0):
+        _check(lib.tyee_learner_init(self._h, int(seed)))
+
+    def params(self):
+        out = np.zeros(N_PARAMS)
+        _check(lib.tyee_learner_get_params(self._h, _ptr(out)))
+        return out
+
+    def set_params(self, theta):
+        t = _f64(theta, N_PARAMS)
+        _check(lib.tyee_learner_set_params(self._h, _ptr(t)))
+
+    def normaliser(self, mu=None, sd=None):
+        mi = None if mu is None else _f64(mu, 8)
+        si = None if sd is None else _f64(sd, 8)
+        mo, so = np.zeros(8), np.zeros(8)
+        _check(lib.tyee_learner_normaliser(self._h, _ptr(mi), _ptr(si), _ptr(mo), _ptr(so)))
+        return mo, so
+
+    def loss_grad(self, want_grad=True, want_errors=False):
+        loss = ctypes.c_double()
+        g = np.zeros(N_PARAMS) if want_grad else None
+        e = np.zeros((self.n_meshes, self.n_waves)) if want_errors else None
+        _check(lib.tyee_learner_loss_grad(self._h, ctypes.byref(loss), _ptr(g), _ptr(e)))
+        return loss.value, g, e
+
+    def train(self, iters, lr):
+        hist = np.zeros(max(1, int(iters)))
+        _check(lib.tyee_learner_train(self._h, int(iters), float(lr), _ptr(hist)))
+        return hist[:int(iters)]
+
+    def gamma(self, mesh):
+        out = np.zeros(mesh.ne)
+        _check(lib.tyee_learner_gamma(self._h, mesh._h, _ptr(out)))
+        return out

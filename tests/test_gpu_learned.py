@@ -1,0 +1,147 @@
+"""GPU: the learned edge scale (features, MLP forward/backward, Adam, gate) against the oracle.
+
+* loss, per-wave phase errors, dL/dtheta and gamma from the HIP kernels vs the FP64 oracle;
+* the initial model (gamma = 1) reproduces the plain method bit-exactly;
+* training on the GPU lowers the loss;
+* the time-stepped phase error of the library equals the oracle's;
+* end to end at reduced size: train, gate and evaluate on held-out meshes, showing what the
+  trained network gains over the plain coefficients.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as OL
+from meshgen import lattice_mesh, periodic_wavevector
+from common import rel_l2, packet_state
+
+pytestmark = pytest.mark.gpu
+
+ANGLES = np.arange(12) * np.pi / 12
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ty():
+    import paper_1812_01448_amd as ty
+    return ty
+
+
+def waves_for(n, cells=(8, 10, 16, 32), angles=ANGLES):
+    return np.array([periodic_wavevector(a, r, 1.0 / n)[0] for a in angles for r in cells])
+
+
+def training_set(ty, sizes, seed0, jitter=0.3):
+    out = []
+    for k, n in enumerate(sizes):
+        xy, tri = lattice_mesh(n, jitter, seed0 + k, periodic=True)
+        m = ty.Mesh(xy, tri, True)
+        om = oracle.OracleMesh(xy, tri, True)
+        lam, _, _ = m.cfl()
+        out.append(dict(n=n, xy=xy, tri=tri, mesh=m, om=om, dt=0.5 * 2 / np.sqrt(lam),
+                        waves=waves_for(n)))
+    return out
+
+
+def test_learner_matches_oracle(ty):
+    _note("case: learner loss/grad/gamma vs oracle on 3 meshes x 48 waves")
+    ts = training_set(ty, [24, 32, 40], 300)
+    W = np.stack([t["waves"] for t in ts])
+    lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts], W)
+    feats = [OL.features(t["om"]) for t in ts]
+    F = np.concatenate(feats)
+    mu, sd = F.mean(0), F.std(0) + 1e-6
+    lr.normaliser(mu, sd)
+    theta = np.random.default_rng(7).uniform(-0.4, 0.4, OL.N_PARAMS)
+    lr.set_params(theta)
+    theta32 = lr.params()                      # the values the GPU holds (FP32)
+    loss, grad, errs = lr.loss_grad(want_errors=True)
+    ref_loss, ref_grad = 0.0, np.zeros(OL.N_PARAMS)
+    for t, f, e_row in zip(ts, feats, errs):
+        gam = OL.mlp_forward(theta32, f, mu, sd)
+        l, dg = OL.rq_loss_grad(t["om"], gam, t["dt"], t["waves"])
+        ref_loss += l / len(ts)
+        ref_grad += OL.mlp_param_grad(theta32, f, mu, sd, dg / len(ts))
+        ref_e = [OL.rq_phase_error(t["om"], gam, t["dt"], k) for k in t["waves"]]
+        assert np.max(np.abs(e_row - ref_e)) < 2e-6
+        g_gpu = lr.gamma(t["mesh"])
+        assert np.max(np.abs(g_gpu - gam)) < 2e-6
+    _note(f"  loss {loss:.6e} ref {ref_loss:.6e}; grad rel L2 {rel_l2(grad, ref_grad):.2e}")
+    assert abs(loss / ref_loss - 1) < 1e-4
+    assert rel_l2(grad, ref_grad) < 1e-3
+
+
+def test_identity_model_is_plain_and_training_lowers_loss(ty):
+    _note("case: gamma = 1 bit-exact, 150 Adam steps on the GPU")
+    ts = training_set(ty, [32, 40], 400)
+    lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts],
+                    np.stack([t["waves"] for t in ts]))
+    lr.init(seed=3)
+    t = ts[0]
+    g = lr.gamma(t["mesh"])
+    assert np.all(g == 1.0)
+    v = t["mesh"].view()
+    out = []
+    for gamma in (None, g):
+        sim = ty.Sim(t["mesh"], t["dt"], "f32")
+        if gamma is not None:
+            sim.set_edge_scale(gamma)
+        E, B = packet_state(v, t["dt"], t["n"], cells=8.0)
+        sim.set_state("E", E)
+        sim.set_state("B", B)
+        sim.step(40)
+        out.append(sim.get_state("E"))
+    assert np.array_equal(out[0], out[1])
+    hist = lr.train(150, 3e-3)
+    final, _, _ = lr.loss_grad(want_grad=False)
+    _note(f"  loss {hist[0]:.4e} -> {final:.4e}")
+    assert final < 0.6 * hist[0]
+    g2 = lr.gamma(t["mesh"])
+    assert np.all((g2 > 0.9) & (g2 < 1.1)) and np.std(g2) > 0
+
+
+def test_timestepped_phase_error_matches_oracle(ty):
+    _note("case: time-stepped phase error library vs oracle")
+    xy, tri = lattice_mesh(24, 0.25, 11, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    om = oracle.OracleMesh(xy, tri, True)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    k, _, _ = periodic_wavevector(0.3, 8.0, 1 / 24)
+    g = 1 + 0.03 * np.cos(np.arange(om.ne))
+    for gamma in (None, g):
+        a = m.phase_error_timestepped(dt, k, 4000, samples=20, gamma=gamma, prec="f64")
+        b = OL.timestepped_phase_error(om, gamma, dt, k, 4000, samples=20)
+        assert abs(a - b) < 1e-9, (a, b)
+
+
+def test_trained_network_gains_over_plain_on_held_out_meshes(ty):
+    _note("case: train 8 meshes (n=48), gate + evaluate on 3 held-out meshes (n=64)")
+    train = training_set(ty, [48] * 8, 500)
+    lr = ty.Learner([t["mesh"] for t in train], [t["dt"] for t in train],
+                    np.stack([t["waves"] for t in train]))
+    lr.init(seed=1)
+    lr.train(300, 3e-3)
+    held = training_set(ty, [64] * 3, 900)
+    gains = []
+    for t in held:
+        gam = lr.gamma(t["mesh"])
+        w10 = waves_for(t["n"], cells=(10,))
+        gate = t["mesh"].gate(gam, w10)
+        _note(f"  held-out: plain {gate['err_plain']:.4e} learned {gate['err_learned']:.4e} "
+              f"dt ratio {gate['dt_learned'] / gate['dt_plain']:.4f} accepted {gate['accepted']}")
+        assert gate["converged"]
+        assert gate["accepted"] and gate["err_learned"] < gate["err_plain"]
+        gains.append(gate["err_plain"] / gate["err_learned"])
+        # the time-stepped error agrees that the learned scale is better at 10 cells/lambda
+        k = w10[2]
+        ep = t["mesh"].phase_error_timestepped(gate["dt_plain"], k, 3000, samples=15)
+        el = t["mesh"].phase_error_timestepped(gate["dt_learned"], k, 3000, samples=15, gamma=gam)
+        _note(f"    time-stepped at 10 cells/lambda: plain {ep:.4e} learned {el:.4e}")
+        assert abs(el) < abs(ep)
+    assert np.mean(gains) > 1.2
