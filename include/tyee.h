@@ -266,8 +266,10 @@ void tyee_sim_destroy(tyee_sim *sim);
    edge (Fig. 2 allows either direction).  Outer edges repeat their one triangle. */
 int tyee_mesh_features(const tyee_mesh *mesh, double *out);
 
-/* Phase-velocity error of plane waves exp(i k.O) from the Rayleigh quotient of
-   K_gamma = -L_E L_B with edge scale gamma (NULL = 1), with the leap-frog correction:
+/* Rayleigh-quotient estimate of the phase-velocity error of plane waves exp(i k.O) under
+   K_gamma = -L_E L_B with edge scale gamma (NULL = 1), with the leap-frog correction.  It is
+   an upper (arithmetic-mean) estimate: the sampled wave's high-frequency content raises it,
+   so it is a diagnostic, not the measured dispersion (see tyee_phase_error_timestepped):
    omega_RQ^2 = sum_i gamma_i^2 (|e_i|/d_i) |exp(i k.O_R) - exp(i k.O_L)|^2 / sum_j S_j,
    omega = (2/dt) asin(omega_RQ dt/2), out[w] = omega/|k| - 1 (the dispersion of Section 2,
    measured per wave).  waves: [n_waves][2] wavevectors, integer-periodic on a torus.
@@ -288,12 +290,18 @@ typedef struct tyee_learner tyee_learner;
 /* Training set and model on the device.  Model: gamma_i = 1 + 0.1 tanh(w3 . tanh(W2
    tanh(W1 x_i + b1) + b2) + b3), x_i = (f_i - mu)/sd the normalised features of edge i;
    1,377 parameters in the order W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3.
-   Loss: mean over meshes and waves of the squared Rayleigh-quotient phase error (as in
-   tyee_mesh_phase_error_rq, interior edges).  meshes: periodic training meshes; dt [n_meshes];
-   waves [n_meshes][n_waves][2] (n_waves <= 64).  mu and sd default to the mean and
-   standard deviation (+1e-6) of the training features.  Parameters start at zero (gamma = 1). */
+   Loss: the mean over meshes and waves of eps^2, eps the phase error that leap-frog itself
+   produces: each plane wave exp(i k.O) is advanced N = round(phase/(|k| dt)) steps of the
+   scheme in its B-only form (x_{n+1} = (2 - dt^2 K_gamma) x_n - x_{n-1}, started from the exact
+   wave at -dt/2 and +dt/2), and eps = -arg(z_N/z_0)/(|k| N dt) - 1 with z the S-weighted
+   overlap with exp(i k.O).  Its gradient comes from the exact adjoint of that recurrence.
+   meshes: periodic training meshes of at most 4096 triangles (each runs inside one
+   work-group); dt [n_meshes]; waves [n_meshes][n_waves][2]; phase in (0, 3) radians.
+   mu and sd default to the mean and standard deviation (+1e-6) of the training features.
+   Parameters start at zero (gamma = 1). */
 int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
-                        const double *waves, int64_t n_waves, void *stream, tyee_learner **out);
+                        const double *waves, int64_t n_waves, double phase, void *stream,
+                        tyee_learner **out);
 
 /* Glorot-uniform W1, W2 from splitmix64(seed + ...), zero biases and output layer (so the
    initial model is gamma = 1); resets the optimiser. */
@@ -305,7 +313,7 @@ int tyee_learner_get_params(tyee_learner *l, double *theta);
 int tyee_learner_normaliser(tyee_learner *l, const double *mu_in, const double *sd_in,
                             double *mu_out, double *sd_out);
 
-/* Loss, its gradient [1377] (NULL to skip) and the per-(mesh, wave) phase errors
+/* Loss, its gradient [1377] (NULL to skip) and the per-(mesh, wave) phase errors eps
    [n_meshes][n_waves] (NULL to skip) for the current parameters, all computed on the GPU. */
 int tyee_learner_loss_grad(tyee_learner *l, double *loss, double *grad, double *errors);
 
@@ -323,16 +331,17 @@ typedef struct {
     int32_t converged;     /* both power iterations converged */
     double omega_plain, omega_learned;  /* omega_max without and with gamma */
     double dt_plain, dt_learned;        /* cfl * 2 / omega_max */
-    double err_plain, err_learned;      /* mean |RQ phase error| over the held-out waves,
-                                           each at its own dt */
+    double err_plain, err_learned;      /* mean |time-stepped phase error| over the held-out
+                                           waves, each at its own dt */
 } tyee_gate_result;
 
 /* Per-mesh acceptance of a learned scale: omega_max with and without gamma by power
-   iteration (the eq. 20 bound fixes dt = cfl * 2/omega_max for each), then the mean
-   absolute phase error over held-out waves [n_waves][2].  Callers use gamma and
-   dt_learned only when accepted, else the plain coefficients and dt_plain. */
+   iteration (the eq. 20 bound fixes dt = cfl * 2/omega_max for each), then the mean absolute
+   time-stepped phase error (tyee_phase_error_timestepped, about `phase` radians of travel,
+   20 samples) over held-out waves [n_waves][2], each method at its own dt.  Callers use
+   gamma and dt_learned only when accepted, else the plain coefficients and dt_plain. */
 int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
-              double cfl, tyee_gate_result *out);
+              double cfl, double phase, int32_t prec, void *stream, tyee_gate_result *out);
 
 /* ---------------------------------------------------------------- batch ---- */
 

@@ -176,3 +176,76 @@ def timestepped_phase_error(om, gamma, dt, k, nsteps, samples=20):
     t = np.array(ts)
     slope = np.polyfit(t, phase, 1)[0]
     return slope / kn - 1.0
+
+
+def _K_sparse(om, gamma):
+    """K_gamma = -L_E L_B as a sparse matrix: (K x)_j = (1/S_j) sum over interior edges of j of
+    gamma^2 (|e|/d) (x_j - x_other)."""
+    import scipy.sparse as sp
+    i = om.interior
+    R, Lt = om.R[i], om.L[i]
+    g = np.ones(om.ne) if gamma is None else np.asarray(gamma, np.float64)
+    w = g[i] ** 2 * om.elen[i] / om.d[i]
+    rows = np.concatenate([R, Lt, R, Lt])
+    cols = np.concatenate([R, Lt, Lt, R])
+    K = sp.csr_matrix((np.concatenate([w, w, -w, -w]), (rows, cols)), shape=(om.nt, om.nt))
+    return sp.diags(1.0 / om.S) @ K
+
+
+def ts_steps(k, dt, phase=2.0):
+    """Number of leap-frog steps for the wave to advance about `phase` radians."""
+    return max(1, int(round(phase / (np.hypot(k[0], k[1]) * dt))))
+
+
+def ts_phase_error_grad(om, gamma, dt, k, nsteps):
+    """Phase error of a plane wave advanced by leap-frog, and its gradient in gamma.
+
+    In vacuum, eliminating E from the two half-steps gives, for x_n = B^{n+1/2},
+        x_{n+1} = (2 - dt^2 K) x_n - x_{n-1}.
+    Start from x_{-1} = exp(i(k.O + |k| dt/2)), x_0 = exp(i(k.O - |k| dt/2)) (the exact wave
+    at t = -dt/2 and +dt/2), take z_n = sum_j S_j conj(Bhat_j) x_{n,j} with Bhat = exp(i k.O),
+    phi = -arg(z_N / z_0) and error = phi/(|k| N dt) - 1.
+    Gradient: with v_m the same recurrence from v_{-1} = 0, v_0 = Bhat (Chebyshev polynomials
+    of the second kind in (2 - dt^2 K)/2 applied to Bhat), a perturbation dK changes z_N by
+    -dt^2 sum_{n<N} v_{N-1-n}^H S dK x_n; for edge i,
+        dz_N/dgamma_i = -2 dt^2 gamma_i (|e_i|/d_i) sum_n conj(v_{N-1-n,R} - v_{N-1-n,L})
+                                                         (x_{n,R} - x_{n,L}).
+    The v sequence is run forward to N and then backwards (the recurrence is reversible)."""
+    K = _K_sparse(om, gamma)
+    k = np.asarray(k, np.float64)
+    kn = np.hypot(k[0], k[1])
+    Bh = np.exp(1j * (om.O @ k))
+    step = lambda cur, prev: 2.0 * cur - dt * dt * (K @ cur) - prev
+    x_prev, x = Bh * np.exp(1j * kn * dt / 2), Bh * np.exp(-1j * kn * dt / 2)
+    z0 = np.sum(om.S * np.conj(Bh) * x)
+    v_prev, v = np.zeros_like(Bh), Bh.copy()
+    for _ in range(nsteps):
+        x, x_prev = step(x, x_prev), x
+        v, v_prev = step(v, v_prev), v
+    zN = np.sum(om.S * np.conj(Bh) * x)
+    i = om.interior
+    R, Lt = om.R[i], om.L[i]
+    acc = np.zeros(int(i.sum()), complex)
+    x_prev, x = Bh * np.exp(1j * kn * dt / 2), Bh * np.exp(-1j * kn * dt / 2)
+    vb, vb_next = v_prev, v                       # v_{N-1}, v_N
+    for _ in range(nsteps):
+        acc += np.conj(vb[R] - vb[Lt]) * (x[R] - x[Lt])
+        x, x_prev = step(x, x_prev), x
+        vb, vb_next = step(vb, vb_next), vb
+    g = np.ones(om.ne) if gamma is None else np.asarray(gamma, np.float64)
+    dz = np.zeros(om.ne, complex)
+    dz[i] = -2.0 * dt * dt * g[i] * om.elen[i] / om.d[i] * acc
+    T = kn * nsteps * dt
+    err = -np.angle(zN / z0) / T - 1.0
+    derr = -np.imag(np.conj(zN) * dz) / np.abs(zN) ** 2 / T
+    return err, derr
+
+
+def ts_loss_grad(om, gamma, dt, waves, phase=2.0):
+    """Mean squared time-stepped phase error over `waves` and its gradient in gamma."""
+    loss, grad = 0.0, np.zeros(om.ne)
+    for k in waves:
+        e, de = ts_phase_error_grad(om, gamma, dt, k, ts_steps(k, dt, phase))
+        loss += e * e
+        grad += 2.0 * e * de
+    return loss / len(waves), grad / len(waves)

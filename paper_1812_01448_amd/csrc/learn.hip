@@ -6,19 +6,26 @@
 // 1,377 parameters in the order W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3).  Scaling
 // the eq. 3 and eq. 4 coefficients of an edge by the same gamma keeps metric (7) conserved.
 //
-// Training signal: the phase error of integer-periodic plane waves exp(i k.O) on training
-// meshes.  On a torus |exp(i k.O_j)| = 1, so the Rayleigh quotient of K_gamma = -L_E L_B is
-//   omega_RQ^2 = sum_i gamma_i^2 a_i(k) / A,   a_i(k) = (|e_i|/d_i) 4 sin^2(k.(O_R - O_L)/2),
-// with A the mesh area; with the leap-frog correction omega = (2/dt) asin(omega_RQ dt/2) the
-// error is eps = omega/|k| - 1 and the loss is the mean of eps^2 over meshes and waves.  Its
-// gradient in gamma_i is gamma_i sum_w c_w a_i(w) with per-wave coefficients c_w, so one
-// pass over the edges gives dL/dgamma, and backpropagation through the MLP gives dL/dtheta.
+// Training signal: the phase error that leap-frog itself produces on plane waves over small
+// periodic training meshes.  Eliminating E from the two half-steps, x_n = B^{n+1/2} obeys
+//   x_{n+1} = (2 - dt^2 K_gamma) x_n - x_{n-1},   (K_gamma x)_j = (1/S_j) sum_q gamma^2 |e|/d (x_j - x_nb),
+// started from the exact wave exp(i(k.O -+ |k| dt/2)).  After N steps (about 2 radians of
+// phase) the overlap z_N = sum_j S_j conj(exp(i k.O_j)) x_N,j gives eps = -arg(z_N/z_0)/(|k| N dt) - 1,
+// and the loss is the mean of eps^2 over meshes and waves.  Its exact gradient pairs the
+// forward sequence x_n with the second-kind Chebyshev sequence v_m (v_{-1} = 0, v_0 =
+// exp(i k.O)) run backwards from m = N - 1 (the recurrence is reversible):
+//   dz_N/dgamma_i = -2 dt^2 gamma_i (|e_i|/d_i) sum_n conj(v_{N-1-n,R} - v_{N-1-n,L}) (x_{n,R} - x_{n,L}).
+// Both recurrences run in the difference form y_{n+1} = y_n - dt^2 K x_n, x_{n+1} = x_n + y_{n+1},
+// which keeps the small per-step increments accurate in FP32.
 //
-// Kernels (all FP32 arithmetic on edges, FP64 for the per-wave sums and coefficients):
+// Kernels:
 //   k_mlp_gamma     one work-item per edge: the MLP forward pass;
-//   k_wave_sums     per chunk of a mesh's edges: partial sums of gamma^2 a(k) for every wave;
-//   k_wave_reduce   per (mesh, wave): sum of the chunk partials in chunk order;
-//   k_wave_coef     per (mesh, wave): eps, the loss and c_w;
+//   k_ts_adjoint    one work-group per (training mesh, wave): the whole mesh lives in LDS
+//                   (up to 4096 triangles), each work-item keeps its triangles' state and its
+//                   edges' accumulators in registers; forward pass, then the reversed pass
+//                   with the per-edge accumulation; writes eps and the wave's share of dL/dgamma;
+//   k_wave_sum      per edge: dL/dgamma summed over the waves in wave order;
+//   k_loss          one block: the loss from the eps values;
 //   k_mlp_backward  per block: forward + backward of its edges, the per-edge activation and
 //                   delta vectors staged in LDS, then each work-item accumulates the gradient
 //                   of its own parameters over the staged edges (no atomics);
@@ -41,8 +48,6 @@ constexpr int kParams = kH1 * kFeatures + kH1 + kH2 * kH1 + kH2 + kH2 + 1;  // 1
 constexpr int oW1 = 0, oB1 = oW1 + kH1 * kFeatures, oW2 = oB1 + kH1, oB2 = oW2 + kH2 * kH1,
               oW3 = oB2 + kH2, oB3 = oW3 + kH2;
 constexpr float kSpan = 0.1f;
-constexpr int kMaxWaves = 64;
-constexpr int kWaveChunk = 4096;   // edges per chunk of k_wave_sums
 constexpr int kBwdEdges = 128;     // edges staged per round of k_mlp_backward
 constexpr int kBwdRounds = 32;     // rounds (chunks of kBwdEdges) per block
 constexpr int kRow = 139;          // staged floats per edge (138 used, odd stride for LDS banks)
@@ -94,112 +99,283 @@ __global__ __launch_bounds__(256) void k_mlp_gamma(int n, const float *__restric
     gamma[i] = 1.0f + kSpan * mlp_edge(sP, x, h1, h2);
 }
 
-__device__ __forceinline__ float rq_term(float ebyd, float dox, float doz, float kx, float kz) {
-    const float s = sinf(0.5f * (kx * dox + kz * doz));
-    return ebyd * 4.0f * s * s;
-}
+constexpr int kTsThreads = 512, kTsTris = 8, kTsEdges = 12;  // per work-item
+constexpr int kTsMaxTris = kTsThreads * kTsTris, kTsMaxEdges = kTsThreads * kTsEdges;
 
-// chunk c covers edges [cbeg[c], cend[c]) of mesh cmesh[c]; partial[c][w] = sum gamma^2 a_w.
-// Waves are taken in groups of 16 so that the accumulators stay in registers.
-__global__ __launch_bounds__(256) void k_wave_sums(const int32_t *__restrict__ cmesh, const int32_t *__restrict__ cbeg,
-                                                   const int32_t *__restrict__ cend, int W,
-                                                   const float *__restrict__ gamma, const float *__restrict__ ebyd,
-                                                   const float *__restrict__ dO, const float *__restrict__ waves,
-                                                   double *__restrict__ partial) {
-    constexpr int kGroup = 16;
-    __shared__ float sk[2 * kMaxWaves];
-    __shared__ double red[256 / 64][kGroup];
-    const int c = blockIdx.x, m = cmesh[c];
-    for (int w = threadIdx.x; w < 2 * W; w += blockDim.x) sk[w] = waves[2 * size_t(m) * W + w];
+struct TsMesh {
+    int32_t t_off, nt, e_off, ne;
+    double dt, area;
+};
+
+// One work-group per (mesh m, wave w) = blockIdx.x = m * W + w.
+//   tri_word[t][q] = neighbour local triangle | (local edge << 16);  tri_invS, tri_O
+//   edge_RL[e] = R | (L << 16) (local triangles);  edge_ebyd = |e|/d;  gamma per edge
+__global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const TsMesh *__restrict__ meshes,
+                                                           const float *__restrict__ waves,
+                                                           const int32_t *__restrict__ nsteps,
+                                                           const uint32_t *__restrict__ tri_word,
+                                                           const float *__restrict__ tri_invS,
+                                                           const float *__restrict__ tri_O,
+                                                           const uint32_t *__restrict__ edge_RL,
+                                                           const float *__restrict__ edge_ebyd,
+                                                           const float *__restrict__ gamma, double inv_mw,
+                                                           double *__restrict__ eps_out,
+                                                           float *__restrict__ grad_out, int64_t grad_stride) {
+    __shared__ float xr[kTsMaxTris], xi[kTsMaxTris], vr[kTsMaxTris], vi[kTsMaxTris];
+    __shared__ double red[kTsThreads / 64][2];
+    const int m = blockIdx.x / W, w = blockIdx.x % W, tid = threadIdx.x;
+    const TsMesh M = meshes[m];
+    const int N = nsteps[blockIdx.x];
+    const float kx = waves[2 * blockIdx.x], kz = waves[2 * blockIdx.x + 1];
+    const double kn = sqrt(double(kx) * kx + double(kz) * kz);
+    const float dt2 = float(M.dt * M.dt);
+    const float ca = float(cos(kn * M.dt / 2)), sa = float(sin(kn * M.dt / 2));
+
+    // own triangles: neighbour words, coupling sigma = gamma^2 |e|/d per side, 1/S
+    uint32_t word[kTsTris][3];
+    float sig[kTsTris][3], invS[kTsTris];  // sig = -dt^2 gamma^2 (|e|/d) / S per side
+    float x_r[kTsTris], x_i[kTsTris], y_r[kTsTris], y_i[kTsTris];
+    float v_r[kTsTris], v_i[kTsTris], u_r[kTsTris], u_i[kTsTris];
+#pragma unroll
+    for (int r = 0; r < kTsTris; ++r) {
+        const int t = tid + r * kTsThreads;
+        invS[r] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            word[r][q] = 0;
+            sig[r][q] = 0.0f;
+        }
+        x_r[r] = x_i[r] = y_r[r] = y_i[r] = v_r[r] = v_i[r] = u_r[r] = u_i[r] = 0.0f;
+        if (t < M.nt) {
+            const int g = M.t_off + t;
+            invS[r] = tri_invS[g];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const uint32_t wd = tri_word[3 * size_t(g) + q];
+                const int e = M.e_off + int(wd >> 16);
+                const float ga = gamma[e];
+                word[r][q] = wd;
+                sig[r][q] = -dt2 * invS[r] * (ga * ga * edge_ebyd[e]);
+            }
+            // exact wave at t = +dt/2 (x_0) and t = -dt/2 (x_{-1}); y_0 = x_0 - x_{-1}
+            const float ph = kx * tri_O[2 * g] + kz * tri_O[2 * g + 1];
+            const float br = cosf(ph), bi = sinf(ph);
+            x_r[r] = br * ca + bi * sa;     // B e^{-i a}
+            x_i[r] = bi * ca - br * sa;
+            y_r[r] = 2.0f * bi * sa;        // B (e^{-i a} - e^{i a}) = -2i sin(a) B
+            y_i[r] = -2.0f * br * sa;
+            v_r[r] = br;                    // v_0 = B, v_{-1} = 0
+            v_i[r] = bi;
+            u_r[r] = br;
+            u_i[r] = bi;
+            xr[t] = x_r[r];
+            xi[t] = x_i[r];
+            vr[t] = v_r[r];
+            vi[t] = v_i[r];
+        }
+    }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int g0 = 0; g0 < W; g0 += kGroup) {
-        float acc[kGroup];
+
+    // one step of y <- y - dt^2 K s, s <- s + y for the sequences held in (sr, si) / LDS (lr, li)
+#define TS_STEP(SR, SI, YR, YI, LR, LI)                                                     \
+    {                                                                                       \
+        float kr = 0.0f, ki = 0.0f;                                                         \
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) {                                     \
+            const int nb = int(word[r][q] & 0xFFFFu);                                       \
+            kr = fmaf(sig[r][q], SR[r] - LR[nb], kr);                                       \
+            ki = fmaf(sig[r][q], SI[r] - LI[nb], ki);                                       \
+        }                                                                                   \
+        YR[r] += kr;                                                                        \
+        YI[r] += ki;                                                                        \
+    }
+
+    // pass 1: x and v forward N steps
+    for (int n = 0; n < N; ++n) {
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q) acc[q] = 0.0f;
-        for (int i = cbeg[c] + threadIdx.x; i < cend[c]; i += blockDim.x) {
-            const float g2 = gamma[i] * gamma[i], e = ebyd[i], dx = dO[2 * i], dz = dO[2 * i + 1];
+        for (int r = 0; r < kTsTris; ++r) {
+            if (tid + r * kTsThreads < M.nt) {
+                TS_STEP(x_r, x_i, y_r, y_i, xr, xi);
+                TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
+            }
+        }
+        __syncthreads();
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const int w = g0 + q;
-                if (w < W) acc[q] = fmaf(g2, rq_term(e, dx, dz, sk[2 * w], sk[2 * w + 1]), acc[q]);
+        for (int r = 0; r < kTsTris; ++r) {
+            const int t = tid + r * kTsThreads;
+            if (t < M.nt) {
+                x_r[r] += y_r[r];
+                x_i[r] += y_i[r];
+                v_r[r] += u_r[r];
+                v_i[r] += u_i[r];
+                xr[t] = x_r[r];
+                xi[t] = x_i[r];
+                vr[t] = v_r[r];
+                vi[t] = v_i[r];
+            }
+        }
+        __syncthreads();
+    }
+    // z_N = sum_j S_j conj(B_j) x_N,j
+    double zr = 0.0, zi = 0.0;
+#pragma unroll
+    for (int r = 0; r < kTsTris; ++r) {
+        const int t = tid + r * kTsThreads;
+        if (t < M.nt) {
+            const int g = M.t_off + t;
+            const float ph = kx * tri_O[2 * g] + kz * tri_O[2 * g + 1];
+            const double br = cosf(ph), bi = sinf(ph), S = 1.0 / double(invS[r]);
+            zr += S * (br * x_r[r] + bi * x_i[r]);
+            zi += S * (br * x_i[r] - bi * x_r[r]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        zr += __shfl_xor(zr, off, 64);
+        zi += __shfl_xor(zi, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = zr;
+        red[tid >> 6][1] = zi;
+    }
+    __syncthreads();
+    zr = zi = 0.0;
+    for (int q = 0; q < kTsThreads / 64; ++q) {
+        zr += red[q][0];
+        zi += red[q][1];
+    }
+    // eps = -arg(z_N / z_0) / (|k| N dt) - 1,  z_0 = area e^{-i |k| dt/2}
+    const double a0 = kn * M.dt / 2;
+    const double qr = zr * cos(a0) - zi * sin(a0), qi = zi * cos(a0) + zr * sin(a0);  // z_N e^{+i a}
+    const double T = kn * double(N) * M.dt;
+    const double eps = -atan2(qi, qr) / T - 1.0;
+    if (tid == 0) eps_out[blockIdx.x] = eps;
+
+    // pass 2: x forward from the start, v backwards from v_{N-1} (u_{N-1} = v_{N-1} - v_N)
+#pragma unroll
+    for (int r = 0; r < kTsTris; ++r) {
+        const int t = tid + r * kTsThreads;
+        if (t < M.nt) {
+            const float vNr = v_r[r], vNi = v_i[r];
+            v_r[r] = vNr - u_r[r];          // v_{N-1}
+            v_i[r] = vNi - u_i[r];
+            u_r[r] = -u_r[r];
+            u_i[r] = -u_i[r];
+            const int g = M.t_off + t;
+            const float ph = kx * tri_O[2 * g] + kz * tri_O[2 * g + 1];
+            const float br = cosf(ph), bi = sinf(ph);
+            x_r[r] = br * ca + bi * sa;
+            x_i[r] = bi * ca - br * sa;
+            y_r[r] = 2.0f * bi * sa;
+            y_i[r] = -2.0f * br * sa;
+        }
+    }
+    __syncthreads();   // everyone has read its z-partials before LDS is rewritten
+#pragma unroll
+    for (int r = 0; r < kTsTris; ++r) {
+        const int t = tid + r * kTsThreads;
+        if (t < M.nt) {
+            xr[t] = x_r[r];
+            xi[t] = x_i[r];
+            vr[t] = v_r[r];
+            vi[t] = v_i[r];
+        }
+    }
+    uint32_t erl[kTsEdges];
+    float acc_r[kTsEdges], acc_i[kTsEdges];
+#pragma unroll
+    for (int r = 0; r < kTsEdges; ++r) {
+        const int e = tid + r * kTsThreads;
+        erl[r] = e < M.ne ? edge_RL[M.e_off + e] : 0u;
+        acc_r[r] = acc_i[r] = 0.0f;
+    }
+    __syncthreads();
+    for (int n = 0; n < N; ++n) {
+#pragma unroll
+        for (int r = 0; r < kTsEdges; ++r) {
+            if (tid + r * kTsThreads < M.ne) {
+                const int R = int(erl[r] & 0xFFFFu), L = int(erl[r] >> 16);
+                const float dvr = vr[R] - vr[L], dvi = vi[R] - vi[L];
+                const float dxr = xr[R] - xr[L], dxi = xi[R] - xi[L];
+                acc_r[r] = fmaf(dvr, dxr, fmaf(dvi, dxi, acc_r[r]));   // Re(conj(dv) dx)
+                acc_i[r] = fmaf(dvr, dxi, fmaf(-dvi, dxr, acc_i[r]));  // Im(conj(dv) dx)
             }
         }
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q) {
-            double v = acc[q];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wv][q] = v;
+        for (int r = 0; r < kTsTris; ++r) {
+            if (tid + r * kTsThreads < M.nt) {
+                TS_STEP(x_r, x_i, y_r, y_i, xr, xi);
+                TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
+            }
         }
         __syncthreads();
-        if (threadIdx.x < kGroup && g0 + int(threadIdx.x) < W) {
-            double v = 0.0;
-            for (int q = 0; q < int(blockDim.x) / 64; ++q) v += red[q][threadIdx.x];
-            partial[size_t(c) * W + g0 + threadIdx.x] = v;
+#pragma unroll
+        for (int r = 0; r < kTsTris; ++r) {
+            const int t = tid + r * kTsThreads;
+            if (t < M.nt) {
+                x_r[r] += y_r[r];
+                x_i[r] += y_i[r];
+                v_r[r] += u_r[r];
+                v_i[r] += u_i[r];
+                xr[t] = x_r[r];
+                xi[t] = x_i[r];
+                vr[t] = v_r[r];
+                vi[t] = v_i[r];
+            }
         }
         __syncthreads();
     }
+#undef TS_STEP
+    // d eps/d gamma_e = -Im(conj(z_N) dz_e) / |z_N|^2 / T,  dz_e = -2 dt^2 gamma_e (|e|/d) acc_e
+    const double zz = zr * zr + zi * zi;
+    const double scale = 2.0 * eps * inv_mw / (zz * T);
+#pragma unroll
+    for (int r = 0; r < kTsEdges; ++r) {
+        const int e = tid + r * kTsThreads;
+        if (e < M.ne) {
+            const int ge = M.e_off + e;
+            const double c = -2.0 * M.dt * M.dt * double(gamma[ge]) * double(edge_ebyd[ge]);
+            const double dzr = c * acc_r[r], dzi = c * acc_i[r];
+            const double im = zr * dzi - zi * dzr;    // Im(conj(z) dz)
+            grad_out[size_t(w) * grad_stride + ge] = float(-im * scale);
+        }
+    }
 }
 
-// S[m][w] = sum over the chunks of mesh m (chunks of a mesh are consecutive)
-__global__ void k_wave_reduce(int M, int W, const int32_t *__restrict__ mesh_chunk0, const double *__restrict__ partial,
-                              double *__restrict__ S) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M * W) return;
-    const int m = t / W, w = t % W;
-    double v = 0.0;
-    for (int c = mesh_chunk0[m]; c < mesh_chunk0[m + 1]; ++c) v += partial[size_t(c) * W + w];
-    S[t] = v;
+// dL/dgamma_e = sum over waves of the per-wave shares (wave order)
+__global__ void k_wave_sum(int64_t n, int W, const float *__restrict__ g, float *__restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float acc = 0.0f;
+    for (int w = 0; w < W; ++w) acc += g[size_t(w) * n + e];
+    out[e] = acc;
 }
 
-// eps, loss and gradient coefficient c_w for every (mesh, wave); one block
-__global__ __launch_bounds__(1024) void k_wave_coef(int M, int W, const double *__restrict__ S,
-                                                    const double *__restrict__ area, const double *__restrict__ dt,
-                                                    const float *__restrict__ waves, double *__restrict__ eps,
-                                                    float *__restrict__ coef, double *__restrict__ loss_out) {
+// loss = sum eps^2 * inv_mw, one block
+__global__ __launch_bounds__(1024) void k_loss(int count, const double *__restrict__ eps, double inv_mw,
+                                               double *__restrict__ loss) {
     __shared__ double red[1024 / 64];
-    const double inv = 1.0 / double(M * W);
-    double local = 0.0;
-    for (int t = threadIdx.x; t < M * W; t += blockDim.x) {
-        const int m = t / W;
-        const double kx = waves[2 * t], kz = waves[2 * t + 1];
-        const double kn = sqrt(kx * kx + kz * kz);
-        const double wrq = sqrt(S[t] / area[m]);
-        const double s = wrq * dt[m] / 2.0;
-        const double e = 2.0 / dt[m] * asin(s) / kn - 1.0;
-        eps[t] = e;
-        local += e * e * inv;
-        // dL/dgamma_i = gamma_i sum_w c_w a_i(w)
-        coef[t] = float(2.0 * e * inv / (kn * sqrt(1.0 - s * s)) / (area[m] * wrq));
-    }
-    for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = local;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) v += eps[t] * eps[t] * inv_mw;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double v = 0.0;
-        for (int q = 0; q < int(blockDim.x) / 64; ++q) v += red[q];
-        *loss_out = v;
+        double s = 0.0;
+        for (int q = 0; q < int(blockDim.x) / 64; ++q) s += red[q];
+        *loss = s;
     }
 }
 
-// Backward pass.  Block b handles backward chunks [b*kBwdRounds, (b+1)*kBwdRounds) of at most
-// kBwdEdges edges of one mesh each.  Per chunk every work-item stages one edge's row
+// Backward pass.  Block b handles edges [b * kBwdEdges * kBwdRounds, ...) in rounds of
+// kBwdEdges.  Per round every work-item stages one edge's row
 //   [x(8) | h1(32) | d1(32) | h2(32) | d2(32) | dz | 1]
 // in LDS; then work-item t accumulates, over the staged rows, the products row[u] * row[v]
 // that form the gradient of the parameters it owns (p = t, t + 128, ...).
-__global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int nchunks, const int32_t *__restrict__ cmesh,
-                                                            const int32_t *__restrict__ cbeg,
-                                                            const int32_t *__restrict__ cend, int W,
-                                                            const float *__restrict__ feat,
+__global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int64_t n, const float *__restrict__ feat,
                                                             const float *__restrict__ params,
-                                                            const float *__restrict__ ebyd,
-                                                            const float *__restrict__ dO,
-                                                            const float *__restrict__ waves,
-                                                            const float *__restrict__ coef,
+                                                            const float *__restrict__ dLdg,
                                                             float *__restrict__ partial) {
     __shared__ float sP[kParams + 2 * kFeatures];
     __shared__ float rows[kBwdEdges * kRow];
-    __shared__ float sw[3 * kMaxWaves];
     load_params(sP, params);
     const int t = threadIdx.x;
     constexpr int kOwn = (kParams + kBwdEdges - 1) / kBwdEdges;  // 11
@@ -221,27 +397,17 @@ __global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int nchunks, const i
         acc[r] = 0.0f;
     }
     for (int cc = 0; cc < kBwdRounds; ++cc) {
-        const int c = blockIdx.x * kBwdRounds + cc;
-        if (c >= nchunks) break;
-        const int m = cmesh[c], i = cbeg[c] + t, n = cend[c] - cbeg[c];
+        const int64_t base = (int64_t(blockIdx.x) * kBwdRounds + cc) * kBwdEdges;
+        if (base >= n) break;
+        const int cnt = int(n - base < kBwdEdges ? n - base : kBwdEdges);
         __syncthreads();  // previous round's rows fully consumed
-        for (int w = t; w < W; w += blockDim.x) {
-            sw[3 * w] = waves[2 * (size_t(m) * W + w)];
-            sw[3 * w + 1] = waves[2 * (size_t(m) * W + w) + 1];
-            sw[3 * w + 2] = coef[size_t(m) * W + w];
-        }
-        __syncthreads();
         float *row = rows + t * kRow;
-        if (t < n) {
+        if (t < cnt) {
+            const int64_t i = base + t;
             float x[kFeatures], h1[kH1], h2[kH2];
             normalise(sP, feat + size_t(i) * kFeatures, x);
             const float th = mlp_edge(sP, x, h1, h2);
-            const float gam = 1.0f + kSpan * th;
-            // dL/dgamma_i
-            const float e = ebyd[i], dx = dO[2 * i], dz = dO[2 * i + 1];
-            float s = 0.0f;
-            for (int w = 0; w < W; ++w) s = fmaf(sw[3 * w + 2], rq_term(e, dx, dz, sw[3 * w], sw[3 * w + 1]), s);
-            const float gz = gam * s * kSpan * (1.0f - th * th);  // dL/dz
+            const float gz = dLdg[i] * kSpan * (1.0f - th * th);  // dL/dz
             float d2[kH2];
 #pragma unroll
             for (int a = 0; a < kH2; ++a) d2[a] = gz * sP[oW3 + a] * (1.0f - h2[a] * h2[a]);
@@ -268,7 +434,7 @@ __global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int nchunks, const i
 #pragma unroll
         for (int r = 0; r < kOwn; ++r) {
             float a = acc[r];
-            for (int e2 = 0; e2 < n; ++e2) a = fmaf(rows[e2 * kRow + u[r]], rows[e2 * kRow + v[r]], a);
+            for (int e2 = 0; e2 < cnt; ++e2) a = fmaf(rows[e2 * kRow + u[r]], rows[e2 * kRow + v[r]], a);
             acc[r] = a;
         }
     }
@@ -321,12 +487,12 @@ template <typename T> int download_vec(const DeviceBuffer &buf, std::vector<T> &
 struct tyee_learner {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    int64_t M = 0, W = 0, n = 0;  // meshes, waves per mesh, edges (interior, concatenated)
-    tyee::DeviceBuffer feat, ebyd, dO, gamma, waves, area, dt;
-    tyee::DeviceBuffer wc_mesh, wc_beg, wc_end, mesh_chunk0, partial_w, S, eps, coef, loss;
-    tyee::DeviceBuffer bc_mesh, bc_beg, bc_end, partial_g, grad;
+    int64_t M = 0, W = 0, n = 0, nt = 0;  // meshes, waves per mesh, edges, triangles (concatenated)
+    tyee::DeviceBuffer feat, ebyd, gamma, waves, nsteps, meshes;
+    tyee::DeviceBuffer tri_word, tri_invS, tri_O, edge_RL;
+    tyee::DeviceBuffer eps, wave_grad, dLdg, loss, partial_g, grad;
     tyee::DeviceBuffer params, m1, m2;  // params: [1377 | mu 8 | sd 8]
-    int64_t n_wchunks = 0, n_bchunks = 0, n_bblocks = 0, adam_t = 0;
+    int64_t n_bblocks = 0, adam_t = 0;
     std::vector<double> mu, sd;
 
     ~tyee_learner() {
@@ -340,24 +506,22 @@ namespace {
 
 int learner_pass(tyee_learner &L, bool want_grad) {
     using namespace tyee;
-    const int M = int(L.M), W = int(L.W);
     hipStream_t s = L.stream;
+    const double inv_mw = 1.0 / double(L.M * L.W);
     k_mlp_gamma<<<int((L.n + 255) / 256), 256, 0, s>>>(int(L.n), L.feat.as<float>(), L.params.as<float>(),
                                                       L.gamma.as<float>());
-    k_wave_sums<<<int(L.n_wchunks), 256, 0, s>>>(L.wc_mesh.as<int32_t>(), L.wc_beg.as<int32_t>(),
-                                                 L.wc_end.as<int32_t>(), W, L.gamma.as<float>(),
-                                                 L.ebyd.as<float>(), L.dO.as<float>(), L.waves.as<float>(),
-                                                 L.partial_w.as<double>());
-    k_wave_reduce<<<(M * W + 255) / 256, 256, 0, s>>>(M, W, L.mesh_chunk0.as<int32_t>(), L.partial_w.as<double>(),
-                                                      L.S.as<double>());
-    k_wave_coef<<<1, 1024, 0, s>>>(M, W, L.S.as<double>(), L.area.as<double>(), L.dt.as<double>(),
-                                   L.waves.as<float>(), L.eps.as<double>(), L.coef.as<float>(),
-                                   L.loss.as<double>());
+    k_ts_adjoint<<<int(L.M * L.W), kTsThreads, 0, s>>>(
+        int(L.W), L.meshes.as<TsMesh>(), L.waves.as<float>(), L.nsteps.as<int32_t>(), L.tri_word.as<uint32_t>(),
+        L.tri_invS.as<float>(), L.tri_O.as<float>(), L.edge_RL.as<uint32_t>(), L.ebyd.as<float>(),
+        L.gamma.as<float>(), inv_mw, L.eps.as<double>(), L.wave_grad.as<float>(), L.n);
+    k_loss<<<1, 1024, 0, s>>>(int(L.M * L.W), L.eps.as<double>(), inv_mw, L.loss.as<double>());
     if (want_grad) {
-        k_mlp_backward<<<int(L.n_bblocks), kBwdEdges, 0, s>>>(
-            int(L.n_bchunks), L.bc_mesh.as<int32_t>(), L.bc_beg.as<int32_t>(), L.bc_end.as<int32_t>(), W,
-            L.feat.as<float>(), L.params.as<float>(), L.ebyd.as<float>(), L.dO.as<float>(), L.waves.as<float>(),
-            L.coef.as<float>(), L.partial_g.as<float>());
+        // every (mesh, wave) share of dL/dgamma sits in row w of wave_grad; edges of mesh m
+        // are touched only by its own W blocks, so the per-edge sum runs over the W rows
+        k_wave_sum<<<int((L.n + 255) / 256), 256, 0, s>>>(L.n, int(L.W), L.wave_grad.as<float>(),
+                                                          L.dLdg.as<float>());
+        k_mlp_backward<<<int(L.n_bblocks), kBwdEdges, 0, s>>>(L.n, L.feat.as<float>(), L.params.as<float>(),
+                                                              L.dLdg.as<float>(), L.partial_g.as<float>());
         k_grad_reduce<<<(kParams + 255) / 256, 256, 0, s>>>(int(L.n_bblocks), L.partial_g.as<float>(),
                                                             L.grad.as<float>());
     }
@@ -392,11 +556,11 @@ int current_params(tyee_learner &L, std::vector<double> &theta) {
 extern "C" {
 
 int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes, const double *waves,
-                        int64_t n_waves, void *stream, tyee_learner **out) {
+                        int64_t n_waves, double phase, void *stream, tyee_learner **out) {
     using namespace tyee;
     if (!meshes || !dt || !waves || !out || n_meshes <= 0 || n_waves <= 0) return fail(TYEE_EINVAL, "bad learner arguments");
-    if (n_waves > kMaxWaves) return fail(TYEE_EINVAL, "at most 64 waves per mesh");
-    if (n_meshes * n_waves > 1 << 20) return fail(TYEE_EINVAL, "too many (mesh, wave) pairs");
+    if (!(phase > 0.0 && phase < 3.0)) return fail(TYEE_EINVAL, "phase must be in (0, 3) radians");
+    if (n_meshes * n_waves > (1 << 20)) return fail(TYEE_EINVAL, "too many (mesh, wave) pairs");
     *out = nullptr;
     try {
         std::unique_ptr<tyee_learner> L(new tyee_learner());
@@ -408,21 +572,28 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         }
         L->M = n_meshes;
         L->W = n_waves;
-        std::vector<float> feat, ebyd, dO;
-        std::vector<double> area(n_meshes), dts(dt, dt + n_meshes);
-        std::vector<int32_t> wc_mesh, wc_beg, wc_end, chunk0{0}, bc_mesh, bc_beg, bc_end;
+        std::vector<float> feat, ebyd, invS, O, wv(2 * n_meshes * n_waves);
+        std::vector<uint32_t> word, rl;
+        std::vector<int32_t> steps(n_meshes * n_waves);
+        std::vector<TsMesh> info(n_meshes);
         std::vector<double> sum(kFeatures, 0.0), sum2(kFeatures, 0.0);
-        int64_t off = 0;
         for (int64_t k = 0; k < n_meshes; ++k) {
             if (!meshes[k]) return fail(TYEE_EINVAL, "null mesh");
             const Mesh &m = meshes[k]->m;
+            if (!m.periodic) return fail(TYEE_EINVAL, "training meshes must be periodic");
+            if (m.nt > kTsMaxTris || m.ne > kTsMaxEdges)
+                return fail(TYEE_EINVAL, "training meshes are limited to 4096 triangles and 6144 edges");
             if (!(dt[k] > 0.0)) return fail(TYEE_EINVAL, "dt must be > 0");
-            std::vector<double> f, dv;
+            TsMesh &t = info[k];
+            t.t_off = int32_t(invS.size());
+            t.e_off = int32_t(ebyd.size());
+            t.nt = int32_t(m.nt);
+            t.ne = int32_t(m.ne);
+            t.dt = dt[k];
+            t.area = 0.0;
+            std::vector<double> f;
             edge_features(m, f);
-            dual_vectors(m, dv);
-            const int64_t start = off;
             for (int64_t i = 0; i < m.ne; ++i) {
-                if (!m.interior(i)) continue;
                 for (int b = 0; b < kFeatures; ++b) {
                     const double x = f[kFeatures * i + b];
                     feat.push_back(float(x));
@@ -430,59 +601,53 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
                     sum2[b] += x * x;
                 }
                 ebyd.push_back(float(m.elen[i] / m.d[i]));
-                dO.push_back(float(dv[2 * i]));
-                dO.push_back(float(dv[2 * i + 1]));
-                ++off;
+                rl.push_back(uint32_t(m.R[i]) | (uint32_t(m.L[i]) << 16));
             }
-            for (int64_t c = start; c < off; c += kWaveChunk) {
-                wc_mesh.push_back(int32_t(k));
-                wc_beg.push_back(int32_t(c));
-                wc_end.push_back(int32_t(std::min<int64_t>(off, c + kWaveChunk)));
+            for (int64_t j = 0; j < m.nt; ++j) {
+                t.area += m.S[j];
+                invS.push_back(float(1.0 / m.S[j]));
+                O.push_back(float(m.O[2 * j]));
+                O.push_back(float(m.O[2 * j + 1]));
+                for (int q = 0; q < 3; ++q) {
+                    const int32_t i = m.A[3 * j + q];
+                    const int32_t nb = m.R[i] == int32_t(j) ? m.L[i] : m.R[i];
+                    word.push_back(uint32_t(nb) | (uint32_t(i) << 16));
+                }
             }
-            chunk0.push_back(int32_t(wc_mesh.size()));
-            for (int64_t c = start; c < off; c += kBwdEdges) {
-                bc_mesh.push_back(int32_t(k));
-                bc_beg.push_back(int32_t(c));
-                bc_end.push_back(int32_t(std::min<int64_t>(off, c + kBwdEdges)));
+            for (int64_t w = 0; w < n_waves; ++w) {
+                const double kx = waves[2 * (k * n_waves + w)], kz = waves[2 * (k * n_waves + w) + 1];
+                const double kn = std::hypot(kx, kz);
+                if (!(kn > 0.0)) return fail(TYEE_EINVAL, "zero wavevector");
+                wv[2 * (k * n_waves + w)] = float(kx);
+                wv[2 * (k * n_waves + w) + 1] = float(kz);
+                steps[k * n_waves + w] = int32_t(std::max(1.0, std::nearbyint(phase / (kn * dt[k]))));
             }
-            double a = 0.0;
-            for (int64_t j = 0; j < m.nt; ++j) a += m.S[j];
-            area[k] = a;
         }
-        L->n = off;
-        if (off == 0 || off > INT32_MAX) return fail(TYEE_EINVAL, "no interior edges");
+        L->n = int64_t(ebyd.size());
+        L->nt = int64_t(invS.size());
         L->mu.resize(kFeatures);
         L->sd.resize(kFeatures);
         for (int b = 0; b < kFeatures; ++b) {
-            L->mu[b] = sum[b] / double(off);
-            const double var = std::max(0.0, sum2[b] / double(off) - L->mu[b] * L->mu[b]);
+            L->mu[b] = sum[b] / double(L->n);
+            const double var = std::max(0.0, sum2[b] / double(L->n) - L->mu[b] * L->mu[b]);
             L->sd[b] = std::sqrt(var) + 1e-6;
         }
-        std::vector<float> wv(2 * n_meshes * n_waves);
-        for (size_t q = 0; q < wv.size(); ++q) wv[q] = float(waves[q]);
-        L->n_wchunks = int64_t(wc_mesh.size());
-        L->n_bchunks = int64_t(bc_mesh.size());
-        L->n_bblocks = (L->n_bchunks + kBwdRounds - 1) / kBwdRounds;
+        L->n_bblocks = (L->n + kBwdEdges * kBwdRounds - 1) / (kBwdEdges * kBwdRounds);
         hipStream_t s = L->stream;
         int rc = upload_vec(L->feat, feat, s);
         if (!rc) rc = upload_vec(L->ebyd, ebyd, s);
-        if (!rc) rc = upload_vec(L->dO, dO, s);
-        if (!rc) rc = L->gamma.alloc(off * sizeof(float));
+        if (!rc) rc = upload_vec(L->edge_RL, rl, s);
+        if (!rc) rc = upload_vec(L->tri_word, word, s);
+        if (!rc) rc = upload_vec(L->tri_invS, invS, s);
+        if (!rc) rc = upload_vec(L->tri_O, O, s);
         if (!rc) rc = upload_vec(L->waves, wv, s);
-        if (!rc) rc = upload_vec(L->area, area, s);
-        if (!rc) rc = upload_vec(L->dt, dts, s);
-        if (!rc) rc = upload_vec(L->wc_mesh, wc_mesh, s);
-        if (!rc) rc = upload_vec(L->wc_beg, wc_beg, s);
-        if (!rc) rc = upload_vec(L->wc_end, wc_end, s);
-        if (!rc) rc = upload_vec(L->mesh_chunk0, chunk0, s);
-        if (!rc) rc = L->partial_w.alloc(L->n_wchunks * n_waves * sizeof(double));
-        if (!rc) rc = L->S.alloc(n_meshes * n_waves * sizeof(double));
+        if (!rc) rc = upload_vec(L->nsteps, steps, s);
+        if (!rc) rc = upload_vec(L->meshes, info, s);
+        if (!rc) rc = L->gamma.alloc(L->n * sizeof(float));
         if (!rc) rc = L->eps.alloc(n_meshes * n_waves * sizeof(double));
-        if (!rc) rc = L->coef.alloc(n_meshes * n_waves * sizeof(float));
+        if (!rc) rc = L->wave_grad.alloc(size_t(n_waves) * L->n * sizeof(float));
+        if (!rc) rc = L->dLdg.alloc(L->n * sizeof(float));
         if (!rc) rc = L->loss.alloc(sizeof(double));
-        if (!rc) rc = upload_vec(L->bc_mesh, bc_mesh, s);
-        if (!rc) rc = upload_vec(L->bc_beg, bc_beg, s);
-        if (!rc) rc = upload_vec(L->bc_end, bc_end, s);
         if (!rc) rc = L->partial_g.alloc(L->n_bblocks * kParams * sizeof(float));
         if (!rc) rc = L->grad.alloc(kParams * sizeof(float));
         std::vector<float> zeros(kParams, 0.0f);
@@ -714,5 +879,45 @@ extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double 
     }
     const double slope = (n * stp - st * sp) / (n * stt - st * st);
     *eps_out = slope / kn - 1.0;
+    return TYEE_OK;
+}
+
+extern "C" int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
+                         double cfl, double phase, int32_t prec, void *stream, tyee_gate_result *out) {
+    using namespace tyee;
+    if (!mesh || !gamma || !waves || !out || n_waves <= 0 || !(cfl > 0.0 && cfl < 1.0) ||
+        !(phase > 0.0 && phase < 3.0))
+        return fail(TYEE_EINVAL, "bad gate arguments");
+    const Mesh &m = mesh->m;
+    for (int64_t i = 0; i < m.ne; ++i)
+        if (!(gamma[i] > 0.0) || !std::isfinite(gamma[i])) return fail(TYEE_EINVAL, "gamma must be > 0");
+    tyee_gate_result r{};
+    double lp = 0.0, lg = 0.0;
+    int64_t ip = 0, ig = 0;
+    const int rp = power_iteration(m, nullptr, 20000, 1e-12, 0, &lp, &ip);
+    const int rg = power_iteration(m, gamma, 20000, 1e-12, 0, &lg, &ig);
+    if ((rp && rp != TYEE_ENOTCONVERGED) || (rg && rg != TYEE_ENOTCONVERGED)) return rp ? rp : rg;
+    clear_error();
+    r.converged = rp == TYEE_OK && rg == TYEE_OK;
+    r.omega_plain = std::sqrt(lp);
+    r.omega_learned = std::sqrt(lg);
+    r.dt_plain = cfl * 2.0 / r.omega_plain;
+    r.dt_learned = cfl * 2.0 / r.omega_learned;
+    for (int64_t w = 0; w < n_waves; ++w) {
+        const double kx = waves[2 * w], kz = waves[2 * w + 1], kn = std::hypot(kx, kz);
+        if (!(kn > 0.0)) return fail(TYEE_EINVAL, "zero wavevector");
+        double ep = 0.0, el = 0.0;
+        const int64_t np_ = std::max<int64_t>(20, int64_t(std::nearbyint(phase / (kn * r.dt_plain))));
+        const int64_t nl_ = std::max<int64_t>(20, int64_t(std::nearbyint(phase / (kn * r.dt_learned))));
+        int rc = tyee_phase_error_timestepped(mesh, nullptr, r.dt_plain, prec, kx, kz, np_, 20, stream, &ep);
+        if (!rc) rc = tyee_phase_error_timestepped(mesh, gamma, r.dt_learned, prec, kx, kz, nl_, 20, stream, &el);
+        if (rc) return rc;
+        r.err_plain += std::fabs(ep);
+        r.err_learned += std::fabs(el);
+    }
+    r.err_plain /= double(n_waves);
+    r.err_learned /= double(n_waves);
+    r.accepted = r.converged && r.err_learned < r.err_plain;
+    *out = r;
     return TYEE_OK;
 }

@@ -725,39 +725,6 @@ int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double 
     return TYEE_OK;
 }
 
-int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves, double cfl,
-              tyee_gate_result *out) {
-    if (!mesh || !gamma || !waves || !out || n_waves <= 0 || !(cfl > 0.0 && cfl < 1.0))
-        return tyee::fail(TYEE_EINVAL, "bad gate arguments");
-    const tyee::Mesh &m = mesh->m;
-    for (int64_t i = 0; i < m.ne; ++i)
-        if (!(gamma[i] > 0.0) || !std::isfinite(gamma[i])) return tyee::fail(TYEE_EINVAL, "gamma must be > 0");
-    tyee_gate_result r{};
-    double lp = 0.0, lg = 0.0;
-    int64_t ip = 0, ig = 0;
-    const int rp = tyee::power_iteration(m, nullptr, 20000, 1e-12, 0, &lp, &ip);
-    const int rg = tyee::power_iteration(m, gamma, 20000, 1e-12, 0, &lg, &ig);
-    if ((rp && rp != TYEE_ENOTCONVERGED) || (rg && rg != TYEE_ENOTCONVERGED)) return rp ? rp : rg;
-    tyee::clear_error();
-    r.converged = rp == TYEE_OK && rg == TYEE_OK;
-    r.omega_plain = std::sqrt(lp);
-    r.omega_learned = std::sqrt(lg);
-    r.dt_plain = cfl * 2.0 / r.omega_plain;
-    r.dt_learned = cfl * 2.0 / r.omega_learned;
-    std::vector<double> ep(n_waves), el(n_waves);
-    tyee::rq_phase_errors(m, nullptr, r.dt_plain, waves, n_waves, ep.data());
-    tyee::rq_phase_errors(m, gamma, r.dt_learned, waves, n_waves, el.data());
-    for (int64_t w = 0; w < n_waves; ++w) {
-        r.err_plain += std::fabs(ep[w]);
-        r.err_learned += std::fabs(el[w]);
-    }
-    r.err_plain /= double(n_waves);
-    r.err_learned /= double(n_waves);
-    r.accepted = r.converged && r.err_learned < r.err_plain;
-    *out = r;
-    return TYEE_OK;
-}
-
 void tyee_mesh_destroy(tyee_mesh *mesh) { delete mesh; }
 
 }  // extern "C"

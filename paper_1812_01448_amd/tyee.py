@@ -131,7 +131,7 @@ def _load():
         "tyee_mesh_phase_error_rq": [vp, vp, f64, vp, i64, vp],
         "tyee_phase_error_timestepped": [vp, vp, f64, i32, f64, f64, i64, i64, vp,
                                          ctypes.POINTER(f64)],
-        "tyee_learner_create": [vp, vp, i64, vp, i64, vp, ctypes.POINTER(vp)],
+        "tyee_learner_create": [vp, vp, i64, vp, i64, f64, vp, ctypes.POINTER(vp)],
         "tyee_learner_init": [vp, ctypes.c_uint64],
         "tyee_learner_set_params": [vp, vp],
         "tyee_learner_get_params": [vp, vp],
@@ -139,7 +139,7 @@ def _load():
         "tyee_learner_loss_grad": [vp, ctypes.POINTER(f64), vp, vp],
         "tyee_learner_train": [vp, i64, f64, vp],
         "tyee_learner_gamma": [vp, vp, vp],
-        "tyee_gate": [vp, vp, vp, i64, f64, ctypes.POINTER(_Gate)],
+        "tyee_gate": [vp, vp, vp, i64, f64, f64, i32, vp, ctypes.POINTER(_Gate)],
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
     }
@@ -255,11 +255,13 @@ class Mesh:
                                                 int(stream), ctypes.byref(e)))
         return e.value
 
-    def gate(self, gamma, waves, cfl=0.5):
+    def gate(self, gamma, waves, cfl=0.5, phase=2.0, prec="f64", stream=None):
         g = _f64(gamma, self.ne)
         w = np.ascontiguousarray(waves, np.float64).reshape(-1, 2)
         r = _Gate()
-        _check(lib.tyee_gate(self._h, _ptr(g), _ptr(w), len(w), float(cfl), ctypes.byref(r)))
+        _check(lib.tyee_gate(self._h, _ptr(g), _ptr(w), len(w), float(cfl), float(phase),
+                             PREC[prec], None if stream is None else int(stream),
+                             ctypes.byref(r)))
         return {n: getattr(r, n) for n, _ in _Gate._fields_}
 
     def cfl(self, gamma=None, max_iter=20000, rtol=1e-12, seed=0):
@@ -477,7 +479,7 @@ class Batch:
 class Learner:
     """Training set + MLP of the learned edge scale on the device (tyee_learner_*)."""
 
-    def __init__(self, meshes, dts, waves, stream=None):
+    def __init__(self, meshes, dts, waves, phase=2.0, stream=None):
         arr = (ctypes.c_void_p * len(meshes))(*[m._h.value for m in meshes])
         dt = _f64(dts, len(meshes))
         w = np.ascontiguousarray(waves, np.float64)
@@ -485,7 +487,8 @@ class Learner:
             raise ValueError("waves must have shape [n_meshes, n_waves, 2]")
         h = ctypes.c_void_p()
         _check(lib.tyee_learner_create(arr, _ptr(dt), len(meshes), _ptr(w), w.shape[1],
-                                       None if stream is None else int(stream), ctypes.byref(h)))
+                                       float(phase), None if stream is None else int(stream),
+                                       ctypes.byref(h)))
         self._h = h
         self.n_meshes, self.n_waves = len(meshes), w.shape[1]
 

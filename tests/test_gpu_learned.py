@@ -50,10 +50,12 @@ def training_set(ty, sizes, seed0, jitter=0.3):
 
 
 def test_learner_matches_oracle(ty):
-    _note("case: learner loss/grad/gamma vs oracle on 3 meshes x 48 waves")
-    ts = training_set(ty, [24, 32, 40], 300)
+    _note("case: learner loss/grad/gamma vs oracle on 3 meshes x 12 waves")
+    ts = training_set(ty, [16, 20, 24], 300)
+    for t in ts:
+        t["waves"] = waves_for(t["n"], cells=(8, 16), angles=np.arange(6) * np.pi / 6)
     W = np.stack([t["waves"] for t in ts])
-    lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts], W)
+    lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts], W, phase=2.0)
     feats = [OL.features(t["om"]) for t in ts]
     F = np.concatenate(feats)
     mu, sd = F.mean(0), F.std(0) + 1e-6
@@ -65,23 +67,23 @@ def test_learner_matches_oracle(ty):
     ref_loss, ref_grad = 0.0, np.zeros(OL.N_PARAMS)
     for t, f, e_row in zip(ts, feats, errs):
         gam = OL.mlp_forward(theta32, f, mu, sd)
-        l, dg = OL.rq_loss_grad(t["om"], gam, t["dt"], t["waves"])
+        assert np.max(np.abs(lr.gamma(t["mesh"]) - gam)) < 2e-6
+        l, dg = OL.ts_loss_grad(t["om"], gam, t["dt"], t["waves"], phase=2.0)
         ref_loss += l / len(ts)
         ref_grad += OL.mlp_param_grad(theta32, f, mu, sd, dg / len(ts))
-        ref_e = [OL.rq_phase_error(t["om"], gam, t["dt"], k) for k in t["waves"]]
-        assert np.max(np.abs(e_row - ref_e)) < 2e-6
-        g_gpu = lr.gamma(t["mesh"])
-        assert np.max(np.abs(g_gpu - gam)) < 2e-6
+        ref_e = [OL.ts_phase_error_grad(t["om"], gam, t["dt"], k, OL.ts_steps(k, t["dt"]))[0]
+                 for k in t["waves"]]
+        assert np.max(np.abs(e_row - ref_e)) < 2e-6, np.max(np.abs(e_row - ref_e))
     _note(f"  loss {loss:.6e} ref {ref_loss:.6e}; grad rel L2 {rel_l2(grad, ref_grad):.2e}")
-    assert abs(loss / ref_loss - 1) < 1e-4
-    assert rel_l2(grad, ref_grad) < 1e-3
+    assert abs(loss / ref_loss - 1) < 1e-3
+    assert rel_l2(grad, ref_grad) < 1e-2
 
 
 def test_identity_model_is_plain_and_training_lowers_loss(ty):
     _note("case: gamma = 1 bit-exact, 150 Adam steps on the GPU")
     ts = training_set(ty, [32, 40], 400)
     lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts],
-                    np.stack([t["waves"] for t in ts]))
+                    np.stack([t["waves"] for t in ts]), phase=2.0)
     lr.init(seed=3)
     t = ts[0]
     g = lr.gamma(t["mesh"])
@@ -101,7 +103,7 @@ def test_identity_model_is_plain_and_training_lowers_loss(ty):
     hist = lr.train(150, 3e-3)
     final, _, _ = lr.loss_grad(want_grad=False)
     _note(f"  loss {hist[0]:.4e} -> {final:.4e}")
-    assert final < 0.6 * hist[0]
+    assert final < 0.5 * hist[0]
     g2 = lr.gamma(t["mesh"])
     assert np.all((g2 > 0.9) & (g2 < 1.1)) and np.std(g2) > 0
 
@@ -121,27 +123,33 @@ def test_timestepped_phase_error_matches_oracle(ty):
 
 
 def test_trained_network_gains_over_plain_on_held_out_meshes(ty):
-    _note("case: train 8 meshes (n=48), gate + evaluate on 3 held-out meshes (n=64)")
-    train = training_set(ty, [48] * 8, 500)
+    _note("case: train 8 meshes (n=32), gate + evaluate on 3 held-out meshes (n=48)")
+    angles = np.arange(6) * np.pi / 6
+    train = training_set(ty, [32] * 8, 500)
     lr = ty.Learner([t["mesh"] for t in train], [t["dt"] for t in train],
-                    np.stack([t["waves"] for t in train]))
+                    np.stack([waves_for(32, cells=(8, 10, 16), angles=angles)] * len(train)))
     lr.init(seed=1)
-    lr.train(300, 3e-3)
-    held = training_set(ty, [64] * 3, 900)
+    hist = lr.train(200, 3e-3)
+    _note(f"  training loss {hist[0]:.4e} -> {hist[-1]:.4e}")
+    held = training_set(ty, [48] * 3, 900)
     gains = []
     for t in held:
         gam = lr.gamma(t["mesh"])
-        w10 = waves_for(t["n"], cells=(10,))
+        w10 = waves_for(t["n"], cells=(10,), angles=angles)
         gate = t["mesh"].gate(gam, w10)
-        _note(f"  held-out: plain {gate['err_plain']:.4e} learned {gate['err_learned']:.4e} "
-              f"dt ratio {gate['dt_learned'] / gate['dt_plain']:.4f} accepted {gate['accepted']}")
-        assert gate["converged"]
-        assert gate["accepted"] and gate["err_learned"] < gate["err_plain"]
+        _note(f"  held-out (time-stepped, 10 cells/lambda): plain {gate['err_plain']:.4e} "
+              f"learned {gate['err_learned']:.4e} dt ratio "
+              f"{gate['dt_learned'] / gate['dt_plain']:.4f} accepted {gate['accepted']}")
+        assert gate["converged"] and gate["accepted"]
         gains.append(gate["err_plain"] / gate["err_learned"])
-        # the time-stepped error agrees that the learned scale is better at 10 cells/lambda
-        k = w10[2]
-        ep = t["mesh"].phase_error_timestepped(gate["dt_plain"], k, 3000, samples=15)
-        el = t["mesh"].phase_error_timestepped(gate["dt_learned"], k, 3000, samples=15, gamma=gam)
-        _note(f"    time-stepped at 10 cells/lambda: plain {ep:.4e} learned {el:.4e}")
+        # the oracle's own time stepping agrees on one wave
+        k = w10[1]
+        om = t["om"]
+        ep = OL.timestepped_phase_error(om, None, gate["dt_plain"], k,
+                                        OL.ts_steps(k, gate["dt_plain"]), samples=20)
+        el = OL.timestepped_phase_error(om, gam, gate["dt_learned"], k,
+                                        OL.ts_steps(k, gate["dt_learned"]), samples=20)
+        _note(f"    oracle at {np.degrees(np.arctan2(k[1], k[0])):.0f} deg: plain {ep:.4e} "
+              f"learned {el:.4e}")
         assert abs(el) < abs(ep)
-    assert np.mean(gains) > 1.2
+    assert np.mean(gains) > 2.0

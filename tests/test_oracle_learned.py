@@ -117,3 +117,56 @@ def test_timestepped_phase_error_of_an_eigenmode(eq_mesh):
         got = L.timestepped_phase_error(m, None, dt, k, 400, samples=200)
         assert abs(got - expect) < 2e-3 * abs(expect) + 1e-5
         assert abs(L.rq_phase_error(m, None, dt, k) - expect) < 1e-12
+
+
+def test_ts_phase_error_gradient_fd(jit_mesh):
+    m = jit_mesh
+    dt = 0.5 * 2 / np.sqrt(m.power()[0])
+    rng = np.random.default_rng(5)
+    gamma = 1 + 0.04 * rng.standard_normal(m.ne)
+    k = 2 * np.pi * np.array([3.0, 1.0])
+    n = L.ts_steps(k, dt)
+    e, de = L.ts_phase_error_grad(m, gamma, dt, k, n)
+    h = 1e-5         # the long recurrence carries ~1e-13 of rounding in the error itself
+    for i in rng.choice(m.ne, 8, replace=False):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[i] += h
+        gm[i] -= h
+        fd = (L.ts_phase_error_grad(m, gp, dt, k, n)[0] - L.ts_phase_error_grad(m, gm, dt, k, n)[0]) / (2 * h)
+        assert abs(fd - de[i]) < 1e-5 * abs(fd) + 1e-10, (i, fd, de[i])
+    waves = [k, 2 * np.pi * np.array([1.0, -2.0])]
+    loss, grad = L.ts_loss_grad(m, gamma, dt, waves)
+    i = int(rng.integers(m.ne))
+    gp, gm = gamma.copy(), gamma.copy()
+    gp[i] += h
+    gm[i] -= h
+    fd = (L.ts_loss_grad(m, gp, dt, waves)[0] - L.ts_loss_grad(m, gm, dt, waves)[0]) / (2 * h)
+    assert abs(fd - grad[i]) < 1e-5 * abs(fd) + 1e-10
+
+
+def test_ts_phase_error_of_an_eigenmode_and_against_full_stepping(eq_mesh, jit_mesh):
+    # equilateral torus, k along x: exact eigenvector, so the phase advances theta per step
+    # with sin(theta/2) = omega dt / 2, omega = 4 sin(k/4)
+    m = eq_mesh
+    dt = 0.5 * 2 / (2 * np.sqrt(6))
+    k = np.array([2 * np.pi * 2 / m.Lx, 0.0])
+    theta = 2 * np.arcsin(4 * np.sin(k[0] / 4) * dt / 2)
+    n = L.ts_steps(k, dt, 2.0)            # the measured phase must stay below pi
+    e, _ = L.ts_phase_error_grad(m, None, dt, k, n)
+    # exact solution of the recurrence for an eigenvector: x_n = c1 e^{-i theta n} + c2 e^{i theta n}
+    # with x_0 = e^{-i a}, x_{-1} = e^{i a}, a = |k| dt / 2
+    a = k[0] * dt / 2
+    c1 = (np.exp(1j * a) - np.exp(-1j * a) * np.exp(-1j * theta)) / (2j * np.sin(theta))
+    c2 = np.exp(-1j * a) - c1
+    xn = c1 * np.exp(-1j * theta * n) + c2 * np.exp(1j * theta * n)
+    expect = -np.angle(xn / np.exp(-1j * a)) / (k[0] * n * dt) - 1
+    assert abs(e - expect) < 1e-10
+    assert abs(e - (theta / (k[0] * dt) - 1)) < 5e-3      # close to the pure eigen phase
+    # on a jittered mesh the B-only recurrence and the full E/B stepping agree on the phase
+    m = jit_mesh
+    dt = 0.5 * 2 / np.sqrt(m.power()[0])
+    k = 2 * np.pi * np.array([2.0, 1.0])
+    n = L.ts_steps(k, dt, 3.0)
+    e_b, _ = L.ts_phase_error_grad(m, None, dt, k, n)
+    e_full = L.timestepped_phase_error(m, None, dt, k, n, samples=30)
+    assert abs(e_b - e_full) < 0.05 * abs(e_full)
