@@ -303,6 +303,12 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
                         const double *waves, int64_t n_waves, double phase, void *stream,
                         tyee_learner **out);
 
+/* Stiff-edge term added to the loss: beta * mean over training edges with d/|e| < tau of
+   (gamma - target)^2.  Such edges hardly change smooth waves but set omega_max, so gamma
+   below 1 there lengthens the stable time step of eq. 20.  Defaults: tau 0.02, beta 1e-3,
+   target 0.9; beta = 0 removes the term. */
+int tyee_learner_regulariser(tyee_learner *l, double tau, double beta, double target);
+
 /* Glorot-uniform W1, W2 from splitmix64(seed + ...), zero biases and output layer (so the
    initial model is gamma = 1); resets the optimiser. */
 int tyee_learner_init(tyee_learner *l, uint64_t seed);

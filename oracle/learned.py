@@ -249,3 +249,12 @@ def ts_loss_grad(om, gamma, dt, waves, phase=2.0):
         loss += e * e
         grad += 2.0 * e * de
     return loss / len(waves), grad / len(waves)
+
+
+def stiff_reg_loss_grad(feat, gamma, tau=0.02, beta=1e-3, target=0.9):
+    """beta * mean over edges with d/|e| < tau of (gamma - target)^2, and its gradient."""
+    g = np.asarray(gamma, np.float64)
+    sel = np.asarray(feat)[:, 0] < tau
+    n = max(1, int(sel.sum()))
+    d = np.where(sel, g - target, 0.0)
+    return beta * np.sum(d * d) / n, 2.0 * beta * d / n

@@ -349,6 +349,33 @@ __global__ void k_wave_sum(int64_t n, int W, const float *__restrict__ g, float 
     out[e] = acc;
 }
 
+// Stiff-edge term: beta * mean over the listed edges of (gamma - target)^2.  Edges with a
+// tiny dual length barely affect smooth waves but set omega_max (and so dt); pulling their
+// gamma below 1 lengthens the stable time step.  One block; adds its gradient to dL/dgamma
+// (each listed edge once) and its value to the loss.
+__global__ __launch_bounds__(1024) void k_stiff_reg(int count, const int32_t *__restrict__ idx,
+                                                    const float *__restrict__ gamma, float beta, float target,
+                                                    float *__restrict__ dLdg, double *__restrict__ loss,
+                                                    int want_grad) {
+    __shared__ double red[1024 / 64];
+    double v = 0.0;
+    const float inv = 1.0f / float(count > 0 ? count : 1);
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+        const int e = idx[t];
+        const float d = gamma[e] - target;
+        v += double(beta) * double(d) * double(d) * double(inv);
+        if (want_grad) dLdg[e] += 2.0f * beta * d * inv;
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < int(blockDim.x) / 64; ++q) sum += red[q];
+        *loss += sum;
+    }
+}
+
 // loss = sum eps^2 * inv_mw, one block
 __global__ __launch_bounds__(1024) void k_loss(int count, const double *__restrict__ eps, double inv_mw,
                                                double *__restrict__ loss) {
@@ -491,6 +518,10 @@ struct tyee_learner {
     tyee::DeviceBuffer feat, ebyd, gamma, waves, nsteps, meshes;
     tyee::DeviceBuffer tri_word, tri_invS, tri_O, edge_RL;
     tyee::DeviceBuffer eps, wave_grad, dLdg, loss, partial_g, grad;
+    tyee::DeviceBuffer stiff;            // edges of the stiff-edge term
+    int64_t n_stiff = 0;
+    double reg_tau = 0.02, reg_beta = 1e-3, reg_target = 0.9;
+    std::vector<float> f0;               // d/|e| of every training edge (host)
     tyee::DeviceBuffer params, m1, m2;  // params: [1377 | mu 8 | sd 8]
     int64_t n_bblocks = 0, adam_t = 0;
     std::vector<double> mu, sd;
@@ -515,11 +546,16 @@ int learner_pass(tyee_learner &L, bool want_grad) {
         L.tri_invS.as<float>(), L.tri_O.as<float>(), L.edge_RL.as<uint32_t>(), L.ebyd.as<float>(),
         L.gamma.as<float>(), inv_mw, L.eps.as<double>(), L.wave_grad.as<float>(), L.n);
     k_loss<<<1, 1024, 0, s>>>(int(L.M * L.W), L.eps.as<double>(), inv_mw, L.loss.as<double>());
-    if (want_grad) {
+    if (want_grad)
         // every (mesh, wave) share of dL/dgamma sits in row w of wave_grad; edges of mesh m
         // are touched only by its own W blocks, so the per-edge sum runs over the W rows
         k_wave_sum<<<int((L.n + 255) / 256), 256, 0, s>>>(L.n, int(L.W), L.wave_grad.as<float>(),
                                                           L.dLdg.as<float>());
+    if (L.n_stiff > 0 && L.reg_beta > 0.0)
+        k_stiff_reg<<<1, 1024, 0, s>>>(int(L.n_stiff), L.stiff.as<int32_t>(), L.gamma.as<float>(),
+                                       float(L.reg_beta), float(L.reg_target), L.dLdg.as<float>(),
+                                       L.loss.as<double>(), want_grad ? 1 : 0);
+    if (want_grad) {
         k_mlp_backward<<<int(L.n_bblocks), kBwdEdges, 0, s>>>(L.n, L.feat.as<float>(), L.params.as<float>(),
                                                               L.dLdg.as<float>(), L.partial_g.as<float>());
         k_grad_reduce<<<(kParams + 255) / 256, 256, 0, s>>>(int(L.n_bblocks), L.partial_g.as<float>(),
@@ -527,6 +563,14 @@ int learner_pass(tyee_learner &L, bool want_grad) {
     }
     TYEE_HIP(hipGetLastError());
     return TYEE_OK;
+}
+
+int set_stiff_edges(tyee_learner &L) {
+    std::vector<int32_t> idx;
+    for (int64_t e = 0; e < L.n; ++e)
+        if (double(L.f0[e]) < L.reg_tau) idx.push_back(int32_t(e));
+    L.n_stiff = int64_t(idx.size());
+    return tyee::upload_vec(L.stiff, idx.empty() ? std::vector<int32_t>{0} : idx, L.stream);
 }
 
 int upload_params(tyee_learner &L, const std::vector<double> &theta) {
@@ -601,6 +645,7 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
                     sum2[b] += x * x;
                 }
                 ebyd.push_back(float(m.elen[i] / m.d[i]));
+                L->f0.push_back(float(f[kFeatures * i]));
                 rl.push_back(uint32_t(m.R[i]) | (uint32_t(m.L[i]) << 16));
             }
             for (int64_t j = 0; j < m.nt; ++j) {
@@ -654,6 +699,7 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         if (!rc) rc = upload_vec(L->m1, zeros, s);
         if (!rc) rc = upload_vec(L->m2, zeros, s);
         if (!rc) rc = upload_params(*L, std::vector<double>(kParams, 0.0));
+        if (!rc) rc = set_stiff_edges(*L);
         if (rc) return rc;
         *out = L.release();
         return TYEE_OK;
@@ -682,6 +728,16 @@ int tyee_learner_init(tyee_learner *L, uint64_t seed) {
     int rc = upload_vec(L->m1, zeros, L->stream);
     if (!rc) rc = upload_vec(L->m2, zeros, L->stream);
     return rc ? rc : upload_params(*L, th);
+}
+
+int tyee_learner_regulariser(tyee_learner *L, double tau, double beta, double target) {
+    if (!L) return fail(TYEE_EINVAL, "null learner");
+    if (!(tau >= 0.0) || !(beta >= 0.0) || !(target >= 0.9 && target <= 1.1))
+        return fail(TYEE_EINVAL, "tau, beta >= 0 and target in [0.9, 1.1] required");
+    L->reg_tau = tau;
+    L->reg_beta = beta;
+    L->reg_target = target;
+    return set_stiff_edges(*L);
 }
 
 int tyee_learner_set_params(tyee_learner *L, const double *theta) {

@@ -80,6 +80,7 @@ EXPORTS = [
     "tyee_learner_create", "tyee_learner_init", "tyee_learner_set_params",
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
+    "tyee_learner_regulariser",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -133,6 +134,7 @@ def _load():
                                          ctypes.POINTER(f64)],
         "tyee_learner_create": [vp, vp, i64, vp, i64, f64, vp, ctypes.POINTER(vp)],
         "tyee_learner_init": [vp, ctypes.c_uint64],
+        "tyee_learner_regulariser": [vp, f64, f64, f64],
         "tyee_learner_set_params": [vp, vp],
         "tyee_learner_get_params": [vp, vp],
         "tyee_learner_normaliser": [vp, vp, vp, vp, vp],
@@ -500,6 +502,9 @@ class Learner:
 
     def init(self, seed=0):
         _check(lib.tyee_learner_init(self._h, int(seed)))
+
+    def regulariser(self, tau=0.02, beta=1e-3, target=0.9):
+        _check(lib.tyee_learner_regulariser(self._h, float(tau), float(beta), float(target)))
 
     def params(self):
         out = np.zeros(N_PARAMS)

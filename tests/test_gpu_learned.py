@@ -56,6 +56,7 @@ def test_learner_matches_oracle(ty):
         t["waves"] = waves_for(t["n"], cells=(8, 16), angles=np.arange(6) * np.pi / 6)
     W = np.stack([t["waves"] for t in ts])
     lr = ty.Learner([t["mesh"] for t in ts], [t["dt"] for t in ts], W, phase=2.0)
+    lr.regulariser(tau=0.05, beta=1e-3, target=0.9)
     feats = [OL.features(t["om"]) for t in ts]
     F = np.concatenate(feats)
     mu, sd = F.mean(0), F.std(0) + 1e-6
@@ -71,6 +72,14 @@ def test_learner_matches_oracle(ty):
         l, dg = OL.ts_loss_grad(t["om"], gam, t["dt"], t["waves"], phase=2.0)
         ref_loss += l / len(ts)
         ref_grad += OL.mlp_param_grad(theta32, f, mu, sd, dg / len(ts))
+    # the stiff-edge term is a mean over all training meshes' stiff edges
+    gall = np.concatenate([OL.mlp_forward(theta32, f, mu, sd) for f in feats])
+    rl, rg = OL.stiff_reg_loss_grad(F, gall, tau=0.05, beta=1e-3, target=0.9)
+    assert np.count_nonzero(F[:, 0] < 0.05) > 0
+    ref_loss += rl
+    ref_grad += OL.mlp_param_grad(theta32, F, mu, sd, rg)
+    for t, f, e_row in zip(ts, feats, errs):
+        gam = OL.mlp_forward(theta32, f, mu, sd)
         ref_e = [OL.ts_phase_error_grad(t["om"], gam, t["dt"], k, OL.ts_steps(k, t["dt"]))[0]
                  for k in t["waves"]]
         assert np.max(np.abs(e_row - ref_e)) < 2e-6, np.max(np.abs(e_row - ref_e))
