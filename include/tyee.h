@@ -277,13 +277,14 @@ int tyee_mesh_features(const tyee_mesh *mesh, double *out);
 int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double dt,
                              const double *waves, int64_t n_waves, double *out);
 
-/* Time-stepped phase error of one plane wave: two simulations (real and imaginary parts of
-   B = exp(i (k.O - |k| dt/2)), E = exp(i k.C) (t . (n x k^))) are advanced nsteps on the GPU
-   in `samples` chunks; the phase of the overlap z = sum w E conj(E0) + sum S B conj(B0)
-   (metric (7)) is unwrapped and fitted by least squares, *eps = slope/|k| - 1. */
+/* Time-stepped phase errors of plane waves [n_waves][2]: for each wave two simulations
+   (real and imaginary parts of B = exp(i (k.O - |k| dt/2)), E = exp(i k.C) (t . (n x k^)))
+   are advanced N = max(samples, round(phase/(|k| dt))) steps on the GPU in `samples` chunks;
+   the phase of the overlap z = sum w E conj(E0) + sum S B conj(B0) (metric (7)) is unwrapped
+   and fitted by least squares, eps[w] = slope/|k| - 1.  gamma: edge scale or NULL. */
 int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double *gamma, double dt,
-                                 int32_t prec, double kx, double kz, int64_t nsteps,
-                                 int64_t samples, void *stream, double *eps);
+                                 int32_t prec, const double *waves, int64_t n_waves,
+                                 double phase, int64_t samples, void *stream, double *eps);
 
 typedef struct tyee_learner tyee_learner;
 
@@ -344,7 +345,7 @@ typedef struct {
 /* Per-mesh acceptance of a learned scale: omega_max with and without gamma by power
    iteration (the eq. 20 bound fixes dt = cfl * 2/omega_max for each), then the mean absolute
    time-stepped phase error (tyee_phase_error_timestepped, about `phase` radians of travel,
-   20 samples) over held-out waves [n_waves][2], each method at its own dt.  Callers use
+   10 samples) over held-out waves [n_waves][2], each method at its own dt.  Callers use
    gamma and dt_learned only when accepted, else the plain coefficients and dt_plain. */
 int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
               double cfl, double phase, int32_t prec, void *stream, tyee_gate_result *out);

@@ -845,30 +845,16 @@ void tyee_learner_destroy(tyee_learner *L) { delete L; }
 }  // extern "C"
 
 extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double *gamma, double dt, int32_t prec,
-                                            double kx, double kz, int64_t nsteps, int64_t samples, void *stream,
-                                            double *eps_out) {
+                                            const double *waves, int64_t n_waves, double phase, int64_t samples,
+                                            void *stream, double *eps_out) {
     using namespace tyee;
-    if (!mesh || !eps_out || !(dt > 0.0) || nsteps <= 0 || samples < 2 || samples > nsteps)
+    if (!mesh || !waves || !eps_out || n_waves <= 0 || !(dt > 0.0) || samples < 2 || !(phase > 0.0))
         return fail(TYEE_EINVAL, "bad phase-error arguments");
-    const double kn = std::hypot(kx, kz);
-    if (!(kn > 0.0)) return fail(TYEE_EINVAL, "zero wavevector");
     const Mesh &m = mesh->m;
-    // complex plane wave: B = exp(i (k.O - |k| dt/2)) at t = dt/2, E = exp(i k.C) (t . (n x k^)) at t = 0
-    std::vector<double> Er(m.ne), Ei(m.ne), Br(m.nt), Bi(m.nt), w(m.ne, 0.0);
-    const double px = -kz / kn, pz = kx / kn;
-    for (int64_t j = 0; j < m.nt; ++j) {
-        const double ph = kx * m.O[2 * j] + kz * m.O[2 * j + 1] - kn * dt / 2.0;
-        Br[j] = std::cos(ph);
-        Bi[j] = std::sin(ph);
-    }
-    for (int64_t i = 0; i < m.ne; ++i) {
-        const double ph = kx * m.C[2 * i] + kz * m.C[2 * i + 1];
-        const double proj = (m.evec[2 * i] * px + m.evec[2 * i + 1] * pz) / m.elen[i];
-        const bool inner = m.interior(i);
-        Er[i] = inner ? std::cos(ph) * proj : 0.0;
-        Ei[i] = inner ? std::sin(ph) * proj : 0.0;
-        if (inner) w[i] = m.d[i] * m.elen[i];
-    }
+    std::vector<double> w(m.ne, 0.0);
+    for (int64_t i = 0; i < m.ne; ++i)
+        if (m.interior(i)) w[i] = m.d[i] * m.elen[i];
+    // two simulations (real and imaginary parts), created once: the tiles are reused
     tyee_sim *sims[2] = {nullptr, nullptr};
     auto cleanup = [&]() {
         tyee_sim_destroy(sims[0]);
@@ -878,64 +864,78 @@ extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double 
     for (int r = 0; r < 2 && !rc; ++r) {
         rc = tyee_sim_create(mesh, prec, dt, stream, &sims[r]);
         if (!rc && gamma) rc = tyee_sim_set_edge_scale(sims[r], gamma);
-        if (!rc) rc = tyee_sim_set_state(sims[r], TYEE_FIELD_E, r ? Ei.data() : Er.data());
-        if (!rc) rc = tyee_sim_set_state(sims[r], TYEE_FIELD_B, r ? Bi.data() : Br.data());
         if (!rc) rc = tyee_sim_set_fusion(sims[r], 4, 0);
     }
-    if (rc) {
-        cleanup();
-        return rc;
-    }
-    const int64_t chunk = nsteps / samples;
-    std::vector<double> ts, phase;
-    std::vector<double> E[2], B[2];
-    double prev = 0.0, unwrap = 0.0;
-    for (int64_t q = 0; q < samples && !rc; ++q) {
+    std::vector<double> Er(m.ne), Ei(m.ne), Br(m.nt), Bi(m.nt), E[2], B[2];
+    for (int64_t wv = 0; wv < n_waves && !rc; ++wv) {
+        const double kx = waves[2 * wv], kz = waves[2 * wv + 1], kn = std::hypot(kx, kz);
+        if (!(kn > 0.0)) {
+            rc = fail(TYEE_EINVAL, "zero wavevector");
+            break;
+        }
+        // B = exp(i (k.O - |k| dt/2)) at t = dt/2, E = exp(i k.C) (t . (n x k^)) at t = 0
+        const double px = -kz / kn, pz = kx / kn;
+        for (int64_t j = 0; j < m.nt; ++j) {
+            const double ph = kx * m.O[2 * j] + kz * m.O[2 * j + 1] - kn * dt / 2.0;
+            Br[j] = std::cos(ph);
+            Bi[j] = std::sin(ph);
+        }
+        for (int64_t i = 0; i < m.ne; ++i) {
+            const double ph = kx * m.C[2 * i] + kz * m.C[2 * i + 1];
+            const double proj = (m.evec[2 * i] * px + m.evec[2 * i + 1] * pz) / m.elen[i];
+            const bool inner = m.interior(i);
+            Er[i] = inner ? std::cos(ph) * proj : 0.0;
+            Ei[i] = inner ? std::sin(ph) * proj : 0.0;
+        }
         for (int r = 0; r < 2 && !rc; ++r) {
-            rc = tyee_sim_step(sims[r], chunk);
-            E[r].resize(m.ne);
-            B[r].resize(m.nt);
-            if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_E, E[r].data());
-            if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_B, B[r].data());
+            rc = tyee_sim_set_state(sims[r], TYEE_FIELD_E, r ? Ei.data() : Er.data());
+            if (!rc) rc = tyee_sim_set_state(sims[r], TYEE_FIELD_B, r ? Bi.data() : Br.data());
         }
         if (rc) break;
-        // z = sum w E conj(E0) + sum S B conj(B0)
-        double zr = 0.0, zi = 0.0;
-        for (int64_t i = 0; i < m.ne; ++i) {
-            zr += w[i] * (E[0][i] * Er[i] + E[1][i] * Ei[i]);
-            zi += w[i] * (E[1][i] * Er[i] - E[0][i] * Ei[i]);
+        const int64_t nsteps = std::max<int64_t>(samples, int64_t(std::nearbyint(phase / (kn * dt))));
+        const int64_t chunk = nsteps / samples;
+        double st = 0, sp = 0, stt = 0, stp = 0, prev = 0.0, unwrap = 0.0;
+        for (int64_t q = 0; q < samples && !rc; ++q) {
+            for (int r = 0; r < 2 && !rc; ++r) {
+                rc = tyee_sim_step(sims[r], chunk);
+                E[r].resize(m.ne);
+                B[r].resize(m.nt);
+                if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_E, E[r].data());
+                if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_B, B[r].data());
+            }
+            if (rc) break;
+            // z = sum w E conj(E0) + sum S B conj(B0)  (metric (7))
+            double zr = 0.0, zi = 0.0;
+            for (int64_t i = 0; i < m.ne; ++i) {
+                zr += w[i] * (E[0][i] * Er[i] + E[1][i] * Ei[i]);
+                zi += w[i] * (E[1][i] * Er[i] - E[0][i] * Ei[i]);
+            }
+            for (int64_t j = 0; j < m.nt; ++j) {
+                zr += m.S[j] * (B[0][j] * Br[j] + B[1][j] * Bi[j]);
+                zi += m.S[j] * (B[1][j] * Br[j] - B[0][j] * Bi[j]);
+            }
+            const double ph = -std::atan2(zi, zr);
+            if (q > 0) {
+                double dphi = ph - prev;
+                while (dphi > M_PI) dphi -= 2.0 * M_PI;
+                while (dphi < -M_PI) dphi += 2.0 * M_PI;
+                unwrap += dphi;
+            } else {
+                unwrap = ph;
+            }
+            prev = ph;
+            const double t = double((q + 1) * chunk) * dt;
+            st += t;
+            sp += unwrap;
+            stt += t * t;
+            stp += t * unwrap;
         }
-        for (int64_t j = 0; j < m.nt; ++j) {
-            zr += m.S[j] * (B[0][j] * Br[j] + B[1][j] * Bi[j]);
-            zi += m.S[j] * (B[1][j] * Br[j] - B[0][j] * Bi[j]);
-        }
-        const double ph = -std::atan2(zi, zr);
-        if (q > 0) {
-            double dphi = ph - prev;
-            while (dphi > M_PI) dphi -= 2.0 * M_PI;
-            while (dphi < -M_PI) dphi += 2.0 * M_PI;
-            unwrap += dphi;
-        } else {
-            unwrap = ph;
-        }
-        prev = ph;
-        ts.push_back(double((q + 1) * chunk) * dt);
-        phase.push_back(unwrap);
+        if (rc) break;
+        const double n = double(samples);
+        eps_out[wv] = (n * stp - st * sp) / (n * stt - st * st) / kn - 1.0;  // least-squares slope
     }
     cleanup();
-    if (rc) return rc;
-    // least-squares slope of phase(t)
-    const double n = double(ts.size());
-    double st = 0, sp = 0, stt = 0, stp = 0;
-    for (size_t q = 0; q < ts.size(); ++q) {
-        st += ts[q];
-        sp += phase[q];
-        stt += ts[q] * ts[q];
-        stp += ts[q] * phase[q];
-    }
-    const double slope = (n * stp - st * sp) / (n * stt - st * st);
-    *eps_out = slope / kn - 1.0;
-    return TYEE_OK;
+    return rc;
 }
 
 extern "C" int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
@@ -959,17 +959,16 @@ extern "C" int tyee_gate(const tyee_mesh *mesh, const double *gamma, const doubl
     r.omega_learned = std::sqrt(lg);
     r.dt_plain = cfl * 2.0 / r.omega_plain;
     r.dt_learned = cfl * 2.0 / r.omega_learned;
+    std::vector<double> ep(n_waves), el(n_waves);
+    int rc = tyee_phase_error_timestepped(mesh, nullptr, r.dt_plain, prec, waves, n_waves, phase, 10, stream,
+                                          ep.data());
+    if (!rc)
+        rc = tyee_phase_error_timestepped(mesh, gamma, r.dt_learned, prec, waves, n_waves, phase, 10, stream,
+                                          el.data());
+    if (rc) return rc;
     for (int64_t w = 0; w < n_waves; ++w) {
-        const double kx = waves[2 * w], kz = waves[2 * w + 1], kn = std::hypot(kx, kz);
-        if (!(kn > 0.0)) return fail(TYEE_EINVAL, "zero wavevector");
-        double ep = 0.0, el = 0.0;
-        const int64_t np_ = std::max<int64_t>(20, int64_t(std::nearbyint(phase / (kn * r.dt_plain))));
-        const int64_t nl_ = std::max<int64_t>(20, int64_t(std::nearbyint(phase / (kn * r.dt_learned))));
-        int rc = tyee_phase_error_timestepped(mesh, nullptr, r.dt_plain, prec, kx, kz, np_, 20, stream, &ep);
-        if (!rc) rc = tyee_phase_error_timestepped(mesh, gamma, r.dt_learned, prec, kx, kz, nl_, 20, stream, &el);
-        if (rc) return rc;
-        r.err_plain += std::fabs(ep);
-        r.err_learned += std::fabs(el);
+        r.err_plain += std::fabs(ep[w]);
+        r.err_learned += std::fabs(el[w]);
     }
     r.err_plain /= double(n_waves);
     r.err_learned /= double(n_waves);

@@ -130,8 +130,7 @@ def _load():
         "tyee_batch_tune": [vp, i64, vp, i64, ctypes.POINTER(i64)],
         "tyee_mesh_features": [vp, vp],
         "tyee_mesh_phase_error_rq": [vp, vp, f64, vp, i64, vp],
-        "tyee_phase_error_timestepped": [vp, vp, f64, i32, f64, f64, i64, i64, vp,
-                                         ctypes.POINTER(f64)],
+        "tyee_phase_error_timestepped": [vp, vp, f64, i32, vp, i64, f64, i64, vp, vp],
         "tyee_learner_create": [vp, vp, i64, vp, i64, f64, vp, ctypes.POINTER(vp)],
         "tyee_learner_init": [vp, ctypes.c_uint64],
         "tyee_learner_regulariser": [vp, f64, f64, f64],
@@ -247,15 +246,19 @@ class Mesh:
         _check(lib.tyee_mesh_phase_error_rq(self._h, _ptr(g), float(dt), _ptr(w), len(w), _ptr(out)))
         return out
 
-    def phase_error_timestepped(self, dt, k, nsteps, samples=20, gamma=None, prec="f64",
+    def phase_error_timestepped(self, dt, waves, phase=2.0, samples=10, gamma=None, prec="f64",
                                 stream=None):
+        """Time-stepped phase error of each wave in `waves` ([n, 2] or one [2] wavevector)."""
+        w = np.ascontiguousarray(waves, np.float64)
+        single = w.ndim == 1
+        w = w.reshape(-1, 2)
         g = None if gamma is None else _f64(gamma, self.ne)
-        e = ctypes.c_double()
-        _check(lib.tyee_phase_error_timestepped(self._h, _ptr(g), float(dt), PREC[prec],
-                                                float(k[0]), float(k[1]), int(nsteps),
-                                                int(samples), None if stream is None else
-                                                int(stream), ctypes.byref(e)))
-        return e.value
+        out = np.zeros(len(w))
+        _check(lib.tyee_phase_error_timestepped(self._h, _ptr(g), float(dt), PREC[prec], _ptr(w),
+                                                len(w), float(phase), int(samples),
+                                                None if stream is None else int(stream),
+                                                _ptr(out)))
+        return float(out[0]) if single else out
 
     def gate(self, gamma, waves, cfl=0.5, phase=2.0, prec="f64", stream=None):
         g = _f64(gamma, self.ne)

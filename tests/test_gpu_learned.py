@@ -125,10 +125,17 @@ def test_timestepped_phase_error_matches_oracle(ty):
     dt = 0.5 * 2 / np.sqrt(om.power()[0])
     k, _, _ = periodic_wavevector(0.3, 8.0, 1 / 24)
     g = 1 + 0.03 * np.cos(np.arange(om.ne))
+    n = 4000
+    phase = n * np.hypot(*k) * dt          # N = round(phase/(|k| dt)) = 4000
     for gamma in (None, g):
-        a = m.phase_error_timestepped(dt, k, 4000, samples=20, gamma=gamma, prec="f64")
-        b = OL.timestepped_phase_error(om, gamma, dt, k, 4000, samples=20)
+        a = m.phase_error_timestepped(dt, k, phase=phase, samples=20, gamma=gamma, prec="f64")
+        b = OL.timestepped_phase_error(om, gamma, dt, k, n, samples=20)
         assert abs(a - b) < 1e-9, (a, b)
+    # several waves in one call equal one call per wave
+    ks = np.array([k, periodic_wavevector(1.1, 10.0, 1 / 24)[0]])
+    many = m.phase_error_timestepped(dt, ks, phase=2.0, samples=10, prec="f64")
+    one = [m.phase_error_timestepped(dt, kk, phase=2.0, samples=10, prec="f64") for kk in ks]
+    np.testing.assert_array_equal(many, one)
 
 
 def test_trained_network_gains_over_plain_on_held_out_meshes(ty):
