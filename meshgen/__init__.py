@@ -16,12 +16,13 @@ from .lattice import (lattice_mesh, incircle, lawson_flip, count_non_delaunay, e
                       triangle_centroids, scramble)
 from .fields import (cavity_mode, plane_wave_packet, periodic_wavevector,
                      random_angle, source_waveform)
-from .media import triangle_particle_mask, line_source_pairs
-from .workloads import WORKLOADS, make_workload
+from .media import (triangle_particle_mask, line_source_pairs, conforming_particle_mesh,
+                    particle_corners)
+from .workloads import WORKLOADS, make_workload, plasma_workload
 
 __all__ = [
     "lattice_mesh", "incircle", "lawson_flip", "count_non_delaunay", "triangle_centroids",
     "scramble", "equilateral_torus", "cavity_mode", "plane_wave_packet", "periodic_wavevector", "random_angle",
-    "source_waveform", "triangle_particle_mask", "line_source_pairs", "WORKLOADS",
-    "make_workload",
+    "source_waveform", "triangle_particle_mask", "line_source_pairs", "conforming_particle_mesh",
+    "particle_corners", "WORKLOADS", "make_workload", "plasma_workload",
 ]

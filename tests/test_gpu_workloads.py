@@ -4,6 +4,9 @@
   FP64 oracle element by element (relative L2 <= 1e-5), then 10^4 more steps checked through
   properties that hold at any size (leap-frog energy, nodal divergence).
 * 10^4-step FP32 parity (<= 1e-3) on a reduced torus where the oracle runs in seconds.
+* plasma2830 (16,017,830 triangles, conforming plasma particle, soft line source) FP32: 100
+  steps against the oracle (E, B, J, Q), then 5,000 steps checked through the discrete Gauss
+  law, which holds at any size.
 """
 import sys
 
@@ -11,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from meshgen import lattice_mesh, make_workload
+from meshgen import lattice_mesh, make_workload, plasma_workload
 from common import rel_l2, packet_state
 
 pytestmark = pytest.mark.gpu
@@ -80,3 +83,53 @@ def test_fp32_ten_thousand_steps_reduced_torus(ty):
     eE, eB = rel_l2(sim.get_state("E"), ref["E"]), rel_l2(sim.get_state("B"), ref["B"])
     _note(f"  rel L2 E {eE:.2e} B {eB:.2e}")
     assert eE < 1e-3 and eB < 1e-3
+
+
+def test_plasma2830_full_size_fp32(ty):
+    _note("case: plasma2830 full size fp32 (particle + source, bench configuration)")
+    w = plasma_workload()
+    xy, tri, n = w["xy"], w["tri"], w["n"]
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    lam, _, ok = m.cfl()
+    assert ok
+    dt = 0.5 * 2 / np.sqrt(lam)
+    v = m.view()
+    src = (w["src_pairs"], w["src_weights"], w["src_omega"], w["src_cycles"])
+    sim = ty.Sim(m, dt, "f32")
+    sim.set_fusion(0, 0)
+    sim.set_media(w["wp2_tri"], w["nu"])
+    sim.set_source(*src)
+    # a packet centred on the particle, so the plasma current is driven from the first step
+    fn = lambda side: packet_state(side, dt, n, cells=20.0)
+    E0, B0 = fn(v)
+    sim.set_state("E", E0)
+    sim.set_state("B", B0)
+    g0 = sim.gauss()
+    sim.step(100)
+    got = {f: sim.get_state(f) for f in ("E", "B", "J", "Q")}
+    _note("  oracle: mesh + 100 steps")
+    om = oracle.OracleMesh(xy, tri, True)
+    ref = om.step(*fn(om), dt, 100, wp2=om.edge_wp2(w["wp2_tri"]), nu=w["nu"], src=src)
+    errs = {f: rel_l2(got[f], ref[f]) for f in got}
+    _note("  rel L2 " + " ".join(f"{f} {e:.2e}" for f, e in errs.items()))
+    assert np.max(np.abs(ref["J"])) > 0 and np.max(np.abs(ref["Q"])) > 0
+    for f, e in errs.items():
+        assert e < 1e-5, f
+    del om, ref
+    # 5,000 further steps: (D E - Q) stays at its initial value (continuity, any size)
+    sim.step(5000)
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0
+    g1 = sim.gauss()
+    # scale: the largest nodal sum of |d E| (the terms FP32 rounds), and the charge itself
+    E1 = sim.get_state("E")
+    mag = np.zeros(len(g1))
+    np.add.at(mag, v["edge_nodes"][:, 0], np.abs(v["d"] * E1))
+    np.add.at(mag, v["edge_nodes"][:, 1], np.abs(v["d"] * E1))
+    Q1 = sim.get_state("Q")
+    res = np.max(np.abs(g1 - g0))
+    _note(f"  Gauss-law residual after 5,100 steps {res:.3e} (max nodal |d E| sum "
+          f"{np.max(mag):.3e}, max |Q| {np.max(np.abs(Q1)):.3e})")
+    assert np.max(np.abs(Q1)) > 1e-2 * np.max(mag)      # the charge is not negligible
+    assert res < 1e-3 * np.max(mag)
