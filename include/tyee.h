@@ -249,9 +249,10 @@ int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds);
 int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *total_ms);
 
 /* Fusion in use: out = {steps per launch, tile size in triangles, number of tiles, local
-   triangles summed over tiles, local edges summed over tiles}; the last four are 0 until
-   the first fused launch has built the tiles. */
-int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]);
+   triangles summed over tiles, local edges summed over tiles, tiles holding a special edge
+   (run by the special-edge variant of the fused kernel)}; the last five are 0 until the
+   first fused launch has built the tiles. */
+int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[6]);
 
 int64_t tyee_sim_steps(const tyee_sim *sim);
 void tyee_sim_destroy(tyee_sim *sim);

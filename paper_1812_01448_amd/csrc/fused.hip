@@ -15,6 +15,13 @@
 // neighbour's already-advanced values; the runtime swaps the two buffers after each launch.
 // The per-cell arithmetic is exactly that of k_edge / k_tri (same fma, same q order), so any
 // fusion depth gives bit-identical fields.
+//
+// Special edges (plasma current, eq. 5, and the soft source) ride along: the work-item that
+// holds such an edge also holds its current j and Drude coefficients and applies the same
+// correction k_special does, in the same order, just before the edge half-step.  Halo copies
+// of j advance redundantly like the fields; each tile writes back j of its own edges (into
+// the other j buffer) and, per step, their decrements, from which k_charge then advances the
+// nodal charge step by step, so E, B, j and Q stay bit-identical to single-step launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,18 +46,33 @@ template <> __device__ __forceinline__ double lds_signed<double>(const double *v
     return __longlong_as_double(__double_as_longlong(x) ^ (static_cast<long long>(half & 0x8000u) << 48));
 }
 
-template <typename T, int NT, int RT, int RE>
+// Arguments of the special-edge variant (unused by the plain kernel).
+template <typename T> struct SpecialArgs {
+    const int32_t *el_sp;  // per local edge: special-list index or -1
+    const T *j_in;
+    T *j_out;
+    const T *ca, *cb, *w;  // Drude coefficients and source weight per special entry
+    T *delta;              // [step][nsp] decrements of owned special edges
+    int nsp;
+    T dt;
+    T g[kMaxFusion];       // source waveform at the midpoint of each step of the launch
+};
+
+template <typename T, int NT, int RT, int RE, bool SP>
 __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInfo *__restrict__ tiles,
                                               const T *__restrict__ Et_in, const T *__restrict__ B_in,
                                               T *__restrict__ Et_out, T *__restrict__ B_out,
                                               const int32_t *__restrict__ tl_glob, const T *__restrict__ tl_coef,
                                               const uint32_t *__restrict__ tl_i0, const uint32_t *__restrict__ tl_i1,
                                               const int32_t *__restrict__ el_glob, const T *__restrict__ el_coef,
-                                              const uint32_t *__restrict__ el_idx) {
+                                              const uint32_t *__restrict__ el_idx,
+                                              const int32_t *__restrict__ tile_ids, const SpecialArgs<T> sp) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *sB = reinterpret_cast<T *>(lds_raw);
     T *sE = sB + lds_tris;
-    const TileInfo &ti = tiles[xcd_group(blockIdx.x, gridDim.x)];
+    int t = xcd_group(blockIdx.x, gridDim.x);
+    if (tile_ids) t = tile_ids[t];  // a subset of the tiles (one class of a split launch)
+    const TileInfo &ti = tiles[t];
     const int tid = threadIdx.x;
     const int nT = ti.cntT[K], nE = ti.cntE[K - 1];
 
@@ -72,18 +94,31 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
             sB[l] = vb[r];
         }
     }
+    int spk[RE];
+    T jr[RE], sa[RE], sb[RE], sw[RE];
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int l = tid + r * NT;
         ve[r] = T(0);
         ce[r] = T(0);
         ie[r] = 0;
+        spk[r] = -1;
+        jr[r] = sa[r] = sb[r] = sw[r] = T(0);
         if (l < nE) {
             const int p = ti.edge_off + l;
             ve[r] = Et_in[el_glob[p]];
             ce[r] = el_coef[p];
             ie[r] = el_idx[p];
             sE[l] = ve[r];
+            if constexpr (SP) {
+                spk[r] = sp.el_sp[p];
+                if (spk[r] >= 0) {
+                    jr[r] = sp.j_in[spk[r]];
+                    sa[r] = sp.ca[spk[r]];
+                    sb[r] = sp.cb[spk[r]];
+                    sw[r] = sp.w[spk[r]];
+                }
+            }
         }
     }
     __syncthreads();
@@ -95,7 +130,17 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
             const int l = tid + r * NT;
             if (l < le) {
                 const T diff = sB[ie[r] & 0xFFFFu] - sB[ie[r] >> 16];
-                ve[r] = fma(ce[r], diff, ve[r]);
+                T e = ve[r];
+                if constexpr (SP) {
+                    if (spk[r] >= 0) {  // k_special's correction, same operations
+                        const T j = fma(sa[r], jr[r], sb[r] * e);
+                        jr[r] = j;
+                        const T dl = fma(sp.dt, j, sw[r] * sp.g[s - 1]);
+                        if (l < ti.n_own) sp.delta[int64_t(s - 1) * sp.nsp + spk[r]] = dl;
+                        e = e - dl;
+                    }
+                }
+                ve[r] = fma(ce[r], diff, e);
                 sE[l] = ve[r];
             }
         }
@@ -121,7 +166,12 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int l = tid + r * NT;
-        if (l < ti.n_own) Et_out[el_glob[ti.edge_off + l]] = ve[r];
+        if (l < ti.n_own) {
+            Et_out[el_glob[ti.edge_off + l]] = ve[r];
+            if constexpr (SP) {
+                if (spk[r] >= 0) sp.j_out[spk[r]] = jr[r];
+            }
+        }
     }
 }
 
@@ -131,13 +181,25 @@ struct Capacity {
 };
 constexpr Capacity kMenu[] = {{2, 3}, {3, 4}, {3, 5}, {4, 6}, {5, 7}, {6, 9}, {7, 10}, {8, 12}};
 
-template <typename T, int RT, int RE> void launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo) {
+// Tiles without any special edge (the plain class, listed first) run the plain kernel; the
+// few that hold one run the special variant, whose extra registers would otherwise lower the
+// occupancy of every tile.
+template <typename T, int RT, int RE>
+void launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo, const SpecialArgs<T> &sp) {
     Tiling &tg = *s.tiling;
     const size_t lds = size_t(tg.maxT + tg.maxE) * sizeof(T);
-    k_fused<T, kFusedThreads, RT, RE><<<int(tg.ntiles), kFusedThreads, lds, s.stream>>>(
-        K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
-        tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
-        tg.el_idx.as<uint32_t>());
+    const int64_t n_plain = tg.ntiles - tg.n_sp_tiles;
+    const int32_t *ids = tg.n_sp_tiles > 0 ? tg.tile_ids.as<int32_t>() : nullptr;
+    if (n_plain > 0)
+        k_fused<T, kFusedThreads, RT, RE, false><<<int(n_plain), kFusedThreads, lds, s.stream>>>(
+            K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
+            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
+            tg.el_idx.as<uint32_t>(), ids, SpecialArgs<T>{});
+    if (tg.n_sp_tiles > 0)
+        k_fused<T, kFusedThreads, RT, RE, true><<<int(tg.n_sp_tiles), kFusedThreads, lds, s.stream>>>(
+            K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
+            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
+            tg.el_idx.as<uint32_t>(), ids + n_plain, sp);
 }
 
 template <typename T> int upload_vec(Sim &s, DeviceBuffer &buf, const std::vector<T> &v) {
@@ -172,7 +234,7 @@ int refresh_tiling_coefficients(Sim &s) {
 // Cut the device numbering into tiles of `tile` consecutive triangles and record, for each,
 // its K rings of neighbours and the edges they need (see the file comment).
 int build_tiling(Sim &s, int K, int tile_tris) {
-    if (K < 2 || K > 8) return fail(TYEE_EINVAL, "fusion depth must be 2..8");
+    if (K < 2 || K > kMaxFusion) return fail(TYEE_EINVAL, "fusion depth must be 2..8");
     int device = 0, lds_limit = 65536;
     TYEE_HIP(hipGetDevice(&device));
     TYEE_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
@@ -334,13 +396,35 @@ int build_tiling(Sim &s, int K, int tile_tris) {
                 if ((w & 0xFFFFu) >= uint32_t(nT) || (w >> 16) >= uint32_t(nT))
                     return fail(TYEE_EINVAL, "internal: local triangle index out of range");
             }
-            if (ti.n_core > nT || ti.n_own > nE || nT > tg->maxT || nE > tg->maxE)
+            if (ti.n_core > nT || ti.n_own > ti.cntE[0] || nT > tg->maxT || nE > tg->maxE)
                 return fail(TYEE_EINVAL, "internal: tile counts out of range");
             for (int v = 1; v <= K; ++v)
                 if (ti.cntT[v] < ti.cntT[v - 1] || ti.cntE[v] < ti.cntE[v - 1])
                     return fail(TYEE_EINVAL, "internal: tile levels not nested");
         }
+        std::vector<int32_t> el_sp, ids;
+        if (s.n_special > 0) {
+            std::vector<int32_t> sp_of_slot(ne, -1);
+            for (int64_t k = 0; k < s.n_special; ++k) sp_of_slot[s.slot_e[s.sp_edge[k]]] = int32_t(k);
+            el_sp.resize(tg->h_el_glob.size());
+            for (size_t p = 0; p < el_sp.size(); ++p) el_sp[p] = sp_of_slot[tg->h_el_glob[p]];
+            tg->has_sp = true;
+            // tile classes: no special edge among a tile's local edges -> plain kernel
+            std::vector<int32_t> special_tiles;
+            for (int64_t t = 0; t < tg->ntiles; ++t) {
+                const TileInfo &ti = info[t];
+                bool any = false;
+                for (int32_t a = 0; a < ti.cntE[K - 1] && !any; ++a) any = el_sp[ti.edge_off + a] >= 0;
+                (any ? special_tiles : ids).push_back(int32_t(t));
+            }
+            tg->n_sp_tiles = int64_t(special_tiles.size());
+            ids.insert(ids.end(), special_tiles.begin(), special_tiles.end());
+            for (int32_t v : el_sp)
+                if (v >= int64_t(s.n_special)) return fail(TYEE_EINVAL, "internal: special index out of range");
+        }
         int rc = upload_vec(s, tg->info, info);
+        if (!rc && tg->has_sp) rc = upload_vec(s, tg->el_sp, el_sp);
+        if (!rc && tg->has_sp) rc = upload_vec(s, tg->tile_ids, ids);
         if (!rc) rc = upload_vec(s, tg->tl_glob, tg->h_tl_glob);
         if (!rc) rc = upload_vec(s, tg->tl_i0, ti0);
         if (!rc) rc = upload_vec(s, tg->tl_i1, ti1);
@@ -355,17 +439,33 @@ int build_tiling(Sim &s, int K, int tile_tris) {
 
 template <typename T> int launch_fused(Sim &s, int k) {
     Tiling &tg = *s.tiling;
+    if (k != tg.K || k < 2 || k > kMaxFusion) return fail(TYEE_EINVAL, "internal: fused depth mismatch");
+    if (tg.has_sp != (s.n_special > 0)) return fail(TYEE_EINVAL, "internal: tiling out of date with specials");
     const T *ei = s.Et_buf[s.cur].as<T>(), *bi = s.B_buf[s.cur].as<T>();
     T *eo = s.Et_buf[1 - s.cur].as<T>(), *bo = s.B_buf[1 - s.cur].as<T>();
+    SpecialArgs<T> sp{};
+    if (tg.has_sp) {
+        sp.el_sp = tg.el_sp.as<int32_t>();
+        sp.j_in = s.sp_j_buf[s.cur].as<T>();
+        sp.j_out = s.sp_j_buf[1 - s.cur].as<T>();
+        sp.ca = s.sp_ca.as<T>();
+        sp.cb = s.sp_cb.as<T>();
+        sp.w = s.sp_w.as<T>();
+        sp.delta = s.sp_delta.as<T>();
+        sp.nsp = int(s.n_special);
+        sp.dt = T(s.dt);
+        for (int q = 0; q < k; ++q)
+            sp.g[q] = T(waveform((double(s.step + q) + 0.5) * s.dt, s.src_omega, s.src_cycles));
+    }
     switch (tg.rt * 100 + tg.re) {
-    case 203: launch_one<T, 2, 3>(s, k, ei, bi, eo, bo); break;
-    case 304: launch_one<T, 3, 4>(s, k, ei, bi, eo, bo); break;
-    case 305: launch_one<T, 3, 5>(s, k, ei, bi, eo, bo); break;
-    case 406: launch_one<T, 4, 6>(s, k, ei, bi, eo, bo); break;
-    case 507: launch_one<T, 5, 7>(s, k, ei, bi, eo, bo); break;
-    case 609: launch_one<T, 6, 9>(s, k, ei, bi, eo, bo); break;
-    case 710: launch_one<T, 7, 10>(s, k, ei, bi, eo, bo); break;
-    case 812: launch_one<T, 8, 12>(s, k, ei, bi, eo, bo); break;
+    case 203: launch_one<T, 2, 3>(s, k, ei, bi, eo, bo, sp); break;
+    case 304: launch_one<T, 3, 4>(s, k, ei, bi, eo, bo, sp); break;
+    case 305: launch_one<T, 3, 5>(s, k, ei, bi, eo, bo, sp); break;
+    case 406: launch_one<T, 4, 6>(s, k, ei, bi, eo, bo, sp); break;
+    case 507: launch_one<T, 5, 7>(s, k, ei, bi, eo, bo, sp); break;
+    case 609: launch_one<T, 6, 9>(s, k, ei, bi, eo, bo, sp); break;
+    case 710: launch_one<T, 7, 10>(s, k, ei, bi, eo, bo, sp); break;
+    case 812: launch_one<T, 8, 12>(s, k, ei, bi, eo, bo, sp); break;
     default: return fail(TYEE_EINVAL, "internal: no fused kernel for this capacity");
     }
     s.cur = 1 - s.cur;

@@ -70,17 +70,23 @@ __global__ __launch_bounds__(256) void k_special(int n, const int32_t *__restric
     Et[e] = e_old - dl;
 }
 
-// Nodal charge by continuity: Q_v -= sum over its special edges of coef * delta.
+// Nodal charge by continuity: Q_v -= sum over its special edges of coef * delta, once per
+// step for `steps` consecutive steps whose decrements are stored `stride` apart.
 template <typename T>
 __global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict__ node,
                                                 const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
                                                 const T *__restrict__ coef, const T *__restrict__ delta,
-                                                T *__restrict__ Q) {
+                                                int steps, int stride, T *__restrict__ Q) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    T acc = T(0);
-    for (int r = off[k]; r < off[k + 1]; ++r) acc = fma(coef[r], delta[inc[r]], acc);
-    Q[node[k]] -= acc;
+    T q = Q[node[k]];
+    for (int s = 0; s < steps; ++s) {
+        const T *dl = delta + int64_t(s) * stride;
+        T acc = T(0);
+        for (int r = off[k]; r < off[k + 1]; ++r) acc = fma(coef[r], dl[inc[r]], acc);
+        q -= acc;
+    }
+    Q[node[k]] = q;
 }
 
 // Probe: copy field values at the listed device slots into one row of the sample buffer.
@@ -110,8 +116,9 @@ inline void launch_special(hipStream_t s, int64_t n, const int32_t *slot, T *Et,
 
 template <typename T>
 inline void launch_charge(hipStream_t s, int64_t n, const int32_t *node, const int32_t *off, const int32_t *inc,
-                          const T *coef, const T *delta, T *Q) {
-    if (n > 0) k_charge<T><<<int((n + 255) / 256), 256, 0, s>>>(int(n), node, off, inc, coef, delta, Q);
+                          const T *coef, const T *delta, int steps, int stride, T *Q) {
+    if (n > 0)
+        k_charge<T><<<int((n + 255) / 256), 256, 0, s>>>(int(n), node, off, inc, coef, delta, steps, stride, Q);
 }
 
 }  // namespace tyee

@@ -154,12 +154,15 @@ int rebuild_specials(Sim &s) {
         w[which[i]] += s.dt * s.scale(i) * s.src_w[r];
     }
     int rc = upload_raw(s.sp_slot, slot, s.stream);
-    if (!rc) rc = upload_field(s, s.sp_j, zero);
+    for (int b = 0; b < 2 && !rc; ++b) rc = upload_field(s, s.sp_j_buf[b], zero);
     if (!rc) rc = upload_field(s, s.sp_ca, ca);
     if (!rc) rc = upload_field(s, s.sp_cb, cb);
     if (!rc) rc = upload_field(s, s.sp_w, w);
-    if (!rc) rc = upload_field(s, s.sp_delta, zero);
+    if (!rc) rc = upload_field(s, s.sp_delta, std::vector<double>(size_t(n) * kMaxFusion, 0.0));
     if (rc) return rc;
+    // the fused tiles carry each local edge's special-list index: rebuild them lazily
+    s.tiling.reset();
+    s.graph_dirty = true;
 
     // node incidences: Q_k -= sum sigma(k,i) d_i/scale_i * delta_i  (delta = dt scale (j + Jsrc))
     std::vector<std::vector<std::pair<int32_t, double>>> inc(s.nv);
@@ -195,12 +198,6 @@ int rebuild_specials(Sim &s) {
     return rc;
 }
 
-double waveform(double t, double omega, double cycles) {
-    const double T = cycles * 2.0 * M_PI / omega;
-    if (!(t >= 0.0 && t < T)) return 0.0;
-    const double s = std::sin(M_PI * t / T);
-    return std::sin(omega * t) * s * s;
-}
 
 // Launch one kernel kind, bracketed by timing events when that kind is profiled.
 template <typename F> int timed(Sim &s, int kind, F &&launch) {
@@ -217,7 +214,7 @@ template <typename T> const T *probe_source(Sim &s, const Probe &p) {
     switch (p.field) {
     case TYEE_FIELD_E: return s.Et().as<T>();
     case TYEE_FIELD_B: return s.B().as<T>();
-    case TYEE_FIELD_J: return s.sp_j.as<T>();
+    case TYEE_FIELD_J: return s.sp_j().as<T>();
     default: return s.Q.as<T>();
     }
 }
@@ -283,11 +280,12 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
     int rc = TYEE_OK;
     while (done < n && !rc) {
         T *Et = s.Et().as<T>(), *B = s.B().as<T>();
-        int k = 1;
-        if (special) {
+        int k = s.fusion;
+        if (k > n - done || k > steps_to_next_sample(s)) k = 1;  // remainder: single steps
+        if (special && k == 1) {
             const double g = waveform((double(s.step) + 0.5) * s.dt, s.src_omega, s.src_cycles);
             rc = timed(s, TYEE_KERNEL_SPECIAL, [&] {
-                launch_special<T>(s.stream, s.n_special, s.sp_slot.as<int32_t>(), Et, s.sp_j.as<T>(),
+                launch_special<T>(s.stream, s.n_special, s.sp_slot.as<int32_t>(), Et, s.sp_j().as<T>(),
                                   s.sp_ca.as<T>(), s.sp_cb.as<T>(), s.sp_w.as<T>(), s.sp_delta.as<T>(),
                                   T(g), T(s.dt));
                 return TYEE_OK;
@@ -295,16 +293,15 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
             if (!rc && s.n_qnode > 0)
                 rc = timed(s, TYEE_KERNEL_CHARGE, [&] {
                     launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(),
-                                     s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(),
-                                     s.Q.as<T>());
+                                     s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(), 1,
+                                     int(s.n_special), s.Q.as<T>());
                     return TYEE_OK;
                 });
-        } else {
-            k = s.fusion;
-            if (k > n - done || k > steps_to_next_sample(s)) k = 1;  // remainder: single steps
         }
         if (rc) break;
-        if (k > 1 && s.graph_launches > 0 && k == s.fusion && !s.timer_wants_kernels()) {
+        // graphs replay fixed arguments: the source waveform changes every step, so runs with
+        // special edges launch the fused kernel eagerly
+        if (k > 1 && !special && s.graph_launches > 0 && k == s.fusion && !s.timer_wants_kernels()) {
             const int64_t span = int64_t(k) * s.graph_launches;
             if (n - done >= span && steps_to_next_sample(s) >= span) {
                 if (!s.tiling || s.tiling->K != k) {
@@ -337,6 +334,13 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
         }
         if (k > 1) {
             rc = timed(s, TYEE_KERNEL_FUSED, [&] { return launch_fused<T>(s, k); });
+            if (!rc && special && s.n_qnode > 0)
+                rc = timed(s, TYEE_KERNEL_CHARGE, [&] {
+                    launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(),
+                                     s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(), k,
+                                     int(s.n_special), s.Q.as<T>());
+                    return TYEE_OK;
+                });
         } else {
             rc = timed(s, TYEE_KERNEL_EDGE, [&] {
                 launch_edge<T>(s.stream, s.ne, ge, Et, B, cE, RL);
@@ -482,7 +486,7 @@ int tyee_sim_set_state(tyee_sim *sim, int32_t field, const double *host) {
         for (int64_t i = 0; i < s.ne; ++i)
             if (!listed[i] && host[i] != 0.0) return fail(TYEE_EINVAL, "current on a non-plasma edge");
         if (s.n_special == 0) return TYEE_OK;
-        return tyee::upload_field(s, s.sp_j, dev);
+        return tyee::upload_field(s, s.sp_j(), dev);
     }
     case TYEE_FIELD_Q:
         dev.assign(host, host + s.nv);
@@ -512,7 +516,7 @@ int tyee_sim_get_state(tyee_sim *sim, int32_t field, double *host) {
     case TYEE_FIELD_J:
         std::fill(host, host + s.ne, 0.0);
         if (s.n_special == 0) return TYEE_OK;
-        if ((rc = tyee::download_field(s, s.sp_j, dev, s.n_special))) return rc;
+        if ((rc = tyee::download_field(s, s.sp_j(), dev, s.n_special))) return rc;
         for (int64_t k = 0; k < s.n_special; ++k)
             if (s.sp_plasma[k]) host[s.sp_edge[k]] = dev[k] / s.scale(s.sp_edge[k]);
         return TYEE_OK;
@@ -708,7 +712,7 @@ int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *t
     return TYEE_OK;
 }
 
-int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]) {
+int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[6]) {
     if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
     const tyee::Sim &s = sim->s;
     out[0] = s.fusion;
@@ -717,6 +721,7 @@ int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[5]) {
     out[2] = built ? s.tiling->ntiles : 0;
     out[3] = built ? s.tiling->sumT : 0;
     out[4] = built ? s.tiling->sumE : 0;
+    out[5] = built ? s.tiling->n_sp_tiles : 0;
     return TYEE_OK;
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <cstdint>
 #include <memory>
@@ -124,6 +126,16 @@ struct LaunchTimer {
 
 struct Tiling;
 
+constexpr int kMaxFusion = 8;  // largest number of steps one fused launch advances
+
+// Soft-source waveform g(t) = sin(omega t) sin^2(pi t / T) for 0 <= t < T, T = cycles 2 pi/omega.
+inline double waveform(double t, double omega, double cycles) {
+    const double T = cycles * 2.0 * M_PI / omega;
+    if (!(t >= 0.0 && t < T)) return 0.0;
+    const double s = std::sin(M_PI * t / T);
+    return std::sin(omega * t) * s * s;
+}
+
 struct Probe {
     int32_t field = 0;
     int64_t n = 0, every = 1, capacity = 0, taken = 0;
@@ -172,7 +184,9 @@ struct Sim {
     int64_t n_special = 0;
     std::vector<int32_t> sp_edge;  // canonical edge of each special entry
     std::vector<uint8_t> sp_plasma;
-    DeviceBuffer sp_slot, sp_j, sp_ca, sp_cb, sp_w, sp_delta;
+    DeviceBuffer sp_slot, sp_j_buf[2], sp_ca, sp_cb, sp_w;
+    DeviceBuffer sp_delta;         // [steps of one launch][n_special] decrements, for the charge
+    DeviceBuffer &sp_j() { return sp_j_buf[cur]; }  // current flips with the field buffers
     // nodal charge
     int64_t n_qnode = 0;
     DeviceBuffer Q, q_node, q_off, q_inc, q_coef;
@@ -203,6 +217,10 @@ struct Tiling {
     int K = 0, tile = 0, threads = 0, rt = 0, re = 0;
     int64_t ntiles = 0, maxT = 0, maxE = 0, sumT = 0, sumE = 0;
     DeviceBuffer info, tl_glob, tl_coef, tl_i0, tl_i1, el_glob, el_coef, el_idx;
+    DeviceBuffer el_sp;     // special-list index of each local edge, -1 if none (when specials exist)
+    DeviceBuffer tile_ids;  // plain-class tiles, then tiles holding a special edge
+    int64_t n_sp_tiles = 0;
+    bool has_sp = false;
     std::vector<int32_t> h_tl_glob, h_el_glob;  // local cell -> device slot (for coefficient refresh)
 };
 

@@ -364,10 +364,10 @@ class Sim:
         self.graph_launches = int(launches)
 
     def fusion_info(self):
-        out = np.zeros(5, np.int64)
+        out = np.zeros(6, np.int64)
         _check(lib.tyee_sim_get_fusion(self._h, _ptr(out)))
-        return dict(zip(["steps_per_launch", "tile", "tiles", "local_tris", "local_edges"],
-                        (int(v) for v in out)))
+        return dict(zip(["steps_per_launch", "tile", "tiles", "local_tris", "local_edges",
+                         "special_tiles"], (int(v) for v in out)))
 
     def fusion_used(self):
         return self.fusion_info()["steps_per_launch"]

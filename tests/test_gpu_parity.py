@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from meshgen import (lattice_mesh, make_workload, triangle_particle_mask, line_source_pairs,
-                     scramble)
+                     scramble, plasma_workload)
 from common import rel_l2, cavity_state, packet_state
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +34,7 @@ def _pair(xy, tri, periodic):
 
 
 def run_gpu(ty, xy, tri, periodic, dt, E0_fn, steps, prec, order="none", seed=0, fusion=1,
-            media=None, source=None, gamma=None, chunks=1, tile=0):
+            media=None, source=None, gamma=None, chunks=1, tile=0, want_info=False):
     m = ty.Mesh(xy, tri, periodic)
     m.reorder(order, seed)
     view = m.view()
@@ -52,6 +52,8 @@ def run_gpu(ty, xy, tri, periodic, dt, E0_fn, steps, prec, order="none", seed=0,
     for c in range(chunks):
         sim.step(steps // chunks + (steps % chunks if c == chunks - 1 else 0))
     out = {f: sim.get_state(f) for f in ("E", "B", "J", "Q")}
+    if want_info:
+        return out, view, sim.fusion_info()
     return out, view
 
 
@@ -132,6 +134,35 @@ def test_plasma_and_source(ty, prec, tol):
     for f in ("E", "B", "J", "Q"):
         assert rel_l2(got[f], ref[f]) < tol, f
     assert np.max(np.abs(ref["Q"])) > 0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("fusion,tile,chunks", [(2, 0, 1), (4, 0, 3), (8, 1024, 1), (4, 256, 2)])
+def test_plasma_fused_bit_identical(ty, prec, fusion, tile, chunks):
+    # conforming particle and line source: the fused launch splits tiles into a plain class
+    # and a class holding special edges; every field, the current and the charge must equal
+    # the single-step launches bit for bit (203 steps: fused launches plus single-step tails)
+    w = plasma_workload(64)
+    n, xy, tri = w["n"], w["xy"], w["tri"]
+    _note(f"case: plasma{n} {prec} fusion={fusion} tile={tile} chunks={chunks} bit-exactness")
+    om = oracle.OracleMesh(xy, tri, True)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    fn = lambda side: packet_state(side, dt, n, cells=8.0)
+    media = (w["wp2_tri"], w["nu"])
+    src = (w["src_pairs"], w["src_weights"], w["src_omega"], w["src_cycles"])
+    base, _ = run_gpu(ty, xy, tri, True, dt, fn, 203, prec, order="morton", fusion=1,
+                      media=media, source=src)
+    got, _, info = run_gpu(ty, xy, tri, True, dt, fn, 203, prec, order="morton", fusion=fusion,
+                           media=media, source=src, tile=tile, chunks=chunks, want_info=True)
+    assert info["steps_per_launch"] == fusion
+    assert 0 < info["special_tiles"] < info["tiles"] or info["tiles"] == 1
+    for f in ("E", "B", "J", "Q"):
+        assert np.array_equal(got[f], base[f]), f
+    ref = om.step(*fn(om), dt, 203, wp2=om.edge_wp2(w["wp2_tri"]), nu=w["nu"], src=src)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    for f in ("E", "B", "J", "Q"):
+        assert rel_l2(got[f], ref[f]) < tol, f
+    assert np.max(np.abs(ref["J"])) > 0 and np.max(np.abs(ref["Q"])) > 0
 
 
 def test_edge_scale_fp64(ty):
