@@ -12,6 +12,7 @@ and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -52,10 +53,19 @@ def parse():
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (for counter calibration)")
+    p.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                          "COPY_WRITE_DIR"),
+                   help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs of this bench "
+                        "and of --copy-calibration into the stored traffic figure of k_fused "
+                        "for --workload, then exit (no GPU use)")
     return p.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_fused_torus1415_f32.json")
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_k_fused_{workload}_f32.json")
+
+
+COPY_BYTES = 128 * 1024 * 1024 * 4     # --copy-calibration: bytes read and written per copy
 KERNEL_SOURCES = ["paper_1812_01448_amd/csrc/fused.hip", "paper_1812_01448_amd/csrc/kernels.hpp",
                   "paper_1812_01448_amd/csrc/sim.hpp"]
 
@@ -69,10 +79,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, config):
+def measured_traffic(kernel, config, workload="torus1415"):
     """HBM bytes per launch from the committed counter summary, if it still applies."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -94,6 +104,79 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+def _pmc_values(folder, counter):
+    """{kernel name: [counter value per dispatch]} from a rocprofv3 --pmc csv folder."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter:
+                    out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def traffic_summary(args):
+    """Scaled HBM bytes per fused launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch).
+
+    Each counter is scaled by what it reads for the calibration copy (COPY_BYTES read and
+    written per dispatch). A fused launch is one dispatch of k_fused per tile class, so its
+    traffic is the sum over the k_fused kernels of their median per-dispatch values."""
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = args.traffic_summary
+
+    def copy_kib(folder, counter):
+        vals = sorted(v for k, vs in _pmc_values(folder, counter).items() if "copyBuffer" in k
+                      for v in vs)
+        big = vals[-5:]                       # the five 512 MiB copies
+        return float(np.median(big))
+
+    cf, cw = copy_kib(cfetch_dir, "FETCH_SIZE"), copy_kib(cwrite_dir, "WRITE_SIZE")
+    fetch_scale, write_scale = COPY_BYTES / 1024 / cf, COPY_BYTES / 1024 / cw
+    per = {}
+    for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        for name, vals in _pmc_values(folder, counter).items():
+            if "k_fused" in name:
+                per.setdefault(name, {})[counter] = (float(np.median(vals)), len(vals),
+                                                     float(min(vals)), float(max(vals)))
+    fetch = sum(v["FETCH_SIZE"][0] for v in per.values())
+    write = sum(v["WRITE_SIZE"][0] for v in per.values())
+    total = fetch * 1024 * fetch_scale + write * 1024 * write_scale
+    cfg = {"torus1415": {"triangles": 4004450, "steps_per_launch": 4, "tile_tris": 2048,
+                         "prec": "f32", "order": "morton"},
+           "plasma2830": {"triangles": 16017830, "steps_per_launch": 4, "tile_tris": 2048,
+                          "prec": "f32", "order": "morton"}}[args.workload]
+    out = {"kernel": "k_fused", "workload": args.workload, "source_hash": kernel_source_hash(),
+           "config": cfg, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": round(fetch_scale, 6), "write_scale": round(write_scale, 6),
+           "per_kernel": {re.search(r"k_fused<[^>]*>", k).group(0): v for k, v in per.items()},
+           "fetch_kib_per_launch_raw": fetch, "write_kib_per_launch_raw": write,
+           "bytes_per_launch": int(round(total))}
+    with open(traffic_file(args.workload), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+def measure_copy_bandwidth():
+    """Device-to-device copy rate (bytes read + written per second) of a 512 MiB buffer,
+    the achievable-bandwidth reference beside the published HBM peak."""
+    import torch
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        y.copy_(x)
+    b.record()
+    b.synchronize()
+    gbs = 2 * COPY_BYTES * 10 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -102,6 +185,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.traffic_summary:
+        traffic_summary(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -199,6 +285,11 @@ def main():
             "triangles": nt, "steps_per_launch": K, "tile_tris": fuse["tile"], "prec": args.prec,
             "order": args.order})
 
+    roofline["copy_GBs"] = measure_copy_bandwidth()
+    if roofline.get("traffic"):
+        roofline["traffic_GBs"] = round(roofline["traffic"] / (avg_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac_of_copy"] = round(roofline["traffic_GBs"] / roofline["copy_GBs"], 4)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(xy, tri, dt, E0, B0, args.cpu_steps, view)
@@ -261,7 +352,7 @@ def bench_plasma(args):
     torch.cuda.synchronize()
     # an untimed profiled pass names the dominant kernel; the timed region then brackets
     # only that kernel's launches with HIP events
-    kinds = ["fused", "charge"] if K > 1 else ["edge", "tri", "special", "charge"]
+    kinds = ["fused"] if K > 1 else ["edge", "tri", "special", "charge"]
     sim.set_profiling(True, kinds=kinds)
     sim.step(max(20, min(200, args.steps // 10)))
     sim.sync()
@@ -295,13 +386,12 @@ def bench_plasma(args):
     # special: slot + j r/w + two Drude coefficients + source weight; charge: node, offset,
     # Q r/w, and per incidence its edge and coefficient
     bytes_special = n_special * (4 + 5 * esz)
-    bytes_charge = len(nodes) * (8 + 2 * esz) + n_inc * (4 + esz)
-    # one fused launch (plain-class and special-class tiles) advances K whole steps; its
-    # charge kernel then applies the K steps' decrements
-    algo = {"edge": bytes_edge, "tri": bytes_tri, "special": bytes_special,
-            "charge": bytes_charge if K == 1 else bytes_charge + (K - 1) * n_inc * esz,
-            "fused": K * (bytes_edge + bytes_tri + bytes_special)}
-    step_bytes = bytes_edge + bytes_tri + bytes_special + bytes_charge
+    bytes_charge = len(nodes) * (8 + 2 * esz) + n_inc * (4 + esz)    # plus esz per decrement read
+    # one fused launch (plain-class tiles, special-class tiles and the charge update of its
+    # K steps, which reads each step's decrements) advances K whole steps
+    algo = {"edge": bytes_edge, "tri": bytes_tri, "special": bytes_special, "charge": bytes_charge,
+            "fused": K * (bytes_edge + bytes_tri + bytes_special) + bytes_charge + K * n_inc * esz}
+    step_bytes = bytes_edge + bytes_tri + bytes_special + bytes_charge + n_inc * esz
     avg_ms = prof[dom]["total_ms"] / prof[dom]["count"]
     achieved = algo[dom] / (avg_ms * 1e-3) / 1e9
     cells = ne + nt
@@ -321,15 +411,24 @@ def bench_plasma(args):
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": prof[dom]["name"], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_fused", {
+                         "triangles": nt, "steps_per_launch": K, "tile_tris": fuse["tile"],
+                         "prec": args.prec, "order": args.order}, "plasma2830")
+                     if dom == "fused" else None,
                      "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": algo[dom],
                      "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)},
+        "copy_GBs": measure_copy_bandwidth(),
         "kernels": {kk: {"name": v["name"], "count": v["count"],
                          "avg_ms": round(v["total_ms"] / max(1, v["count"]), 5),
                          "algorithmic_GBs": round(algo[kk] / (v["total_ms"] / max(1, v["count"])
                                                                * 1e-3) / 1e9, 1)}
                     for kk, v in prof_all.items()},
     }
+    tr = out["roofline"]["traffic"]
+    if tr:
+        out["roofline"]["traffic_GBs"] = round(tr / (avg_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac_of_copy"] = round(out["roofline"]["traffic_GBs"] / out["copy_GBs"], 4)
     print(json.dumps(out), flush=True)
 
 

@@ -183,9 +183,11 @@ constexpr Capacity kMenu[] = {{2, 3}, {3, 4}, {3, 5}, {4, 6}, {5, 7}, {6, 9}, {7
 
 // Tiles without any special edge (the plain class, listed first) run the plain kernel; the
 // few that hold one run the special variant, whose extra registers would otherwise lower the
-// occupancy of every tile.
+// occupancy of every tile.  Both read the "in" buffers and write disjoint cells of the "out"
+// buffers.  The charge update of the K steps follows; it reads only the decrements the
+// special-class tiles wrote.
 template <typename T, int RT, int RE>
-void launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo, const SpecialArgs<T> &sp) {
+int launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo, const SpecialArgs<T> &sp) {
     Tiling &tg = *s.tiling;
     const size_t lds = size_t(tg.maxT + tg.maxE) * sizeof(T);
     const int64_t n_plain = tg.ntiles - tg.n_sp_tiles;
@@ -195,11 +197,15 @@ void launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo, const Spe
             K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
             tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
             tg.el_idx.as<uint32_t>(), ids, SpecialArgs<T>{});
-    if (tg.n_sp_tiles > 0)
+    if (tg.n_sp_tiles > 0) {
         k_fused<T, kFusedThreads, RT, RE, true><<<int(tg.n_sp_tiles), kFusedThreads, lds, s.stream>>>(
             K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
             tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
             tg.el_idx.as<uint32_t>(), ids + n_plain, sp);
+        launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(), s.q_inc.as<int32_t>(),
+                         s.q_coef.as<T>(), s.sp_delta.as<T>(), K, int(s.n_special), s.Q.as<T>());
+    }
+    return TYEE_OK;
 }
 
 template <typename T> int upload_vec(Sim &s, DeviceBuffer &buf, const std::vector<T> &v) {
@@ -457,17 +463,19 @@ template <typename T> int launch_fused(Sim &s, int k) {
         for (int q = 0; q < k; ++q)
             sp.g[q] = T(waveform((double(s.step + q) + 0.5) * s.dt, s.src_omega, s.src_cycles));
     }
+    int rc;
     switch (tg.rt * 100 + tg.re) {
-    case 203: launch_one<T, 2, 3>(s, k, ei, bi, eo, bo, sp); break;
-    case 304: launch_one<T, 3, 4>(s, k, ei, bi, eo, bo, sp); break;
-    case 305: launch_one<T, 3, 5>(s, k, ei, bi, eo, bo, sp); break;
-    case 406: launch_one<T, 4, 6>(s, k, ei, bi, eo, bo, sp); break;
-    case 507: launch_one<T, 5, 7>(s, k, ei, bi, eo, bo, sp); break;
-    case 609: launch_one<T, 6, 9>(s, k, ei, bi, eo, bo, sp); break;
-    case 710: launch_one<T, 7, 10>(s, k, ei, bi, eo, bo, sp); break;
-    case 812: launch_one<T, 8, 12>(s, k, ei, bi, eo, bo, sp); break;
+    case 203: rc = launch_one<T, 2, 3>(s, k, ei, bi, eo, bo, sp); break;
+    case 304: rc = launch_one<T, 3, 4>(s, k, ei, bi, eo, bo, sp); break;
+    case 305: rc = launch_one<T, 3, 5>(s, k, ei, bi, eo, bo, sp); break;
+    case 406: rc = launch_one<T, 4, 6>(s, k, ei, bi, eo, bo, sp); break;
+    case 507: rc = launch_one<T, 5, 7>(s, k, ei, bi, eo, bo, sp); break;
+    case 609: rc = launch_one<T, 6, 9>(s, k, ei, bi, eo, bo, sp); break;
+    case 710: rc = launch_one<T, 7, 10>(s, k, ei, bi, eo, bo, sp); break;
+    case 812: rc = launch_one<T, 8, 12>(s, k, ei, bi, eo, bo, sp); break;
     default: return fail(TYEE_EINVAL, "internal: no fused kernel for this capacity");
     }
+    if (rc) return rc;
     s.cur = 1 - s.cur;
     return TYEE_OK;
 }

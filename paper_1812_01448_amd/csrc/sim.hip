@@ -333,14 +333,8 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
             if (rc) break;
         }
         if (k > 1) {
+            // with special edges this also advances the nodal charge
             rc = timed(s, TYEE_KERNEL_FUSED, [&] { return launch_fused<T>(s, k); });
-            if (!rc && special && s.n_qnode > 0)
-                rc = timed(s, TYEE_KERNEL_CHARGE, [&] {
-                    launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(),
-                                     s.q_inc.as<int32_t>(), s.q_coef.as<T>(), s.sp_delta.as<T>(), k,
-                                     int(s.n_special), s.Q.as<T>());
-                    return TYEE_OK;
-                });
         } else {
             rc = timed(s, TYEE_KERNEL_EDGE, [&] {
                 launch_edge<T>(s.stream, s.ne, ge, Et, B, cE, RL);
