@@ -11,6 +11,9 @@
 //   - field values in LDS (they are exchanged between work-items each half-step),
 //   - coefficients and local neighbour indices in VGPRs (each work-item keeps its cells),
 // so HBM sees one read of the tile's cells and one write of its own cells per K steps.
+// Core triangles are a run of device slots, and so are the owned edges under the Morton and
+// RCM numberings (edges numbered by first appearance over the triangles): their slots are
+// computed, only halo cells carry a stored slot.
 // Work-groups read the "in" buffers and write the "out" buffers, so a tile never sees a
 // neighbour's already-advanced values; the runtime swaps the two buffers after each launch.
 // The per-cell arithmetic is exactly that of k_edge / k_tri (same fma, same q order), so any
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
                                               const T *__restrict__ Et_in, const T *__restrict__ B_in,
                                               T *__restrict__ Et_out, T *__restrict__ B_out,
                                               const int32_t *__restrict__ tl_glob, const T *__restrict__ tl_coef,
-                                              const uint32_t *__restrict__ tl_i0, const uint32_t *__restrict__ tl_i1,
+                                              const uint32_t *__restrict__ tl_i0, const uint16_t *__restrict__ tl_i1,
                                               const int32_t *__restrict__ el_glob, const T *__restrict__ el_coef,
                                               const uint32_t *__restrict__ el_idx,
                                               const int32_t *__restrict__ tile_ids, const SpecialArgs<T> sp) {
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
         i1[r] = 0;
         if (l < nT) {
             const int p = ti.tri_off + l;
-            vb[r] = B_in[tl_glob[p]];
+            vb[r] = B_in[l < ti.n_core ? ti.core_base + l : tl_glob[p]];
             cb[r] = tl_coef[p];
             i0[r] = tl_i0[p];
             i1[r] = tl_i1[p];
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
         jr[r] = sa[r] = sb[r] = sw[r] = T(0);
         if (l < nE) {
             const int p = ti.edge_off + l;
-            ve[r] = Et_in[el_glob[p]];
+            ve[r] = Et_in[(ti.own_base >= 0 && l < ti.n_own) ? ti.own_base + l : el_glob[p]];
             ce[r] = el_coef[p];
             ie[r] = el_idx[p];
             sE[l] = ve[r];
@@ -161,13 +164,13 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
         const int l = tid + r * NT;
-        if (l < ti.n_core) B_out[tl_glob[ti.tri_off + l]] = vb[r];
+        if (l < ti.n_core) B_out[ti.core_base + l] = vb[r];
     }
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int l = tid + r * NT;
         if (l < ti.n_own) {
-            Et_out[el_glob[ti.edge_off + l]] = ve[r];
+            Et_out[ti.own_base >= 0 ? ti.own_base + l : el_glob[ti.edge_off + l]] = ve[r];
             if constexpr (SP) {
                 if (spk[r] >= 0) sp.j_out[spk[r]] = jr[r];
             }
@@ -195,12 +198,12 @@ int launch_one(Sim &s, int K, const T *ei, const T *bi, T *eo, T *bo, const Spec
     if (n_plain > 0)
         k_fused<T, kFusedThreads, RT, RE, false><<<int(n_plain), kFusedThreads, lds, s.stream>>>(
             K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
-            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
+            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint16_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
             tg.el_idx.as<uint32_t>(), ids, SpecialArgs<T>{});
     if (tg.n_sp_tiles > 0) {
         k_fused<T, kFusedThreads, RT, RE, true><<<int(tg.n_sp_tiles), kFusedThreads, lds, s.stream>>>(
             K, int(tg.maxT), tg.info.as<TileInfo>(), ei, bi, eo, bo, tg.tl_glob.as<int32_t>(), tg.tl_coef.as<T>(),
-            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint32_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
+            tg.tl_i0.as<uint32_t>(), tg.tl_i1.as<uint16_t>(), tg.el_glob.as<int32_t>(), tg.el_coef.as<T>(),
             tg.el_idx.as<uint32_t>(), ids + n_plain, sp);
         launch_charge<T>(s.stream, s.n_qnode, s.q_node.as<int32_t>(), s.q_off.as<int32_t>(), s.q_inc.as<int32_t>(),
                          s.q_coef.as<T>(), s.sp_delta.as<T>(), K, int(s.n_special), s.Q.as<T>());
@@ -277,7 +280,8 @@ int build_tiling(Sim &s, int K, int tile_tris) {
         tg->ntiles = (nt + tile - 1) / tile;
         std::vector<TileInfo> info(tg->ntiles);
         std::vector<int32_t> level(nt, -1), local_t(nt, -1), local_e(ne, -1);
-        std::vector<uint32_t> ti0, ti1, eidx;
+        std::vector<uint32_t> ti0, eidx;
+        std::vector<uint16_t> ti1;
         bool too_big = false;
         for (int64_t t = 0; t < tg->ntiles && !too_big; ++t) {
             const int32_t c0 = int32_t(t * tile), c1 = int32_t(std::min<int64_t>(nt, (t + 1) * tile));
@@ -334,6 +338,10 @@ int build_tiling(Sim &s, int K, int tile_tris) {
             TileInfo &ti = info[t];
             ti.n_core = c1 - c0;
             ti.n_own = n_own;
+            ti.core_base = c0;
+            ti.own_base = n_own > 0 ? edges[0].second : -1;
+            for (int32_t a = 0; a < n_own && ti.own_base >= 0; ++a)
+                if (edges[a].second != ti.own_base + a) ti.own_base = -1;  // not a run: stored slots
             ti.tri_off = int32_t(tg->h_tl_glob.size());
             ti.edge_off = int32_t(tg->h_el_glob.size());
             for (int v = 0; v <= 8; ++v) {
@@ -348,7 +356,7 @@ int build_tiling(Sim &s, int K, int tile_tris) {
                     for (int q = 0; q < 3; ++q)
                         h[q] = uint32_t(local_e[eslot[3 * k + q]]) | (esgn[3 * k + q] < 0 ? 0x8000u : 0u);
                 ti0.push_back(h[0] | (h[1] << 16));
-                ti1.push_back(h[2]);
+                ti1.push_back(uint16_t(h[2]));
             }
             for (auto &e : edges) {
                 const int32_t m = e.second;
@@ -393,12 +401,16 @@ int build_tiling(Sim &s, int K, int tile_tris) {
             const int32_t nT = ti.cntT[K], nE = ti.cntE[K - 1];
             for (int32_t a = 0; a < nT; ++a) {
                 const uint32_t w0 = ti0[ti.tri_off + a], w1 = ti1[ti.tri_off + a];
+                if (a < ti.n_core && tg->h_tl_glob[ti.tri_off + a] != ti.core_base + a)
+                    return fail(TYEE_EINVAL, "internal: core triangles are not a run of slots");
                 if ((w0 & 0x7FFFu) >= uint32_t(nE) || ((w0 >> 16) & 0x7FFFu) >= uint32_t(nE) ||
                     (w1 & 0x7FFFu) >= uint32_t(nE))
                     return fail(TYEE_EINVAL, "internal: local edge index out of range");
             }
             for (int32_t a = 0; a < nE; ++a) {
                 const uint32_t w = eidx[ti.edge_off + a];
+                if (a < ti.n_own && ti.own_base >= 0 && tg->h_el_glob[ti.edge_off + a] != ti.own_base + a)
+                    return fail(TYEE_EINVAL, "internal: owned edges are not a run of slots");
                 if ((w & 0xFFFFu) >= uint32_t(nT) || (w >> 16) >= uint32_t(nT))
                     return fail(TYEE_EINVAL, "internal: local triangle index out of range");
             }

@@ -205,10 +205,12 @@ struct Sim {
 
 // Temporal tiling for the fused K-step kernel (built by fused.hip).
 struct TileInfo {
-    int32_t n_core;      // core triangles are local [0, n_core)
+    int32_t n_core;      // core triangles are local [0, n_core), device slots core_base + l
     int32_t n_own;       // owned edges are local [0, n_own)
     int32_t tri_off;     // offset of this tile in the packed triangle arrays
     int32_t edge_off;    // offset of this tile in the packed edge arrays
+    int32_t core_base;   // device slot of the first core triangle
+    int32_t own_base;    // device slot of the first owned edge when they are contiguous, else -1
     int32_t cntT[9];     // local triangles with ring level <= m
     int32_t cntE[9];     // local edges with level <= m
 };
