@@ -71,7 +71,12 @@ __global__ __launch_bounds__(256) void k_special(int n, const int32_t *__restric
 }
 
 // Nodal charge by continuity: Q_v -= sum over its special edges of coef * delta, once per
-// step for `steps` consecutive steps whose decrements are stored `stride` apart.
+// step for `steps` consecutive steps whose decrements are stored `stride` apart.  A node
+// with up to kChargeRegs incidences keeps them in registers and issues all its decrement
+// loads before the arithmetic (the loads are independent; only the sums are ordered); the
+// sums run in incidence order either way, so the result does not depend on the path.
+constexpr int kChargeRegs = 12;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict__ node,
                                                 const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
@@ -79,12 +84,34 @@ __global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict
                                                 int steps, int stride, T *__restrict__ Q) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    const int r0 = off[k], deg = off[k + 1] - r0;
     T q = Q[node[k]];
-    for (int s = 0; s < steps; ++s) {
-        const T *dl = delta + int64_t(s) * stride;
-        T acc = T(0);
-        for (int r = off[k]; r < off[k + 1]; ++r) acc = fma(coef[r], dl[inc[r]], acc);
-        q -= acc;
+    if (deg <= kChargeRegs) {
+        int ii[kChargeRegs];
+        T cc[kChargeRegs];
+#pragma unroll
+        for (int r = 0; r < kChargeRegs; ++r) {
+            ii[r] = r < deg ? inc[r0 + r] : 0;
+            cc[r] = r < deg ? coef[r0 + r] : T(0);
+        }
+        for (int s = 0; s < steps; ++s) {
+            const T *dl = delta + int64_t(s) * stride;
+            T dv[kChargeRegs];
+#pragma unroll
+            for (int r = 0; r < kChargeRegs; ++r) dv[r] = r < deg ? dl[ii[r]] : T(0);
+            T acc = T(0);
+#pragma unroll
+            for (int r = 0; r < kChargeRegs; ++r)
+                if (r < deg) acc = fma(cc[r], dv[r], acc);
+            q -= acc;
+        }
+    } else {
+        for (int s = 0; s < steps; ++s) {
+            const T *dl = delta + int64_t(s) * stride;
+            T acc = T(0);
+            for (int r = r0; r < r0 + deg; ++r) acc = fma(coef[r], dl[inc[r]], acc);
+            q -= acc;
+        }
     }
     Q[node[k]] = q;
 }
