@@ -169,3 +169,19 @@ def test_trained_network_gains_over_plain_on_held_out_meshes(ty):
               f"learned {el:.4e}")
         assert abs(el) < abs(ep)
     assert np.mean(gains) > 2.0
+
+
+def test_gate_rejects_a_scale_that_slows_the_waves(ty):
+    # a uniform scale c multiplies every coupling by c^2, so omega_max scales by c exactly;
+    # c = 0.95 slows waves that already lag (plain errors are negative here): rejected
+    _note("case: gate with gamma = 0.95 everywhere on a held-out mesh (n=48)")
+    xy, tri = lattice_mesh(48, 0.3, 910, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    w10 = waves_for(48, cells=(10,), angles=np.arange(4) * np.pi / 4)
+    gate = m.gate(np.full(m.ne, 0.95), w10)
+    _note(f"  plain {gate['err_plain']:.4e} scaled {gate['err_learned']:.4e} "
+          f"omega ratio {gate['omega_learned'] / gate['omega_plain']:.12f}")
+    assert gate["converged"] and not gate["accepted"]
+    assert abs(gate["omega_learned"] / gate["omega_plain"] - 0.95) < 1e-9
+    assert abs(gate["dt_learned"] * 0.95 - gate["dt_plain"]) < 1e-9 * gate["dt_plain"]
+    assert gate["err_learned"] > gate["err_plain"]
