@@ -440,6 +440,7 @@ def bench_plasma(args):
                      "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": algo[dom],
                      "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)},
         "copy_GBs": measure_copy_bandwidth(),
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_plasma(708),
         "kernels": {kk: {"name": v["name"], "count": v["count"],
                          "avg_ms": round(v["total_ms"] / max(1, v["count"]), 5),
                          "algorithmic_GBs": round(algo[kk] / (v["total_ms"] / max(1, v["count"])
@@ -462,10 +463,11 @@ def bench_batch(args):
 
     sizes = batch_lattice_sizes(256, seed=4)
     rng = np.random.default_rng(5)
-    meshes, dts, init = [], [], []
+    meshes, dts, init, init_xy = [], [], [], []
     t0 = time.time()
     for k, n in enumerate(sizes):
         xy, tri = lattice_mesh(int(n), 0.25, 1000 + k, periodic=True)
+        init_xy.append((xy, tri))
         m = ty.Mesh(xy, tri, True)
         m.reorder(args.order)
         lam, _, _ = m.cfl()
@@ -532,8 +534,36 @@ def bench_batch(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
                      "algorithmic_bytes_per_launch": per_launch, "traffic": None},
         "tune": tuned,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_batch(sizes, dts, init_xy),
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(sizes, dts, meshes_xy, samples=8):
+    """The FP64 oracle stepping 8 members of the batch (evenly spread over the sizes),
+    single-threaded; rate = their cell-updates over their summed time."""
+    import oracle
+    order = np.argsort(sizes)
+    pick = order[np.linspace(0, len(order) - 1, samples).astype(int)]
+    cells, secs, desc = 0, 0.0, []
+    for k in pick:
+        xy, tri = meshes_xy[k]
+        om = oracle.OracleMesh(xy, tri, True)
+        E0 = np.zeros(om.ne)
+        B0 = np.cos(2 * np.pi * om.O[:, 0])
+        t1 = time.perf_counter()
+        om.step(E0, B0, dts[k], 2)
+        per = (time.perf_counter() - t1) / 2
+        steps = int(max(2, min(2000, 1.5 / max(per, 1e-9))))
+        t1 = time.perf_counter()
+        om.step(E0, B0, dts[k], steps)
+        secs += time.perf_counter() - t1
+        cells += (om.ne + om.nt) * steps
+        desc.append(f"{om.nt}x{steps}")
+    log(f"oracle batch sample: {cells / secs:.3e} cell-updates/s")
+    return {"value": cells / secs, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 steps of 8 members (triangles x steps: " + ", ".join(desc) +
+                      "), single-threaded plain C oracle"}
 
 
 def _waves(n, cells, angles):
@@ -650,6 +680,27 @@ def bench_learned(args):
             f"learned {row['cost_ratio_learned']:.3f} const {row['cost_ratio_const']:.3f} "
             f"({time.perf_counter() - t_mesh:.1f} s)")
     ratio = float(np.mean([r["cost_ratio_learned"] for r in rows]))
+    cpu = None
+    if not args.no_cpu:
+        # the FP64 oracle's loss and gradient (time-stepped phase error with its adjoint) on a
+        # sample of the training waves, scaled to one full training step (all meshes x waves)
+        import oracle
+        from oracle import learned as OL
+        from meshgen import lattice_mesh as _lm
+        xy, tri = _lm(args.train_n, 0.3, 100, periodic=True)
+        om = oracle.OracleMesh(xy, tri, True)
+        dt0 = train[0][1]
+        sample = W[::12][:4]
+        t1 = time.perf_counter()
+        for kv in sample:
+            OL.ts_phase_error_grad(om, np.ones(om.ne), dt0, kv, OL.ts_steps(kv, dt0))
+        per_wave = (time.perf_counter() - t1) / len(sample)
+        cpu = {"value": per_wave * len(W) * len(train), "unit": "s per training step",
+               "gpu_value": train_s / max(1, args.iters), "cores": 1, "kind": "oracle",
+               "sample": f"loss and exact gradient of {len(sample)} training waves on one "
+                         f"{om.nt}-triangle training mesh ({per_wave:.2f} s per wave), scaled to "
+                         f"{len(train)} meshes x {len(W)} waves; single-threaded numpy/scipy"}
+        log(f"oracle training step (scaled): {cpu['value']:.1f} s vs GPU {cpu['gpu_value']:.3f} s")
     out = {
         "metric": "cell-updates to reach the plain method's phase error at 10 cells/lambda, "
                   "plain / learned",
@@ -674,8 +725,41 @@ def bench_learned(args):
         "dt_ratio": float(np.mean([r["dt_ratio"] for r in rows])),
         "r_grid": r_grid,
         "per_mesh": rows,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _oracle_rate(om, run, budget_s=12.0):
+    """Cell-updates/s of `run(nsteps)` on oracle mesh `om`: a 2-step probe sizes a sample of
+    about budget_s seconds, which is then timed."""
+    t1 = time.perf_counter()
+    run(2)
+    per = (time.perf_counter() - t1) / 2
+    steps = int(max(2, min(5000, budget_s / max(per, 1e-9))))
+    t1 = time.perf_counter()
+    run(steps)
+    el = time.perf_counter() - t1
+    return (om.ne + om.nt) * steps / el, steps
+
+
+def cpu_baseline_plasma(n_sample):
+    """The FP64 oracle on the plasma workload recipe at a smaller lattice (same particle,
+    source, rates in mesh units), single-threaded."""
+    import oracle
+    from meshgen import plasma_workload, periodic_wavevector, plane_wave_packet
+    w = plasma_workload(n_sample)
+    om = oracle.OracleMesh(w["xy"], w["tri"], True)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    k, _, _ = periodic_wavevector(0.7, 20.0, 1.0 / n_sample)
+    B0, E0 = plane_wave_packet(om.O, om.C, om.tangent, k, dt, sigma=0.1, center=(0.5, 0.5))
+    wp2 = om.edge_wp2(w["wp2_tri"])
+    src = (w["src_pairs"], w["src_weights"], w["src_omega"], w["src_cycles"])
+    rate, steps = _oracle_rate(om, lambda m: om.step(E0, B0, dt, m, wp2=wp2, nu=w["nu"], src=src))
+    log(f"oracle plasma{n_sample}: {steps} steps, {rate:.3e} cell-updates/s")
+    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the plasma recipe at {n_sample}x{n_sample} "
+                      f"({om.nt} triangles, particle and source), single-threaded plain C oracle"}
 
 
 def cpu_baseline(xy, tri, dt, E0_lib, B0_lib, steps, view):
