@@ -198,12 +198,14 @@ typedef struct {
                               signed dual length, w = d |e|) */
     double energy_h;       /* W_h = sum w E^n^2 + sum S B^{n-1/2} B^{n+1/2}: the quantity the
                               leap-frog scheme conserves exactly in vacuum (eqs. 7-10);
-                              B^{n-1/2} is rebuilt on the host as B^{n+1/2} - dt L_E E^n */
+                              B^{n-1/2} is rebuilt as B^{n+1/2} - dt L_E E^n */
     double max_abs_E, max_abs_B;
     int32_t nonfinite;     /* 1 if any field value is NaN or infinite */
 } tyee_diag;
 
-/* Diagnostics from the current state, computed on the host in FP64 (synchronises).
+/* Diagnostics from the current state: one device reduction with FP64 accumulation (per-block
+   partial sums added on the host in block order, so repeated calls agree bit for bit); the
+   FP64 weight tables are built on the first call after the coefficients change (synchronises).
    Returns TYEE_EUNSTABLE if a field is not finite (out is still filled). */
 int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out);
 

@@ -116,6 +116,63 @@ __global__ __launch_bounds__(256) void k_charge(int n, const int32_t *__restrict
     Q[node[k]] = q;
 }
 
+// Diagnostics (FP64 accumulation): per block, sum of wE Et^2 over edges, sum S B^2 and
+// sum S B^{n-1/2} B^{n+1/2} over triangles, max |E| = max |Et| invScale, max |B| and the
+// count of non-finite values.  B^{n-1/2} = B^{n+1/2} + (dt/S) ((s0 Et_0 + s1 Et_1) + s2 Et_2)
+// undoes the last triangle half-step.  wE = d/(gamma^2 |e|) (0 on outer edges) turns the
+// scaled field into metric (7)'s w E^2.  One partial row of 6 doubles per block.
+constexpr int kDiagThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kDiagThreads) void k_diag(int ne, int nt, const T *__restrict__ Et,
+                                                      const T *__restrict__ B, const uint32_t *__restrict__ a0,
+                                                      const uint32_t *__restrict__ a1, const uint32_t *__restrict__ a2,
+                                                      const double *__restrict__ wE, const float *__restrict__ inv_scale,
+                                                      const double *__restrict__ S, const double *__restrict__ dtS,
+                                                      double *__restrict__ partial) {
+    __shared__ double red[6][kDiagThreads];
+    const int i = blockIdx.x * kDiagThreads + threadIdx.x;
+    double we = 0.0, sb = 0.0, sh = 0.0, me = 0.0, mb = 0.0, bad = 0.0;
+    if (i < ne) {
+        const double e = double(Et[i]);
+        we = wE[i] * e * e;
+        me = fabs(e * double(inv_scale[i]));
+        bad += isfinite(e) ? 0.0 : 1.0;
+    }
+    if (i < nt) {
+        const double b = double(B[i]);
+        const double circ = (double(signed_load(Et, a0[i])) + double(signed_load(Et, a1[i]))) +
+                            double(signed_load(Et, a2[i]));
+        const double bp = b + dtS[i] * circ;
+        sb = S[i] * b * b;
+        sh = S[i] * bp * b;
+        mb = fabs(b);
+        bad += isfinite(b) ? 0.0 : 1.0;
+    }
+    if (!(me == me)) me = INFINITY;  // NaN never wins a max: record it as infinite
+    if (!(mb == mb)) mb = INFINITY;
+    const int t = threadIdx.x;
+    red[0][t] = we;
+    red[1][t] = sb;
+    red[2][t] = sh;
+    red[3][t] = me;
+    red[4][t] = mb;
+    red[5][t] = bad;
+    __syncthreads();
+    for (int h = kDiagThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+            red[2][t] += red[2][t + h];
+            red[3][t] = fmax(red[3][t], red[3][t + h]);
+            red[4][t] = fmax(red[4][t], red[4][t + h]);
+            red[5][t] += red[5][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 6) partial[6 * size_t(blockIdx.x) + t] = red[t][0];
+}
+
 // Probe: copy field values at the listed device slots into one row of the sample buffer.
 template <typename T>
 __global__ __launch_bounds__(256) void k_probe(int n, const int32_t *__restrict__ slot, const T *__restrict__ src,

@@ -83,6 +83,7 @@ int upload_coefficients(Sim &s) {
     }
     for (int64_t k = 0; k < s.nt; ++k) nb[k] = -s.dt_tri[s.perm_t[k]] / s.S[s.perm_t[k]];
     s.graph_dirty = true;
+    s.diag_ready = false;
     s.ce_dev = ce;
     s.nb_dev = nb;
     int rc = upload_field(s, s.cE, ce);
@@ -423,6 +424,60 @@ int init_sim(Sim &s, const Mesh &m, int32_t prec, const std::vector<double> &dt_
     return TYEE_OK;
 }
 
+namespace {
+
+// FP64 tables of the diagnostics reduction, in device numbering.
+int build_diag_tables(Sim &s) {
+    std::vector<double> wE(s.ne), S(s.nt), dtS(s.nt);
+    std::vector<float> inv(s.ne);
+    for (int64_t k = 0; k < s.ne; ++k) {
+        const int32_t i = s.perm_e[k];
+        const bool inner = s.R[i] >= 0 && s.L[i] >= 0;
+        wE[k] = inner ? s.d[i] / (s.gamma[i] * s.gamma[i] * s.elen[i]) : 0.0;
+        inv[k] = float(1.0 / s.scale(i));
+    }
+    for (int64_t k = 0; k < s.nt; ++k) {
+        const int32_t j = s.perm_t[k];
+        S[k] = s.S[j];
+        dtS[k] = s.dt_tri[j] / s.S[j];
+    }
+    int rc = upload<double>(s.diag_wE, wE, s.stream);
+    if (!rc) rc = upload_raw(s.diag_inv_scale, inv, s.stream);
+    if (!rc) rc = upload<double>(s.diag_S, S, s.stream);
+    if (!rc) rc = upload<double>(s.diag_dtS, dtS, s.stream);
+    const size_t nblocks = size_t((std::max(s.ne, s.nt) + kDiagThreads - 1) / kDiagThreads);
+    if (!rc) rc = s.diag_partial.alloc(size_t(6) * std::max<size_t>(1, nblocks) * sizeof(double));
+    if (!rc) s.diag_ready = true;
+    return rc;
+}
+
+template <typename T> int device_diagnostics(Sim &s, double *sums) {
+    const int64_t n = std::max(s.ne, s.nt);
+    const int nb = int((n + kDiagThreads - 1) / kDiagThreads);
+    k_diag<T><<<nb, kDiagThreads, 0, s.stream>>>(int(s.ne), int(s.nt), s.Et().as<T>(), s.B().as<T>(),
+                                                 s.A0.as<uint32_t>(), s.A1.as<uint32_t>(), s.A2.as<uint32_t>(),
+                                                 s.diag_wE.as<double>(), s.diag_inv_scale.as<float>(),
+                                                 s.diag_S.as<double>(), s.diag_dtS.as<double>(),
+                                                 s.diag_partial.as<double>());
+    TYEE_HIP(hipGetLastError());
+    std::vector<double> part(size_t(6) * nb);
+    TYEE_HIP(hipMemcpyAsync(part.data(), s.diag_partial.p, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            s.stream));
+    TYEE_HIP(hipStreamSynchronize(s.stream));
+    for (int q = 0; q < 6; ++q) sums[q] = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sums[0] += part[6 * size_t(b)];
+        sums[1] += part[6 * size_t(b) + 1];
+        sums[2] += part[6 * size_t(b) + 2];
+        sums[3] = std::max(sums[3], part[6 * size_t(b) + 3]);
+        sums[4] = std::max(sums[4], part[6 * size_t(b) + 4]);
+        sums[5] += part[6 * size_t(b) + 5];
+    }
+    return TYEE_OK;
+}
+
+}  // namespace
+
 }  // namespace tyee
 
 // ---------------------------------------------------------------------------------------
@@ -650,42 +705,27 @@ int tyee_sim_last_step_ms(tyee_sim *sim, double *ms) {
     return TYEE_OK;
 }
 
+
 int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out) {
     if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
     tyee::Sim &s = sim->s;
-    std::vector<double> E(s.ne), B(s.nt);
-    int rc = tyee_sim_get_state(sim, TYEE_FIELD_E, E.data());
-    if (!rc) rc = tyee_sim_get_state(sim, TYEE_FIELD_B, B.data());
+    int rc = TYEE_OK;
+    if (!s.diag_ready) rc = tyee::build_diag_tables(s);
+    if (rc) return rc;
+    if (int64_t(std::max(s.ne, s.nt)) >= int64_t(INT32_MAX)) return fail(TYEE_EINVAL, "mesh too large");
+    double v[6];
+    rc = s.f64 ? tyee::device_diagnostics<double>(s, v) : tyee::device_diagnostics<float>(s, v);
     if (rc) return rc;
     tyee_diag d{};
     d.step = s.step;
     d.time = double(s.step) * s.dt;
-    // B^{n-1/2} = B^{n+1/2} + (dt/S) sum_q s gamma |e| E^n  (undo the last triangle half-step)
-    for (int64_t j = 0; j < s.nt; ++j) {
-        double circ = 0.0;
-        for (int q = 0; q < 3; ++q) {
-            const int32_t i = s.A[3 * j + q];
-            circ += double(s.sgn[3 * j + q]) * s.scale(i) * E[i];
-        }
-        d.energy_h += s.S[j] * (B[j] + s.dt_tri[j] / s.S[j] * circ) * B[j];
-    }
-    bool bad = false;
-    for (int64_t i = 0; i < s.ne; ++i) {
-        bad |= !std::isfinite(E[i]);
-        d.max_abs_E = std::max(d.max_abs_E, std::fabs(E[i]));
-        if (s.R[i] >= 0 && s.L[i] >= 0) {
-            d.energy += s.d[i] * s.elen[i] * E[i] * E[i];
-            d.energy_h += s.d[i] * s.elen[i] * E[i] * E[i];
-        }
-    }
-    for (int64_t j = 0; j < s.nt; ++j) {
-        bad |= !std::isfinite(B[j]);
-        d.max_abs_B = std::max(d.max_abs_B, std::fabs(B[j]));
-        d.energy += s.S[j] * B[j] * B[j];
-    }
-    d.nonfinite = bad;
+    d.energy = v[0] + v[1];
+    d.energy_h = v[0] + v[2];
+    d.max_abs_E = v[3];
+    d.max_abs_B = v[4];
+    d.nonfinite = v[5] > 0.0;
     *out = d;
-    return bad ? fail(TYEE_EUNSTABLE, "non-finite field value") : TYEE_OK;
+    return d.nonfinite ? fail(TYEE_EUNSTABLE, "non-finite field value") : TYEE_OK;
 }
 
 int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds) {

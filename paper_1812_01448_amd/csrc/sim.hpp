@@ -191,6 +191,10 @@ struct Sim {
     int64_t n_qnode = 0;
     DeviceBuffer Q, q_node, q_off, q_inc, q_coef;
 
+    // diagnostics tables (FP64 weights in device numbering), built on first use
+    bool diag_ready = false;
+    DeviceBuffer diag_wE, diag_inv_scale, diag_S, diag_dtS, diag_partial;
+
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     LaunchTimer timer;
     std::vector<std::unique_ptr<Probe>> probes;

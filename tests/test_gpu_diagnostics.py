@@ -114,3 +114,38 @@ def test_gauss_law_and_plasma_probes(ty, prec, tol):
         t_tol = 1e-11 if prec == "f64" else 1e-4
         assert rel_l2(sj[t], J[plasma_edges]) < t_tol
         assert rel_l2(sq[t], Q[::7]) < t_tol
+
+
+@pytest.mark.parametrize("prec,periodic,tol", [("f64", True, 1e-12), ("f32", True, 1e-6),
+                                               ("f64", False, 1e-12)])
+def test_device_diagnostics_match_host_sums(ty, prec, periodic, tol):
+    n = 36
+    _note(f"case: diagnostics reduction vs host sums, {prec} periodic={periodic}, learned scale")
+    xy, tri = lattice_mesh(n, 0.25, 13, periodic=periodic)
+    m = ty.Mesh(xy, tri, periodic)
+    m.reorder("rcm")
+    v = m.view()
+    gamma = 1.0 + 0.05 * np.sin(np.arange(m.ne) * 0.7)
+    lam, _, _ = m.cfl(gamma=gamma)
+    dt = 0.5 * 2 / np.sqrt(lam)
+    sim = ty.Sim(m, dt, prec)
+    sim.set_edge_scale(gamma)
+    rng = np.random.default_rng(4)
+    sim.set_state("E", rng.standard_normal(m.ne))
+    sim.set_state("B", rng.standard_normal(m.nt))
+    sim.set_fusion(4, 0)
+    sim.step(37)
+    d = sim.diagnostics()
+    E, B = sim.get_state("E"), sim.get_state("B")
+    inner = (v["R"] >= 0) & (v["L"] >= 0)
+    w = np.where(inner, v["d"] * v["elen"], 0.0)
+    # B^{n-1/2} = B^{n+1/2} + (dt/S) sum_q s(j,q) gamma |e| E
+    circ = np.sum(v["sgn"] * (gamma * v["elen"] * E)[v["A"]], axis=1)
+    Bp = B + dt / v["S"] * circ
+    We = np.sum(w * E * E)
+    assert abs(d["energy"] / (We + np.sum(v["S"] * B * B)) - 1) < tol
+    assert abs(d["energy_h"] / (We + np.sum(v["S"] * Bp * B)) - 1) < tol
+    assert abs(d["max_abs_E"] / np.max(np.abs(E)) - 1) < 1e-6
+    assert d["max_abs_B"] == np.max(np.abs(B))
+    assert d["nonfinite"] == 0 and d["step"] == 37
+    assert sim.diagnostics() == d                      # deterministic
