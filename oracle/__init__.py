@@ -8,6 +8,11 @@ loader builds it on first use when it is missing.
 Python-side helpers here are the evaluation formulas that sit on top of the stepper:
 plasma-frequency averaging onto edges, source lookup by node pairs, and the plane-wave phase
 overlap used for the dispersion metric.
+
+Parity unpinned: `OracleMesh.edge_wp2` (the half-dual weighted average of per-triangle plasma
+frequencies onto an edge of the particle boundary; the paper gives no rule) and the source
+waveform of the C core; both are readings shared with the library, with no independent check
+beyond the Gauss law and linearity tests that hold for any such rule.
 """
 import ctypes
 import os
@@ -161,7 +166,8 @@ class OracleMesh:
         """Per-edge plasma frequency squared from per-triangle values.
 
         Each interior edge takes the half-dual-length weighted mean of its two triangles,
-        (hR wp2_R + hL wp2_L)/d; outer edges carry no field and get 0.
+        (hR wp2_R + hL wp2_L)/d; outer edges carry no field and get 0 (a reading of the
+        particle boundary of Fig. 3; parity unpinned).
         """
         wt = np.asarray(wp2_tri, np.float64)
         out = np.zeros(self.ne)

@@ -21,6 +21,10 @@
  *    s(j,q) = +1 if j = R(A(j,q)), else -1 (the sign of eq. 4, read topologically);
  *  - dual length d_i = hR_i + hL_i, signed half lengths from the edge midpoint to the
  *    two circumcentres along the left normal of e_i (|O_R O_L| of eq. 3 on a Delaunay mesh).
+ *
+ * Parity unpinned: the source waveform g(t) (`waveform`): the paper does not specify its
+ * source, so its values are a reading shared with the library, checked only through the
+ * linearity of the response and the Gauss law with the source charge.
  */
 #include <math.h>
 #include <stdint.h>
@@ -319,6 +323,8 @@ void orc_apply_LE(const orc_mesh *m, const double *gamma, const double *E, doubl
 /* leap-frog stepping with Drude current, nodal charge and soft source          */
 /* ------------------------------------------------------------------------- */
 
+/* soft-source envelope g(t) = sin(omega t) sin^2(pi t / T), T = cycles 2 pi / omega, zero
+   outside [0, T) (a reading: Fig. 3's source is unspecified; parity unpinned) */
 static double waveform(double t, double omega, double cycles)
 {
     double T = cycles * 2.0 * M_PI / omega;

@@ -185,3 +185,44 @@ def test_gate_rejects_a_scale_that_slows_the_waves(ty):
     assert abs(gate["omega_learned"] / gate["omega_plain"] - 0.95) < 1e-9
     assert abs(gate["dt_learned"] * 0.95 - gate["dt_plain"]) < 1e-9 * gate["dt_plain"]
     assert gate["err_learned"] > gate["err_plain"]
+
+
+def test_learned_pieces_at_the_held_out_size(ty):
+    # a held-out evaluation mesh at full size (707 x 707, 999,698 triangles): the scale at
+    # every edge, the power iteration of the gate, and one time-stepped phase error (a short
+    # sampled wave, so the oracle's two FP64 runs finish in seconds) against the oracle
+    n = 707
+    _note(f"case: learned pieces on a {n}x{n} held-out mesh vs oracle")
+    xy, tri = lattice_mesh(n, 0.3, 200, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    om = oracle.OracleMesh(xy, tri, True)
+    small = training_set(ty, [24], 77)
+    lr = ty.Learner([small[0]["mesh"]], [small[0]["dt"]], np.stack([small[0]["waves"]]))
+    F = OL.features(om)
+    mu, sd = F.mean(0), F.std(0) + 1e-6
+    lr.normaliser(mu, sd)
+    lr.set_params(np.random.default_rng(11).uniform(-0.4, 0.4, OL.N_PARAMS))
+    theta32 = lr.params()
+    g = lr.gamma(m)
+    g_ref = OL.mlp_forward(theta32, F, mu, sd)
+    _note(f"  gamma max |diff| {np.max(np.abs(g - g_ref)):.2e} over {m.ne} edges")
+    assert np.max(np.abs(g - g_ref)) < 2e-6
+    # the gate's stability part: omega_max with and without the scale
+    w = waves_for(n, cells=(10,), angles=np.array([0.3]))
+    gate = m.gate(g, w, prec="f32")
+    lam_p, _, ok_p = om.power()
+    lam_l, _, ok_l = om.power(gamma=g)
+    _note(f"  omega_max plain {gate['omega_plain']:.9e} (oracle {np.sqrt(lam_p):.9e}), "
+          f"scaled {gate['omega_learned']:.9e} (oracle {np.sqrt(lam_l):.9e})")
+    assert gate["converged"] and ok_p and ok_l
+    assert abs(gate["omega_plain"] / np.sqrt(lam_p) - 1) < 1e-8
+    assert abs(gate["omega_learned"] / np.sqrt(lam_l) - 1) < 1e-8
+    # one time-stepped phase error (5 cells per wavelength, 0.5 rad of travel), FP32 stepping
+    dt = gate["dt_learned"]
+    k = periodic_wavevector(0.9, 5.0, 1.0 / n)[0]
+    nsteps = max(10, int(round(0.5 / (np.hypot(*k) * dt))))
+    got = m.phase_error_timestepped(dt, k, phase=0.5, samples=10, gamma=g, prec="f32")
+    ref = OL.timestepped_phase_error(om, g, dt, k, nsteps, samples=10)
+    _note(f"  phase error {got:.9e} oracle {ref:.9e} ({nsteps} steps)")
+    assert abs(got - ref) < 1e-6

@@ -170,3 +170,25 @@ def test_ts_phase_error_of_an_eigenmode_and_against_full_stepping(eq_mesh, jit_m
     e_b, _ = L.ts_phase_error_grad(m, None, dt, k, n)
     e_full = L.timestepped_phase_error(m, None, dt, k, n, samples=30)
     assert abs(e_b - e_full) < 0.05 * abs(e_full)
+
+
+def test_stiff_edge_term_value_and_gradient():
+    # beta * mean over edges with d/|e| < tau of (gamma - target)^2: a hand-computed case
+    feat = np.zeros((5, L.N_FEAT))
+    feat[:, 0] = [0.001, 0.5, 0.01, 0.3, 0.019]        # edges 0, 2, 4 are below tau = 0.02
+    gamma = np.array([1.0, 1.05, 0.95, 1.1, 0.9])
+    loss, grad = L.stiff_reg_loss_grad(feat, gamma, tau=0.02, beta=2.0, target=0.9)
+    expect = 2.0 * ((1.0 - 0.9) ** 2 + (0.95 - 0.9) ** 2 + 0.0) / 3
+    assert abs(loss - expect) < 1e-15
+    assert np.all(grad[[1, 3]] == 0.0) and grad[4] == 0.0
+    h = 1e-7
+    for i in range(5):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[i] += h
+        gm[i] -= h
+        fd = (L.stiff_reg_loss_grad(feat, gp, 0.02, 2.0, 0.9)[0]
+              - L.stiff_reg_loss_grad(feat, gm, 0.02, 2.0, 0.9)[0]) / (2 * h)
+        assert abs(fd - grad[i]) < 1e-8
+    # no stiff edge: no term
+    feat[:, 0] = 0.5
+    assert L.stiff_reg_loss_grad(feat, gamma, 0.02, 2.0, 0.9)[0] == 0.0
