@@ -130,7 +130,10 @@ int tyee_mesh_create(const double *xy, int64_t n_nodes, const int32_t *tri, int6
    are always canonical. */
 int tyee_mesh_reorder(tyee_mesh *mesh, int32_t kind, uint64_t seed);
 
+/* Counts and the Section 3 quality measures of a mesh (out: caller-owned).  Errors: EINVAL. */
 int tyee_mesh_query(const tyee_mesh *mesh, tyee_mesh_info *out);
+/* Borrowed pointers to the mesh's host arrays (layouts in tyee_mesh_arrays), valid until the
+   mesh is destroyed or reordered.  Errors: EINVAL. */
 int tyee_mesh_view(const tyee_mesh *mesh, tyee_mesh_arrays *out);
 
 /* omega_max^2 of K = -L_E L_B by normalised iteration in the S-weighted product (the
@@ -150,7 +153,8 @@ void tyee_mesh_destroy(tyee_mesh *mesh);
    (geometry stays FP64 on the host; coefficients are folded with dt and rounded once).
    stream: a hipStream_t, or NULL to let the library create a stream of its own (the legacy
    default stream cannot be captured into graphs).  Fields start at zero.  The simulation
-   copies what it needs: the mesh may be destroyed afterwards. */
+   copies what it needs: the mesh may be destroyed afterwards.  Errors: EINVAL (prec, dt not
+   positive and finite), EDEVICE (no HIP device), ENOMEM. */
 int tyee_sim_create(const tyee_mesh *mesh, int32_t prec, double dt, void *stream,
                     tyee_sim **out);
 
@@ -177,15 +181,17 @@ int tyee_sim_set_source(tyee_sim *sim, const int32_t *node_pairs, const double *
    edge i (the learned correction); NULL restores gamma = 1.  Physical fields are kept. */
 int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma);
 
-/* Temporal fusion for vacuum runs: advance steps_per_launch (1, 2, 4 or 8; 0 = 4) steps in
-   one launch.  The device numbering is cut into tiles of tile_tris consecutive triangles
+/* Temporal fusion: advance steps_per_launch (1, 2, 4 or 8; 0 = 4) steps in one launch, with
+   or without plasma and source edges (tiles that hold such an edge run a variant of the kernel
+   that also advances their currents, and the nodal charge follows once per launch).  The device numbering is cut into tiles of tile_tris consecutive triangles
    (0 = a default for the depth; else 256..8192); each work-group loads its tile with
    steps_per_launch rings of neighbours into LDS, advances them, and writes its own cells to
    the other of two field buffers.  Results are bit-identical for every setting.  A mesh
    whose tiles exceed the kernel's capacity falls back to one launch per half-step. */
 int tyee_sim_set_fusion(tyee_sim *sim, int32_t steps_per_launch, int32_t tile_tris);
 
-/* Enqueue n leap-frog steps on the simulation's stream (asynchronous). */
+/* Enqueue n leap-frog steps on the simulation's stream (asynchronous; n = 0 does nothing).
+   Errors: EINVAL (n < 0), EDEVICE (a launch failed). */
 int tyee_sim_step(tyee_sim *sim, int64_t n);
 
 /* Wait for all enqueued work. */
@@ -284,7 +290,10 @@ int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double 
    (real and imaginary parts of B = exp(i (k.O - |k| dt/2)), E = exp(i k.C) (t . (n x k^)))
    are advanced N = max(samples, round(phase/(|k| dt))) steps on the GPU in `samples` chunks;
    the phase of the overlap z = sum w E conj(E0) + sum S B conj(B0) (metric (7)) is unwrapped
-   and fitted by least squares, eps[w] = slope/|k| - 1.  gamma: edge scale or NULL. */
+   and fitted by least squares, eps[w] = slope/|k| - 1 (the dispersion of Section 2 as the
+   scheme produces it).  gamma: edge scale or NULL; eps: [n_waves] caller-owned; the mesh
+   must be periodic with integer-periodic wavevectors.  Errors: EINVAL (zero wavevector,
+   samples < 2, phase or dt not positive), EDEVICE. */
 int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double *gamma, double dt,
                                  int32_t prec, const double *waves, int64_t n_waves,
                                  double phase, int64_t samples, void *stream, double *eps);
@@ -302,7 +311,8 @@ typedef struct tyee_learner tyee_learner;
    meshes: periodic training meshes of at most 4096 triangles (each runs inside one
    work-group); dt [n_meshes]; waves [n_meshes][n_waves][2]; phase in (0, 3) radians.
    mu and sd default to the mean and standard deviation (+1e-6) of the training features.
-   Parameters start at zero (gamma = 1). */
+   Parameters start at zero (gamma = 1).  Errors: EINVAL (a mesh not periodic or larger than
+   4096 triangles / 6144 edges, dt not positive, phase out of range), EDEVICE, ENOMEM. */
 int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
                         const double *waves, int64_t n_waves, double phase, void *stream,
                         tyee_learner **out);
@@ -367,12 +377,14 @@ typedef struct tyee_batch tyee_batch;
 int tyee_batch_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
                       int32_t prec, void *stream, tyee_batch **out);
 
-/* Member k's E [n_edges_k] or B [n_tris_k] in the member's own canonical numbering. */
+/* Member k's E [n_edges_k] or B [n_tris_k] in the member's own canonical numbering (FP64
+   host, copied; get synchronises).  Errors: EINVAL (k out of range, other fields). */
 int tyee_batch_set_state(tyee_batch *b, int64_t k, int32_t field, const double *host);
 int tyee_batch_get_state(tyee_batch *b, int64_t k, int32_t field, double *host);
 
 /* Renumber every member (as tyee_mesh_reorder); fields are kept. */
 int tyee_batch_reorder(tyee_batch *b, int32_t kind, uint64_t seed);
+/* As tyee_sim_set_fusion / _set_graph / _step / _sync, for the union of the members. */
 int tyee_batch_set_fusion(tyee_batch *b, int32_t steps_per_launch, int32_t tile_tris);
 int tyee_batch_set_graph(tyee_batch *b, int32_t launches);
 int tyee_batch_step(tyee_batch *b, int64_t n);
