@@ -851,6 +851,7 @@ extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double 
     if (!mesh || !waves || !eps_out || n_waves <= 0 || !(dt > 0.0) || samples < 2 || !(phase > 0.0))
         return fail(TYEE_EINVAL, "bad phase-error arguments");
     const Mesh &m = mesh->m;
+    if (!m.periodic) return fail(TYEE_EINVAL, "plane-wave phase errors need a periodic mesh");
     std::vector<double> w(m.ne, 0.0);
     for (int64_t i = 0; i < m.ne; ++i)
         if (m.interior(i)) w[i] = m.d[i] * m.elen[i];

@@ -112,3 +112,11 @@ def test_cfl_matches_oracle_and_closed_form(ty):
         lam, _, ok = m.cfl(gamma=g)
         lam_o, _, ok_o = o.power(gamma=g)
         assert ok and ok_o and abs(lam / lam_o - 1) < 1e-10
+
+
+def test_phase_error_needs_a_periodic_mesh(ty):
+    # argument checks happen on the host before any device work
+    xy, tri = lattice_mesh(10, 0.2, 0, periodic=False)
+    m = ty.Mesh(xy, tri, False)
+    with pytest.raises(ty.TyeeError):
+        m.phase_error_timestepped(1e-3, np.array([2 * np.pi, 0.0]))
