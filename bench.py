@@ -66,8 +66,8 @@ def traffic_file(workload):
 
 
 COPY_BYTES = 128 * 1024 * 1024 * 4     # --copy-calibration: bytes read and written per copy
-KERNEL_SOURCES = ["paper_1812_01448_amd/csrc/fused.hip", "paper_1812_01448_amd/csrc/kernels.hpp",
-                  "paper_1812_01448_amd/csrc/sim.hpp"]
+# the fused kernel and its device-side contract (tile records, XCD mapping)
+KERNEL_SOURCES = ["paper_1812_01448_amd/csrc/fused.hip", "paper_1812_01448_amd/csrc/tile.hpp"]
 
 
 def kernel_source_hash():

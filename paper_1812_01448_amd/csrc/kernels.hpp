@@ -7,17 +7,9 @@
 
 #include <cstdint>
 
-namespace tyee {
+#include "tile.hpp"
 
-// Work-groups are dispatched round-robin over the 8 XCDs of the chip (group g runs on
-// XCD g mod 8).  Remap so that each XCD works on one contiguous run of groups: the
-// neighbour gathers of adjacent groups then hit the same XCD-private L2.
-__device__ __forceinline__ int xcd_group(int g, int ngroups) {
-    constexpr int kXcd = 8;
-    const int q = ngroups / kXcd, r = ngroups % kXcd;
-    const int x = g % kXcd, k = g / kXcd;
-    return x * q + (x < r ? x : r) + k;
-}
+namespace tyee {
 
 // Sign in bit 31 of a packed edge index: flip the sign bit of the value.
 __device__ __forceinline__ float signed_load(const float *__restrict__ v, uint32_t packed) {

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "tile.hpp"
 
 #define TYEE_HIP(call)                                                                           \
     do {                                                                                         \
@@ -126,7 +127,6 @@ struct LaunchTimer {
 
 struct Tiling;
 
-constexpr int kMaxFusion = 8;  // largest number of steps one fused launch advances
 
 // Soft-source waveform g(t) = sin(omega t) sin^2(pi t / T) for 0 <= t < T, T = cycles 2 pi/omega.
 inline double waveform(double t, double omega, double cycles) {
@@ -207,18 +207,7 @@ struct Sim {
 };
 
 
-// Temporal tiling for the fused K-step kernel (built by fused.hip).
-struct TileInfo {
-    int32_t n_core;      // core triangles are local [0, n_core), device slots core_base + l
-    int32_t n_own;       // owned edges are local [0, n_own)
-    int32_t tri_off;     // offset of this tile in the packed triangle arrays
-    int32_t edge_off;    // offset of this tile in the packed edge arrays
-    int32_t core_base;   // device slot of the first core triangle
-    int32_t own_base;    // device slot of the first owned edge when they are contiguous, else -1
-    int32_t cntT[9];     // local triangles with ring level <= m
-    int32_t cntE[9];     // local edges with level <= m
-};
-
+// Temporal tiling for the fused K-step kernel (built by fused.hip); TileInfo is in tile.hpp.
 struct Tiling {
     int K = 0, tile = 0, threads = 0, rt = 0, re = 0;
     int64_t ntiles = 0, maxT = 0, maxE = 0, sumT = 0, sumE = 0;
