@@ -239,7 +239,7 @@ def main():
     torch.cuda.synchronize()
     # HIP events bracket every launch of the dominant kernel inside the timed region (every
     # graph replay when the fused launches run from a captured graph)
-    use_graph = args.graph > 0 and K > 1
+    use_graph = args.graph > 0
     sim.set_profiling(True, kinds=["graph"] if use_graph else (["fused"] if K > 1 else ["edge", "tri"]))
     t_start = time.perf_counter()
     sim.step(args.steps)
@@ -265,7 +265,8 @@ def main():
     avg_ms = prof[dom]["total_ms"] / launches
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     step_bytes = bytes_edge + bytes_tri
-    roofline = {"bound": "hbm", "kernel": "k_fused" if dom in ("fused", "graph") else prof[dom]["name"],
+    kname = ("k_fused" if K > 1 else "k_edge+k_tri") if dom in ("fused", "graph") else prof[dom]["name"]
+    roofline = {"bound": "hbm", "kernel": kname,
                 "timed_with": "HIP events per graph replay of %d launches" % args.graph
                 if dom == "graph" else "HIP events per launch",
                 "achieved": round(achieved, 1),

@@ -237,10 +237,11 @@ int tyee_sim_read_probe(tyee_sim *sim, int32_t probe, double *out, int64_t capac
    the simulation's stream (synchronises). */
 int tyee_sim_last_step_ms(tyee_sim *sim, double *ms);
 
-/* Replay fused launches from a captured HIP graph, `launches` (an even number, 0 = off) per
-   graph, for vacuum runs; the graph is captured on first use and again after any change of
-   fusion, tiling or coefficients.  Stepping with per-launch timing of TYEE_KERNEL_FUSED
-   enabled launches eagerly instead. */
+/* Replay launches from a captured HIP graph, `launches` (an even number, 0 = off) per graph,
+   for vacuum runs: fused launches, or with one step per launch the edge and triangle
+   half-steps of `launches` steps.  The graph is captured on first use and again after any
+   change of fusion, tiling or coefficients.  Stepping with per-launch timing of any single
+   kernel kind enabled launches eagerly instead. */
 int tyee_sim_set_graph(tyee_sim *sim, int32_t launches);
 
 /* Kernels of one step, for per-launch timing; TYEE_KERNEL_GRAPH times whole graph replays. */

@@ -252,7 +252,16 @@ template <typename T> int replay_graph(Sim &s, int k) {
         const int cur0 = s.cur;
         TYEE_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
         int rc = TYEE_OK;
-        for (int g = 0; g < s.graph_launches && !rc; ++g) rc = launch_fused<T>(s, k);
+        if (k > 1) {
+            for (int g = 0; g < s.graph_launches && !rc; ++g) rc = launch_fused<T>(s, k);
+        } else {  // one step per "launch": the edge and the triangle half-step
+            const int ge = blocks_for(s.ne), gt = blocks_for(s.nt);
+            for (int g = 0; g < s.graph_launches; ++g) {
+                launch_edge<T>(s.stream, s.ne, ge, s.Et().as<T>(), s.B().as<T>(), s.cE.as<T>(), s.RL.as<int2>());
+                launch_tri<T>(s.stream, s.nt, gt, s.B().as<T>(), s.Et().as<T>(), s.nB.as<T>(), s.A0.as<uint32_t>(),
+                              s.A1.as<uint32_t>(), s.A2.as<uint32_t>());
+            }
+        }
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(s.stream, &graph);
         s.cur = cur0;
@@ -302,10 +311,10 @@ template <typename T> int enqueue_steps(Sim &s, int64_t n) {
         if (rc) break;
         // graphs replay fixed arguments: the source waveform changes every step, so runs with
         // special edges launch the fused kernel eagerly
-        if (k > 1 && !special && s.graph_launches > 0 && k == s.fusion && !s.timer_wants_kernels()) {
+        if (!special && s.graph_launches > 0 && k == s.fusion && !s.timer_wants_kernels()) {
             const int64_t span = int64_t(k) * s.graph_launches;
             if (n - done >= span && steps_to_next_sample(s) >= span) {
-                if (!s.tiling || s.tiling->K != k) {
+                if (k > 1 && (!s.tiling || s.tiling->K != k)) {
                     rc = build_tiling(s, k, s.tile_tris);
                     if (rc == TYEE_EINVAL) {  // this mesh does not tile at that depth
                         clear_error();

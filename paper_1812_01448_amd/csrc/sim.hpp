@@ -202,8 +202,8 @@ struct Sim {
     ~Sim();
 
     double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
-    // per-launch timing of fused kernels needs eager launches
-    bool timer_wants_kernels() const { return (timer.mask & (1u << TYEE_KERNEL_FUSED)) != 0; }
+    // per-launch timing of single kernels needs eager launches (graph replays are timed whole)
+    bool timer_wants_kernels() const { return (timer.mask & ~(1u << TYEE_KERNEL_GRAPH)) != 0; }
 };
 
 

@@ -6,7 +6,8 @@ single-step launches.
   torus, at every fusion depth;
 * a torus split into two tiles whose halos cover each other completely (K = 8);
 * zero-step calls, all-zero media, empty sources and a current set on non-plasma edges;
-* argument errors of the launch configuration.
+* argument errors of the launch configuration;
+* HIP-graph replay (fused or one step per launch) equal to eager launches, with tails.
 """
 import sys
 
@@ -151,3 +152,27 @@ def test_launch_configuration_errors(ty):
         sim.set_source(np.array([[0, 0]], np.int32), np.ones(1), 1.0, 1.0)
     with pytest.raises(ty.TyeeError):
         ty.Sim(m, -1.0, "f32")
+
+
+@pytest.mark.parametrize("fusion", [1, 4])
+def test_graph_replay_equals_eager_launches(ty, fusion):
+    n = 40
+    _note(f"case: torus{n} fp32 graph replay (8 launches) vs eager, fusion {fusion}, 203 steps")
+    xy, tri = lattice_mesh(n, 0.25, 21, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    lam, _, _ = m.cfl()
+    dt = 0.5 * 2 / np.sqrt(lam)
+    v = m.view()
+    E0, B0 = packet_state(v, dt, n, cells=8.0)
+    out = []
+    for graph in (0, 8):
+        sim = ty.Sim(m, dt, "f32")
+        sim.set_state("E", E0)
+        sim.set_state("B", B0)
+        sim.set_fusion(fusion, 0)
+        sim.set_graph(graph)
+        for chunk in (50, 100, 53):      # replays, then eager tails
+            sim.step(chunk)
+        out.append((sim.get_state("E"), sim.get_state("B")))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
