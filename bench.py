@@ -681,6 +681,23 @@ def bench_learned(args):
             f"learned {row['cost_ratio_learned']:.3f} const {row['cost_ratio_const']:.3f} "
             f"({time.perf_counter() - t_mesh:.1f} s)")
     ratio = float(np.mean([r["cost_ratio_learned"] for r in rows]))
+    # LDS roofline of the training step's dominant kernel (k_ts_adjoint, one work-group per
+    # mesh and wave): per leap-frog step of the B-only recurrence each triangle reads its 3
+    # neighbours' x and v (complex: 12 floats) and writes its own 4, in both passes, and the
+    # second pass reads 8 floats per edge for the gradient: (32 n_t + 8 n_e) x 4 B per step.
+    lds_bytes = 0.0
+    for m_, dt_ in train:
+        for kv in W:
+            nsteps = max(1, int(round(2.0 / (np.hypot(*kv) * dt_))))
+            lds_bytes += nsteps * (32 * m_.nt + 8 * m_.ne) * 4.0
+    step_s = train_s / max(1, args.iters)
+    lds_peak = 256 * 128 * 2.4e9 / 1e12        # TB/s: 256 CUs x 128 B/clk x 2.4 GHz
+    roofline = {"bound": "lds", "kernel": "k_ts_adjoint", "unit": "TB/s",
+                "achieved": round(lds_bytes / step_s / 1e12, 2), "peak": round(lds_peak, 1),
+                "frac": round(lds_bytes / step_s / 1e12 / lds_peak, 4),
+                "algorithmic_bytes_per_launch": lds_bytes, "avg_launch_ms": round(step_s * 1e3, 2),
+                "timed_with": "wall time of the training steps (the adjoint kernel is ~95 % of it)",
+                "peak_assumes": "128 B per clock per CU of LDS bandwidth", "traffic": None}
     cpu = None
     if not args.no_cpu:
         # the FP64 oracle's loss and gradient (time-stepped phase error with its adjoint) on a
@@ -726,6 +743,7 @@ def bench_learned(args):
         "dt_ratio": float(np.mean([r["dt_ratio"] for r in rows])),
         "r_grid": r_grid,
         "per_mesh": rows,
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
