@@ -35,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <numeric>
 #include <memory>
 
 #include "internal.hpp"
@@ -107,10 +108,11 @@ struct TsMesh {
     double dt, area;
 };
 
-// One work-group per (mesh m, wave w) = blockIdx.x = m * W + w.
+// One work-group per (mesh m, wave w), b = m * W + w = order[blockIdx.x].
 //   tri_word[t][q] = neighbour local triangle | (local edge << 16);  tri_invS, tri_O
 //   edge_RL[e] = R | (L << 16) (local triangles);  edge_ebyd = |e|/d;  gamma per edge
-__global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const TsMesh *__restrict__ meshes,
+__global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t *__restrict__ order,
+                                                           const TsMesh *__restrict__ meshes,
                                                            const float *__restrict__ waves,
                                                            const int32_t *__restrict__ nsteps,
                                                            const uint32_t *__restrict__ tri_word,
@@ -123,10 +125,12 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const TsMesh *
                                                            float *__restrict__ grad_out, int64_t grad_stride) {
     __shared__ float xr[kTsMaxTris], xi[kTsMaxTris], vr[kTsMaxTris], vi[kTsMaxTris];
     __shared__ double red[kTsThreads / 64][2];
-    const int m = blockIdx.x / W, w = blockIdx.x % W, tid = threadIdx.x;
+    // work-groups start longest recurrence first (order sorts (mesh, wave) pairs by steps)
+    const int b = order[blockIdx.x];
+    const int m = b / W, w = b % W, tid = threadIdx.x;
     const TsMesh M = meshes[m];
-    const int N = nsteps[blockIdx.x];
-    const float kx = waves[2 * blockIdx.x], kz = waves[2 * blockIdx.x + 1];
+    const int N = nsteps[b];
+    const float kx = waves[2 * b], kz = waves[2 * b + 1];
     const double kn = sqrt(double(kx) * kx + double(kz) * kz);
     const float dt2 = float(M.dt * M.dt);
     const float ca = float(cos(kn * M.dt / 2)), sa = float(sin(kn * M.dt / 2));
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const TsMesh *
     const double qr = zr * cos(a0) - zi * sin(a0), qi = zi * cos(a0) + zr * sin(a0);  // z_N e^{+i a}
     const double T = kn * double(N) * M.dt;
     const double eps = -atan2(qi, qr) / T - 1.0;
-    if (tid == 0) eps_out[blockIdx.x] = eps;
+    if (tid == 0) eps_out[b] = eps;
 
     // pass 2: x forward from the start, v backwards from v_{N-1} (u_{N-1} = v_{N-1} - v_N)
 #pragma unroll
@@ -515,7 +519,7 @@ struct tyee_learner {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int64_t M = 0, W = 0, n = 0, nt = 0;  // meshes, waves per mesh, edges, triangles (concatenated)
-    tyee::DeviceBuffer feat, ebyd, gamma, waves, nsteps, meshes;
+    tyee::DeviceBuffer feat, ebyd, gamma, waves, nsteps, order, meshes;
     tyee::DeviceBuffer tri_word, tri_invS, tri_O, edge_RL;
     tyee::DeviceBuffer eps, wave_grad, dLdg, loss, partial_g, grad;
     tyee::DeviceBuffer stiff;            // edges of the stiff-edge term
@@ -542,7 +546,8 @@ int learner_pass(tyee_learner &L, bool want_grad) {
     k_mlp_gamma<<<int((L.n + 255) / 256), 256, 0, s>>>(int(L.n), L.feat.as<float>(), L.params.as<float>(),
                                                       L.gamma.as<float>());
     k_ts_adjoint<<<int(L.M * L.W), kTsThreads, 0, s>>>(
-        int(L.W), L.meshes.as<TsMesh>(), L.waves.as<float>(), L.nsteps.as<int32_t>(), L.tri_word.as<uint32_t>(),
+        int(L.W), L.order.as<int32_t>(), L.meshes.as<TsMesh>(), L.waves.as<float>(), L.nsteps.as<int32_t>(),
+        L.tri_word.as<uint32_t>(),
         L.tri_invS.as<float>(), L.tri_O.as<float>(), L.edge_RL.as<uint32_t>(), L.ebyd.as<float>(),
         L.gamma.as<float>(), inv_mw, L.eps.as<double>(), L.wave_grad.as<float>(), L.n);
     k_loss<<<1, 1024, 0, s>>>(int(L.M * L.W), L.eps.as<double>(), inv_mw, L.loss.as<double>());
@@ -687,6 +692,10 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         if (!rc) rc = upload_vec(L->tri_O, O, s);
         if (!rc) rc = upload_vec(L->waves, wv, s);
         if (!rc) rc = upload_vec(L->nsteps, steps, s);
+        std::vector<int32_t> ord(steps.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return steps[a] > steps[b]; });
+        if (!rc) rc = upload_vec(L->order, ord, s);
         if (!rc) rc = upload_vec(L->meshes, info, s);
         if (!rc) rc = L->gamma.alloc(L->n * sizeof(float));
         if (!rc) rc = L->eps.alloc(n_meshes * n_waves * sizeof(double));
