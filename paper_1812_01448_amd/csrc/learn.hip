@@ -24,7 +24,11 @@
 //                   (up to 4096 triangles), each work-item keeps its triangles' state and its
 //                   edges' accumulators in registers; forward pass, then the reversed pass
 //                   with the per-edge accumulation; writes eps and the wave's share of dL/dgamma;
+//                   work-groups are dispatched longest recurrence first, so the last ones to
+//                   start are short and the launch ends with little idle time;
 //   k_wave_sum      per edge: dL/dgamma summed over the waves in wave order;
+//   k_stiff_reg     per stiff edge (d/|e| below a threshold): the pull of gamma toward its
+//                   target, added to dL/dgamma (it lowers omega_max, so the eq. 20 step grows);
 //   k_loss          one block: the loss from the eps values;
 //   k_mlp_backward  per block: forward + backward of its edges, the per-edge activation and
 //                   delta vectors staged in LDS, then each work-item accumulates the gradient
