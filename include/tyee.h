@@ -414,6 +414,13 @@ int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *re
 
 void tyee_batch_destroy(tyee_batch *b);
 
+/* Achievable device bandwidth, the reference beside the published HBM peak in roofline
+   reports: copies `bytes` (1 MiB .. 16 GiB) between two device buffers `reps` times with
+   16-byte non-temporal loads and stores (one element per work-item) on a stream of its own,
+   timed with HIP events; *gbs = bytes read + written per second / 1e9.  Allocates and frees
+   its two buffers.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
+
 const char *tyee_last_error(void);
 
 #ifdef __cplusplus

@@ -516,6 +516,71 @@ template <typename T> int download_vec(const DeviceBuffer &buf, std::vector<T> &
     return TYEE_OK;
 }
 
+// Overlap of a complex plane-wave state held by two simulations (real and imaginary parts)
+// with its initial value: z = sum_i cE_i (Et0_i + i Et1_i) + sum_j cB_j (B0_j + i B1_j), the
+// weights cE = (d/gamma) conj(E0) and cB = S conj(B0) in device numbering (metric (7) with
+// the scaled edge field).  FP64 partial sums per block, added on the host in block order.
+constexpr int kOverlapThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kOverlapThreads) void k_overlap(int ne, int nt, const T *__restrict__ Et0,
+                                                            const T *__restrict__ Et1, const T *__restrict__ B0,
+                                                            const T *__restrict__ B1, const double2 *__restrict__ cE,
+                                                            const double2 *__restrict__ cB,
+                                                            double *__restrict__ partial) {
+    __shared__ double red[2][kOverlapThreads];
+    const int i = blockIdx.x * kOverlapThreads + threadIdx.x;
+    double zr = 0.0, zi = 0.0;
+    if (i < ne) {
+        const double a = double(Et0[i]), b = double(Et1[i]);
+        const double2 c = cE[i];
+        zr += a * c.x - b * c.y;
+        zi += a * c.y + b * c.x;
+    }
+    if (i < nt) {
+        const double a = double(B0[i]), b = double(B1[i]);
+        const double2 c = cB[i];
+        zr += a * c.x - b * c.y;
+        zi += a * c.y + b * c.x;
+    }
+    const int t = threadIdx.x;
+    red[0][t] = zr;
+    red[1][t] = zi;
+    __syncthreads();
+    for (int h = kOverlapThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 2) partial[2 * size_t(blockIdx.x) + t] = red[t][0];
+}
+
+template <typename T>
+int overlap(Sim &s0, Sim &s1, const DeviceBuffer &cE, const DeviceBuffer &cB, DeviceBuffer &partial, double *zr,
+            double *zi) {
+    const int64_t n = std::max(s0.ne, s0.nt);
+    const int nb = int((n + kOverlapThreads - 1) / kOverlapThreads);
+    int rc = partial.alloc(size_t(2) * nb * sizeof(double));
+    if (rc) return rc;
+    TYEE_HIP(hipStreamSynchronize(s1.stream));
+    k_overlap<T><<<nb, kOverlapThreads, 0, s0.stream>>>(int(s0.ne), int(s0.nt), s0.Et().as<T>(), s1.Et().as<T>(),
+                                                        s0.B().as<T>(), s1.B().as<T>(), cE.as<double2>(),
+                                                        cB.as<double2>(), partial.as<double>());
+    TYEE_HIP(hipGetLastError());
+    std::vector<double> part;
+    rc = download_vec(partial, part, size_t(2) * nb, s0.stream);
+    if (rc) return rc;
+    *zr = *zi = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        *zr += part[2 * size_t(b)];
+        *zi += part[2 * size_t(b) + 1];
+    }
+    return TYEE_OK;
+}
+
+
 }  // namespace
 }  // namespace tyee
 
@@ -880,7 +945,8 @@ extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double 
         if (!rc && gamma) rc = tyee_sim_set_edge_scale(sims[r], gamma);
         if (!rc) rc = tyee_sim_set_fusion(sims[r], 4, 0);
     }
-    std::vector<double> Er(m.ne), Ei(m.ne), Br(m.nt), Bi(m.nt), E[2], B[2];
+    std::vector<double> Er(m.ne), Ei(m.ne), Br(m.nt), Bi(m.nt);
+    DeviceBuffer dcE, dcB, dpart;
     for (int64_t wv = 0; wv < n_waves && !rc; ++wv) {
         const double kx = waves[2 * wv], kz = waves[2 * wv + 1], kn = std::hypot(kx, kz);
         if (!(kn > 0.0)) {
@@ -909,25 +975,30 @@ extern "C" int tyee_phase_error_timestepped(const tyee_mesh *mesh, const double 
         const int64_t nsteps = std::max<int64_t>(samples, int64_t(std::nearbyint(phase / (kn * dt))));
         const int64_t chunk = nsteps / samples;
         double st = 0, sp = 0, stt = 0, stp = 0, prev = 0.0, unwrap = 0.0;
+        // overlap weights of this wave in device numbering: (d/gamma) conj(E0), S conj(B0)
+        Sim &s0 = sims[0]->s, &s1 = sims[1]->s;
+        std::vector<double> cE(2 * m.ne), cB(2 * m.nt);
+        for (int64_t k = 0; k < m.ne; ++k) {
+            const int32_t i = s0.perm_e[k];
+            const double f = m.interior(i) ? w[i] / s0.scale(i) : 0.0;  // d |e| / (gamma |e|)
+            cE[2 * k] = f * Er[i];
+            cE[2 * k + 1] = -f * Ei[i];
+        }
+        for (int64_t k = 0; k < m.nt; ++k) {
+            const int32_t j = s0.perm_t[k];
+            cB[2 * k] = m.S[j] * Br[j];
+            cB[2 * k + 1] = -m.S[j] * Bi[j];
+        }
+        rc = upload_vec(dcE, cE, s0.stream);
+        if (!rc) rc = upload_vec(dcB, cB, s0.stream);
         for (int64_t q = 0; q < samples && !rc; ++q) {
-            for (int r = 0; r < 2 && !rc; ++r) {
-                rc = tyee_sim_step(sims[r], chunk);
-                E[r].resize(m.ne);
-                B[r].resize(m.nt);
-                if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_E, E[r].data());
-                if (!rc) rc = tyee_sim_get_state(sims[r], TYEE_FIELD_B, B[r].data());
-            }
+            for (int r = 0; r < 2 && !rc; ++r) rc = tyee_sim_step(sims[r], chunk);
             if (rc) break;
-            // z = sum w E conj(E0) + sum S B conj(B0)  (metric (7))
+            // z = sum w E conj(E0) + sum S B conj(B0)  (metric (7)), reduced on the device
             double zr = 0.0, zi = 0.0;
-            for (int64_t i = 0; i < m.ne; ++i) {
-                zr += w[i] * (E[0][i] * Er[i] + E[1][i] * Ei[i]);
-                zi += w[i] * (E[1][i] * Er[i] - E[0][i] * Ei[i]);
-            }
-            for (int64_t j = 0; j < m.nt; ++j) {
-                zr += m.S[j] * (B[0][j] * Br[j] + B[1][j] * Bi[j]);
-                zi += m.S[j] * (B[1][j] * Br[j] - B[0][j] * Bi[j]);
-            }
+            rc = s0.f64 ? overlap<double>(s0, s1, dcE, dcB, dpart, &zr, &zi)
+                        : overlap<float>(s0, s1, dcE, dcB, dpart, &zr, &zi);
+            if (rc) break;
             const double ph = -std::atan2(zi, zr);
             if (q > 0) {
                 double dphi = ph - prev;

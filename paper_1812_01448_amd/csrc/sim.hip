@@ -487,6 +487,16 @@ template <typename T> int device_diagnostics(Sim &s, double *sums) {
 
 }  // namespace
 
+// Device copy-rate probe: one 16-byte element per work-item, non-temporal loads and stores
+// (streaming data that is not reused), the form that reaches the highest copy rate.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy_probe(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst,
+                                                    int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 }  // namespace tyee
 
 // ---------------------------------------------------------------------------------------
@@ -766,6 +776,42 @@ int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[6]) {
     out[4] = built ? s.tiling->sumE : 0;
     out[5] = built ? s.tiling->n_sp_tiles : 0;
     return TYEE_OK;
+}
+
+int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs) {
+    if (!gbs || bytes < (int64_t(1) << 20) || bytes > (int64_t(1) << 34) || reps < 1 || reps > 1000)
+        return fail(TYEE_EINVAL, "bytes must be in [1 MiB, 16 GiB] and reps in [1, 1000]");
+    const int64_t n = bytes / 16;
+    tyee::DeviceBuffer a, b;
+    int rc = a.alloc(size_t(n) * 16);
+    if (!rc) rc = b.alloc(size_t(n) * 16);
+    if (rc) return rc;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TYEE_HIP(hipStreamCreate(&st));
+    auto done = [&](int code) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+        return code;
+    };
+    if (hipMemsetAsync(a.p, 0, size_t(n) * 16, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        return done(fail(TYEE_EDEVICE, "copy probe set-up failed"));
+    const int64_t blocks = (n + 255) / 256;
+    const tyee::f32x4 *src = a.as<tyee::f32x4>();
+    tyee::f32x4 *dst = b.as<tyee::f32x4>();
+    tyee::k_copy_probe<<<dim3(unsigned(blocks)), 256, 0, st>>>(src, dst, n);  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) tyee::k_copy_probe<<<dim3(unsigned(blocks)), 256, 0, st>>>(src, dst, n);
+    (void)hipEventRecord(e1, st);
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return done(fail(TYEE_EDEVICE, "copy probe launch failed"));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *gbs = 2.0 * double(n) * 16.0 * reps / (double(ms) * 1e-3) / 1e9;
+    return done(TYEE_OK);
 }
 
 int tyee_sim_gauss(tyee_sim *sim, double *out) {

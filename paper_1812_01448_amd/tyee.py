@@ -80,7 +80,7 @@ EXPORTS = [
     "tyee_learner_create", "tyee_learner_init", "tyee_learner_set_params",
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
-    "tyee_learner_regulariser",
+    "tyee_learner_regulariser", "tyee_copy_bandwidth",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -143,6 +143,7 @@ def _load():
         "tyee_gate": [vp, vp, vp, i64, f64, f64, i32, vp, ctypes.POINTER(_Gate)],
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
+        "tyee_copy_bandwidth": [i64, i32, ctypes.POINTER(f64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -277,6 +278,14 @@ class Mesh:
         rc = _check(lib.tyee_mesh_cfl(self._h, _ptr(g), int(max_iter), float(rtol), int(seed),
                                       ctypes.byref(lam), ctypes.byref(it)), allow=(ENOTCONVERGED,))
         return lam.value, it.value, rc == OK
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device copy rate in GB/s (bytes read + written per second) with 16-byte non-temporal
+    loads and stores: the achievable-bandwidth reference beside the HBM peak."""
+    g = ctypes.c_double()
+    _check(lib.tyee_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)))
+    return g.value
 
 
 class Sim:
