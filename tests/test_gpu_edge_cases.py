@@ -176,3 +176,10 @@ def test_graph_replay_equals_eager_launches(ty, fusion):
             sim.step(chunk)
         out.append((sim.get_state("E"), sim.get_state("B")))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_copy_probe_rate_is_plausible(ty):
+    _note("case: device copy-rate probe, 256 MiB x 5")
+    gbs = ty.copy_bandwidth(256 << 20, 5)
+    _note(f"  {gbs:.0f} GB/s")
+    assert 1000.0 < gbs < 8000.0 * 1.05        # below the published 8 TB/s peak

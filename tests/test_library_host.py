@@ -120,3 +120,9 @@ def test_phase_error_needs_a_periodic_mesh(ty):
     m = ty.Mesh(xy, tri, False)
     with pytest.raises(ty.TyeeError):
         m.phase_error_timestepped(1e-3, np.array([2 * np.pi, 0.0]))
+
+
+def test_copy_probe_rejects_bad_sizes(ty):
+    for nbytes, reps in ((100, 1), (1 << 20, 0), (1 << 40, 1)):
+        with pytest.raises(ty.TyeeError):
+            ty.copy_bandwidth(nbytes, reps)
