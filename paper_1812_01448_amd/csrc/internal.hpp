@@ -51,8 +51,7 @@ constexpr int kFeatures = 8;
 void edge_features(const Mesh &m, std::vector<double> &out);
 // Minimum-image O_R - O_L per edge (0 on outer edges).
 void dual_vectors(const Mesh &m, std::vector<double> &out);
-// Plane-wave phase error from the Rayleigh quotient of K_gamma (host FP64).
-double rq_phase_error(const Mesh &m, const double *gamma, double dt, double kx, double kz);
+// Plane-wave phase errors from the Rayleigh quotient of K_gamma (host FP64).
 void rq_phase_errors(const Mesh &m, const double *gamma, double dt, const double *waves, int64_t n_waves,
                      double *out);
 uint32_t morton_key(uint32_t qx, uint32_t qz);

@@ -485,13 +485,6 @@ void rq_phase_errors(const Mesh &m, const double *gamma, double dt, const double
     }
 }
 
-double rq_phase_error(const Mesh &m, const double *gamma, double dt, double kx, double kz) {
-    const double k[2] = {kx, kz};
-    double out = 0.0;
-    rq_phase_errors(m, gamma, dt, k, 1, &out);
-    return out;
-}
-
 int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out) {
     if (parts.empty()) return fail(TYEE_EINVAL, "no meshes to merge");
     out = Mesh();

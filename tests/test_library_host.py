@@ -126,3 +126,27 @@ def test_copy_probe_rejects_bad_sizes(ty):
     for nbytes, reps in ((100, 1), (1 << 20, 0), (1 << 40, 1)):
         with pytest.raises(ty.TyeeError):
             ty.copy_bandwidth(nbytes, reps)
+
+
+def test_rayleigh_quotient_diagnostic_matches_oracle(ty):
+    # host FP64 diagnostic: equals the oracle's Rayleigh-quotient phase error with and without
+    # a per-edge scale, and the honeycomb closed form on the equilateral torus
+    from oracle import learned as OL
+    xy, tri = lattice_mesh(24, 0.3, 3, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    om = oracle.OracleMesh(xy, tri, True)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    waves = 2 * np.pi * np.array([[1.0, 0.0], [2.0, 3.0], [-1.0, 4.0]])
+    gamma = 1.0 + 0.05 * np.sin(np.arange(om.ne) * 0.3)
+    for g in (None, gamma):
+        got = m.phase_error_rq(dt, waves, gamma=g)
+        ref = [OL.rq_phase_error(om, g, dt, k) for k in waves]
+        np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-14)
+    xy, tri, Lx, Ly = equilateral_torus(12, 8, a=1.0)
+    m = ty.Mesh(xy, tri, True, L=Lx, Ly=Ly)
+    delta = np.array([[0.0, -1 / np.sqrt(3)], [0.5, 1 / (2 * np.sqrt(3))], [-0.5, 1 / (2 * np.sqrt(3))]])
+    k = 2 * np.pi * np.array([2 / Lx, 1 / Ly])
+    w2 = 4.0 * (3.0 - np.sum(np.cos(delta @ k)))
+    expect = 2 / 0.1 * np.arcsin(np.sqrt(w2) * 0.1 / 2) / np.hypot(*k) - 1
+    assert abs(m.phase_error_rq(0.1, k)[0] - expect) < 1e-12
