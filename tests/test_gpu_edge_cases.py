@@ -183,3 +183,42 @@ def test_copy_probe_rate_is_plausible(ty):
     gbs = ty.copy_bandwidth(256 << 20, 5)
     _note(f"  {gbs:.0f} GB/s")
     assert 1000.0 < gbs < 8000.0 * 1.05        # below the published 8 TB/s peak
+
+
+def test_launch_timing_counts(ty):
+    # per-kind HIP-event timing counts every launch of the kinds asked for; graph replays are
+    # timed whole; the last step call's time covers its launches
+    n = 48
+    _note(f"case: torus{n} launch timing counts (single, fused, graph) and a batch's borrowed sim")
+    xy, tri = lattice_mesh(n, 0.25, 23, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    lam, _, _ = m.cfl()
+    dt = 0.5 * 2 / np.sqrt(lam)
+    sim = ty.Sim(m, dt, "f32")
+    sim.set_fusion(1, 0)
+    sim.set_profiling(True, kinds=["edge", "tri"])
+    sim.step(10)
+    t = sim.kernel_times()
+    assert t["edge"]["count"] == 10 and t["tri"]["count"] == 10 and t["edge"]["total_ms"] > 0
+    assert sim.last_step_ms() >= 0.5 * (t["edge"]["total_ms"] + t["tri"]["total_ms"])
+    sim.set_fusion(4, 0)
+    sim.set_profiling(True, kinds=["fused"])
+    sim.step(40)
+    t = sim.kernel_times()
+    assert set(t) == {"fused"} and t["fused"]["count"] == 10
+    sim.set_graph(4)
+    sim.set_profiling(True, kinds=["graph"])
+    sim.step(48)                                  # 3 replays of 4 launches of 4 steps
+    t = sim.kernel_times()
+    assert set(t) == {"graph"} and t["graph"]["count"] == 3
+    sim.set_profiling(False)
+    sim.step(8)
+    assert sim.kernel_times() == {} and sim.steps == 10 + 40 + 48 + 8
+    # a batch hands out its union's simulation for the same queries
+    b = ty.Batch([m, m], [dt, dt], "f32")
+    b.set_fusion(4, 0)
+    b.step(8)
+    u = b.sim()
+    assert u.fusion_info()["steps_per_launch"] == 4 and u.steps == 8
+    assert u.diagnostics()["nonfinite"] == 0
