@@ -26,18 +26,23 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False):
+    """Compile every source (independent objects, in parallel up to MAX_JOBS, at most 16)
+    and link libtyee.so; always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
         if src.endswith(".cpp"):
-            _run(["g++"] + HOST_FLAGS + ["-c", path, "-o", obj], verbose)
+            jobs.append((["g++"] + HOST_FLAGS + ["-c", path, "-o", obj], obj))
         elif src.endswith(".hip"):
-            _run([HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj], verbose)
-        else:
-            continue
-        objs.append(obj)
+            jobs.append(([HIPCC] + HIP_FLAGS + ["-c", path, "-o", obj], obj))
+    workers = max(1, min(16, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), len(jobs)))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()                                   # re-raises a failed compile
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp] + objs + ["-pthread"], verbose)
     os.replace(tmp, LIB)
