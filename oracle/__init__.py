@@ -1,6 +1,6 @@
 """Plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
 
-The C core in ``oracle.c`` is the reference that the GPU library is judged against. Only the
+The C core in ``oracle.c`` is the reference that the GPU library is checked against. Only the
 test-suite, the smoke check and the benchmark's CPU-baseline leg import this package; the
 library never does. ``build()`` compiles the core with gcc (-O2 -ffp-contract=off); the
 loader builds it on first use when it is missing.

@@ -4,7 +4,7 @@
  * triangular meshes", arXiv:1812.01448).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct reference that the
- * GPU library is judged against.  Only the test-suite, the smoke check and the CPU
+ * GPU library is checked against.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark may load it.  It shares no code with the library.
  *
  * Every routine is a scalar loop in the order the paper (or the reading noted beside it)

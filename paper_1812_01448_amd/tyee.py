@@ -1,8 +1,8 @@
 """Thin ctypes binding of libtyee (the C ABI declared in include/tyee.h).
 
 Argument marshalling only: every step of the solver runs in the native library. The
-library must have been built (``python -m paper_1812_01448_amd.build`` or
-``__graft_entry__.build()``); importing this module without it raises immediately.
+library must have been built (``python paper_1812_01448_amd/build.py``); importing this
+module without it raises immediately.
 """
 import ctypes
 import os
@@ -91,7 +91,7 @@ KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special":
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libtyee.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        raise ImportError(f"libtyee.so is not built ({LIB_PATH}); run python paper_1812_01448_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
