@@ -263,6 +263,19 @@ int tyee_sim_kernel_times(tyee_sim *sim, int32_t kind, int64_t *count, double *t
    first fused launch has built the tiles. */
 int tyee_sim_get_fusion(const tyee_sim *sim, int64_t out[6]);
 
+/* Zero-copy access to the fields: bind caller-owned device memory (for instance two torch
+   tensors) as the two buffers of E or B.  Fused launches read one buffer and write the other
+   (single-step launches update the current one in place); tyee_sim_current_buffer says which
+   of the two holds the state after a call.  Layout: device numbering (perm_e / perm_t of
+   tyee_mesh_view), the simulation's precision; E holds the scaled field gamma_i |e_i| E_i (0 on
+   outer edges), B holds B_j.  buf0, buf1: n_edges (E) or n_tris (B) elements each, distinct,
+   aligned to the element size, valid and not written by anyone else while bound; the current
+   state is copied into the buffer of the current parity.  NULL, NULL unbinds: the state
+   moves back into library memory.  The library never frees bound memory.  Errors: EINVAL
+   (field other than E or B, one NULL, equal or misaligned buffers), ENOMEM, EDEVICE. */
+int tyee_sim_bind_external(tyee_sim *sim, int32_t field, void *buf0, void *buf1);
+int tyee_sim_current_buffer(const tyee_sim *sim, int32_t *which);
+
 int64_t tyee_sim_steps(const tyee_sim *sim);
 void tyee_sim_destroy(tyee_sim *sim);
 

@@ -814,6 +814,44 @@ int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs) {
     return done(TYEE_OK);
 }
 
+int tyee_sim_bind_external(tyee_sim *sim, int32_t field, void *buf0, void *buf1) {
+    if (!sim) return fail(TYEE_EINVAL, "null sim");
+    if (field != TYEE_FIELD_E && field != TYEE_FIELD_B) return fail(TYEE_EINVAL, "only E and B can be bound");
+    if ((buf0 == nullptr) != (buf1 == nullptr)) return fail(TYEE_EINVAL, "give both buffers or neither");
+    tyee::Sim &s = sim->s;
+    tyee::DeviceBuffer *buf = field == TYEE_FIELD_E ? s.Et_buf : s.B_buf;
+    const size_t n = size_t(field == TYEE_FIELD_E ? s.ne : s.nt) * s.esz;
+    void *ext[2] = {buf0, buf1};
+    if (buf0) {
+        if (buf0 == buf1) return fail(TYEE_EINVAL, "the two buffers must differ");
+        for (void *e : ext)
+            if (reinterpret_cast<uintptr_t>(e) % s.esz) return fail(TYEE_EINVAL, "misaligned buffer");
+        // the current state moves into the caller's buffer of the same parity
+        if (n) TYEE_HIP(hipMemcpyAsync(ext[s.cur], buf[s.cur].p, n, hipMemcpyDeviceToDevice, s.stream));
+        TYEE_HIP(hipStreamSynchronize(s.stream));
+        for (int b = 0; b < 2; ++b) buf[b].borrow(ext[b], n);
+    } else {
+        if (buf[0].owned) return TYEE_OK;  // nothing bound
+        void *own[2] = {nullptr, nullptr};
+        for (int b = 0; b < 2; ++b)
+            if (n && hipMalloc(&own[b], n) != hipSuccess) {
+                if (own[0]) (void)hipFree(own[0]);
+                return fail(TYEE_ENOMEM, "hipMalloc failed");
+            }
+        if (n) TYEE_HIP(hipMemcpyAsync(own[s.cur], buf[s.cur].p, n, hipMemcpyDeviceToDevice, s.stream));
+        TYEE_HIP(hipStreamSynchronize(s.stream));
+        for (int b = 0; b < 2; ++b) buf[b].adopt(own[b], n);
+    }
+    s.graph_dirty = true;  // graphs hold buffer addresses
+    return TYEE_OK;
+}
+
+int tyee_sim_current_buffer(const tyee_sim *sim, int32_t *which) {
+    if (!sim || !which) return fail(TYEE_EINVAL, "null argument");
+    *which = sim->s.cur;
+    return TYEE_OK;
+}
+
 int tyee_sim_gauss(tyee_sim *sim, double *out) {
     if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
     tyee::Sim &s = sim->s;

@@ -33,13 +33,18 @@ inline int blocks_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 struct DeviceBuffer {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;  // false: caller memory bound with tyee_sim_bind_external
+    DeviceBuffer() = default;
+    DeviceBuffer(const DeviceBuffer &) = delete;
+    DeviceBuffer &operator=(const DeviceBuffer &) = delete;
     ~DeviceBuffer() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
     }
     // (Re)allocate n bytes; an existing buffer of the same size is kept, so device
     // addresses captured in a graph stay valid across state uploads.
     int alloc(size_t n) {
         if (p && bytes == n) return TYEE_OK;
+        if (!owned) return fail(TYEE_EINVAL, "a bound external buffer cannot be resized");
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = n;
@@ -52,6 +57,20 @@ struct DeviceBuffer {
         return TYEE_OK;
     }
     template <typename T> T *as() const { return static_cast<T *>(p); }
+    // Use caller memory of n bytes (not freed here); frees what this buffer owned.
+    void borrow(void *ptr, size_t n) {
+        if (p && owned) (void)hipFree(p);
+        p = ptr;
+        bytes = n;
+        owned = false;
+    }
+    // Take ownership of memory allocated with hipMalloc (n bytes).
+    void adopt(void *ptr, size_t n) {
+        if (p && owned) (void)hipFree(p);
+        p = ptr;
+        bytes = n;
+        owned = true;
+    }
 };
 
 // Per-launch HIP-event timing of the stepping kernels (enabled per kernel kind).  A ring

@@ -80,7 +80,8 @@ EXPORTS = [
     "tyee_learner_create", "tyee_learner_init", "tyee_learner_set_params",
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
-    "tyee_learner_regulariser", "tyee_copy_bandwidth",
+    "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
+    "tyee_sim_current_buffer",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -89,9 +90,28 @@ KERNEL_NAMES = {"edge": "k_edge", "tri": "k_tri", "fused": "k_fused", "special":
                 "charge": "k_charge", "graph": "graph of k_fused"}
 
 
+def _preload_hip_runtime():
+    """PyTorch-ROCm wheels bundle their own HIP runtime under the same soname as the system
+    one, and a process holds only the first one loaded; torch finds no GPU when it gets a
+    runtime other than its own.  When such a wheel is installed (and torch is not imported
+    yet), load its runtime before this library, so that both share it whatever the import
+    order.  torch itself is not imported."""
+    import importlib.util
+    import sys
+    if "torch" in sys.modules:
+        return
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return
+    path = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libtyee.so is not built ({LIB_PATH}); run python paper_1812_01448_amd/build.py")
+    _preload_hip_runtime()
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -144,6 +164,8 @@ def _load():
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
         "tyee_copy_bandwidth": [i64, i32, ctypes.POINTER(f64)],
+        "tyee_sim_bind_external": [vp, i32, vp, vp],
+        "tyee_sim_current_buffer": [vp, ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -366,6 +388,24 @@ class Sim:
                 out[name] = {"count": c.value, "total_ms": t.value, "name": KERNEL_NAMES[name],
                              "steps_per_launch": self.fusion_used() if name == "fused" else 1}
         return out
+
+    def bind_external(self, field, buf0, buf1):
+        """Use two caller-owned device buffers (torch tensors or raw device addresses) for E or
+        B (device numbering, scaled E); None, None unbinds.  Tensors are kept referenced while
+        bound."""
+        def addr(b):
+            if b is None:
+                return None
+            return int(b.data_ptr()) if hasattr(b, "data_ptr") else int(b)
+        _check(lib.tyee_sim_bind_external(self._h, FIELD[field], addr(buf0), addr(buf1)))
+        self._bound = getattr(self, "_bound", {})
+        self._bound[field] = None if buf0 is None else (buf0, buf1)
+
+    def current_buffer(self):
+        """Which of the two field buffers (0 or 1) holds the current state."""
+        w = ctypes.c_int32()
+        _check(lib.tyee_sim_current_buffer(self._h, ctypes.byref(w)))
+        return w.value
 
     def set_graph(self, launches):
         """Fused launches per captured HIP graph (even; 0 = eager launches)."""
