@@ -53,6 +53,9 @@ def parse():
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (for counter calibration)")
+    p.add_argument("--copy-sweep", action="store_true",
+                   help="only print device copy rates against buffer size (torch copy and the "
+                        "library's non-temporal probe), from 16 MiB to 4 GiB per buffer")
     p.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
                                                           "COPY_WRITE_DIR"),
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs of this bench "
@@ -102,6 +105,35 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
                       "launches": 5}), flush=True)
+
+
+def copy_sweep():
+    """Copy rate (bytes read + written per second) against buffer size. torch's copy uses
+    ordinary loads and stores, whose lines the 256 MB Infinity Cache can keep between copies
+    while source and destination fit in it; the library's probe uses non-temporal loads and
+    stores. One JSON line per size."""
+    import torch
+    import paper_1812_01448_amd as ty
+    for mib in (16, 32, 64, 96, 128, 192, 256, 512, 1024, 4096):
+        nbytes = mib << 20
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        reps = max(20, int(2e9 // nbytes))
+        for _ in range(5):
+            y.copy_(x)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            y.copy_(x)
+        b.record()
+        b.synchronize()
+        us = a.elapsed_time(b) * 1e3 / reps
+        del x, y
+        torch.cuda.empty_cache()
+        nt = ty.copy_bandwidth(nbytes, min(reps, 1000))
+        print(json.dumps({"mib_per_buffer": mib, "torch_copy_GBs": round(2 * nbytes / us / 1e3, 1),
+                          "torch_copy_us": round(us, 2), "nt_probe_GBs": round(nt, 1),
+                          "reps": reps}), flush=True)
 
 
 def _pmc_values(folder, counter):
@@ -192,6 +224,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.copy_sweep:
+        copy_sweep()
         return
     if args.traffic_summary:
         traffic_summary(args)
