@@ -60,7 +60,7 @@ typedef enum {
     TYEE_ENOMEM = -6,        /* host or device allocation failed */
     TYEE_EDEVICE = -7,       /* a HIP runtime call failed */
     TYEE_EUNSTABLE = -8,     /* non-finite field detected */
-    TYEE_ENOTCONVERGED = -9  /* power iteration hit max_iter */
+    TYEE_ENOTCONVERGED = -9  /* an iteration hit its limit (power iteration, modes) */
 } tyee_status;
 
 typedef enum { TYEE_PEC_BOX = 0, TYEE_PERIODIC = 1 } tyee_domain_kind;
@@ -433,6 +433,52 @@ void tyee_batch_destroy(tyee_batch *b);
    timed with HIP events; *gbs = bytes read + written per second / 1e9.  Allocates and frees
    its two buffers.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
+
+/* Work done by one tyee_mesh_modes call. */
+typedef struct {
+    int32_t iters;         /* outer iterations (filter, orthonormalisation, Rayleigh-Ritz) */
+    int64_t applies;       /* applications of K to the whole block */
+    double lambda_bound;   /* Gershgorin bound on lambda_max that closes the filter interval */
+    double filter_ms;      /* HIP-event time of the filter launches on the stream */
+    double total_ms;       /* host wall time of the call, uploads and readback included */
+} tyee_modes_stats;
+
+/* Lowest eigenmodes of the resonator (Section 2: eigenvectors of the Maxwell operator, which
+   the energy law (10) makes real and orthogonal in metric (7), and the "complex time"
+   iteration that finds them; Fig. 4).  With E eliminated, eqs. 3-4 give for B the operator
+   K = -L_E L_B, (K B)_j = (1/S_j) sum over interior edges i of j of
+   gamma_i^2 |e_i|/d_i (B_j - B_other), self-adjoint and non-negative in the weights S_j;
+   K v = lambda v, omega = sqrt(lambda); the constant field is the static mode (lambda = 0).
+   Outer edges carry E = 0 (PEC) and add nothing.
+
+   Computed on the device in FP64 by a block iteration: a polynomial filter run as the
+   three-term (leap-frog) recurrence of the shifted K, with the unwanted part of the spectrum
+   inside the eq. 20 bound (bounded) and the wanted modes outside it (growing, as in complex
+   time); S-orthonormalisation of the block (deflation in metric (7)); Rayleigh-Ritz.
+     gamma     [n_edges] per-edge scale in canonical order, or NULL.
+     n_modes   1 .. min(n_triangles, 256) lowest pairs wanted.
+     block     vectors iterated, max(n_modes, 2) .. min(n_triangles, 256); 0 chooses
+               n_modes + max(16, n_modes / 4) (capped).  n_triangles x block < 2^31.
+     degree    largest filter degree per outer iteration, 1 .. 100000; 0 chooses 64.  An
+               iteration lowers it so that the lowest Ritz value grows at most 1e10 times more
+               than the cut (the block stays well enough conditioned to orthonormalise).
+     tol       converged when ||K v_c - lambda_c v_c||_S <= tol * lambda_bound for every wanted
+               c (v_c S-normalised).
+     max_iter  outer iterations allowed (>= 1).
+     seed      start block x[j][c] = 2u - 1, u = (splitmix64(seed + j block + c) >> 11) 2^-53
+               with j canonical (the same splitmix64 as tyee_mesh_cfl).
+     stream    HIP stream, or NULL for the default stream.
+     omega2    [n_modes] host out: lambda ascending.
+     modes     [n_modes][n_triangles] host out (canonical triangle order), S-orthonormal, or NULL.
+     residual  [n_modes] host out: residual norm / lambda_bound, or NULL.
+     stats     host out, or NULL.
+   Allocates about 5 x n_triangles x block doubles of device memory for the call and frees it;
+   blocks on the stream.  Errors: EINVAL (arguments; a mesh with no interior edge), ENOMEM,
+   EDEVICE, EUNSTABLE (the block lost rank), ENOTCONVERGED (outputs are still written from the
+   last iteration). */
+int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64_t n_modes, int32_t block,
+                    int32_t degree, double tol, int32_t max_iter, uint64_t seed, void *stream,
+                    double *omega2, double *modes, double *residual, tyee_modes_stats *stats);
 
 const char *tyee_last_error(void);
 

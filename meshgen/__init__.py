@@ -12,7 +12,7 @@ no stepping. It produces
 
 Every random draw comes from ``numpy.random.default_rng(seed)``.
 """
-from .lattice import (lattice_mesh, incircle, lawson_flip, count_non_delaunay, equilateral_torus,
+from .lattice import (lattice_mesh, box_mesh, box_tri_mesh, incircle, lawson_flip, count_non_delaunay, equilateral_torus,
                       triangle_centroids, scramble)
 from .fields import (cavity_mode, plane_wave_packet, periodic_wavevector,
                      random_angle, source_waveform)
@@ -21,7 +21,7 @@ from .media import (triangle_particle_mask, line_source_pairs, conforming_partic
 from .workloads import WORKLOADS, make_workload, plasma_workload
 
 __all__ = [
-    "lattice_mesh", "incircle", "lawson_flip", "count_non_delaunay", "triangle_centroids",
+    "lattice_mesh", "box_mesh", "box_tri_mesh", "incircle", "lawson_flip", "count_non_delaunay", "triangle_centroids",
     "scramble", "equilateral_torus", "cavity_mode", "plane_wave_packet", "periodic_wavevector", "random_angle",
     "source_waveform", "triangle_particle_mask", "line_source_pairs", "conforming_particle_mesh",
     "particle_corners", "WORKLOADS", "make_workload", "plasma_workload",

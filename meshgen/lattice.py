@@ -88,6 +88,81 @@ def lattice_mesh(n, jitter, seed, periodic, L=1.0):
     return xy, tri
 
 
+def box_mesh(nx, ny, jitter, seed, h=1.0):
+    """Delaunay triangulation of a jittered lattice filling the closed box [0, nx h] x [0, ny h].
+
+    (nx + 1) x (ny + 1) points with spacing h; points on the box sides stay fixed, interior
+    points move by U(-jitter*h, +jitter*h) per axis. Node (i, j) has index j*(nx+1) + i.
+    Returns (xy float64[n_v, 2], tri int32[2 nx ny, 3], Lx, Ly); triangles counter-clockwise.
+    """
+    nx, ny = int(nx), int(ny)
+    if nx < 1 or ny < 1:
+        raise ValueError("box needs nx, ny >= 1")
+    rng = np.random.default_rng(seed)
+    j, i = np.meshgrid(np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    jit = rng.uniform(-jitter, jitter, size=(len(i), 2))
+    jit[(i == 0) | (i == nx) | (j == 0) | (j == ny)] = 0.0
+    xy = (np.stack([i, j], axis=1).astype(np.float64) + jit) * h
+    xy[i == nx, 0] = nx * h
+    xy[j == ny, 1] = ny * h
+    qj, qi = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    qi, qj = qi.ravel(), qj.ravel()
+    idx = lambda ii, jj: jj * (nx + 1) + ii
+    a, b, c, d = idx(qi, qj), idx(qi + 1, qj), idx(qi + 1, qj + 1), idx(qi, qj + 1)
+    use_bd = incircle(xy[a], xy[b], xy[c], xy[d]) > 0.0
+    t1 = np.where(use_bd[:, None], np.stack([a, b, d], 1), np.stack([a, b, c], 1))
+    t2 = np.where(use_bd[:, None], np.stack([b, c, d], 1), np.stack([a, c, d], 1))
+    tri = np.concatenate([t1, t2], axis=0).astype(np.int32)
+    tri, _ = lawson_flip(xy, tri, False, max(nx, ny) * h)
+    return xy, tri, nx * h, ny * h
+
+
+def box_tri_mesh(Lx, Ly, h, jitter, seed):
+    """Delaunay triangulation of a jittered triangular lattice filling the box [0, Lx] x [0, Ly].
+
+    Rows are hy = Ly / round(Ly / (h sqrt(3)/2)) apart; even rows hold nx + 1 points at
+    x = k hx (hx = Lx / round(Lx / h)), odd rows are shifted by hx/2 and close with a point on
+    each side, so nearly every triangle is close to equilateral. Points on the box sides stay
+    fixed; the others move by U(-jitter*hx, +jitter*hx) per axis. Neighbouring rows are joined
+    by merging them in x order, and Lawson flips make the result Delaunay.
+    Returns (xy float64[n_v, 2], tri int32[n_t, 3], Lx, Ly); triangles counter-clockwise.
+    """
+    nx = max(1, int(round(Lx / h)))
+    ny = max(1, int(round(Ly / (h * np.sqrt(3.0) / 2.0))))
+    hx, hy = Lx / nx, Ly / ny
+    rng = np.random.default_rng(seed)
+    rows, pts = [], []
+    for r in range(ny + 1):
+        xs = np.arange(nx + 1) * hx if r % 2 == 0 else \
+            np.concatenate([[0.0], (np.arange(nx) + 0.5) * hx, [Lx]])
+        ids = np.arange(len(xs)) + sum(len(p) for p in pts)
+        p = np.stack([xs, np.full(len(xs), r * hy)], axis=1)
+        pts.append(p)
+        rows.append(ids)
+    xy = np.concatenate(pts)
+    jit = rng.uniform(-jitter, jitter, size=xy.shape) * hx
+    side = (xy[:, 0] <= 0.0) | (xy[:, 0] >= Lx) | (xy[:, 1] <= 0.0) | (xy[:, 1] >= Ly)
+    jit[side] = 0.0
+    xy = xy + jit
+    tri = []
+    for r in range(ny):
+        lo, hi = rows[r], rows[r + 1]
+        i = k = 0
+        while i < len(lo) - 1 or k < len(hi) - 1:
+            # advance along the row whose next point lies further left
+            step_lo = k == len(hi) - 1 or (i < len(lo) - 1 and xy[lo[i + 1], 0] <= xy[hi[k + 1], 0])
+            if step_lo:
+                tri.append((lo[i], lo[i + 1], hi[k]))
+                i += 1
+            else:
+                tri.append((lo[i], hi[k + 1], hi[k]))
+                k += 1
+    tri = np.array(tri, dtype=np.int32)
+    tri, _ = lawson_flip(xy, tri, False, max(Lx, Ly))
+    return xy, tri, float(Lx), float(Ly)
+
+
 def _interior_pairs(tri, nv):
     """Half-edge index pairs (t*3+q) that share an undirected edge."""
     u = tri.reshape(-1).astype(np.int64)

@@ -6,8 +6,9 @@ library never does. ``build()`` compiles the core with gcc (-O2 -ffp-contract=of
 loader builds it on first use when it is missing.
 
 Python-side helpers here are the evaluation formulas that sit on top of the stepper:
-plasma-frequency averaging onto edges, source lookup by node pairs, and the plane-wave phase
-overlap used for the dispersion metric.
+plasma-frequency averaging onto edges, source lookup by node pairs, the plane-wave phase
+overlap used for the dispersion metric, and the resonator modes (eigenpairs of K = -L_E L_B
+from the core's own operators and a library symmetric eigensolver).
 
 Parity unpinned: `OracleMesh.edge_wp2` (the half-dual weighted average of per-triangle plasma
 frequencies onto an edge of the particle boundary; the paper gives no rule) and the source
@@ -160,6 +161,89 @@ class OracleMesh:
         g = None if gamma is None else np.ascontiguousarray(gamma, np.float64)
         _load().orc_apply_LE(self._h, _p(g), _p(E), _p(out))
         return out
+
+    def sparse_ops(self, gamma=None):
+        """L_B (n_e x n_t) and L_E (n_t x n_e) as sparse matrices, read off this core's own
+        operators: a row of L_B touches the two triangles of its edge, a row of L_E the three
+        edges of its triangle, so applying each operator to the indicator of one colour class
+        of a greedy colouring (no two columns of one row share a colour) yields every
+        coefficient of that class at once."""
+        import scipy.sparse as sp
+
+        def colour(rows):
+            # rows: [n_rows, k] column ids (-1 = none); colour columns so that each row's
+            # columns differ
+            ncol = int(rows.max()) + 1
+            col = np.full(ncol, -1, np.int64)
+            users = [[] for _ in range(ncol)]
+            for r, cs in enumerate(rows.tolist()):
+                for c in cs:
+                    if c >= 0:
+                        users[c].append(r)
+            for c in range(ncol):
+                taken = {int(col[o]) for r in users[c] for o in rows[r] if o >= 0 and o != c}
+                k = 0
+                while k in taken:
+                    k += 1
+                col[c] = k
+            return col
+
+        tri_of_edge = np.stack([self.R, self.L], 1)
+        ct = colour(tri_of_edge)
+        r_idx, c_idx, val = [], [], []
+        for k in range(int(ct.max()) + 1):
+            y = self.apply_LB((ct == k).astype(np.float64), gamma)
+            for side in (self.R, self.L):
+                hit = (side >= 0) & (ct[np.maximum(side, 0)] == k) & (y != 0.0)
+                r_idx.append(np.nonzero(hit)[0])
+                c_idx.append(side[hit])
+                val.append(y[hit])
+        LB = sp.csr_matrix((np.concatenate(val), (np.concatenate(r_idx), np.concatenate(c_idx))),
+                           shape=(self.ne, self.nt))
+        ce = colour(self.A)
+        r_idx, c_idx, val = [], [], []
+        rows = np.arange(self.nt)
+        for k in range(int(ce.max()) + 1):
+            y = self.apply_LE((ce == k).astype(np.float64), gamma)
+            for q in range(3):
+                e = self.A[:, q]
+                hit = (ce[e] == k) & (y != 0.0)
+                r_idx.append(rows[hit])
+                c_idx.append(e[hit])
+                val.append(y[hit])
+        LE = sp.csr_matrix((np.concatenate(val), (np.concatenate(r_idx), np.concatenate(c_idx))),
+                           shape=(self.nt, self.ne))
+        return LB, LE
+
+    def modes(self, count, gamma=None):
+        """Lowest `count` eigenpairs of K = -L_E L_B, the operator that eqs. 3-4 give for B
+        once E is eliminated (Section 2, eigenvectors and the "complex time" method).
+
+        K is self-adjoint and non-negative in the B part of metric (7) (weights S_j), so
+        S^(1/2) K S^(-1/2) is symmetric; its eigenpairs come from a library symmetric solver
+        (dense for up to 4,000 triangles, else sparse shift-invert about a point just below
+        zero). Returns (lam ascending [count], V [n_t, count]) with sum_j S_j V_jc V_jd =
+        delta_cd; omega = sqrt(lam). The constant B is the static mode (lam = 0).
+        """
+        import scipy.linalg
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as sla
+        count = int(count)
+        if not 1 <= count <= self.nt:
+            raise OracleError(EINVAL, "modes count")
+        LB, LE = self.sparse_ops(gamma)
+        K = -(LE @ LB)
+        rs, irs = np.sqrt(self.S), 1.0 / np.sqrt(self.S)
+        A = sp.diags(rs) @ K @ sp.diags(irs)
+        A = 0.5 * (A + A.T)
+        if self.nt <= 4000:
+            lam, U = scipy.linalg.eigh(A.toarray(), subset_by_index=[0, count - 1])
+        else:
+            top = float(abs(A).sum(axis=1).max())
+            lam, U = sla.eigsh(A.tocsc(), k=count, sigma=-1e-6 * top, which="LM")
+            order = np.argsort(lam)
+            lam, U = lam[order], U[:, order]
+        return lam, irs[:, None] * U
 
     # -- media and sources defined on the input ----------------------------------------
     def edge_wp2(self, wp2_tri):

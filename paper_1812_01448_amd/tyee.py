@@ -59,6 +59,12 @@ class _Gate(ctypes.Structure):
                 ("err_plain", ctypes.c_double), ("err_learned", ctypes.c_double)]
 
 
+class _ModesStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("applies", ctypes.c_int64),
+                ("lambda_bound", ctypes.c_double), ("filter_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
 class _Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
                 ("energy_h", ctypes.c_double), ("max_abs_E", ctypes.c_double),
@@ -81,7 +87,7 @@ EXPORTS = [
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
-    "tyee_sim_current_buffer",
+    "tyee_sim_current_buffer", "tyee_mesh_modes",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -166,6 +172,8 @@ def _load():
         "tyee_copy_bandwidth": [i64, i32, ctypes.POINTER(f64)],
         "tyee_sim_bind_external": [vp, i32, vp, vp],
         "tyee_sim_current_buffer": [vp, ctypes.POINTER(i32)],
+        "tyee_mesh_modes": [vp, vp, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
+                            ctypes.POINTER(_ModesStats)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -300,6 +308,30 @@ class Mesh:
         rc = _check(lib.tyee_mesh_cfl(self._h, _ptr(g), int(max_iter), float(rtol), int(seed),
                                       ctypes.byref(lam), ctypes.byref(it)), allow=(ENOTCONVERGED,))
         return lam.value, it.value, rc == OK
+
+
+    def modes(self, n_modes, gamma=None, block=0, degree=0, tol=1e-10, max_iter=200, seed=0,
+              stream=None, want_vectors=True):
+        """Lowest n_modes eigenpairs of K = -L_E L_B on the device (FP64).
+
+        Returns a dict: omega2 [n_modes] ascending, modes [n_modes, n_t] (canonical triangle
+        order, S-orthonormal; None unless want_vectors), residual [n_modes] (relative to the
+        Gershgorin bound), converged, and the call's stats (iters, applies, lambda_bound,
+        filter_ms, total_ms)."""
+        n_modes = int(n_modes)
+        om2 = np.zeros(n_modes)
+        vec = np.zeros((n_modes, self.nt)) if want_vectors else None
+        res = np.zeros(n_modes)
+        st = _ModesStats()
+        g = None if gamma is None else _f64(gamma, self.ne)
+        rc = _check(lib.tyee_mesh_modes(self._h, _ptr(g), n_modes, int(block), int(degree),
+                                        float(tol), int(max_iter), int(seed),
+                                        None if stream is None else int(stream), _ptr(om2),
+                                        _ptr(vec), _ptr(res), ctypes.byref(st)),
+                    allow=(ENOTCONVERGED,))
+        out = {"omega2": om2, "modes": vec, "residual": res, "converged": rc == OK}
+        out.update({n: getattr(st, n) for n, _ in _ModesStats._fields_})
+        return out
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

@@ -128,6 +128,20 @@ def test_copy_probe_rejects_bad_sizes(ty):
             ty.copy_bandwidth(nbytes, reps)
 
 
+def test_mode_solver_rejects_bad_arguments(ty):
+    # all checked on the host before any device call
+    xy, tri = lattice_mesh(6, 0.2, 1, periodic=False)        # 50 triangles
+    m = ty.Mesh(xy, tri, False)
+    bad = [dict(n_modes=0), dict(n_modes=51), dict(n_modes=300),
+           dict(n_modes=10, block=9), dict(n_modes=10, block=51), dict(n_modes=1, block=1),
+           dict(n_modes=10, degree=-1), dict(n_modes=10, degree=100001),
+           dict(n_modes=10, tol=0.0), dict(n_modes=10, max_iter=0)]
+    for kw in bad:
+        with pytest.raises(ty.TyeeError) as e:
+            m.modes(**kw)
+        assert e.value.code == -1, kw                          # TYEE_EINVAL
+
+
 def test_rayleigh_quotient_diagnostic_matches_oracle(ty):
     # host FP64 diagnostic: equals the oracle's Rayleigh-quotient phase error with and without
     # a per-edge scale, and the honeycomb closed form on the equilateral torus

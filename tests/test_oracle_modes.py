@@ -1,0 +1,91 @@
+"""Pins of the oracle's lowest-mode solver (``OracleMesh.modes``) against facts from outside it.
+
+* its sparse operators equal the C core's operators applied to unit vectors;
+* the equilateral torus gives the honeycomb closed form, all modes;
+* a closed box gives the resonator frequencies pi sqrt((m/Lx)^2 + (n/Ly)^2) with second-order
+  convergence, through the dense and the sparse solver;
+* the top mode equals the C core's power iteration; a uniform scale gamma multiplies every
+  eigenvalue by gamma^2;
+* every pair is an eigenpair of the C core's matrix-free operator, S-orthonormal, with one
+  static (zero) mode on a connected mesh.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from meshgen import lattice_mesh, box_mesh, equilateral_torus
+
+SQ3 = np.sqrt(3.0)
+
+
+def test_sparse_operators_equal_unit_vector_application():
+    for periodic in (False, True):
+        xy, tri = lattice_mesh(9, 0.25, 4, periodic=periodic)
+        m = oracle.OracleMesh(xy, tri, periodic)
+        gamma = 1.0 + 0.1 * np.cos(np.arange(m.ne))
+        for g in (None, gamma):
+            LB, LE = m.sparse_ops(g)
+            LBd = np.stack([m.apply_LB(np.eye(m.nt)[j], g) for j in range(m.nt)], axis=1)
+            LEd = np.stack([m.apply_LE(np.eye(m.ne)[i], g) for i in range(m.ne)], axis=1)
+            assert np.array_equal(LB.toarray(), LBd) and np.array_equal(LE.toarray(), LEd)
+
+
+def test_all_modes_of_the_equilateral_torus_are_the_honeycomb_closed_form():
+    nx, ny, a = 6, 4, 1.0
+    xy, tri, Lx, Ly = equilateral_torus(nx, ny, a)
+    m = oracle.OracleMesh(xy, tri, True, Lx, Ly)
+    lam, V = m.modes(m.nt)
+    delta = np.array([[0.0, -a / SQ3], [a / 2, a / (2 * SQ3)], [-a / 2, a / (2 * SQ3)]])
+    ex = []
+    for m1 in range(nx):
+        for m2 in range(ny):
+            k = 2 * np.pi * np.array([m1 / Lx, m2 / Ly])
+            f = np.abs(np.exp(1j * delta @ k).sum())
+            ex += [4 / a ** 2 * (3 - f), 4 / a ** 2 * (3 + f)]
+    np.testing.assert_allclose(lam, np.sort(ex), atol=1e-12)
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_box_modes_converge_to_the_resonator_frequencies(sparse):
+    # box 1 x 1.5: exact omega^2 = pi^2 ((m/1)^2 + (n/1.5)^2), m, n >= 0 not both zero
+    Lx, Ly = 1.0, 1.5
+    exact = np.sort([np.pi ** 2 * ((p / Lx) ** 2 + (q / Ly) ** 2)
+                     for p in range(6) for q in range(6)])[1:9]
+    errs = []
+    for n in ((12, 24) if not sparse else (30, 60)):
+        xy, tri, _, _ = box_mesh(n, int(1.5 * n), 0.2, 3, h=1.0 / n)
+        m = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+        assert (m.nt > 4000) == (sparse and n == 60) or not sparse
+        lam, _ = m.modes(9)
+        assert abs(lam[0]) < 1e-9 * lam[1]
+        errs.append(np.max(np.abs(np.sqrt(lam[1:]) / np.sqrt(exact) - 1)))
+    assert errs[1] < errs[0] / 2.5                 # second order: about 4x per halving of h
+    assert errs[1] < (2e-3 if sparse else 1e-2)
+
+
+def test_top_mode_is_the_power_iteration_and_gamma_scales_the_spectrum():
+    xy, tri = lattice_mesh(10, 0.25, 6, periodic=True)
+    m = oracle.OracleMesh(xy, tri, True)
+    lam, _ = m.modes(m.nt)
+    top, _, ok = m.power(rtol=1e-14, max_iter=200000)
+    assert ok and abs(lam[-1] - top) < 1e-9 * top
+    lam2, _ = m.modes(20, gamma=np.full(m.ne, 1.1))
+    np.testing.assert_allclose(lam2[1:], 1.21 * lam[1:20], rtol=1e-10)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_modes_are_s_orthonormal_eigenpairs_of_the_matrix_free_operator(periodic):
+    xy, tri = lattice_mesh(14, 0.25, 8, periodic=periodic)
+    m = oracle.OracleMesh(xy, tri, periodic)
+    gamma = 1.0 + 0.05 * np.sin(np.arange(m.ne) * 0.7)
+    lam, V = m.modes(40, gamma)
+    top = m.power(gamma)[0]
+    for c in range(40):
+        kv = -m.apply_LE(m.apply_LB(V[:, c], gamma), gamma)
+        assert np.sqrt(np.sum(m.S * (kv - lam[c] * V[:, c]) ** 2)) < 1e-10 * top
+    G = V.T @ (m.S[:, None] * V)
+    assert np.max(np.abs(G - np.eye(40))) < 1e-12
+    assert np.all(lam[1:] > 1e-6 * top) and abs(lam[0]) < 1e-10 * top
+    # the static mode is the constant field
+    v0 = V[:, 0] / V[np.argmax(np.abs(V[:, 0])), 0]
+    assert np.max(np.abs(v0 - 1.0)) < 1e-9
