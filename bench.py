@@ -39,10 +39,12 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
     p.add_argument("--workload", default="torus1415",
-                   choices=["torus1415", "plasma2830", "batch256", "learned"],
+                   choices=["torus1415", "plasma2830", "batch256", "learned", "modes70x101"],
                    help="torus1415 (the reported line), plasma2830 (16M triangles with a plasma "
-                        "particle and a line source), batch256 (256 uneven meshes) or learned "
-                        "(train and evaluate the learned edge scale)")
+                        "particle and a line source), batch256 (256 uneven meshes), learned "
+                        "(train and evaluate the learned edge scale) or modes70x101 (the 128 "
+                        "lowest modes of the 70 x 101 resonator of Fig. 4; --steps timed "
+                        "solves, at most 20)")
     p.add_argument("--train-meshes", type=int, default=64)
     p.add_argument("--train-n", type=int, default=40)
     p.add_argument("--eval-meshes", type=int, default=16)
@@ -51,6 +53,8 @@ def parse():
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--graph", type=int, default=8, help="fused launches per HIP graph (0 = eager)")
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
+    p.add_argument("--modes-degree", type=int, default=0,
+                   help="modes70x101: largest filter degree per iteration (0 = library default)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (for counter calibration)")
     p.add_argument("--copy-sweep", action="store_true",
@@ -243,6 +247,9 @@ def main():
         return
     if args.workload == "plasma2830":
         bench_plasma(args)
+        return
+    if args.workload == "modes70x101":
+        bench_modes(args)
         return
 
     import torch
@@ -581,6 +588,100 @@ def bench_batch(args):
         "cpu_baseline": None if args.no_cpu else cpu_baseline_batch(sizes, dts, init_xy),
     }
     print(json.dumps(out), flush=True)
+
+
+MODES_WANTED, MODES_BLOCK, MODES_TOL = 128, 160, 1e-11
+
+
+def fig4_mesh():
+    """The 70 x 101 closed resonator of Fig. 4 at h = 1: jittered (+-0.1 h) triangular lattice."""
+    from meshgen import box_tri_mesh
+    return box_tri_mesh(70.0, 101.0, 1.0, 0.1, 0)
+
+
+def fig4_reference_curves(count, Lx=70.0, Ly=101.0, h=1.0):
+    """omega^2 of the closed resonator, lowest `count`: the continuum pi^2 ((m/Lx)^2 +
+    (n/Ly)^2) and the structured square Yee grid of spacing h (B at the Lx/h x Ly/h cell
+    centres), (4/h^2)(sin^2(m pi h/(2 Lx)) + sin^2(n pi h/(2 Ly))), m, n >= 0."""
+    nx, ny = int(round(Lx / h)), int(round(Ly / h))
+    mm, nn = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    exact = np.sort((np.pi ** 2 * ((mm / Lx) ** 2 + (nn / Ly) ** 2)).ravel())[:count]
+    quad = np.sort((4 / h ** 2 * (np.sin(mm * np.pi * h / (2 * Lx)) ** 2 +
+                                  np.sin(nn * np.pi * h / (2 * Ly)) ** 2)).ravel())[:count]
+    return exact, quad
+
+
+def bench_modes(args):
+    """Lowest 128 modes of the Fig. 4 resonator (FP64), solved on the device end to end."""
+    import torch
+    import paper_1812_01448_amd as ty
+
+    xy, tri, Lx, Ly = fig4_mesh()
+    mesh = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    mesh.reorder("morton")
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    solves = max(1, min(args.steps, 20))
+    kw = dict(block=MODES_BLOCK, degree=args.modes_degree, tol=MODES_TOL, max_iter=400,
+              stream=stream)
+    for _ in range(min(args.warmup, 1)):
+        mesh.modes(MODES_WANTED, want_vectors=False, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [mesh.modes(MODES_WANTED, want_vectors=False, **kw) for _ in range(solves)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    r = runs[-1]
+    assert all(x["converged"] for x in runs)
+    nt, nb = len(tri), MODES_BLOCK
+    filter_applies = r["applies"] - (r["iters"] + 1)
+    avg_ms = r["filter_ms"] / filter_applies
+    # per apply: read the block row and the older row, write one row (24 nb B) + tables (44 B)
+    per_launch = nt * (24 * nb + 44)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    exact, quad = fig4_reference_curves(MODES_WANTED, Lx, Ly)
+    om2 = r["omega2"]
+    rel = lambda a, b: float(np.max(np.abs(np.sqrt(a[1:]) / np.sqrt(b[1:]) - 1)))
+    log(f"{solves} solves: {r['iters']} iterations, {r['applies']} applies, filter "
+        f"{r['filter_ms']:.1f} ms of {r['total_ms']:.1f} ms")
+    out = {
+        "metric": "resonator modes/s (lowest 128, residual <= 1e-11 of the lambda bound)",
+        "value": MODES_WANTED * solves / elapsed, "unit": "modes/s", "n_gpus": 1,
+        "steps": solves, "warmup": min(args.warmup, 1), "ms_per_step": elapsed * 1e3 / solves,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Fig. 4 closed resonator 70 x 101, h = 1, jittered (+-0.1h) "
+                               "triangular-lattice Delaunay mesh", "triangles": nt,
+                   "modes": MODES_WANTED, "block": nb, "max_degree": args.modes_degree,
+                   "iterations": r["iters"],
+                   "applies": r["applies"], "lambda_bound": r["lambda_bound"]},
+        "roofline": {"bound": "hbm", "kernel": "k_modes_apply",
+                     "timed_with": "HIP events around the filter launches",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
+                     "algorithmic_bytes_per_launch": per_launch, "traffic": None,
+                     "filter_share_of_solve": round(r["filter_ms"] / r["total_ms"], 4)},
+        "fig4": {"max_rel_omega_dev_unstructured_vs_analytic": rel(om2, exact),
+                 "max_rel_omega_dev_structured_quad_vs_analytic": rel(quad, exact),
+                 "omega_mode_1_8": [float(v) for v in np.sqrt(np.abs(om2[1:9]))],
+                 "omega_analytic_1_8": [float(v) for v in np.sqrt(exact[1:9])]},
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_modes(xy, tri, Lx, Ly),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_modes(xy, tri, Lx, Ly):
+    """The oracle's lowest 128 modes of the same mesh (library sparse shift-invert solver),
+    one host thread."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        om.modes(MODES_WANTED)
+        el = time.perf_counter() - t0
+    return {"value": MODES_WANTED / el, "unit": "modes/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve of the same 128 modes ({el:.1f} s)"}
 
 
 def cpu_baseline_batch(sizes, dts, meshes_xy, samples=8):

@@ -459,8 +459,8 @@ typedef struct {
      n_modes   1 .. min(n_triangles, 256) lowest pairs wanted.
      block     vectors iterated, max(n_modes, 2) .. min(n_triangles, 256); 0 chooses
                n_modes + max(16, n_modes / 4) (capped).  n_triangles x block < 2^31.
-     degree    largest filter degree per outer iteration, 1 .. 100000; 0 chooses 64.  An
-               iteration lowers it so that the lowest Ritz value grows at most 1e10 times more
+     degree    largest filter degree per outer iteration, 1 .. 100000; 0 chooses 128.  An
+               iteration lowers it so that the lowest Ritz value grows at most 1e7 times more
                than the cut (the block stays well enough conditioned to orthonormalise).
      tol       converged when ||K v_c - lambda_c v_c||_S <= tol * lambda_bound for every wanted
                c (v_c S-normalised).

@@ -19,9 +19,9 @@
 //     and grow exponentially (the complex-time amplification).  The recurrence is the scaled
 //     Chebyshev filter of Zhou and Saad (J. Comput. Phys. 2007), which keeps the block in
 //     range;
-//   * deflation: the filtered block is made S-orthonormal (Cholesky QR three times, the first
-//     with a small diagonal shift: shifted CholeskyQR3 of Fukaya et al., SIAM J. Sci. Comput.
-//     2020), so every vector is orthogonal in metric (7) to the others;
+//   * deflation: the filtered block is made S-orthonormal (Cholesky QR twice; the shifted
+//     CholeskyQR3 of Fukaya et al., SIAM J. Sci. Comput. 2020, when a factorisation fails), so
+//     every vector is orthogonal in metric (7) to the others;
 //   * Rayleigh-Ritz: H = V^T S K V is diagonalised (cyclic Jacobi) and V rotated into Ritz
 //     vectors; the largest Ritz value of the block becomes the next a.
 // b is a Gershgorin bound on lambda_max of the symmetric form S^(1/2) K S^(-1/2).
@@ -43,6 +43,7 @@ constexpr int kMaxBlock = 256;
 constexpr int kRotRows = 16;        // rows of the block per work-group in k_rotate
 constexpr int kGramTile = 32;       // output tile of k_gram (32 x 32)
 constexpr int kGramRows = 64;       // rows staged in LDS per pass of k_gram
+constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 
 // y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null)
 __global__ void k_modes_apply(int32_t n, int32_t nb, const double *__restrict__ y,
@@ -299,6 +300,243 @@ __global__ void __launch_bounds__(256) k_jacobi(int32_t nb, double *__restrict__
     if (tid == 0) *sweeps_out = sweep;
 }
 
+// Packed upper triangle (row-major) of an nb x nb symmetric matrix: element (i, j), i <= j.
+__device__ __forceinline__ int packed(int nb, int i, int j) { return i * (2 * nb - i - 1) / 2 + j; }
+
+constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kernels
+constexpr int kInvRows = 16;          // rows of R^-1 finished per pass
+
+// The same as k_chol_inverse with g held in LDS (packed upper triangle, nb (nb + 1)/2 doubles
+// of dynamic shared memory).  R^-1 is formed from the bottom in passes of kInvRows rows: each
+// column first takes the contributions of all finished rows into kInvRows register
+// accumulators (independent loads, so they overlap), then the pass's rows are finished in
+// order.  g is only read.
+__global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, const double *__restrict__ g,
+                                                                    double shift, double *__restrict__ m,
+                                                                    int32_t *__restrict__ info) {
+    extern __shared__ double P[];
+    __shared__ int bad;
+    __shared__ double piv;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < nb * nb; e += nt) {
+        const int r = e / nb, c = e % nb;
+        if (c >= r) P[packed(nb, r, c)] = g[e] + (r == c ? shift : 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        if (tid == 0) {
+            const double d = P[packed(nb, k, k)];
+            if (!(d > 0.0) || !std::isfinite(d)) bad = k + 1;
+            else {
+                piv = std::sqrt(d);
+                P[packed(nb, k, k)] = piv;
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        const double inv = 1.0 / piv;
+        const int rowk = packed(nb, k, 0);
+        for (int c = k + 1 + tid; c < nb; c += nt) P[rowk + c] *= inv;
+        __syncthreads();
+        // trailing update of rows r > k, columns c >= r: one row of the trailing triangle per
+        // group of threads
+        const int t = nb - k - 1;
+        for (int e = tid; e < t * t; e += nt) {
+            const int r = k + 1 + e / t, c = k + 1 + e % t;
+            if (c >= r) P[packed(nb, r, c)] -= P[rowk + r] * P[rowk + c];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *info = bad;
+    if (bad) return;
+    // R M = I, M upper triangular: m[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] m[k][c]) / R[r][r]
+    for (int hi = nb; hi > 0; hi -= kInvRows) {
+        const int lo = hi > kInvRows ? hi - kInvRows : 0;
+        for (int c = tid; c < nb; c += nt) {
+            double acc[kInvRows];
+#pragma unroll
+            for (int q = 0; q < kInvRows; ++q) acc[q] = (lo + q < hi && lo + q == c) ? 1.0 : 0.0;
+            for (int k = hi; k <= c; ++k) {
+                const double mk = m[k * nb + c];
+#pragma unroll
+                for (int q = 0; q < kInvRows; ++q)
+                    if (lo + q < hi) acc[q] -= P[packed(nb, lo + q, k)] * mk;
+            }
+            // finish rows hi-1 .. lo of this column in order (entries left of the diagonal are 0)
+            for (int q = hi - lo - 1; q >= 0; --q) {
+                const int r = lo + q;
+                if (c < r) {
+                    m[r * nb + c] = 0.0;
+                    continue;
+                }
+                double a = acc[q];
+                for (int k = r + 1; k < hi && k <= c; ++k) a -= P[packed(nb, r, k)] * m[k * nb + c];
+                m[r * nb + c] = a / P[packed(nb, r, r)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Cyclic Jacobi on the symmetric h held in LDS (packed upper triangle, dynamic shared
+// memory), nb/2 disjoint rotations per round in round-robin order, one barrier per round:
+// each 2 x 2 block of h that two rotation pairs share is updated by one thread, J_s^T B J_t.
+// The rotations are written to rot[sweep][round][pair] = (c, s) for k_jacobi_vectors; on
+// return theta holds the eigenvalues ascending, order[i] the diagonal position of the i-th,
+// and sweeps_out the sweeps done.
+__global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const double *__restrict__ h,
+                                                              double2 *__restrict__ rot, double *__restrict__ theta,
+                                                              int32_t *__restrict__ order_out, int32_t max_sweeps,
+                                                              int32_t *__restrict__ sweeps_out) {
+    extern __shared__ double P[];
+    __shared__ double cs[kMaxBlock / 2 + 1], sn[kMaxBlock / 2 + 1];
+    __shared__ int pp[kMaxBlock / 2 + 1], qq[kMaxBlock / 2 + 1];
+    __shared__ double red[kSmallThreads / 64][2];
+    __shared__ int order[kMaxBlock];
+    __shared__ int rotated;            // a rotation was applied in the current sweep
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int np = nb + (nb & 1), half = np / 2;
+    if (tid == 0) rotated = 0;
+    for (int e = tid; e < nb * nb; e += nt) {
+        const int r = e / nb, c = e % nb;
+        if (c >= r) P[packed(nb, r, c)] = 0.5 * (h[r * nb + c] + h[c * nb + r]);
+    }
+    __syncthreads();
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        // off-diagonal mass against the whole matrix (wave sums, then one thread)
+        double off = 0.0, all = 0.0;
+        for (int e = tid; e < nb * nb; e += nt) {
+            const int r = e / nb, c = e % nb;
+            if (c < r) continue;
+            const double v = P[packed(nb, r, c)];
+            all += (r == c ? 1.0 : 2.0) * v * v;
+            if (r != c) off += 2.0 * v * v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            all += __shfl_xor(all, o);
+        }
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = off;
+            red[tid >> 6][1] = all;
+        }
+        __syncthreads();
+        double off_sum = 0.0, all_sum = 0.0;
+        for (int w = 0; w < nt / 64; ++w) {
+            off_sum += red[w][0];
+            all_sum += red[w][1];
+        }
+        const bool none_last = sweep > 0 && !rotated;
+        __syncthreads();
+        if (off_sum <= 1e-30 * all_sum || all_sum == 0.0 || none_last) break;
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int t = tid; t < half; t += nt) {
+                auto player = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + round) % (np - 1); };
+                const int u = player(t), v = player(np - 1 - t);
+                const int a = u < v ? u : v, b = u < v ? v : u;
+                double c = 1.0, s = 0.0;
+                if (b < nb) {
+                    const double apq = P[packed(nb, a, b)], app = P[packed(nb, a, a)], aqq = P[packed(nb, b, b)];
+                    // rotations below rounding of the two diagonal entries are skipped
+                    if (std::fabs(apq) > 1e-16 * (std::fabs(app) + std::fabs(aqq))) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = tau >= 0.0 ? 1.0 / (tau + std::sqrt(1.0 + tau * tau))
+                                                     : -1.0 / (-tau + std::sqrt(1.0 + tau * tau));
+                        c = 1.0 / std::sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                        rotated = 1;
+                    }
+                }
+                pp[t] = a;
+                qq[t] = b;
+                cs[t] = c;
+                sn[t] = s;
+                rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, s);
+            }
+            __syncthreads();
+            // block pairs (s, t), s <= t, over a half x half grid (the lower half idles)
+            for (int e = tid; e < half * half; e += nt) {
+                const int s_ = e / half, t_ = e % half;
+                if (t_ < s_) continue;
+                const int a1 = pp[s_], b1 = qq[s_], a2 = pp[t_], b2 = qq[t_];
+                const double c1 = cs[s_], s1 = sn[s_], c2 = cs[t_], s2 = sn[t_];
+                if (s_ == t_) {
+                    if (b1 >= nb || s1 == 0.0) continue;
+                    const double x = P[packed(nb, a1, a1)], y = P[packed(nb, b1, b1)], z = P[packed(nb, a1, b1)];
+                    // J^T [[x, z], [z, y]] J with J = [[c, s], [-s, c]]
+                    P[packed(nb, a1, a1)] = c1 * c1 * x - 2.0 * c1 * s1 * z + s1 * s1 * y;
+                    P[packed(nb, b1, b1)] = s1 * s1 * x + 2.0 * c1 * s1 * z + c1 * c1 * y;
+                    P[packed(nb, a1, b1)] = 0.0;
+                    continue;
+                }
+                if ((s1 == 0.0 || b1 >= nb) && (s2 == 0.0 || b2 >= nb)) continue;
+                auto at = [&](int i, int j) { return i <= j ? packed(nb, i, j) : packed(nb, j, i); };
+                const bool rb = b1 < nb, cb = b2 < nb;
+                const int i00 = at(a1, a2), i01 = cb ? at(a1, b2) : 0;
+                const int i10 = rb ? at(b1, a2) : 0, i11 = (rb && cb) ? at(b1, b2) : 0;
+                const double h00 = P[i00], h01 = cb ? P[i01] : 0.0;
+                const double h10 = rb ? P[i10] : 0.0, h11 = (rb && cb) ? P[i11] : 0.0;
+                // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
+                const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
+                const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
+                P[i00] = c2 * r00 - s2 * r01;
+                if (cb) P[i01] = s2 * r00 + c2 * r01;
+                if (rb) P[i10] = c2 * r10 - s2 * r11;
+                if (rb && cb) P[i11] = s2 * r10 + c2 * r11;
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < nb; i += nt) {
+        const double v = P[packed(nb, i, i)];
+        int rank = 0;
+        for (int k = 0; k < nb; ++k) {
+            const double u = P[packed(nb, k, k)];
+            rank += (u < v) || (u == v && k < i);
+        }
+        order[rank] = i;
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += nt) {
+        theta[i] = P[packed(nb, order[i], order[i])];
+        order_out[i] = order[i];
+    }
+    if (tid == 0) *sweeps_out = sweep;
+}
+
+// Eigenvectors from the rotation log of k_jacobi_lds: row k of Q (one work-group per row)
+// starts as e_k and takes every round's rotations of its entries, Q <- Q J; the columns are
+// then put in the order of the sorted eigenvalues.  blockDim >= nb/2.
+__global__ void k_jacobi_vectors(int32_t nb, const double2 *__restrict__ rot, const int32_t *__restrict__ sweeps,
+                                 const int32_t *__restrict__ order, double *__restrict__ q) {
+    __shared__ double row[kMaxBlock + 1];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const int np = nb + (nb & 1), half = np / 2;
+    for (int i = tid; i < np; i += blockDim.x) row[i] = i == k ? 1.0 : 0.0;
+    __syncthreads();
+    const int ns = *sweeps;
+    for (int sweep = 0; sweep < ns; ++sweep)
+        for (int round = 0; round < np - 1; ++round) {
+            if (tid < half) {
+                auto player = [&](int kk) { return kk == 0 ? 0 : 1 + (kk - 1 + round) % (np - 1); };
+                const int u = player(tid), v = player(np - 1 - tid);
+                const int a = u < v ? u : v, b = u < v ? v : u;
+                const double2 r = rot[(size_t(sweep) * (np - 1) + round) * half + tid];
+                if (b < nb && r.y != 0.0) {
+                    const double x = row[a], y = row[b];
+                    row[a] = r.x * x - r.y * y;
+                    row[b] = r.y * x + r.x * y;
+                }
+            }
+            __syncthreads();
+        }
+    for (int c = tid; c < nb; c += blockDim.x) q[k * nb + c] = row[order[c]];
+}
+
 // partial[chunk][c] = sum over the chunk's rows of S_j (kv[j][c] - theta_c v[j][c])^2
 __global__ void k_residual(int32_t n, int32_t nb, int32_t rows_per_chunk, const double *__restrict__ v,
                            const double *__restrict__ kv, const double *__restrict__ theta,
@@ -339,10 +577,11 @@ struct EventPair {
 
 struct ModeSolver {
     int32_t n = 0, nb = 0, chunks = 0, rows_per_chunk = 0;
+    size_t packed_bytes = 0;           // LDS for a packed nb x nb triangle, 0 = does not fit
     hipStream_t st = nullptr;
     DeviceBuffer nbr, wt, inv_s, s, canon;
     DeviceBuffer buf[5];               // block-sized buffers
-    DeviceBuffer g, m, h, q, work, theta, partial, small_i;
+    DeviceBuffer g, m, h, q, work, theta, partial, small_i, rot, order;
 
     double *B(int i) const { return buf[i].as<double>(); }
 
@@ -393,7 +632,16 @@ struct ModeSolver {
         if (!rc) rc = theta.alloc(size_t(nb) * 8);
         if (!rc) rc = partial.alloc(size_t(chunks) * nb * nb * sizeof(double));
         if (!rc) rc = small_i.alloc(2 * sizeof(int32_t));
+        const int np = nb + (nb & 1);
+        if (!rc) rc = rot.alloc(size_t(kJacobiSweeps) * (np - 1) * (np / 2) * sizeof(double2));
+        if (!rc) rc = order.alloc(size_t(nb) * sizeof(int32_t));
         if (rc) return rc;
+        int device = 0, lds_limit = 65536;
+        TYEE_HIP(hipGetDevice(&device));
+        TYEE_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        // the small kernels also hold up to about 7 KB of static shared memory
+        const size_t tri_bytes = size_t(nb) * (nb + 1) / 2 * sizeof(double);
+        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) ? tri_bytes : 0;
         TYEE_HIP(hipMemcpyAsync(nbr.p, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, st));
         TYEE_HIP(hipMemcpyAsync(wt.p, hw.data(), hw.size() * 8, hipMemcpyHostToDevice, st));
         TYEE_HIP(hipMemcpyAsync(inv_s.p, hinv.data(), nt * 8, hipMemcpyHostToDevice, st));
@@ -433,37 +681,57 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
-    // x (in buffer ix) -> S-orthonormal block in buffer iy, by Cholesky QR three times (the
-    // first with a small diagonal shift, which keeps the factorisation defined for a block
-    // that the filter has made nearly dependent).  Returns TYEE_EUNSTABLE when a
-    // factorisation fails.
-    int orthonormalise(int ix, int iy) {
-        int src = ix, dst = iy;
-        for (int pass = 0; pass < 3; ++pass) {
-            int rc = gram(B(src), B(src), g.as<double>());
-            if (rc) return rc;
-            double shift = 0.0;
-            if (pass == 0) {
-                // shift = 11 (n nb + nb (nb + 1)) u ||G||_2, ||G||_2 bounded by the trace
-                std::vector<double> hg(size_t(nb) * nb);
-                TYEE_HIP(hipMemcpyAsync(hg.data(), g.p, hg.size() * 8, hipMemcpyDeviceToHost, st));
-                TYEE_HIP(hipStreamSynchronize(st));
-                double tr = 0.0;
-                for (int i = 0; i < nb; ++i) tr += hg[size_t(i) * nb + i];
-                shift = 11.0 * (double(n) * nb + double(nb) * (nb + 1)) * 0x1.0p-53 * tr;
-            }
-            hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3(256), 0, st, nb, g.as<double>(), shift, m.as<double>(),
-                               small_i.as<int32_t>());
-            TYEE_HIP(hipGetLastError());
-            int32_t info = 0;
-            TYEE_HIP(hipMemcpyAsync(&info, small_i.p, 4, hipMemcpyDeviceToHost, st));
+    // One Cholesky QR pass: src -> dst (src is left intact when the factorisation fails).
+    // *ok = false when a pivot is not positive.
+    int cholqr_pass(int src, int dst, bool shifted, bool *ok) {
+        int rc = gram(B(src), B(src), g.as<double>());
+        if (rc) return rc;
+        double shift = 0.0;
+        if (shifted) {
+            // shift = 11 (n nb + nb (nb + 1)) u ||G||_2, ||G||_2 bounded by the trace
+            std::vector<double> hg(size_t(nb) * nb);
+            TYEE_HIP(hipMemcpyAsync(hg.data(), g.p, hg.size() * 8, hipMemcpyDeviceToHost, st));
             TYEE_HIP(hipStreamSynchronize(st));
-            if (info) return fail(TYEE_EUNSTABLE, "mode block lost rank (Cholesky pivot " + std::to_string(info) + ")");
-            rc = rotate(B(src), m.as<double>(), B(dst), true);
-            if (rc) return rc;
-            std::swap(src, dst);
+            double tr = 0.0;
+            for (int i = 0; i < nb; ++i) tr += hg[size_t(i) * nb + i];
+            shift = 11.0 * (double(n) * nb + double(nb) * (nb + 1)) * 0x1.0p-53 * tr;
         }
-        // three passes: the result sits in iy
+        if (packed_bytes)
+            hipLaunchKernelGGL(k_chol_inverse_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb,
+                               g.as<double>(), shift, m.as<double>(), small_i.as<int32_t>());
+        else
+            hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3(256), 0, st, nb, g.as<double>(), shift,
+                               m.as<double>(), small_i.as<int32_t>());
+        TYEE_HIP(hipGetLastError());
+        int32_t info = 0;
+        TYEE_HIP(hipMemcpyAsync(&info, small_i.p, 4, hipMemcpyDeviceToHost, st));
+        TYEE_HIP(hipStreamSynchronize(st));
+        *ok = info == 0;
+        return *ok ? rotate(B(src), m.as<double>(), B(dst), true) : TYEE_OK;
+    }
+
+    // The block in buffer ix made S-orthonormal, using buffer iy as well; *out names the
+    // buffer that holds the result.  Cholesky QR twice, which suffices while the block's
+    // condition number stays below about u^(-1/2) (the filter degree is capped for that);
+    // if a factorisation fails, the shifted Cholesky QR three times (Fukaya et al., SIAM J.
+    // Sci. Comput. 2020) from the same block.  TYEE_EUNSTABLE when that fails too.
+    int orthonormalise(int ix, int iy, int *out) {
+        bool ok = false;
+        int rc = cholqr_pass(ix, iy, false, &ok);
+        if (!rc && ok) rc = cholqr_pass(iy, ix, false, &ok);
+        if (rc) return rc;
+        if (ok) {
+            *out = ix;
+            return TYEE_OK;
+        }
+        // ix still holds the block when either pass failed (a pass writes only on success,
+        // and a failed second pass leaves the first pass's input, ix, as it was)
+        rc = cholqr_pass(ix, iy, true, &ok);
+        if (!rc && ok) rc = cholqr_pass(iy, ix, false, &ok);
+        if (!rc && ok) rc = cholqr_pass(ix, iy, false, &ok);
+        if (rc) return rc;
+        if (!ok) return fail(TYEE_EUNSTABLE, "mode block lost rank");
+        *out = iy;
         return TYEE_OK;
     }
 
@@ -473,8 +741,17 @@ struct ModeSolver {
         int rc = apply(B(iv), nullptr, B(iz), 1.0, 0.0, 0.0);
         if (!rc) rc = gram(B(iv), B(iz), h.as<double>());
         if (rc) return rc;
-        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, nb, h.as<double>(), work.as<double>(), q.as<double>(),
-                           theta.as<double>(), int32_t(40), small_i.as<int32_t>() + 1);
+        if (packed_bytes) {
+            hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb, h.as<double>(),
+                               rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), kJacobiSweeps,
+                               small_i.as<int32_t>() + 1);
+            TYEE_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(128), 0, st, nb, rot.as<double2>(),
+                               small_i.as<int32_t>() + 1, order.as<int32_t>(), q.as<double>());
+        } else {
+            hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, nb, h.as<double>(), work.as<double>(),
+                               q.as<double>(), theta.as<double>(), kJacobiSweeps, small_i.as<int32_t>() + 1);
+        }
         TYEE_HIP(hipGetLastError());
         rc = rotate(B(iv), q.as<double>(), B(3), false);
         if (!rc) rc = rotate(B(iz), q.as<double>(), B(4), false);
@@ -541,7 +818,7 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
     if (nb < std::max<int64_t>(n_modes, 2) || nb > std::min<int64_t>(nt, kMaxBlock))
         return fail(TYEE_EINVAL, "block must be in max(n_modes, 2) .. min(n_triangles, 256)");
     if (nt * nb >= (int64_t(1) << 31)) return fail(TYEE_EINVAL, "n_triangles x block must be below 2^31");
-    if (degree == 0) degree = 64;
+    if (degree == 0) degree = 128;
     if (degree < 1 || degree > 100000) return fail(TYEE_EINVAL, "degree must be in 1 .. 100000");
     if (!(tol > 0.0) || max_iter < 1) return fail(TYEE_EINVAL, "tol > 0 and max_iter >= 1 required");
     const auto t_start = std::chrono::steady_clock::now();
@@ -561,9 +838,10 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
         hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
                            sv.canon.as<int32_t>(), seed, sv.B(0));
         TYEE_HIP(hipGetLastError());
-        rc = sv.orthonormalise(0, 1);
+        int ob = 1;
+        rc = sv.orthonormalise(0, 1, &ob);
         std::vector<double> ritz, res;
-        if (!rc) rc = sv.rayleigh_ritz(1, 2, ritz);
+        if (!rc) rc = sv.rayleigh_ritz(ob, 2, ritz);
         if (!rc) rc = sv.residuals(res);
         applies += 1;
         auto converged = [&]() {
@@ -579,12 +857,12 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
             const bool filtered = nb < nt && a < b_up * (1.0 - 1e-12) && a0 < a;
             int fo = 0;
             if (filtered) {
-                // cap the degree so that the lowest mode grows at most 1e10 times more than
+                // cap the degree so that the lowest mode grows at most 1e7 times more than
                 // the modes at the cut: the filtered block then keeps a condition number that
-                // the shifted Cholesky QR recovers from
+                // Cholesky QR twice handles
                 const double x0 = (0.5 * (b_up + a) - a0) / (0.5 * (b_up - a));
                 int deg = degree;
-                if (x0 > 1.0) deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e10) / std::acosh(x0)))));
+                if (x0 > 1.0) deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e7) / std::acosh(x0)))));
                 TYEE_HIP(hipEventRecord(ev.a, sv.st));
                 rc = sv.filter(deg, a, b_up, a0, &fo);
                 TYEE_HIP(hipEventRecord(ev.b, sv.st));
@@ -595,8 +873,9 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
             if (rc) break;
             const int other = fo == 0 ? 1 : 0;
             const int spare = 3 - fo - other;      // the third of buffers 0, 1, 2
-            rc = sv.orthonormalise(fo, other);
-            if (!rc) rc = sv.rayleigh_ritz(other, spare, ritz);
+            int ob = other;
+            rc = sv.orthonormalise(fo, other, &ob);
+            if (!rc) rc = sv.rayleigh_ritz(ob, spare, ritz);
             if (!rc) rc = sv.residuals(res);
             if (rc) break;
             if (filtered) {
