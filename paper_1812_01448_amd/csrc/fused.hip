@@ -81,48 +81,68 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
 
     T vb[RT], cb[RT], ve[RE], ce[RE];
     uint32_t i0[RT], i1[RT], ie[RE];
+    int32_t gt[RT], ge[RE];
+    int spk[RE];
+    T jr[RE], sa[RE], sb[RE], sw[RE];
+    // The loads are issued in three waves so that a work-item keeps all of them in flight at
+    // once: the stored slots of halo cells, then the coefficient and index tables, then the
+    // field values through the slots.  Loading cell by cell, with the slot chosen at the load,
+    // serialises every cell on two memory round trips.  Table and value loads are unconditional
+    // (cells past the tile read the tile's last table entry and slot 0, and are never used),
+    // so no branch sits between them and the compiler waits once.
+    const bool own_run = ti.own_base >= 0;
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
         const int l = tid + r * NT;
-        vb[r] = T(0);
-        cb[r] = T(0);
-        i0[r] = 0;
-        i1[r] = 0;
-        if (l < nT) {
-            const int p = ti.tri_off + l;
-            vb[r] = B_in[l < ti.n_core ? ti.core_base + l : tl_glob[p]];
-            cb[r] = tl_coef[p];
-            i0[r] = tl_i0[p];
-            i1[r] = tl_i1[p];
-            sB[l] = vb[r];
-        }
+        gt[r] = l < ti.n_core ? ti.core_base + l : 0;
+        if (l >= ti.n_core && l < nT) gt[r] = tl_glob[ti.tri_off + l];
     }
-    int spk[RE];
-    T jr[RE], sa[RE], sb[RE], sw[RE];
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
         const int l = tid + r * NT;
-        ve[r] = T(0);
-        ce[r] = T(0);
-        ie[r] = 0;
+        ge[r] = (own_run && l < ti.n_own) ? ti.own_base + l : 0;
+        if ((!own_run || l >= ti.n_own) && l < nE) ge[r] = el_glob[ti.edge_off + l];
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int p = ti.tri_off + min(tid + r * NT, nT - 1);
+        cb[r] = tl_coef[p];
+        i0[r] = tl_i0[p];
+        i1[r] = tl_i1[p];
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        const int l = tid + r * NT;
+        const int p = ti.edge_off + min(l, nE - 1);
+        ce[r] = el_coef[p];
+        ie[r] = el_idx[p];
         spk[r] = -1;
         jr[r] = sa[r] = sb[r] = sw[r] = T(0);
-        if (l < nE) {
-            const int p = ti.edge_off + l;
-            ve[r] = Et_in[(ti.own_base >= 0 && l < ti.n_own) ? ti.own_base + l : el_glob[p]];
-            ce[r] = el_coef[p];
-            ie[r] = el_idx[p];
-            sE[l] = ve[r];
-            if constexpr (SP) {
-                spk[r] = sp.el_sp[p];
-                if (spk[r] >= 0) {
-                    jr[r] = sp.j_in[spk[r]];
-                    sa[r] = sp.ca[spk[r]];
-                    sb[r] = sp.cb[spk[r]];
-                    sw[r] = sp.w[spk[r]];
-                }
+        if constexpr (SP) spk[r] = l < nE ? sp.el_sp[p] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) vb[r] = B_in[gt[r]];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        ve[r] = Et_in[ge[r]];
+        if constexpr (SP) {
+            if (spk[r] >= 0) {
+                jr[r] = sp.j_in[spk[r]];
+                sa[r] = sp.ca[spk[r]];
+                sb[r] = sp.cb[spk[r]];
+                sw[r] = sp.w[spk[r]];
             }
         }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int l = tid + r * NT;
+        if (l < nT) sB[l] = vb[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+        const int l = tid + r * NT;
+        if (l < nE) sE[l] = ve[r];
     }
     __syncthreads();
 
@@ -170,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
     for (int r = 0; r < RE; ++r) {
         const int l = tid + r * NT;
         if (l < ti.n_own) {
-            Et_out[ti.own_base >= 0 ? ti.own_base + l : el_glob[ti.edge_off + l]] = ve[r];
+            Et_out[ge[r]] = ve[r];
             if constexpr (SP) {
                 if (spk[r] >= 0) sp.j_out[spk[r]] = jr[r];
             }
