@@ -540,7 +540,9 @@ def bench_batch(args):
     tuned = None
     if args.tune:
         batch.set_graph(args.graph)
-        tuned = batch.tune(32)
+        tuned = batch.tune(32, progress=lambda r: log(
+            f"trial {r['order']} K={r['steps_per_launch']} tile={r['tile_tris']}: "
+            f"{r['ms_per_step'] * 1e3:.1f} us per step"))
         best = min(tuned, key=lambda r: r["ms_per_step"])
         log(f"tuned: {best}")
     else:

@@ -425,6 +425,15 @@ typedef struct {
 int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results,
                     int64_t capacity, int64_t *n_results);
 
+/* Called after each autotuner trial with its record (borrowed for the call) and the caller's
+   pointer; it must not call back into the batch. */
+typedef void (*tyee_tune_progress)(const tyee_tune_result *trial, void *user);
+/* tyee_batch_tune that reports every trial as it ends through on_trial (may be NULL, which is
+   tyee_batch_tune itself).  Same arguments, results and errors. */
+int tyee_batch_tune_progress(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results,
+                             int64_t capacity, int64_t *n_results, tyee_tune_progress on_trial,
+                             void *user);
+
 void tyee_batch_destroy(tyee_batch *b);
 
 /* Achievable device bandwidth, the reference beside the published HBM peak in roofline

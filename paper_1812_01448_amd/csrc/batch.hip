@@ -252,6 +252,11 @@ int tyee_batch_info(const tyee_batch *b, int64_t out[4]) {
 
 int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results, int64_t capacity,
                     int64_t *n_results) {
+    return tyee_batch_tune_progress(b, steps_per_trial, results, capacity, n_results, nullptr, nullptr);
+}
+
+int tyee_batch_tune_progress(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results,
+                             int64_t capacity, int64_t *n_results, tyee_tune_progress on_trial, void *user) {
     if (!b || steps_per_trial <= 0 || (capacity > 0 && !results)) return fail(TYEE_EINVAL, "bad tune arguments");
     const int32_t orders[] = {TYEE_ORDER_MORTON, TYEE_ORDER_RCM};
     const int32_t depths[] = {1, 2, 4, 8};
@@ -262,7 +267,6 @@ int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *re
     int rc = save_fields(*b, E, B);
     if (rc) return rc;
     const int64_t step0 = b->sim->s.step;
-    const int32_t order0 = b->members[0].order_kind;
     {
         tyee::Sim &s0 = b->sim->s;
         std::vector<double> Ec(s0.ne), Bc(s0.nt);
@@ -301,6 +305,7 @@ int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *re
                 const int32_t ran = b->sim->s.fusion;
                 tyee_tune_result r{order, ran, ran == 1 ? 0 : tile, ms / double(n)};
                 all.push_back(r);
+                if (on_trial) on_trial(&r, user);
                 if (r.ms_per_step < best.ms_per_step) best = r;
                 if ((rc = restore(*b))) return rc;
             }
@@ -309,7 +314,6 @@ int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *re
     // apply the winner
     for (auto &m : b->members)
         if ((rc = tyee::reorder_mesh(m, best.order, 0))) return rc;
-    (void)order0;
     b->fusion = best.steps_per_launch;
     b->tile = best.tile_tris;
     if ((rc = rebuild(*b)) || (rc = restore(*b))) return rc;

@@ -52,6 +52,9 @@ class _Tune(ctypes.Structure):
                 ("tile_tris", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
 
+_TUNE_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.POINTER(_Tune), ctypes.c_void_p)
+
+
 class _Gate(ctypes.Structure):
     _fields_ = [("accepted", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("omega_plain", ctypes.c_double), ("omega_learned", ctypes.c_double),
@@ -87,7 +90,7 @@ EXPORTS = [
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
-    "tyee_sim_current_buffer", "tyee_mesh_modes",
+    "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_batch_tune_progress",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -174,6 +177,7 @@ def _load():
         "tyee_sim_current_buffer": [vp, ctypes.POINTER(i32)],
         "tyee_mesh_modes": [vp, vp, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
                             ctypes.POINTER(_ModesStats)],
+        "tyee_batch_tune_progress": [vp, i64, vp, i64, ctypes.POINTER(i64), _TUNE_PROGRESS, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -551,15 +555,20 @@ class Batch:
     def sync(self):
         _check(lib.tyee_batch_sync(self._h))
 
-    def tune(self, steps_per_trial=64):
+    def tune(self, steps_per_trial=64, progress=None):
+        """Autotune (tyee_batch_tune); progress(dict) is called after every trial."""
         cap = 64
         res = (_Tune * cap)()
         n = ctypes.c_int64()
-        _check(lib.tyee_batch_tune(self._h, int(steps_per_trial), res, cap, ctypes.byref(n)))
         names = {v: k for k, v in ORDER.items()}
-        return [{"order": names[r.order], "steps_per_launch": r.steps_per_launch,
-                 "tile_tris": r.tile_tris, "ms_per_step": r.ms_per_step}
-                for r in res[:min(cap, n.value)]]
+        rec = lambda r: {"order": names[r.order], "steps_per_launch": r.steps_per_launch,
+                         "tile_tris": r.tile_tris, "ms_per_step": r.ms_per_step}
+        cb = None
+        if progress is not None:
+            cb = _TUNE_PROGRESS(lambda r, user: progress(rec(r.contents)))
+        _check(lib.tyee_batch_tune_progress(self._h, int(steps_per_trial), res, cap, ctypes.byref(n),
+                                            cb, None))
+        return [rec(r) for r in res[:min(cap, n.value)]]
 
 
 class Learner:
