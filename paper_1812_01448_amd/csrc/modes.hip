@@ -32,6 +32,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <vector>
 
 #include "sim.hpp"
@@ -44,6 +45,7 @@ constexpr int kRotRows = 16;        // rows of the block per work-group in k_rot
 constexpr int kGramTile = 32;       // output tile of k_gram (32 x 32)
 constexpr int kGramRows = 64;       // rows staged in LDS per pass of k_gram
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
+constexpr int kFilterPasses = 2;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
 // y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null)
 __global__ void k_modes_apply(int32_t n, int32_t nb, const double *__restrict__ y,
@@ -735,9 +737,16 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
+    // The lowest buffer index not in `used`.
+    static int pick(std::initializer_list<int> used) {
+        for (int i = 0; i < 5; ++i)
+            if (std::find(used.begin(), used.end(), i) == used.end()) return i;
+        return -1;
+    }
+
     // Rayleigh-Ritz of the S-orthonormal block in buffer iv (scratch iz): Ritz vectors to
-    // buffer 3, K times them to buffer 4, Ritz values to host.
-    int rayleigh_ritz(int iv, int iz, std::vector<double> &ritz) {
+    // buffer ov, K times them to buffer okv (four distinct buffers), Ritz values to host.
+    int rayleigh_ritz(int iv, int iz, int ov, int okv, std::vector<double> &ritz) {
         int rc = apply(B(iv), nullptr, B(iz), 1.0, 0.0, 0.0);
         if (!rc) rc = gram(B(iv), B(iz), h.as<double>());
         if (rc) return rc;
@@ -753,8 +762,8 @@ struct ModeSolver {
                                q.as<double>(), theta.as<double>(), kJacobiSweeps, small_i.as<int32_t>() + 1);
         }
         TYEE_HIP(hipGetLastError());
-        rc = rotate(B(iv), q.as<double>(), B(3), false);
-        if (!rc) rc = rotate(B(iz), q.as<double>(), B(4), false);
+        rc = rotate(B(iv), q.as<double>(), B(ov), false);
+        if (!rc) rc = rotate(B(iz), q.as<double>(), B(okv), false);
         if (rc) return rc;
         ritz.resize(nb);
         TYEE_HIP(hipMemcpyAsync(ritz.data(), theta.p, size_t(nb) * 8, hipMemcpyDeviceToHost, st));
@@ -762,9 +771,9 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
-    int residuals(std::vector<double> &res) {
+    int residuals(int iv, int ikv, std::vector<double> &res) {
         hipLaunchKernelGGL(k_residual, dim3(chunks), dim3(((nb + 63) / 64) * 64), 0, st, n, nb, rows_per_chunk,
-                           B(3), B(4), theta.as<double>(), s.as<double>(), partial.as<double>());
+                           B(iv), B(ikv), theta.as<double>(), s.as<double>(), partial.as<double>());
         TYEE_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_sum_chunks, dim3((nb + 255) / 256), dim3(256), 0, st, chunks, nb, partial.as<double>(),
                            g.as<double>());
@@ -776,19 +785,21 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
-    // Degree-k filter of the block in buffer 3 damping [a, b_up] with a0 the estimate of the
-    // lowest eigenvalue; the result lands in buffer *out (one of 0, 1, 2).
-    int filter(int degree, double a, double b_up, double a0, int *out) {
+    // Degree-k filter of the block in buffer `in` damping [a, b_up] with a0 the estimate of
+    // the lowest eigenvalue; it rotates through three other buffers (`in` is only read) and
+    // the result lands in buffer *out.
+    int filter(int in, int degree, double a, double b_up, double a0, int *out) {
         const double e = 0.5 * (b_up - a), c = 0.5 * (b_up + a);
         const double sigma1 = e / (a0 - c);
         double sigma = sigma1;
+        const int w0 = pick({in}), w1 = pick({in, w0}), w2 = pick({in, w0, w1});
         // y1 = (sigma1 / e) (K - c) y0
-        int rc = apply(B(3), nullptr, B(0), sigma1 / e, -sigma1 * c / e, 0.0);
+        int rc = apply(B(in), nullptr, B(w0), sigma1 / e, -sigma1 * c / e, 0.0);
         if (rc) return rc;
-        int prev = 3, cur = 0;
+        int prev = in, cur = w0;
         for (int k = 2; k <= degree; ++k) {
             const double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
-            const int nxt = (cur + 1) % 3 == prev ? (cur + 2) % 3 : (cur + 1) % 3;
+            const int nxt = (w0 != cur && w0 != prev) ? w0 : (w1 != cur && w1 != prev) ? w1 : w2;
             // y_{k} = (2 sigma_new / e)(K - c) y_{k-1} - sigma sigma_new y_{k-2}
             rc = apply(B(cur), B(prev), B(nxt), 2.0 * sigma_new / e, -2.0 * sigma_new * c / e, -sigma * sigma_new);
             if (rc) return rc;
@@ -841,8 +852,9 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
         int ob = 1;
         rc = sv.orthonormalise(0, 1, &ob);
         std::vector<double> ritz, res;
-        if (!rc) rc = sv.rayleigh_ritz(ob, 2, ritz);
-        if (!rc) rc = sv.residuals(res);
+        int vb = ModeSolver::pick({ob, 2}), kvb = ModeSolver::pick({ob, 2, vb});  // Ritz vectors, K times them
+        if (!rc) rc = sv.rayleigh_ritz(ob, 2, vb, kvb, ritz);
+        if (!rc) rc = sv.residuals(vb, kvb, res);
         applies += 1;
         auto converged = [&]() {
             for (int64_t c = 0; c < n_modes; ++c)
@@ -855,34 +867,37 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
             const double a = ritz[nb - 1], a0 = std::min(ritz[0], a);
             // a block that spans the whole space is exact after Rayleigh-Ritz: no filter
             const bool filtered = nb < nt && a < b_up * (1.0 - 1e-12) && a0 < a;
-            int fo = 0;
-            if (filtered) {
-                // cap the degree so that the lowest mode grows at most 1e7 times more than
-                // the modes at the cut: the filtered block then keeps a condition number that
-                // Cholesky QR twice handles
-                const double x0 = (0.5 * (b_up + a) - a0) / (0.5 * (b_up - a));
-                int deg = degree;
-                if (x0 > 1.0) deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e7) / std::acosh(x0)))));
-                TYEE_HIP(hipEventRecord(ev.a, sv.st));
-                rc = sv.filter(deg, a, b_up, a0, &fo);
-                TYEE_HIP(hipEventRecord(ev.b, sv.st));
-                applies += deg;
-            } else {
-                TYEE_HIP(hipMemcpyAsync(sv.B(0), sv.B(3), size_t(nt) * nb * 8, hipMemcpyDeviceToDevice, sv.st));
+            // cap the degree so that the lowest mode grows at most 1e7 times more than the modes
+            // at the cut: the filtered block then keeps a condition number that Cholesky QR twice
+            // handles
+            const double x0 = (0.5 * (b_up + a) - a0) / (0.5 * (b_up - a));
+            int deg = degree;
+            if (x0 > 1.0) deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e7) / std::acosh(x0)))));
+            // kFilterPasses filter passes, each followed by Cholesky QR, per Rayleigh-Ritz step:
+            // subspace iteration needs no Rayleigh-Ritz between passes
+            int in = vb;
+            for (int pass = 0; pass < (filtered ? kFilterPasses : 1) && !rc; ++pass) {
+                int fo = in;
+                if (filtered) {
+                    TYEE_HIP(hipEventRecord(ev.a, sv.st));
+                    rc = sv.filter(in, deg, a, b_up, a0, &fo);
+                    TYEE_HIP(hipEventRecord(ev.b, sv.st));
+                    applies += deg;
+                }
+                if (!rc) rc = sv.orthonormalise(fo, ModeSolver::pick({fo}), &in);
+                if (!rc && filtered) {
+                    float ms = 0.0f;
+                    TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                    filter_ms += ms;
+                }
             }
             if (rc) break;
-            const int other = fo == 0 ? 1 : 0;
-            const int spare = 3 - fo - other;      // the third of buffers 0, 1, 2
-            int ob = other;
-            rc = sv.orthonormalise(fo, other, &ob);
-            if (!rc) rc = sv.rayleigh_ritz(ob, spare, ritz);
-            if (!rc) rc = sv.residuals(res);
+            const int spare = ModeSolver::pick({in});
+            vb = ModeSolver::pick({in, spare});
+            kvb = ModeSolver::pick({in, spare, vb});
+            rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz);
+            if (!rc) rc = sv.residuals(vb, kvb, res);
             if (rc) break;
-            if (filtered) {
-                float ms = 0.0f;
-                TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-                filter_ms += ms;
-            }
             applies += 1;                          // the Rayleigh-Ritz product K V
             ++it;
             done = converged();
@@ -901,7 +916,7 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
         }
         if (modes) {
             std::vector<double> hv(size_t(nt) * nb);
-            TYEE_HIP(hipMemcpyAsync(hv.data(), sv.B(3), hv.size() * 8, hipMemcpyDeviceToHost, sv.st));
+            TYEE_HIP(hipMemcpyAsync(hv.data(), sv.B(vb), hv.size() * 8, hipMemcpyDeviceToHost, sv.st));
             TYEE_HIP(hipStreamSynchronize(sv.st));
             for (int64_t k = 0; k < nt; ++k) {
                 const int32_t j = msh.perm_t[k];
