@@ -341,12 +341,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, 
         const int rowk = packed(nb, k, 0);
         for (int c = k + 1 + tid; c < nb; c += nt) P[rowk + c] *= inv;
         __syncthreads();
-        // trailing update of rows r > k, columns c >= r: one row of the trailing triangle per
-        // group of threads
-        const int t = nb - k - 1;
-        for (int e = tid; e < t * t; e += nt) {
-            const int r = k + 1 + e / t, c = k + 1 + e % t;
-            if (c >= r) P[packed(nb, r, c)] -= P[rowk + r] * P[rowk + c];
+        // trailing update of rows r > k, columns c >= r: 32 lanes per row, so row k and row r
+        // are both read along contiguous packed runs
+        for (int r = k + 1 + (tid >> 5); r < nb; r += nt >> 5) {
+            const double pr = P[rowk + r];
+            const int rowr = packed(nb, r, 0);
+            for (int c = r + (tid & 31); c < nb; c += 32) P[rowr + c] -= pr * P[rowk + c];
         }
         __syncthreads();
     }
@@ -460,10 +460,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
                 rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, s);
             }
             __syncthreads();
-            // block pairs (s, t), s <= t, over a half x half grid (the lower half idles)
-            for (int e = tid; e < half * half; e += nt) {
-                const int s_ = e / half, t_ = e % half;
-                if (t_ < s_) continue;
+            // block pairs (s, t), s <= t: a group of 32 lanes per s
+            for (int s_ = tid >> 5; s_ < half; s_ += nt >> 5)
+            for (int t_ = s_ + (tid & 31); t_ < half; t_ += 32) {
                 const int a1 = pp[s_], b1 = qq[s_], a2 = pp[t_], b2 = qq[t_];
                 const double c1 = cs[s_], s1 = sn[s_], c2 = cs[t_], s2 = sn[t_];
                 if (s_ == t_) {
