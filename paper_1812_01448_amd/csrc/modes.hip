@@ -309,10 +309,7 @@ constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kerne
 constexpr int kInvRows = 16;          // rows of R^-1 finished per pass
 
 // The same as k_chol_inverse with g held in LDS (packed upper triangle, nb (nb + 1)/2 doubles
-// of dynamic shared memory).  R^-1 is formed from the bottom in passes of kInvRows rows: each
-// column first takes the contributions of all finished rows into kInvRows register
-// accumulators (independent loads, so they overlap), then the pass's rows are finished in
-// order.  g is only read.
+// of dynamic shared memory), R^-1 formed in place of R (see below).  g is only read.
 __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, const double *__restrict__ g,
                                                                     double shift, double *__restrict__ m,
                                                                     int32_t *__restrict__ info) {
@@ -352,32 +349,43 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, 
     }
     if (tid == 0) *info = bad;
     if (bad) return;
-    // R M = I, M upper triangular: m[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] m[k][c]) / R[r][r]
+    // R M = I, M upper triangular: M[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] M[k][c]) / R[r][r].
+    // Row r of M takes the place of row r of R in LDS once row r of R has been read for the
+    // last time, so the whole inverse stays on chip.  One thread per column; rows are finished
+    // from the bottom in passes of kInvRows, each column first taking the contributions of the
+    // finished rows below the pass into registers.
+    const int c = tid;
+    double acc[kInvRows];
     for (int hi = nb; hi > 0; hi -= kInvRows) {
         const int lo = hi > kInvRows ? hi - kInvRows : 0;
-        for (int c = tid; c < nb; c += nt) {
-            double acc[kInvRows];
+        if (c < nb) {
 #pragma unroll
             for (int q = 0; q < kInvRows; ++q) acc[q] = (lo + q < hi && lo + q == c) ? 1.0 : 0.0;
             for (int k = hi; k <= c; ++k) {
-                const double mk = m[k * nb + c];
+                const double mk = P[packed(nb, k, c)];  // row k already holds M
 #pragma unroll
                 for (int q = 0; q < kInvRows; ++q)
                     if (lo + q < hi) acc[q] -= P[packed(nb, lo + q, k)] * mk;
             }
-            // finish rows hi-1 .. lo of this column in order (entries left of the diagonal are 0)
-            for (int q = hi - lo - 1; q >= 0; --q) {
-                const int r = lo + q;
-                if (c < r) {
-                    m[r * nb + c] = 0.0;
-                    continue;
-                }
-                double a = acc[q];
-                for (int k = r + 1; k < hi && k <= c; ++k) a -= P[packed(nb, r, k)] * m[k * nb + c];
-                m[r * nb + c] = a / P[packed(nb, r, r)];
-            }
         }
-        __syncthreads();
+        for (int r = hi - 1; r >= lo; --r) {
+            double val = 0.0;
+            if (c < nb && c >= r) {
+                double a = 0.0;
+#pragma unroll
+                for (int q = 0; q < kInvRows; ++q)
+                    if (lo + q == r) a = acc[q];
+                for (int k = r + 1; k < hi && k <= c; ++k) a -= P[packed(nb, r, k)] * P[packed(nb, k, c)];
+                val = a / P[packed(nb, r, r)];
+            }
+            __syncthreads();  // row r of R is no longer read
+            if (c < nb && c >= r) P[packed(nb, r, c)] = val;
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < nb * nb; e += nt) {
+        const int r = e / nb, cc = e % nb;
+        m[e] = cc >= r ? P[packed(nb, r, cc)] : 0.0;
     }
 }
 
