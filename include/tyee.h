@@ -445,7 +445,8 @@ int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
 
 /* Work done by one tyee_mesh_modes call. */
 typedef struct {
-    int32_t iters;         /* outer iterations (filter, orthonormalisation, Rayleigh-Ritz) */
+    int32_t iters;         /* outer iterations (two filter passes, each followed by the
+                              orthonormalisation, then one Rayleigh-Ritz step) */
     int64_t applies;       /* applications of K to the whole block */
     double lambda_bound;   /* Gershgorin bound on lambda_max that closes the filter interval */
     double filter_ms;      /* HIP-event time of the filter launches on the stream */
@@ -463,14 +464,16 @@ typedef struct {
    Computed on the device in FP64 by a block iteration: a polynomial filter run as the
    three-term (leap-frog) recurrence of the shifted K, with the unwanted part of the spectrum
    inside the eq. 20 bound (bounded) and the wanted modes outside it (growing, as in complex
-   time); S-orthonormalisation of the block (deflation in metric (7)); Rayleigh-Ritz.
+   time); S-orthonormalisation of the block (deflation in metric (7)) after each filter pass;
+   a Rayleigh-Ritz step after every two passes.
      gamma     [n_edges] per-edge scale in canonical order, or NULL.
      n_modes   1 .. min(n_triangles, 256) lowest pairs wanted.
      block     vectors iterated, max(n_modes, 2) .. min(n_triangles, 256); 0 chooses
                n_modes + max(16, n_modes / 4) (capped).  n_triangles x block < 2^31.
-     degree    largest filter degree per outer iteration, 1 .. 100000; 0 chooses 128.  An
-               iteration lowers it so that the lowest Ritz value grows at most 1e7 times more
-               than the cut (the block stays well enough conditioned to orthonormalise).
+     degree    largest filter degree per pass (two passes per outer iteration), 1 .. 100000;
+               0 chooses 128.  A pass lowers it so that the lowest Ritz value grows at most 1e7
+               times more than the cut (the block stays well enough conditioned to
+               orthonormalise).
      tol       converged when ||K v_c - lambda_c v_c||_S <= tol * lambda_bound for every wanted
                c (v_c S-normalised).
      max_iter  outer iterations allowed (>= 1).
