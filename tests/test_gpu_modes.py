@@ -92,8 +92,22 @@ def test_equilateral_torus_closed_form_and_degenerate_clusters(ty):
             f = np.abs(np.exp(1j * delta @ k).sum())
             ex += [4 / a ** 2 * (3 - f), 4 / a ** 2 * (3 + f)]
     ex = np.sort(ex)
-    # the wanted count ends inside a cluster: compare only the complete clusters below it
+    # sorted eigenvalues are unique even where the wanted count ends inside a cluster
     assert np.max(np.abs(got["omega2"] - ex[:48])) <= 1e-9 * got["lambda_bound"]
+    _check(om, got, lam_ref, V_ref)
+
+
+def test_largest_block_uses_the_global_memory_small_kernels(ty):
+    # a block of 256 does not fit a packed triangle in LDS: Cholesky and Jacobi then run on
+    # global memory
+    _note("case: box 30 x 40 triangular lattice, 200 modes, block 256 (global-memory small kernels)")
+    xy, tri, Lx, Ly = box_tri_mesh(30, 40, 1.0, 0.1, 11)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam_ref, V_ref = om.modes(256)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    m.reorder("morton")
+    got = m.modes(200, block=256, tol=1e-11, max_iter=100)
+    _note(f"  iters {got['iters']} applies {got['applies']} total {got['total_ms']:.0f} ms")
     _check(om, got, lam_ref, V_ref)
 
 
