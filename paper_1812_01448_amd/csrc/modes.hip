@@ -49,24 +49,53 @@ constexpr int kGramRows = 64;       // rows staged in LDS per pass of k_gram
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 constexpr int kFilterPasses = 2;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
-// y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null)
-__global__ void k_modes_apply(int32_t n, int32_t nb, const double *__restrict__ y,
-                              const double *__restrict__ yp, double *__restrict__ yo,
-                              const int32_t *__restrict__ nbr, const double *__restrict__ wt,
-                              const double *__restrict__ inv_s, double alpha, double beta, double gam) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= uint32_t(n) * uint32_t(nb)) return;
-    const uint32_t j = g / uint32_t(nb), c = g - j * uint32_t(nb);
-    const double yj = y[g];
-    double acc = 0.0;
+// y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null).  One wave per row
+// (triangle): the row's neighbour slots, weights and 1/S are wave-uniform (scalar loads) and
+// the lanes walk its nb columns, so the three neighbour rows are read as contiguous runs.
+// Work-groups are remapped so that each XCD takes one contiguous run of rows: a row's
+// neighbours (close in the locality numbering) are then gathered through the same XCD's L2.
+constexpr int kApplyWaves = 4;  // rows per work-group of the apply kernel
+template <int CH>                // 64-column chunks per row: ceil(nb / 64)
+__global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply(
+    int32_t n, int32_t nb, const double *__restrict__ y, const double *__restrict__ yp, double *__restrict__ yo,
+    const int32_t *__restrict__ nbr, const double *__restrict__ wt, const double *__restrict__ inv_s, double alpha,
+    double beta, double gam) {
+    const int j = __builtin_amdgcn_readfirstlane(xcd_group(blockIdx.x, gridDim.x) * kApplyWaves +
+                                                 int(threadIdx.x >> 6));
+    if (j >= n) return;
+    const int lane = threadIdx.x & 63;
+    int32_t o[3];
+    double w[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const int32_t o = nbr[3 * j + q];
-        if (o >= 0) acc += wt[3 * j + q] * (yj - y[uint32_t(o) * uint32_t(nb) + c]);
+        o[q] = nbr[3 * j + q];
+        w[q] = wt[3 * j + q];
     }
-    double out = alpha * (acc * inv_s[j]) + beta * yj;
-    if (yp) out += gam * yp[g];
-    yo[g] = out;
+    const double is = inv_s[j];
+    const size_t row = size_t(j) * nb;
+    // all loads of the row first (columns past nb read column nb - 1, and a missing neighbour
+    // reads the row itself: valid addresses whose values are not used), then the updates
+    double yv[CH], g[CH][3], pv[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = min(lane + 64 * k, nb - 1);
+        yv[k] = y[row + c];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[k][q] = y[size_t(o[q] >= 0 ? o[q] : j) * nb + c];
+        pv[k] = yp ? yp[row + c] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int c = lane + 64 * k;
+        if (c >= nb) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (o[q] >= 0) acc += w[q] * (yv[k] - g[k][q]);
+        double out = alpha * (acc * is) + beta * yv[k];
+        if (yp) out += gam * pv[k];
+        yo[row + c] = out;
+    }
 }
 
 // partial[chunk][p][q] = sum over the chunk's rows j of S_j x[j][p] z[j][q]
@@ -123,7 +152,7 @@ __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restri
 __global__ void k_rotate(int32_t n, int32_t nb, const double *__restrict__ x, const double *__restrict__ m,
                          double *__restrict__ y, int32_t upper) {
     __shared__ double xs[kRotRows][kMaxBlock];
-    const int64_t r0 = int64_t(blockIdx.x) * kRotRows;
+    const int64_t r0 = int64_t(xcd_group(blockIdx.x, gridDim.x)) * kRotRows;
     const int rows = int(std::min<int64_t>(kRotRows, n - r0));
     for (int e = threadIdx.x; e < kRotRows * nb; e += blockDim.x) {
         const int rr = e / nb, cc = e % nb;
@@ -665,8 +694,15 @@ struct ModeSolver {
     unsigned grid_items() const { return unsigned((int64_t(n) * nb + kBlock - 1) / kBlock); }
 
     int apply(const double *y, const double *yp, double *yo, double alpha, double beta, double gam) {
-        hipLaunchKernelGGL(k_modes_apply, dim3(grid_items()), dim3(kBlock), 0, st, n, nb, y, yp, yo,
-                           nbr.as<int32_t>(), wt.as<double>(), inv_s.as<double>(), alpha, beta, gam);
+        const dim3 grid((n + kApplyWaves - 1) / kApplyWaves), threads(64 * kApplyWaves);
+        const int32_t *nb_ = nbr.as<int32_t>();
+        const double *wt_ = wt.as<double>(), *is_ = inv_s.as<double>();
+        switch ((nb + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_modes_apply<1>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+        case 2: hipLaunchKernelGGL(k_modes_apply<2>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+        case 3: hipLaunchKernelGGL(k_modes_apply<3>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+        default: hipLaunchKernelGGL(k_modes_apply<4>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+        }
         TYEE_HIP(hipGetLastError());
         return TYEE_OK;
     }
