@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--graph", type=int, default=8, help="fused launches per HIP graph (0 = eager)")
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
+    p.add_argument("--modes-no-scale", action="store_true",
+                   help="modes70x101: leave out the 1.6M-triangle apply measurement")
     p.add_argument("--modes-degree", type=int, default=0,
                    help="modes70x101: largest filter degree per iteration (0 = library default)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -672,9 +674,30 @@ def bench_modes(args):
                  "curves_every_8th": [[k, float(np.sqrt(abs(om2[k]))), float(np.sqrt(quad[k])),
                                        float(np.sqrt(exact[k]))]
                                       for k in list(range(0, MODES_WANTED, 8)) + [MODES_WANTED - 1]]},
+        "apply_at_hbm_scale": None if args.modes_no_scale else modes_apply_at_scale(ty, stream),
         "cpu_baseline": None if args.no_cpu else cpu_baseline_modes(xy, tri, Lx, Ly),
     }
     print(json.dumps(out), flush=True)
+
+
+def modes_apply_at_scale(ty, stream, nb=MODES_BLOCK):
+    """k_modes_apply where the block cannot stay in the caches: one filtering iteration (degree
+    capped by the solver) on a 700 x 1000 resonator (1.6M triangles, block of 160, 1.64 GB per
+    block); HIP-event time per application against its algorithmic bytes."""
+    from meshgen import box_tri_mesh
+    xy, tri, Lx, Ly = box_tri_mesh(700.0, 1000.0, 1.0, 0.1, 3)
+    mesh = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    mesh.reorder("morton")
+    r = mesh.modes(nb // 2, block=nb, degree=200, tol=1e-14, max_iter=1, want_vectors=False,
+                   stream=stream)
+    applies = r["applies"] - (r["iters"] + 1)
+    ms = r["filter_ms"] / applies
+    per = len(tri) * (24 * nb + 44)
+    log(f"apply at scale: {len(tri)} triangles x {nb}: {ms * 1e3:.0f} us per application")
+    return {"triangles": len(tri), "block": nb, "applications": applies,
+            "avg_launch_ms": round(ms, 5), "algorithmic_bytes_per_launch": per,
+            "achieved_GBs": round(per / (ms * 1e-3) / 1e9, 1),
+            "frac_of_8TBs": round(per / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline_modes(xy, tri, Lx, Ly):
