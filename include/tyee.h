@@ -443,6 +443,9 @@ void tyee_batch_destroy(tyee_batch *b);
    its two buffers.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int tyee_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
 
+/* End of the spectrum tyee_mesh_modes computes. */
+typedef enum { TYEE_MODES_LOWEST = 0, TYEE_MODES_HIGHEST = 1 } tyee_modes_end;
+
 /* Work done by one tyee_mesh_modes call. */
 typedef struct {
     int32_t iters;         /* outer iterations (two filter passes, each followed by the
@@ -453,7 +456,7 @@ typedef struct {
     double total_ms;       /* host wall time of the call, uploads and readback included */
 } tyee_modes_stats;
 
-/* Lowest eigenmodes of the resonator (Section 2: eigenvectors of the Maxwell operator, which
+/* Lowest or highest eigenmodes of the resonator (Section 2: eigenvectors of the Maxwell operator, which
    the energy law (10) makes real and orthogonal in metric (7), and the "complex time"
    iteration that finds them; Fig. 4).  With E eliminated, eqs. 3-4 give for B the operator
    K = -L_E L_B, (K B)_j = (1/S_j) sum over interior edges i of j of
@@ -467,7 +470,10 @@ typedef struct {
    time); S-orthonormalisation of the block (deflation in metric (7)) after each filter pass;
    a Rayleigh-Ritz step after every two passes.
      gamma     [n_edges] per-edge scale in canonical order, or NULL.
-     n_modes   1 .. min(n_triangles, 256) lowest pairs wanted.
+     which     TYEE_MODES_LOWEST, or TYEE_MODES_HIGHEST (the paper's order: the largest
+               eigenvalue first; the solver then works on lambda_bound - K, whose lowest modes
+               are K's highest).
+     n_modes   1 .. min(n_triangles, 256) pairs wanted.
      block     vectors iterated, max(n_modes, 2) .. min(n_triangles, 256); 0 chooses
                n_modes + max(16, n_modes / 4) (capped).  n_triangles x block < 2^31.
      degree    largest filter degree per pass (two passes per outer iteration), 1 .. 100000;
@@ -480,7 +486,7 @@ typedef struct {
      seed      start block x[j][c] = 2u - 1, u = (splitmix64(seed + j block + c) >> 11) 2^-53
                with j canonical (the same splitmix64 as tyee_mesh_cfl).
      stream    HIP stream, or NULL for the default stream.
-     omega2    [n_modes] host out: lambda ascending.
+     omega2    [n_modes] host out: lambda, ascending (lowest) or descending (highest).
      modes     [n_modes][n_triangles] host out (canonical triangle order), S-orthonormal, or NULL.
      residual  [n_modes] host out: residual norm / lambda_bound, or NULL.
      stats     host out, or NULL.
@@ -488,9 +494,10 @@ typedef struct {
    blocks on the stream.  Errors: EINVAL (arguments; a mesh with no interior edge), ENOMEM,
    EDEVICE, EUNSTABLE (the block lost rank), ENOTCONVERGED (outputs are still written from the
    last iteration). */
-int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64_t n_modes, int32_t block,
-                    int32_t degree, double tol, int32_t max_iter, uint64_t seed, void *stream,
-                    double *omega2, double *modes, double *residual, tyee_modes_stats *stats);
+int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32_t which, int64_t n_modes,
+                    int32_t block, int32_t degree, double tol, int32_t max_iter, uint64_t seed,
+                    void *stream, double *omega2, double *modes, double *residual,
+                    tyee_modes_stats *stats);
 
 const char *tyee_last_error(void);
 

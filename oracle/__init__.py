@@ -215,34 +215,39 @@ class OracleMesh:
                            shape=(self.nt, self.ne))
         return LB, LE
 
-    def modes(self, count, gamma=None):
-        """Lowest `count` eigenpairs of K = -L_E L_B, the operator that eqs. 3-4 give for B
-        once E is eliminated (Section 2, eigenvectors and the "complex time" method).
+    def modes(self, count, gamma=None, which="lowest"):
+        """Lowest (or highest) `count` eigenpairs of K = -L_E L_B, the operator that eqs. 3-4
+        give for B once E is eliminated (Section 2, eigenvectors and the "complex time" method).
 
         K is self-adjoint and non-negative in the B part of metric (7) (weights S_j), so
         S^(1/2) K S^(-1/2) is symmetric; its eigenpairs come from a library symmetric solver
-        (dense for up to 4,000 triangles, else sparse shift-invert about a point just below
-        zero). Returns (lam ascending [count], V [n_t, count]) with sum_j S_j V_jc V_jd =
-        delta_cd; omega = sqrt(lam). The constant B is the static mode (lam = 0).
+        (dense for up to 4,000 triangles, else sparse: shift-invert about a point just below
+        zero for the lowest, the largest algebraic ones directly for the highest). Returns
+        (lam [count], V [n_t, count]) with sum_j S_j V_jc V_jd = delta_cd, lam ascending for
+        "lowest" and descending for "highest"; omega = sqrt(lam). The constant B is the static
+        mode (lam = 0).
         """
         import scipy.linalg
         import scipy.sparse as sp
         import scipy.sparse.linalg as sla
         count = int(count)
-        if not 1 <= count <= self.nt:
-            raise OracleError(EINVAL, "modes count")
+        if not 1 <= count <= self.nt or which not in ("lowest", "highest"):
+            raise OracleError(EINVAL, "modes count or which")
         LB, LE = self.sparse_ops(gamma)
         K = -(LE @ LB)
         rs, irs = np.sqrt(self.S), 1.0 / np.sqrt(self.S)
         A = sp.diags(rs) @ K @ sp.diags(irs)
         A = 0.5 * (A + A.T)
         if self.nt <= 4000:
-            lam, U = scipy.linalg.eigh(A.toarray(), subset_by_index=[0, count - 1])
-        else:
+            lo = 0 if which == "lowest" else self.nt - count
+            lam, U = scipy.linalg.eigh(A.toarray(), subset_by_index=[lo, lo + count - 1])
+        elif which == "lowest":
             top = float(abs(A).sum(axis=1).max())
             lam, U = sla.eigsh(A.tocsc(), k=count, sigma=-1e-6 * top, which="LM")
-            order = np.argsort(lam)
-            lam, U = lam[order], U[:, order]
+        else:
+            lam, U = sla.eigsh(A.tocsc(), k=count, which="LA", tol=1e-14)
+        order = np.argsort(lam) if which == "lowest" else np.argsort(-lam)
+        lam, U = lam[order], U[:, order]
         return lam, irs[:, None] * U
 
     # -- media and sources defined on the input ----------------------------------------

@@ -617,6 +617,9 @@ struct EventPair {
 
 struct ModeSolver {
     int32_t n = 0, nb = 0, chunks = 0, rows_per_chunk = 0;
+    // highest modes: the solver works on K' = top - K, whose lowest modes are K's highest
+    bool reversed = false;
+    double top = 0.0;
     size_t packed_bytes = 0;           // LDS for a packed nb x nb triangle, 0 = does not fit
     hipStream_t st = nullptr;
     DeviceBuffer nbr, wt, inv_s, s, canon;
@@ -694,6 +697,10 @@ struct ModeSolver {
     unsigned grid_items() const { return unsigned((int64_t(n) * nb + kBlock - 1) / kBlock); }
 
     int apply(const double *y, const double *yp, double *yo, double alpha, double beta, double gam) {
+        if (reversed) {  // alpha (top - K) y + beta y = -alpha K y + (beta + alpha top) y
+            beta += alpha * top;
+            alpha = -alpha;
+        }
         const dim3 grid((n + kApplyWaves - 1) / kApplyWaves), threads(64 * kApplyWaves);
         const int32_t *nb_ = nbr.as<int32_t>();
         const double *wt_ = wt.as<double>(), *is_ = inv_s.as<double>();
@@ -860,11 +867,14 @@ struct ModeSolver {
 }  // namespace
 }  // namespace tyee
 
-extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64_t n_modes, int32_t block,
-                               int32_t degree, double tol, int32_t max_iter, uint64_t seed, void *stream,
-                               double *omega2, double *modes, double *residual, tyee_modes_stats *stats) {
+extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32_t which, int64_t n_modes,
+                               int32_t block, int32_t degree, double tol, int32_t max_iter, uint64_t seed,
+                               void *stream, double *omega2, double *modes, double *residual,
+                               tyee_modes_stats *stats) {
     using namespace tyee;
     if (!mesh || !omega2) return fail(TYEE_EINVAL, "null argument");
+    if (which != TYEE_MODES_LOWEST && which != TYEE_MODES_HIGHEST)
+        return fail(TYEE_EINVAL, "which must be TYEE_MODES_LOWEST or TYEE_MODES_HIGHEST");
     const Mesh &msh = mesh->m;
     const int64_t nt = msh.nt;
     if (n_modes < 1 || n_modes > std::min<int64_t>(nt, kMaxBlock))
@@ -890,6 +900,8 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
         int rc = sv.alloc(msh, gamma, int32_t(nb), &b_up);
         if (rc) return rc;
         if (!(b_up > 0.0)) return fail(TYEE_EINVAL, "mesh has no interior edge");
+        sv.reversed = which == TYEE_MODES_HIGHEST;
+        sv.top = b_up;  // top - K has its spectrum in [0, b_up] too
         // random start, S-orthonormalised, then a first Rayleigh-Ritz for the bounds
         hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
                            sv.canon.as<int32_t>(), seed, sv.B(0));
@@ -948,7 +960,7 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int64
             done = converged();
         }
         if (rc) return rc;
-        for (int64_t c = 0; c < n_modes; ++c) omega2[c] = ritz[c];
+        for (int64_t c = 0; c < n_modes; ++c) omega2[c] = sv.reversed ? b_up - ritz[c] : ritz[c];
         if (residual)
             for (int64_t c = 0; c < n_modes; ++c) residual[c] = res.empty() ? 1.0 : res[c] / b_up;
         if (stats) {

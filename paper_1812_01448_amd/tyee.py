@@ -175,7 +175,7 @@ def _load():
         "tyee_copy_bandwidth": [i64, i32, ctypes.POINTER(f64)],
         "tyee_sim_bind_external": [vp, i32, vp, vp],
         "tyee_sim_current_buffer": [vp, ctypes.POINTER(i32)],
-        "tyee_mesh_modes": [vp, vp, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
+        "tyee_mesh_modes": [vp, vp, i32, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
                             ctypes.POINTER(_ModesStats)],
         "tyee_batch_tune_progress": [vp, i64, vp, i64, ctypes.POINTER(i64), _TUNE_PROGRESS, vp],
     }
@@ -315,20 +315,24 @@ class Mesh:
 
 
     def modes(self, n_modes, gamma=None, block=0, degree=0, tol=1e-10, max_iter=200, seed=0,
-              stream=None, want_vectors=True):
-        """Lowest n_modes eigenpairs of K = -L_E L_B on the device (FP64).
+              stream=None, want_vectors=True, which="lowest"):
+        """Lowest (or, with which="highest", highest) n_modes eigenpairs of K = -L_E L_B on
+        the device (FP64).
 
-        Returns a dict: omega2 [n_modes] ascending, modes [n_modes, n_t] (canonical triangle
-        order, S-orthonormal; None unless want_vectors), residual [n_modes] (relative to the
-        Gershgorin bound), converged, and the call's stats (iters, applies, lambda_bound,
-        filter_ms, total_ms)."""
+        Returns a dict: omega2 [n_modes] (ascending, or descending for the highest), modes
+        [n_modes, n_t] (canonical triangle order, S-orthonormal; None unless want_vectors),
+        residual [n_modes] (relative to the Gershgorin bound), converged, and the call's stats
+        (iters, applies, lambda_bound, filter_ms, total_ms)."""
         n_modes = int(n_modes)
         om2 = np.zeros(n_modes)
         vec = np.zeros((n_modes, self.nt)) if want_vectors else None
         res = np.zeros(n_modes)
         st = _ModesStats()
         g = None if gamma is None else _f64(gamma, self.ne)
-        rc = _check(lib.tyee_mesh_modes(self._h, _ptr(g), n_modes, int(block), int(degree),
+        if which not in ("lowest", "highest"):
+            raise ValueError("which must be 'lowest' or 'highest'")
+        rc = _check(lib.tyee_mesh_modes(self._h, _ptr(g), 0 if which == "lowest" else 1, n_modes,
+                                        int(block), int(degree),
                                         float(tol), int(max_iter), int(seed),
                                         None if stream is None else int(stream), _ptr(om2),
                                         _ptr(vec), _ptr(res), ctypes.byref(st)),

@@ -63,6 +63,21 @@ def test_box_modes_match_oracle(ty, order):
     assert abs(got["omega2"][0]) <= 1e-9 * got["lambda_bound"]          # static mode
 
 
+def test_highest_modes_match_oracle_and_the_power_iteration(ty):
+    _note("case: box 24 x 36 triangular lattice, 16 highest modes (the paper's order)")
+    xy, tri, Lx, Ly = box_tri_mesh(24, 36, 1.0, 0.1, 5)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam_ref, V_ref = om.modes(40, which="highest")
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    m.reorder("morton")
+    got = m.modes(16, which="highest", tol=1e-12, max_iter=400)
+    _note(f"  iters {got['iters']} applies {got['applies']}")
+    assert np.all(np.diff(got["omega2"]) <= 0)                       # descending
+    _check(om, got, lam_ref, V_ref)
+    lam_cfl, _, ok = m.cfl(rtol=1e-14, max_iter=400000)
+    assert ok and abs(got["omega2"][0] - lam_cfl) <= 1e-9 * lam_cfl
+
+
 def test_square_lattice_box_and_gamma(ty):
     _note("case: jittered square-lattice box 14 x 14, per-edge gamma, 24 modes")
     xy, tri, Lx, Ly = box_mesh(14, 14, 0.2, 2, h=1.0 / 14)

@@ -140,6 +140,12 @@ def test_mode_solver_rejects_bad_arguments(ty):
         with pytest.raises(ty.TyeeError) as e:
             m.modes(**kw)
         assert e.value.code == -1, kw                          # TYEE_EINVAL
+    with pytest.raises(ValueError):
+        m.modes(10, which="middle")
+    out = np.zeros(10)
+    from paper_1812_01448_amd import tyee as raw
+    assert raw.lib.tyee_mesh_modes(m._h, None, 7, 10, 0, 0, 1e-10, 10, 0, None,
+                                   out.ctypes.data, None, None, None) == -1
 
 
 def test_rayleigh_quotient_diagnostic_matches_oracle(ty):

@@ -1,11 +1,12 @@
-"""Pins of the oracle's lowest-mode solver (``OracleMesh.modes``) against facts from outside it.
+"""Pins of the oracle's mode solver (``OracleMesh.modes``) against facts from outside it.
 
 * its sparse operators equal the C core's operators applied to unit vectors;
 * the equilateral torus gives the honeycomb closed form, all modes;
 * a closed box gives the resonator frequencies pi sqrt((m/Lx)^2 + (n/Ly)^2) with second-order
   convergence, through the dense and the sparse solver;
-* the top mode equals the C core's power iteration; a uniform scale gamma multiplies every
-  eigenvalue by gamma^2;
+* the top mode (of the whole spectrum, and as the first of the highest modes, dense and sparse)
+  equals the C core's power iteration; a uniform scale gamma multiplies every eigenvalue by
+  gamma^2;
 * every pair is an eigenpair of the C core's matrix-free operator, S-orthonormal, with one
   static (zero) mode on a connected mesh.
 """
@@ -69,8 +70,19 @@ def test_top_mode_is_the_power_iteration_and_gamma_scales_the_spectrum():
     lam, _ = m.modes(m.nt)
     top, _, ok = m.power(rtol=1e-14, max_iter=200000)
     assert ok and abs(lam[-1] - top) < 1e-9 * top
+    # the highest modes are the top of the same spectrum, descending
+    hi, Vh = m.modes(5, which="highest")
+    np.testing.assert_allclose(hi, lam[::-1][:5], rtol=1e-12)
+    assert np.max(np.abs(Vh.T @ (m.S[:, None] * Vh) - np.eye(5))) < 1e-12
     lam2, _ = m.modes(20, gamma=np.full(m.ne, 1.1))
     np.testing.assert_allclose(lam2[1:], 1.21 * lam[1:20], rtol=1e-10)
+    # sparse path (more than 4,000 triangles)
+    xy, tri, Lx, Ly = box_mesh(50, 50, 0.2, 7, h=0.02)
+    mb = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    assert mb.nt > 4000
+    hi, _ = mb.modes(3, which="highest")
+    top, _, ok = mb.power(rtol=1e-14, max_iter=400000)
+    assert ok and abs(hi[0] - top) < 1e-9 * top and hi[0] >= hi[1] >= hi[2]
 
 
 @pytest.mark.parametrize("periodic", [False, True])
