@@ -1,5 +1,6 @@
-// Lowest eigenmodes of the B-field operator K = -L_E L_B (Section 2: eigenvectors of the
-// Maxwell operator in metric (7) and the "complex time" method), on the device in FP64.
+// Lowest (or highest) eigenmodes of the B-field operator K = -L_E L_B (Section 2: eigenvectors
+// of the Maxwell operator in metric (7) and the "complex time" method), on the device in FP64.
+// The highest modes are the lowest of b - K (b the bound below), which the same iteration finds.
 //
 // With E eliminated, eqs. 3-4 give for the field at triangle j
 //     (K B)_j = (1/S_j) sum over interior edges i of j of  w_i (B_j - B_other(i)),
