@@ -341,56 +341,104 @@ constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kerne
 constexpr int kInvRows = 16;          // rows of R^-1 finished per pass
 
 // The same as k_chol_inverse with g held in LDS (packed upper triangle, nb (nb + 1)/2 doubles
-// of dynamic shared memory), R^-1 formed in place of R (see below).  g is only read.
+// of dynamic shared memory), blocked so that the work-group meets at a barrier about 4 nb / 8
+// times instead of 4 nb.  g is only read.
+//   Cholesky: panels of kPanel rows.  One wave factors a panel in registers (lane l holds
+//   columns j0 + l + 64 s), exchanging each pivot and multiplier by a shuffle, with no
+//   barrier; then all work-items apply the panel's rank-kPanel update to the rows below it.
+//   R^-1 (R M = I, M upper triangular, M[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] M[k][c]) /
+//   R[r][r]): passes of kInvRows rows from the bottom.  Each work-item owns one column: it
+//   takes the finished rows below the pass into registers, finishes the pass's rows of its
+//   column in registers, and after one barrier the pass's rows of M replace those of R in LDS.
+constexpr int kPanel = 8;
 __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, const double *__restrict__ g,
                                                                     double shift, double *__restrict__ m,
                                                                     int32_t *__restrict__ info) {
     extern __shared__ double P[];
     __shared__ int bad;
-    __shared__ double piv;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     if (tid == 0) bad = 0;
     for (int e = tid; e < nb * nb; e += nt) {
         const int r = e / nb, c = e % nb;
         if (c >= r) P[packed(nb, r, c)] = g[e] + (r == c ? shift : 0.0);
     }
     __syncthreads();
-    for (int k = 0; k < nb; ++k) {
-        if (tid == 0) {
-            const double d = P[packed(nb, k, k)];
-            if (!(d > 0.0) || !std::isfinite(d)) bad = k + 1;
-            else {
-                piv = std::sqrt(d);
-                P[packed(nb, k, k)] = piv;
+    constexpr int kSlots = kMaxBlock / 64;
+    for (int j0 = 0; j0 < nb; j0 += kPanel) {
+        const int pw = min(kPanel, nb - j0);
+        if (tid < 64) {
+            double pr[kPanel][kSlots];
+#pragma unroll
+            for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    const int c = j0 + lane + 64 * sl;
+                    pr[r][sl] = (r < pw && c < nb && c >= j0 + r) ? P[packed(nb, j0 + r, c)] : 0.0;
+                }
+            int failed = 0;
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k) {
+                if (k >= pw || failed) continue;
+                const double d = __shfl(pr[k][0], k);  // column j0 + k sits in lane k, slot 0
+                if (!(d > 0.0) || !std::isfinite(d)) {
+                    failed = j0 + k + 1;
+                    continue;
+                }
+                const double piv = std::sqrt(d), inv = 1.0 / piv;
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    const int c = j0 + lane + 64 * sl;
+                    if (c == j0 + k) pr[k][sl] = piv;
+                    else if (c > j0 + k) pr[k][sl] *= inv;
+                }
+#pragma unroll
+                for (int r = k + 1; r < kPanel; ++r) {
+                    if (r >= pw) continue;
+                    const double mult = __shfl(pr[k][0], r);  // R[j0 + k][j0 + r]
+#pragma unroll
+                    for (int sl = 0; sl < kSlots; ++sl) {
+                        const int c = j0 + lane + 64 * sl;
+                        if (c >= j0 + r && c < nb) pr[r][sl] -= mult * pr[k][sl];
+                    }
+                }
             }
+#pragma unroll
+            for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    const int c = j0 + lane + 64 * sl;
+                    if (r < pw && c < nb && c >= j0 + r) P[packed(nb, j0 + r, c)] = pr[r][sl];
+                }
+            if (failed && lane == 0) bad = failed;
         }
         __syncthreads();
         if (bad) break;
-        const double inv = 1.0 / piv;
-        const int rowk = packed(nb, k, 0);
-        for (int c = k + 1 + tid; c < nb; c += nt) P[rowk + c] *= inv;
-        __syncthreads();
-        // trailing update of rows r > k, columns c >= r: 32 lanes per row, so row k and row r
-        // are both read along contiguous packed runs
-        for (int r = k + 1 + (tid >> 5); r < nb; r += nt >> 5) {
-            const double pr = P[rowk + r];
+        // rows below the panel: P[r][c] -= sum over the panel rows k of R[k][r] R[k][c]
+        for (int r = j0 + pw + (tid >> 5); r < nb; r += nt >> 5) {
+            double rk[kPanel];
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k) rk[k] = k < pw ? P[packed(nb, j0 + k, r)] : 0.0;
             const int rowr = packed(nb, r, 0);
-            for (int c = r + (tid & 31); c < nb; c += 32) P[rowr + c] -= pr * P[rowk + c];
+            for (int c = r + (tid & 31); c < nb; c += 32) {
+                double acc = P[rowr + c];
+#pragma unroll
+                for (int k = 0; k < kPanel; ++k)
+                    if (k < pw) acc -= rk[k] * P[packed(nb, j0 + k, c)];
+                P[rowr + c] = acc;
+            }
         }
         __syncthreads();
     }
     if (tid == 0) *info = bad;
     if (bad) return;
-    // R M = I, M upper triangular: M[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] M[k][c]) / R[r][r].
-    // Row r of M takes the place of row r of R in LDS once row r of R has been read for the
-    // last time, so the whole inverse stays on chip.  One thread per column; rows are finished
-    // from the bottom in passes of kInvRows, each column first taking the contributions of the
-    // finished rows below the pass into registers.
     const int c = tid;
-    double acc[kInvRows];
     for (int hi = nb; hi > 0; hi -= kInvRows) {
         const int lo = hi > kInvRows ? hi - kInvRows : 0;
+        double mv[kInvRows];
+#pragma unroll
+        for (int q = 0; q < kInvRows; ++q) mv[q] = 0.0;
         if (c < nb) {
+            double acc[kInvRows];
 #pragma unroll
             for (int q = 0; q < kInvRows; ++q) acc[q] = (lo + q < hi && lo + q == c) ? 1.0 : 0.0;
             for (int k = hi; k <= c; ++k) {
@@ -399,21 +447,25 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, 
                 for (int q = 0; q < kInvRows; ++q)
                     if (lo + q < hi) acc[q] -= P[packed(nb, lo + q, k)] * mk;
             }
-        }
-        for (int r = hi - 1; r >= lo; --r) {
-            double val = 0.0;
-            if (c < nb && c >= r) {
-                double a = 0.0;
 #pragma unroll
-                for (int q = 0; q < kInvRows; ++q)
-                    if (lo + q == r) a = acc[q];
-                for (int k = r + 1; k < hi && k <= c; ++k) a -= P[packed(nb, r, k)] * P[packed(nb, k, c)];
-                val = a / P[packed(nb, r, r)];
+            for (int q = kInvRows - 1; q >= 0; --q) {
+                const int r = lo + q;
+                if (r >= hi || c < r) continue;
+                double a = acc[q];
+#pragma unroll
+                for (int q2 = q + 1; q2 < kInvRows; ++q2) {
+                    const int k = lo + q2;
+                    if (k < hi && k <= c) a -= P[packed(nb, r, k)] * mv[q2];
+                }
+                mv[q] = a / P[packed(nb, r, r)];
             }
-            __syncthreads();  // row r of R is no longer read
-            if (c < nb && c >= r) P[packed(nb, r, c)] = val;
-            __syncthreads();
         }
+        __syncthreads();  // the pass's rows of R are no longer read
+        if (c < nb)
+#pragma unroll
+            for (int q = 0; q < kInvRows; ++q)
+                if (lo + q < hi && c >= lo + q) P[packed(nb, lo + q, c)] = mv[q];
+        __syncthreads();
     }
     for (int e = tid; e < nb * nb; e += nt) {
         const int r = e / nb, cc = e % nb;
@@ -770,9 +822,15 @@ struct ModeSolver {
     // condition number stays below about u^(-1/2) (the filter degree is capped for that);
     // if a factorisation fails, the shifted Cholesky QR three times (Fukaya et al., SIAM J.
     // Sci. Comput. 2020) from the same block.  TYEE_EUNSTABLE when that fails too.
-    int orthonormalise(int ix, int iy, int *out) {
+    // With `once`, a single Cholesky QR: the block comes out well conditioned (orthonormal to
+    // about u cond^2), which is all a following filter pass needs.
+    int orthonormalise(int ix, int iy, int *out, bool once = false) {
         bool ok = false;
         int rc = cholqr_pass(ix, iy, false, &ok);
+        if (!rc && ok && once) {
+            *out = iy;
+            return TYEE_OK;
+        }
         if (!rc && ok) rc = cholqr_pass(iy, ix, false, &ok);
         if (rc) return rc;
         if (ok) {
@@ -942,7 +1000,9 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
                     TYEE_HIP(hipEventRecord(ev.b, sv.st));
                     applies += deg;
                 }
-                if (!rc) rc = sv.orthonormalise(fo, ModeSolver::pick({fo}), &in);
+                // a pass that another filter pass follows needs a well-conditioned block only
+                const bool last = pass + 1 == (filtered ? kFilterPasses : 1);
+                if (!rc) rc = sv.orthonormalise(fo, ModeSolver::pick({fo}), &in, !last);
                 if (!rc && filtered) {
                     float ms = 0.0f;
                     TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
