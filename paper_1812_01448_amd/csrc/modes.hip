@@ -473,28 +473,57 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, 
     }
 }
 
-// Cyclic Jacobi on the symmetric h held in LDS (packed upper triangle, dynamic shared
-// memory), nb/2 disjoint rotations per round in round-robin order, one barrier per round:
-// each 2 x 2 block of h that two rotation pairs share is updated by one thread, J_s^T B J_t.
-// The rotations are written to rot[sweep][round][pair] = (c, s) for k_jacobi_vectors; on
-// return theta holds the eigenvalues ascending, order[i] the diagonal position of the i-th,
-// and sweeps_out the sweeps done.
+// Cyclic Jacobi on the symmetric h held in LDS (packed upper triangle of np x np, np = nb
+// rounded up to even, the padding row and column zero; dynamic shared memory), np/2 disjoint
+// rotations per round in round-robin order.  A round: the pairs' rotations (one work-item per
+// pair), a barrier, then every 2 x 2 block of h that two pairs s <= t share becomes
+// J_s^T B J_t, and a barrier.  The blocks are dealt to the work-items once (kJacobiItems at
+// most each, the same (s, t) slots every round; the pairs in a slot change), and a work-item
+// issues the loads of all its blocks before it computes any.  The rotations are written to
+// rot[sweep][round][pair] = (c, s) for k_jacobi_vectors; on return theta holds the
+// eigenvalues ascending, order[i] the diagonal position of the i-th, and sweeps_out the
+// sweeps done.
+constexpr int kJacobiItems = 5;     // blocks per work-item: (98 x 99 / 2) / 1024, rounded up
+constexpr int kJacobiGroup = 3;     // blocks whose loads are issued together
+
+__device__ __forceinline__ int row_offset(int np, int i) { return i * (2 * np - i - 1) / 2; }
+
 __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const double *__restrict__ h,
                                                               double2 *__restrict__ rot, double *__restrict__ theta,
                                                               int32_t *__restrict__ order_out, int32_t max_sweeps,
                                                               int32_t *__restrict__ sweeps_out) {
     extern __shared__ double P[];
-    __shared__ double cs[kMaxBlock / 2 + 1], sn[kMaxBlock / 2 + 1];
-    __shared__ int pp[kMaxBlock / 2 + 1], qq[kMaxBlock / 2 + 1];
+    __shared__ int4 pr[kMaxBlock / 2];       // pair: a < b, row offsets of a and b
+    __shared__ double2 cs[kMaxBlock / 2];    // pair rotation (c, s)
     __shared__ double red[kSmallThreads / 64][2];
     __shared__ int order[kMaxBlock];
     __shared__ int rotated;            // a rotation was applied in the current sweep
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int np = nb + (nb & 1), half = np / 2;
+    const int np = nb + (nb & 1), half = np / 2, nblk = half * (half + 1) / 2;
     if (tid == 0) rotated = 0;
-    for (int e = tid; e < nb * nb; e += nt) {
-        const int r = e / nb, c = e % nb;
-        if (c >= r) P[packed(nb, r, c)] = 0.5 * (h[r * nb + c] + h[c * nb + r]);
+    for (int e = tid; e < np * np; e += nt) {
+        const int r = e / np, c = e % np;
+        if (c >= r) P[row_offset(np, r) + c] = (c < nb) ? 0.5 * (h[r * nb + c] + h[c * nb + r]) : 0.0;
+    }
+    // this work-item's blocks: item k < half is the diagonal block (k, k), item half + m the
+    // m-th block (s, t), s < t, of the strict upper triangle in row-major order; -1 = none
+    int item[kJacobiItems];
+#pragma unroll
+    for (int i = 0; i < kJacobiItems; ++i) {
+        const int k = tid + i * nt;
+        item[i] = -1;
+        if (k < half) {
+            item[i] = (k << 16) | k;
+        } else if (k < nblk) {
+            const int m = k - half;
+            // row s holds half - 1 - s blocks and starts at s (2 half - s - 1) / 2
+            const double w = 2.0 * half - 1.0;
+            int r = int((w - std::sqrt(w * w - 8.0 * m)) * 0.5);
+            r = r < 0 ? 0 : (r > half - 2 ? half - 2 : r);
+            while (r > 0 && r * (2 * half - r - 1) / 2 > m) --r;
+            while ((r + 1) * (2 * half - r - 2) / 2 <= m) ++r;
+            item[i] = (r << 16) | (r + 1 + m - r * (2 * half - r - 1) / 2);
+        }
     }
     __syncthreads();
     int sweep = 0;
@@ -504,7 +533,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
         for (int e = tid; e < nb * nb; e += nt) {
             const int r = e / nb, c = e % nb;
             if (c < r) continue;
-            const double v = P[packed(nb, r, c)];
+            const double v = P[row_offset(np, r) + c];
             all += (r == c ? 1.0 : 2.0) * v * v;
             if (r != c) off += 2.0 * v * v;
         }
@@ -529,73 +558,94 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
         __syncthreads();
         for (int round = 0; round < np - 1; ++round) {
             for (int t = tid; t < half; t += nt) {
-                auto player = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + round) % (np - 1); };
+                // round-robin positions: 0 stays, the others shift by one every round
+                auto player = [&](int k) {
+                    if (k == 0) return 0;
+                    const int z = k - 1 + round;
+                    return 1 + (z >= np - 1 ? z - (np - 1) : z);
+                };
                 const int u = player(t), v = player(np - 1 - t);
                 const int a = u < v ? u : v, b = u < v ? v : u;
-                double c = 1.0, s = 0.0;
+                const int oa = row_offset(np, a), ob = row_offset(np, b);
+                double c = 1.0, sn = 0.0;
                 if (b < nb) {
-                    const double apq = P[packed(nb, a, b)], app = P[packed(nb, a, a)], aqq = P[packed(nb, b, b)];
+                    const double apq = P[oa + b], app = P[oa + a], aqq = P[ob + b];
                     // rotations below rounding of the two diagonal entries are skipped
                     if (std::fabs(apq) > 1e-16 * (std::fabs(app) + std::fabs(aqq))) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         const double tt = tau >= 0.0 ? 1.0 / (tau + std::sqrt(1.0 + tau * tau))
                                                      : -1.0 / (-tau + std::sqrt(1.0 + tau * tau));
                         c = 1.0 / std::sqrt(1.0 + tt * tt);
-                        s = tt * c;
+                        sn = tt * c;
                         rotated = 1;
                     }
                 }
-                pp[t] = a;
-                qq[t] = b;
-                cs[t] = c;
-                sn[t] = s;
-                rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, s);
+                pr[t] = make_int4(a, b, oa, ob);
+                cs[t] = make_double2(c, sn);
+                rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, sn);
             }
             __syncthreads();
-            // block pairs (s, t), s <= t: a group of 32 lanes per s
-            for (int s_ = tid >> 5; s_ < half; s_ += nt >> 5)
-            for (int t_ = s_ + (tid & 31); t_ < half; t_ += 32) {
-                const int a1 = pp[s_], b1 = qq[s_], a2 = pp[t_], b2 = qq[t_];
-                const double c1 = cs[s_], s1 = sn[s_], c2 = cs[t_], s2 = sn[t_];
-                if (s_ == t_) {
-                    if (b1 >= nb || s1 == 0.0) continue;
-                    const double x = P[packed(nb, a1, a1)], y = P[packed(nb, b1, b1)], z = P[packed(nb, a1, b1)];
-                    // J^T [[x, z], [z, y]] J with J = [[c, s], [-s, c]]
-                    P[packed(nb, a1, a1)] = c1 * c1 * x - 2.0 * c1 * s1 * z + s1 * s1 * y;
-                    P[packed(nb, b1, b1)] = s1 * s1 * x + 2.0 * c1 * s1 * z + c1 * c1 * y;
-                    P[packed(nb, a1, b1)] = 0.0;
-                    continue;
+            // packed position of (i, j) from the row offsets
+            auto at = [](int i, int oi, int j, int oj) { return i <= j ? oi + j : oj + i; };
+            // the items in groups of kJacobiGroup: all loads of a group, then its updates
+#pragma unroll
+            for (int g = 0; g < kJacobiItems; g += kJacobiGroup) {
+                if (g * nt >= nblk) break;           // the same for the whole work-group
+                int idx[kJacobiGroup][4];
+                double hv[kJacobiGroup][4];
+#pragma unroll
+                for (int j = 0; j < kJacobiGroup; ++j) {
+                    const int i = g + j;
+                    if (i >= kJacobiItems || i * nt >= nblk) break;
+                    const int code = item[i] < 0 ? 0 : item[i];
+                    const int4 p1 = pr[code >> 16], p2 = pr[code & 0xffff];
+                    idx[j][0] = at(p1.x, p1.z, p2.x, p2.z);
+                    idx[j][1] = at(p1.x, p1.z, p2.y, p2.w);
+                    idx[j][2] = at(p1.y, p1.w, p2.x, p2.z);
+                    idx[j][3] = at(p1.y, p1.w, p2.y, p2.w);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hv[j][q] = P[idx[j][q]];
                 }
-                if ((s1 == 0.0 || b1 >= nb) && (s2 == 0.0 || b2 >= nb)) continue;
-                auto at = [&](int i, int j) { return i <= j ? packed(nb, i, j) : packed(nb, j, i); };
-                const bool rb = b1 < nb, cb = b2 < nb;
-                const int i00 = at(a1, a2), i01 = cb ? at(a1, b2) : 0;
-                const int i10 = rb ? at(b1, a2) : 0, i11 = (rb && cb) ? at(b1, b2) : 0;
-                const double h00 = P[i00], h01 = cb ? P[i01] : 0.0;
-                const double h10 = rb ? P[i10] : 0.0, h11 = (rb && cb) ? P[i11] : 0.0;
-                // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
-                const double r00 = c1 * h00 - s1 * h10, r01 = c1 * h01 - s1 * h11;
-                const double r10 = s1 * h00 + c1 * h10, r11 = s1 * h01 + c1 * h11;
-                P[i00] = c2 * r00 - s2 * r01;
-                if (cb) P[i01] = s2 * r00 + c2 * r01;
-                if (rb) P[i10] = c2 * r10 - s2 * r11;
-                if (rb && cb) P[i11] = s2 * r10 + c2 * r11;
+#pragma unroll
+                for (int j = 0; j < kJacobiGroup; ++j) {
+                    const int i = g + j;
+                    if (i >= kJacobiItems || i * nt >= nblk) break;
+                    if (item[i] < 0) continue;
+                    const double2 r1 = cs[item[i] >> 16], r2 = cs[item[i] & 0xffff];
+                    const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
+                    const double h00 = hv[j][0], h01 = hv[j][1], h10 = hv[j][2], h11 = hv[j][3];
+                    // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
+                    const double x00 = c1 * h00 - s1 * h10, x01 = c1 * h01 - s1 * h11;
+                    const double x10 = s1 * h00 + c1 * h10, x11 = s1 * h01 + c1 * h11;
+                    const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
+                    const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
+                    P[idx[j][0]] = y00;
+                    P[idx[j][3]] = y11;
+                    if ((item[i] >> 16) == (item[i] & 0xffff)) {
+                        // a diagonal block: (a, b) is the one element idx 1 and 2 both name,
+                        // and the pair's own rotation annihilates it
+                        P[idx[j][1]] = s1 != 0.0 ? 0.0 : y01;
+                    } else {
+                        P[idx[j][1]] = y01;
+                        P[idx[j][2]] = y10;
+                    }
+                }
             }
             __syncthreads();
         }
     }
     for (int i = tid; i < nb; i += nt) {
-        const double v = P[packed(nb, i, i)];
+        const double v = P[row_offset(np, i) + i];
         int rank = 0;
         for (int k = 0; k < nb; ++k) {
-            const double u = P[packed(nb, k, k)];
+            const double u = P[row_offset(np, k) + k];
             rank += (u < v) || (u == v && k < i);
         }
         order[rank] = i;
     }
     __syncthreads();
     for (int i = tid; i < nb; i += nt) {
-        theta[i] = P[packed(nb, order[i], order[i])];
+        theta[i] = P[row_offset(np, order[i]) + order[i]];
         order_out[i] = order[i];
     }
     if (tid == 0) *sweeps_out = sweep;
@@ -736,8 +786,12 @@ struct ModeSolver {
         TYEE_HIP(hipGetDevice(&device));
         TYEE_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
         // the small kernels also hold up to about 7 KB of static shared memory
-        const size_t tri_bytes = size_t(nb) * (nb + 1) / 2 * sizeof(double);
-        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) ? tri_bytes : 0;
+        // (np: the Jacobi kernel pads an odd nb by one row and column)
+        const size_t tri_bytes = size_t(np) * (np + 1) / 2 * sizeof(double);
+        const int jh = np / 2;
+        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) && jh * (jh + 1) / 2 <= kJacobiItems * kSmallThreads
+                           ? tri_bytes
+                           : 0;
         TYEE_HIP(hipMemcpyAsync(nbr.p, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, st));
         TYEE_HIP(hipMemcpyAsync(wt.p, hw.data(), hw.size() * 8, hipMemcpyHostToDevice, st));
         TYEE_HIP(hipMemcpyAsync(inv_s.p, hinv.data(), nt * 8, hipMemcpyHostToDevice, st));
