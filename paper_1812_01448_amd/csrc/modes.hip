@@ -337,31 +337,49 @@ __global__ void __launch_bounds__(256) k_jacobi(int32_t nb, double *__restrict__
 // Packed upper triangle (row-major) of an nb x nb symmetric matrix: element (i, j), i <= j.
 __device__ __forceinline__ int packed(int nb, int i, int j) { return i * (2 * nb - i - 1) / 2 + j; }
 
-constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kernels
-constexpr int kInvRows = 16;          // rows of R^-1 finished per pass
+// for e < count: store(e, load(e)), the work-group's items in steps of kStage per work-item
+// with all kStage loads issued before the first store (global memory to LDS staging)
+constexpr int kStage = 8;
+template <typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int count, Load load, Store store) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e0 = 0; e0 < count; e0 += kStage * nt) {
+        double v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * nt + tid;
+            v[u] = e < count ? load(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * nt + tid;
+            if (e < count) store(e, v[u]);
+        }
+    }
+}
 
-// The same as k_chol_inverse with g held in LDS (packed upper triangle, nb (nb + 1)/2 doubles
-// of dynamic shared memory), blocked so that the work-group meets at a barrier about 4 nb / 8
-// times instead of 4 nb.  g is only read.
-//   Cholesky: panels of kPanel rows.  One wave factors a panel in registers (lane l holds
-//   columns j0 + l + 64 s), exchanging each pivot and multiplier by a shuffle, with no
-//   barrier; then all work-items apply the panel's rank-kPanel update to the rows below it.
-//   R^-1 (R M = I, M upper triangular, M[r][c] = (delta_rc - sum_{k=r+1..c} R[r][k] M[k][c]) /
-//   R[r][r]): passes of kInvRows rows from the bottom.  Each work-item owns one column: it
-//   takes the finished rows below the pass into registers, finishes the pass's rows of its
-//   column in registers, and after one barrier the pass's rows of M replace those of R in LDS.
+constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kernels
+
+// The Cholesky factor of g + shift I with g held in LDS (packed upper triangle, nb (nb + 1)/2
+// doubles of dynamic shared memory), blocked in panels of kPanel rows: one wave factors a
+// panel in registers (lane l holds columns j0 + l + 64 s), exchanging each pivot and
+// multiplier by a shuffle, with no barrier; then all work-items apply the panel's rank-kPanel
+// update to the rows below it.  g is only read; R goes to rt packed by columns
+// (rt[c (c + 1)/2 + k] = R[k][c], k <= c) for k_tri_inverse.  info = 0, or 1 + the failing
+// pivot's index.
 constexpr int kPanel = 8;
-__global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, const double *__restrict__ g,
-                                                                    double shift, double *__restrict__ m,
-                                                                    int32_t *__restrict__ info) {
+__global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const double *__restrict__ g, double shift,
+                                                            double *__restrict__ rt, int32_t *__restrict__ info) {
     extern __shared__ double P[];
     __shared__ int bad;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < nb * nb; e += nt) {
-        const int r = e / nb, c = e % nb;
-        if (c >= r) P[packed(nb, r, c)] = g[e] + (r == c ? shift : 0.0);
-    }
+    staged_copy(
+        nb * nb, [&](int e) { return g[e]; },
+        [&](int e, double v) {
+            const int r = e / nb, c = e % nb;
+            if (c >= r) P[packed(nb, r, c)] = v + (r == c ? shift : 0.0);
+        });
     __syncthreads();
     constexpr int kSlots = kMaxBlock / 64;
     for (int j0 = 0; j0 < nb; j0 += kPanel) {
@@ -431,45 +449,74 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_inverse_lds(int32_t nb, 
     }
     if (tid == 0) *info = bad;
     if (bad) return;
-    const int c = tid;
-    for (int hi = nb; hi > 0; hi -= kInvRows) {
-        const int lo = hi > kInvRows ? hi - kInvRows : 0;
-        double mv[kInvRows];
-#pragma unroll
-        for (int q = 0; q < kInvRows; ++q) mv[q] = 0.0;
-        if (c < nb) {
-            double acc[kInvRows];
-#pragma unroll
-            for (int q = 0; q < kInvRows; ++q) acc[q] = (lo + q < hi && lo + q == c) ? 1.0 : 0.0;
-            for (int k = hi; k <= c; ++k) {
-                const double mk = P[packed(nb, k, c)];  // row k already holds M
-#pragma unroll
-                for (int q = 0; q < kInvRows; ++q)
-                    if (lo + q < hi) acc[q] -= P[packed(nb, lo + q, k)] * mk;
-            }
-#pragma unroll
-            for (int q = kInvRows - 1; q >= 0; --q) {
-                const int r = lo + q;
-                if (r >= hi || c < r) continue;
-                double a = acc[q];
-#pragma unroll
-                for (int q2 = q + 1; q2 < kInvRows; ++q2) {
-                    const int k = lo + q2;
-                    if (k < hi && k <= c) a -= P[packed(nb, r, k)] * mv[q2];
-                }
-                mv[q] = a / P[packed(nb, r, r)];
-            }
-        }
-        __syncthreads();  // the pass's rows of R are no longer read
-        if (c < nb)
-#pragma unroll
-            for (int q = 0; q < kInvRows; ++q)
-                if (lo + q < hi && c >= lo + q) P[packed(nb, lo + q, c)] = mv[q];
-        __syncthreads();
-    }
     for (int e = tid; e < nb * nb; e += nt) {
-        const int r = e / nb, cc = e % nb;
-        m[e] = cc >= r ? P[packed(nb, r, cc)] : 0.0;
+        const int c = e / nb, k = e % nb;
+        if (k <= c) rt[c * (c + 1) / 2 + k] = P[packed(nb, k, c)];
+    }
+}
+
+// M = R^-1 from the column-packed R of k_chol_lds (nothing when info != 0), one wave per
+// column of M: column c solves R x = e_c from the bottom, x_r = x_r / R[r][r], then
+// x_k -= R[k][r] x_r for k < r, the lanes holding rows lane + 64 s.  The work-group stages the
+// columns of R that its columns need, and the reciprocals of the diagonal, in LDS.  m is
+// written whole (zero below the diagonal), row-major.
+constexpr int kInvCols = 4;           // columns of M per work-group of k_tri_inverse
+
+__global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const double *__restrict__ rt,
+                                                               double *__restrict__ m,
+                                                               const int32_t *__restrict__ info) {
+    extern __shared__ double Rt[];    // packed columns 0 .. c_last, then 1 / R[r][r]
+    if (*info != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int c_last = min(nb, (int(blockIdx.x) + 1) * kInvCols) - 1;
+    const int len = (c_last + 1) * (c_last + 2) / 2;
+    double *dinv = Rt + len;
+    staged_copy(
+        len, [&](int e) { return rt[e]; }, [&](int e, double v) { Rt[e] = v; });
+    __syncthreads();
+    for (int r = tid; r <= c_last; r += blockDim.x) dinv[r] = 1.0 / Rt[r * (r + 1) / 2 + r];
+    __syncthreads();
+    const int c = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * kInvCols + (tid >> 6));
+    if (c >= nb) return;
+    constexpr int kSlots = kMaxBlock / 64;
+    double x[kSlots];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) x[sl] = lane + 64 * sl == c ? 1.0 : 0.0;
+    // column r of R (clamped to its length) and 1 / R[r][r], loaded one step ahead
+    auto load = [&](int r, double *colv, double &d) {
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) colv[sl] = Rt[r * (r + 1) / 2 + min(lane + 64 * sl, r)];
+        d = dinv[r];
+    };
+    double nxt[kSlots], dnxt;
+    load(c, nxt, dnxt);
+    for (int r = c; r >= 0; --r) {
+        double cur[kSlots];
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) cur[sl] = nxt[sl];
+        const double d = dnxt;
+        if (r > 0) load(r - 1, nxt, dnxt);
+        const int sr = r >> 6;
+        // x_r from its lane (r is the same for the whole wave)
+        double xr = x[0];
+#pragma unroll
+        for (int sl = 1; sl < kSlots; ++sl)
+            if (sl == sr) xr = x[sl];
+        const long long bits = __double_as_longlong(xr);
+        const int lo = __builtin_amdgcn_readlane(int(bits), r & 63);
+        const int hi = __builtin_amdgcn_readlane(int(bits >> 32), r & 63);
+        const double mr = __longlong_as_double((long long)(unsigned(lo)) | ((long long)(hi) << 32)) * d;
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) {
+            const int k = lane + 64 * sl;
+            const double upd = x[sl] - cur[sl] * mr;
+            x[sl] = k < r ? upd : (k == r ? mr : x[sl]);
+        }
+    }
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+        const int k = lane + 64 * sl;
+        if (k < nb) m[size_t(k) * nb + c] = k <= c ? x[sl] : 0.0;
     }
 }
 
@@ -501,10 +548,22 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int np = nb + (nb & 1), half = np / 2, nblk = half * (half + 1) / 2;
     if (tid == 0) rotated = 0;
-    for (int e = tid; e < np * np; e += nt) {
-        const int r = e / np, c = e % np;
-        if (c >= r) P[row_offset(np, r) + c] = (c < nb) ? 0.5 * (h[r * nb + c] + h[c * nb + r]) : 0.0;
-    }
+    // h symmetrised; entries of h below the diagonal are read in the transposed order
+    staged_copy(
+        nb * nb, [&](int e) { return h[e]; },
+        [&](int e, double v) {
+            const int r = e / nb, c = e % nb;
+            if (c >= r) P[row_offset(np, r) + c] = r == c ? v : 0.5 * v;
+        });
+    __syncthreads();
+    staged_copy(
+        nb * nb, [&](int e) { return h[(e % nb) * nb + e / nb]; },
+        [&](int e, double v) {
+            const int r = e / nb, c = e % nb;
+            if (c > r) P[row_offset(np, r) + c] += 0.5 * v;
+        });
+    if (np > nb)
+        for (int r = tid; r < np; r += nt) P[row_offset(np, r) + nb] = 0.0;
     // this work-item's blocks: item k < half is the diagonal block (k, k), item half + m the
     // m-th block (s, t), s < t, of the strict upper triangle in row-major order; -1 = none
     int item[kJacobiItems];
@@ -857,10 +916,14 @@ struct ModeSolver {
             for (int i = 0; i < nb; ++i) tr += hg[size_t(i) * nb + i];
             shift = 11.0 * (double(n) * nb + double(nb) * (nb + 1)) * 0x1.0p-53 * tr;
         }
-        if (packed_bytes)
-            hipLaunchKernelGGL(k_chol_inverse_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb,
-                               g.as<double>(), shift, m.as<double>(), small_i.as<int32_t>());
-        else
+        if (packed_bytes) {
+            hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb, g.as<double>(), shift,
+                               work.as<double>(), small_i.as<int32_t>());
+            TYEE_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_tri_inverse, dim3((nb + kInvCols - 1) / kInvCols), dim3(64 * kInvCols),
+                               (size_t(nb) * (nb + 1) / 2 + nb) * sizeof(double), st, nb, work.as<double>(),
+                               m.as<double>(), small_i.as<int32_t>());
+        } else
             hipLaunchKernelGGL(k_chol_inverse, dim3(1), dim3(256), 0, st, nb, g.as<double>(), shift,
                                m.as<double>(), small_i.as<int32_t>());
         TYEE_HIP(hipGetLastError());

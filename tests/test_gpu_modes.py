@@ -126,6 +126,21 @@ def test_largest_block_uses_the_global_memory_small_kernels(ty):
     _check(om, got, lam_ref, V_ref)
 
 
+@pytest.mark.parametrize("n_modes,block", [(21, 37), (150, 201)])
+def test_odd_block_widths(ty, n_modes, block):
+    # an odd block gives the round-robin Jacobi a ghost row and column: 37 in LDS, 201 (too
+    # large for LDS) in global memory
+    _note(f"case: box 16 x 24 triangular lattice, {n_modes} modes, odd block {block}")
+    xy, tri, Lx, Ly = box_tri_mesh(16, 24, 1.0, 0.1, 3)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam_ref, V_ref = om.modes(min(om.nt, block + 40))
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    m.reorder("morton")
+    got = m.modes(n_modes, block=block, tol=1e-11, max_iter=300)
+    _note(f"  iters {got['iters']} applies {got['applies']}")
+    _check(om, got, lam_ref, V_ref)
+
+
 def test_whole_spectrum_of_a_tiny_mesh(ty):
     _note("case: 2 x 2 box (8 triangles), every mode, block = n_t")
     xy, tri, Lx, Ly = box_mesh(2, 2, 0.1, 1, h=0.5)
