@@ -710,33 +710,62 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
     if (tid == 0) *sweeps_out = sweep;
 }
 
-// Eigenvectors from the rotation log of k_jacobi_lds: row k of Q (one work-group per row)
-// starts as e_k and takes every round's rotations of its entries, Q <- Q J; the columns are
-// then put in the order of the sorted eigenvalues.  blockDim >= nb/2.
+// Eigenvectors from the rotation log of k_jacobi_lds: row k of Q starts as e_k and takes
+// every round's rotations of its entries, Q <- Q J; the columns are then put in the order of
+// the sorted eigenvalues.  A work-group takes kVecRows rows (work-item t applies pair t's
+// rotation to each), and keeps the log entries of the next kVecAhead rounds in flight while it
+// applies the current one.  blockDim >= nb/2.
+constexpr int kVecRows = 4;
+constexpr int kVecAhead = 4;
+
 __global__ void k_jacobi_vectors(int32_t nb, const double2 *__restrict__ rot, const int32_t *__restrict__ sweeps,
                                  const int32_t *__restrict__ order, double *__restrict__ q) {
-    __shared__ double row[kMaxBlock + 1];
-    const int k = blockIdx.x, tid = threadIdx.x;
+    __shared__ double row[kVecRows][kMaxBlock + 1];
+    const int k0 = blockIdx.x * kVecRows, tid = threadIdx.x;
     const int np = nb + (nb & 1), half = np / 2;
-    for (int i = tid; i < np; i += blockDim.x) row[i] = i == k ? 1.0 : 0.0;
+    for (int i = tid; i < kVecRows * np; i += blockDim.x) {
+        const int rr = i / np, c = i % np;
+        row[rr][c] = c == k0 + rr ? 1.0 : 0.0;
+    }
     __syncthreads();
-    const int ns = *sweeps;
-    for (int sweep = 0; sweep < ns; ++sweep)
-        for (int round = 0; round < np - 1; ++round) {
-            if (tid < half) {
-                auto player = [&](int kk) { return kk == 0 ? 0 : 1 + (kk - 1 + round) % (np - 1); };
+    const int total = *sweeps * (np - 1);     // rounds in the log
+    const bool active = tid < half;
+    double2 ring[kVecAhead];
+#pragma unroll
+    for (int j = 0; j < kVecAhead; ++j)
+        ring[j] = active && j < total ? rot[size_t(j) * half + tid] : make_double2(1.0, 0.0);
+    int round = 0;
+    for (int base = 0; base < total; base += kVecAhead) {
+#pragma unroll
+        for (int j = 0; j < kVecAhead; ++j) {
+            const int idx = base + j;
+            if (idx >= total) break;                 // the same for the whole work-group
+            const double2 r = ring[j];
+            if (active && idx + kVecAhead < total) ring[j] = rot[size_t(idx + kVecAhead) * half + tid];
+            if (active && r.y != 0.0) {
+                auto player = [&](int kk) {
+                    if (kk == 0) return 0;
+                    const int z = kk - 1 + round;
+                    return 1 + (z >= np - 1 ? z - (np - 1) : z);
+                };
                 const int u = player(tid), v = player(np - 1 - tid);
                 const int a = u < v ? u : v, b = u < v ? v : u;
-                const double2 r = rot[(size_t(sweep) * (np - 1) + round) * half + tid];
-                if (b < nb && r.y != 0.0) {
-                    const double x = row[a], y = row[b];
-                    row[a] = r.x * x - r.y * y;
-                    row[b] = r.y * x + r.x * y;
-                }
+                if (b < nb)
+#pragma unroll
+                    for (int rr = 0; rr < kVecRows; ++rr) {
+                        const double x = row[rr][a], y = row[rr][b];
+                        row[rr][a] = r.x * x - r.y * y;
+                        row[rr][b] = r.y * x + r.x * y;
+                    }
             }
+            round = round + 1 == np - 1 ? 0 : round + 1;
             __syncthreads();
         }
-    for (int c = tid; c < nb; c += blockDim.x) q[k * nb + c] = row[order[c]];
+    }
+    for (int i = tid; i < kVecRows * nb; i += blockDim.x) {
+        const int rr = i / nb, c = i % nb;
+        if (k0 + rr < nb) q[(k0 + rr) * nb + c] = row[rr][order[c]];
+    }
 }
 
 // partial[chunk][c] = sum over the chunk's rows of S_j (kv[j][c] - theta_c v[j][c])^2
@@ -983,7 +1012,8 @@ struct ModeSolver {
                                rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), kJacobiSweeps,
                                small_i.as<int32_t>() + 1);
             TYEE_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(128), 0, st, nb, rot.as<double2>(),
+            hipLaunchKernelGGL(k_jacobi_vectors, dim3((nb + kVecRows - 1) / kVecRows), dim3(128), 0, st, nb,
+                               rot.as<double2>(),
                                small_i.as<int32_t>() + 1, order.as<int32_t>(), q.as<double>());
         } else {
             hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, nb, h.as<double>(), work.as<double>(),
