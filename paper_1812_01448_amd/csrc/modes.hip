@@ -44,10 +44,10 @@ namespace tyee {
 namespace {
 
 constexpr int kMaxBlock = 256;
-constexpr int kRotRows = 16;        // rows of the block per work-group in k_rotate
 constexpr int kGramTile = 32;       // output tile of k_gram (32 x 32)
 constexpr int kGramRows = 64;       // rows staged in LDS per pass of k_gram
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
+constexpr int kStartSweeps = 3;     // the same for the random starting block
 constexpr int kFilterPasses = 2;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
 // y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null).  One wave per row
@@ -149,29 +149,69 @@ __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restri
     out[k] = acc;
 }
 
-// y[j][c] = sum_k x[j][k] m[k][c]  (m upper triangular when upper != 0); blockDim >= nb
-__global__ void k_rotate(int32_t n, int32_t nb, const double *__restrict__ x, const double *__restrict__ m,
-                         double *__restrict__ y, int32_t upper) {
-    __shared__ double xs[kRotRows][kMaxBlock];
-    const int64_t r0 = int64_t(xcd_group(blockIdx.x, gridDim.x)) * kRotRows;
-    const int rows = int(std::min<int64_t>(kRotRows, n - r0));
-    for (int e = threadIdx.x; e < kRotRows * nb; e += blockDim.x) {
-        const int rr = e / nb, cc = e % nb;
-        xs[rr][cc] = rr < rows ? x[(r0 + rr) * nb + cc] : 0.0;
-    }
-    __syncthreads();
-    const int c = threadIdx.x;
-    if (c >= nb) return;
-    double acc[kRotRows];
+// y[j][c] = sum_k x[j][k] m[k][c]  (m upper triangular when upper != 0), on the FP64 matrix
+// cores: v_mfma_f64_16x16x4 multiplies a 16 x 4 tile of x (lane l holds row l % 16, k l / 16)
+// by a 4 x 16 tile of m (lane l holds k l / 16, column l % 16) into a 16 x 16 tile of y (lane l
+// holds rows 4 i + l / 16, i < 4, column l % 16).  A work-group takes 16 kRotWaves rows (16
+// per wave) and 16 kRotTiles columns; the rows of m that a step needs are staged in LDS, kRotK
+// at a time, and x is read straight into the operand registers.
+constexpr int kRotWaves = 4;
+constexpr int kRotTiles = 4;
+constexpr int kRotK = 32;
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64 * kRotWaves) k_rotate(int32_t n, int32_t nb, const double *__restrict__ x,
+                                                           const double *__restrict__ m, double *__restrict__ y,
+                                                           int32_t upper) {
+    constexpr int kCols = 16 * kRotTiles;
+    __shared__ double ms[kRotK][kCols + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int groups = (nb + kCols - 1) / kCols;
+    const int g = xcd_group(blockIdx.x, gridDim.x);
+    const int64_t r0 = int64_t(g / groups) * 16 * kRotWaves;
+    const int c0 = (g % groups) * kCols;
+    const int64_t arow = r0 + 16 * w + (lane & 15);
+    double4v acc[kRotTiles];
 #pragma unroll
-    for (int r = 0; r < kRotRows; ++r) acc[r] = 0.0;
-    const int kend = upper ? c + 1 : nb;
-    for (int k = 0; k < kend; ++k) {
-        const double mk = m[k * nb + c];
+    for (int t = 0; t < kRotTiles; ++t) acc[t] = double4v{0.0, 0.0, 0.0, 0.0};
+    // with m upper triangular, columns below c0 + kCols need rows of m below that only
+    const int kend = upper ? min(nb, c0 + kCols) : nb;
+    for (int k0 = 0; k0 < kend; k0 += kRotK) {
+        double av[kRotK / 4];
 #pragma unroll
-        for (int r = 0; r < kRotRows; ++r) acc[r] += xs[r][k] * mk;
+        for (int s = 0; s < kRotK / 4; ++s) {
+            const int k = k0 + 4 * s + (lane >> 4);
+            av[s] = arow < n && k < nb ? x[arow * nb + k] : 0.0;
+        }
+        __syncthreads();                       // the previous step's rows of m are used up
+        constexpr int kPer = kRotK * kCols / (64 * kRotWaves);
+        double mv[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + i * 64 * kRotWaves, kk = e / kCols, cc = e % kCols;
+            mv[i] = k0 + kk < nb && c0 + cc < nb ? m[(k0 + kk) * nb + c0 + cc] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + i * 64 * kRotWaves;
+            ms[e / kCols][e % kCols] = mv[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < kRotK / 4; ++s)
+#pragma unroll
+            for (int t = 0; t < kRotTiles; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], ms[4 * s + (lane >> 4)][16 * t + (lane & 15)],
+                                                               acc[t], 0, 0, 0);
     }
-    for (int r = 0; r < rows; ++r) y[(r0 + r) * nb + c] = acc[r];
+#pragma unroll
+    for (int t = 0; t < kRotTiles; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = r0 + 16 * w + 4 * i + (lane >> 4);
+            const int col = c0 + 16 * t + (lane & 15);
+            if (row < n && col < nb) y[row * nb + col] = acc[t][i];
+        }
 }
 
 // One work-group: g (nb x nb, symmetric) + shift on the diagonal = R^T R; m = R^-1 (upper).
@@ -923,9 +963,9 @@ struct ModeSolver {
     }
 
     int rotate(const double *x, const double *mat, double *y, bool upper) {
-        const int threads = ((nb + 63) / 64) * 64;
-        hipLaunchKernelGGL(k_rotate, dim3((n + kRotRows - 1) / kRotRows), dim3(threads), 0, st, n, nb, x, mat, y,
-                           int32_t(upper));
+        const int rows = 16 * kRotWaves, cols = 16 * kRotTiles;
+        hipLaunchKernelGGL(k_rotate, dim3(((n + rows - 1) / rows) * ((nb + cols - 1) / cols)), dim3(64 * kRotWaves), 0,
+                           st, n, nb, x, mat, y, int32_t(upper));
         TYEE_HIP(hipGetLastError());
         return TYEE_OK;
     }
@@ -1003,13 +1043,13 @@ struct ModeSolver {
 
     // Rayleigh-Ritz of the S-orthonormal block in buffer iv (scratch iz): Ritz vectors to
     // buffer ov, K times them to buffer okv (four distinct buffers), Ritz values to host.
-    int rayleigh_ritz(int iv, int iz, int ov, int okv, std::vector<double> &ritz) {
+    int rayleigh_ritz(int iv, int iz, int ov, int okv, std::vector<double> &ritz, int max_sweeps = kJacobiSweeps) {
         int rc = apply(B(iv), nullptr, B(iz), 1.0, 0.0, 0.0);
         if (!rc) rc = gram(B(iv), B(iz), h.as<double>());
         if (rc) return rc;
         if (packed_bytes) {
             hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb, h.as<double>(),
-                               rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), kJacobiSweeps,
+                               rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), max_sweeps,
                                small_i.as<int32_t>() + 1);
             TYEE_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_jacobi_vectors, dim3((nb + kVecRows - 1) / kVecRows), dim3(128), 0, st, nb,
@@ -1017,7 +1057,7 @@ struct ModeSolver {
                                small_i.as<int32_t>() + 1, order.as<int32_t>(), q.as<double>());
         } else {
             hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, nb, h.as<double>(), work.as<double>(),
-                               q.as<double>(), theta.as<double>(), kJacobiSweeps, small_i.as<int32_t>() + 1);
+                               q.as<double>(), theta.as<double>(), max_sweeps, small_i.as<int32_t>() + 1);
         }
         TYEE_HIP(hipGetLastError());
         rc = rotate(B(iv), q.as<double>(), B(ov), false);
@@ -1116,7 +1156,9 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
         rc = sv.orthonormalise(0, 1, &ob);
         std::vector<double> ritz, res;
         int vb = ModeSolver::pick({ob, 2}), kvb = ModeSolver::pick({ob, 2, vb});  // Ritz vectors, K times them
-        if (!rc) rc = sv.rayleigh_ritz(ob, 2, vb, kvb, ritz);
+        // a random block smaller than the space is never converged: a few Jacobi sweeps give
+        // Ritz values close enough for the first filter's bounds
+        if (!rc) rc = sv.rayleigh_ritz(ob, 2, vb, kvb, ritz, nb < nt ? kStartSweeps : kJacobiSweeps);
         if (!rc) rc = sv.residuals(vb, kvb, res);
         applies += 1;
         auto converged = [&]() {
