@@ -44,8 +44,7 @@ namespace tyee {
 namespace {
 
 constexpr int kMaxBlock = 256;
-constexpr int kGramTile = 32;       // output tile of k_gram (32 x 32)
-constexpr int kGramRows = 64;       // rows staged in LDS per pass of k_gram
+typedef double double4v __attribute__((ext_vector_type(4)));   // one lane's share of a 16 x 16 FP64 MFMA tile
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 constexpr int kStartSweeps = 3;     // the same for the random starting block
 constexpr int kFilterPasses = 2;    // filter + Cholesky QR passes per Rayleigh-Ritz step
@@ -99,44 +98,64 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply(
     }
 }
 
-// partial[chunk][p][q] = sum over the chunk's rows j of S_j x[j][p] z[j][q]
-// grid (chunks, tiles_p, tiles_q), 256 threads: a 16 x 16 grid of threads, 2 x 2 outputs each
-__global__ void __launch_bounds__(256) k_gram(int32_t n, int32_t nb, int32_t rows_per_chunk,
-                                              const double *__restrict__ x, const double *__restrict__ z,
-                                              const double *__restrict__ s, double *__restrict__ partial) {
-    __shared__ double xs[kGramRows][kGramTile];
-    __shared__ double zs[kGramRows][kGramTile];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int p0 = blockIdx.y * kGramTile, q0 = blockIdx.z * kGramTile;
+// partial[chunk][p][q] = sum over the chunk's rows j of S_j x[j][p] z[j][q], on the FP64
+// matrix cores: per step of 4 rows, v_mfma_f64_16x16x4 takes (S x)^T as the 16 x 4 operand
+// (lane l: column p0 + l % 16 of row l / 16) and z as the 4 x 16 one (lane l: row l / 16,
+// column q0 + l % 16), both read straight from the block (each 16 lanes read 128 contiguous
+// bytes of a row).  Each wave owns a 32 x 32 block of G (2 x 2 tiles).
+// grid (chunks, ceil(blocks / kGramWaves)), 64 kGramWaves work-items
+constexpr int kGramWaves = 4;
+constexpr int kGramUnroll = 4;      // steps of 4 rows whose loads are issued together
+
+__global__ void __launch_bounds__(64 * kGramWaves) k_gram(int32_t n, int32_t nb, int32_t rows_per_chunk,
+                                                          const double *__restrict__ x, const double *__restrict__ z,
+                                                          const double *__restrict__ s, double *__restrict__ partial) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int bt = (nb + 31) / 32;
+    const int blk = int(blockIdx.y) * kGramWaves + (tid >> 6);
+    if (blk >= bt * bt) return;
+    const int p0 = (blk / bt) * 32, q0 = (blk % bt) * 32;
+    const int kr = lane >> 4, cc = lane & 15;
+    const int pc[2] = {p0 + cc, p0 + 16 + cc}, qc[2] = {q0 + cc, q0 + 16 + cc};
     const int64_t r_begin = int64_t(blockIdx.x) * rows_per_chunk;
     const int64_t r_end = std::min<int64_t>(n, r_begin + rows_per_chunk);
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows) {
-        for (int e = tid; e < kGramRows * kGramTile; e += 256) {
-            const int rr = e / kGramTile, cc = e % kGramTile;
-            const int64_t row = r0 + rr;
+    double4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = double4v{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 4 * kGramUnroll) {
+        double av[kGramUnroll][2], bv[kGramUnroll][2];
+#pragma unroll
+        for (int u = 0; u < kGramUnroll; ++u) {
+            const int64_t row = r0 + 4 * u + kr;
             const bool in = row < r_end;
             const double sw = in ? s[row] : 0.0;
-            xs[rr][cc] = (in && p0 + cc < nb) ? sw * x[row * nb + p0 + cc] : 0.0;
-            zs[rr][cc] = (in && q0 + cc < nb) ? z[row * nb + q0 + cc] : 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                av[u][h] = in && pc[h] < nb ? sw * x[row * nb + pc[h]] : 0.0;
+                bv[u][h] = in && qc[h] < nb ? z[row * nb + qc[h]] : 0.0;
+            }
         }
-        __syncthreads();
-        for (int rr = 0; rr < kGramRows; ++rr) {
-            const double a0 = xs[rr][ty], a1 = xs[rr][ty + 16];
-            const double b0 = zs[rr][tx], b1 = zs[rr][tx + 16];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kGramUnroll; ++u)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][a], bv[u][b], acc[a][b], 0, 0, 0);
     }
+    // the 16 x 16 result tile: lane l holds rows 4 i + l / 16, column l % 16
     double *out = partial + size_t(blockIdx.x) * nb * nb;
+#pragma unroll
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            const int p = p0 + ty + 16 * a, q = q0 + tx + 16 * b;
-            if (p < nb && q < nb) out[p * nb + q] = acc[a][b];
-        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = p0 + 16 * a + 4 * i + kr, q = qc[b];
+                if (p < nb && q < nb) out[p * nb + q] = acc[a][b][i];
+            }
 }
 
 // out[k] = sum over chunks c (in order) of partial[c][k]
@@ -158,7 +177,6 @@ __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restri
 constexpr int kRotWaves = 4;
 constexpr int kRotTiles = 4;
 constexpr int kRotK = 32;
-typedef double double4v __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(64 * kRotWaves) k_rotate(int32_t n, int32_t nb, const double *__restrict__ x,
                                                            const double *__restrict__ m, double *__restrict__ y,
@@ -951,9 +969,9 @@ struct ModeSolver {
 
     // out (nb x nb) = x^T S z
     int gram(const double *x, const double *z, double *out) {
-        const int tiles = (nb + kGramTile - 1) / kGramTile;
-        hipLaunchKernelGGL(k_gram, dim3(chunks, tiles, tiles), dim3(256), 0, st, n, nb, rows_per_chunk, x, z,
-                           s.as<double>(), partial.as<double>());
+        const int bt = (nb + 31) / 32;
+        hipLaunchKernelGGL(k_gram, dim3(chunks, (bt * bt + kGramWaves - 1) / kGramWaves), dim3(64 * kGramWaves), 0, st,
+                           n, nb, rows_per_chunk, x, z, s.as<double>(), partial.as<double>());
         TYEE_HIP(hipGetLastError());
         const int len = nb * nb;
         hipLaunchKernelGGL(k_sum_chunks, dim3((len + 255) / 256), dim3(256), 0, st, chunks, len,
