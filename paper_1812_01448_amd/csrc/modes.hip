@@ -590,6 +590,7 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
 // sweeps done.
 constexpr int kJacobiItems = 5;     // blocks per work-item: (98 x 99 / 2) / 1024, rounded up
 constexpr int kJacobiGroup = 3;     // blocks whose loads are issued together
+constexpr int kJacobiLds = 196 * 197 / 2;   // packed triangle of the largest np that fits LDS
 
 __device__ __forceinline__ int row_offset(int np, int i) { return i * (2 * np - i - 1) / 2; }
 
@@ -597,7 +598,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
                                                               double2 *__restrict__ rot, double *__restrict__ theta,
                                                               int32_t *__restrict__ order_out, int32_t max_sweeps,
                                                               int32_t *__restrict__ sweeps_out) {
-    extern __shared__ double P[];
+    __shared__ double P[kJacobiLds];  // static, so that its address folds into the LDS offsets
     __shared__ int4 pr[kMaxBlock / 2];       // pair: a < b, row offsets of a and b
     __shared__ double2 cs[kMaxBlock / 2];    // pair rotation (c, s)
     __shared__ double red[kSmallThreads / 64][2];
@@ -697,13 +698,15 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
                         rotated = 1;
                     }
                 }
-                pr[t] = make_int4(a, b, oa, ob);
+                pr[t] = make_int4(8 * a, 8 * b, 8 * oa, 8 * ob);
                 cs[t] = make_double2(c, sn);
                 rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, sn);
             }
             __syncthreads();
             // packed position of (i, j) from the row offsets
+            // (byte offsets: the table holds 8 x the indices and row offsets)
             auto at = [](int i, int oi, int j, int oj) { return i <= j ? oi + j : oj + i; };
+            auto el = [&](int off) -> double & { return *reinterpret_cast<double *>(reinterpret_cast<char *>(P) + off); };
             // the items in groups of kJacobiGroup: all loads of a group, then its updates
 #pragma unroll
             for (int g = 0; g < kJacobiItems; g += kJacobiGroup) {
@@ -721,7 +724,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
                     idx[j][2] = at(p1.y, p1.w, p2.x, p2.z);
                     idx[j][3] = at(p1.y, p1.w, p2.y, p2.w);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) hv[j][q] = P[idx[j][q]];
+                    for (int q = 0; q < 4; ++q) hv[j][q] = el(idx[j][q]);
                 }
 #pragma unroll
                 for (int j = 0; j < kJacobiGroup; ++j) {
@@ -732,19 +735,19 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
                     const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
                     const double h00 = hv[j][0], h01 = hv[j][1], h10 = hv[j][2], h11 = hv[j][3];
                     // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
-                    const double x00 = c1 * h00 - s1 * h10, x01 = c1 * h01 - s1 * h11;
-                    const double x10 = s1 * h00 + c1 * h10, x11 = s1 * h01 + c1 * h11;
-                    const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
-                    const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
-                    P[idx[j][0]] = y00;
-                    P[idx[j][3]] = y11;
+                    const double x00 = std::fma(c1, h00, -s1 * h10), x01 = std::fma(c1, h01, -s1 * h11);
+                    const double x10 = std::fma(s1, h00, c1 * h10), x11 = std::fma(s1, h01, c1 * h11);
+                    const double y00 = std::fma(c2, x00, -s2 * x01), y01 = std::fma(s2, x00, c2 * x01);
+                    const double y10 = std::fma(c2, x10, -s2 * x11), y11 = std::fma(s2, x10, c2 * x11);
+                    el(idx[j][0]) = y00;
+                    el(idx[j][3]) = y11;
                     if ((item[i] >> 16) == (item[i] & 0xffff)) {
                         // a diagonal block: (a, b) is the one element idx 1 and 2 both name,
                         // and the pair's own rotation annihilates it
-                        P[idx[j][1]] = s1 != 0.0 ? 0.0 : y01;
+                        el(idx[j][1]) = s1 != 0.0 ? 0.0 : y01;
                     } else {
-                        P[idx[j][1]] = y01;
-                        P[idx[j][2]] = y10;
+                        el(idx[j][1]) = y01;
+                        el(idx[j][2]) = y10;
                     }
                 }
             }
@@ -935,7 +938,8 @@ struct ModeSolver {
         // (np: the Jacobi kernel pads an odd nb by one row and column)
         const size_t tri_bytes = size_t(np) * (np + 1) / 2 * sizeof(double);
         const int jh = np / 2;
-        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) && jh * (jh + 1) / 2 <= kJacobiItems * kSmallThreads
+        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) && jh * (jh + 1) / 2 <= kJacobiItems * kSmallThreads &&
+                               np * (np + 1) / 2 <= kJacobiLds
                            ? tri_bytes
                            : 0;
         TYEE_HIP(hipMemcpyAsync(nbr.p, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, st));
@@ -1066,7 +1070,7 @@ struct ModeSolver {
         if (!rc) rc = gram(B(iv), B(iz), h.as<double>());
         if (rc) return rc;
         if (packed_bytes) {
-            hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kSmallThreads), packed_bytes, st, nb, h.as<double>(),
+            hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kSmallThreads), 0, st, nb, h.as<double>(),
                                rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), max_sweeps,
                                small_i.as<int32_t>() + 1);
             TYEE_HIP(hipGetLastError());
