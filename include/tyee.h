@@ -448,7 +448,7 @@ typedef enum { TYEE_MODES_LOWEST = 0, TYEE_MODES_HIGHEST = 1 } tyee_modes_end;
 
 /* Work done by one tyee_mesh_modes call. */
 typedef struct {
-    int32_t iters;         /* outer iterations (two filter passes, each followed by the
+    int32_t iters;         /* outer iterations (three filter passes, each followed by the
                               orthonormalisation, then one Rayleigh-Ritz step) */
     int64_t applies;       /* applications of K to the whole block */
     double lambda_bound;   /* Gershgorin bound on lambda_max that closes the filter interval */
@@ -476,7 +476,7 @@ typedef struct {
      n_modes   1 .. min(n_triangles, 256) pairs wanted.
      block     vectors iterated, max(n_modes, 2) .. min(n_triangles, 256); 0 chooses
                n_modes + max(16, n_modes / 4) (capped).  n_triangles x block < 2^31.
-     degree    largest filter degree per pass (two passes per outer iteration), 1 .. 100000;
+     degree    largest filter degree per pass (three passes per outer iteration), 1 .. 100000;
                0 chooses 128.  A pass lowers it so that the lowest Ritz value grows at most 1e7
                times more than the cut (the block stays well enough conditioned to
                orthonormalise).

@@ -25,7 +25,7 @@
 //     every vector is orthogonal in metric (7) to the others;
 //   * Rayleigh-Ritz: H = V^T S K V is diagonalised (cyclic Jacobi) and V rotated into Ritz
 //     vectors; the largest Ritz value of the block becomes the next a.
-// An outer iteration runs two filter passes, each followed by the orthonormalisation (subspace
+// An outer iteration runs three filter passes, each followed by the orthonormalisation (subspace
 // iteration needs no Rayleigh-Ritz in between), then one Rayleigh-Ritz step.
 // b is a Gershgorin bound on lambda_max of the symmetric form S^(1/2) K S^(-1/2).
 //
@@ -47,7 +47,7 @@ constexpr int kMaxBlock = 256;
 typedef double double4v __attribute__((ext_vector_type(4)));   // one lane's share of a 16 x 16 FP64 MFMA tile
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 constexpr int kStartSweeps = 3;     // the same for the random starting block
-constexpr int kFilterPasses = 2;    // filter + Cholesky QR passes per Rayleigh-Ritz step
+constexpr int kFilterPasses = 3;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
 // y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null).  One wave per row
 // (triangle): the row's neighbour slots, weights and 1/S are wave-uniform (scalar loads) and
