@@ -468,7 +468,7 @@ typedef struct {
    three-term (leap-frog) recurrence of the shifted K, with the unwanted part of the spectrum
    inside the eq. 20 bound (bounded) and the wanted modes outside it (growing, as in complex
    time); S-orthonormalisation of the block (deflation in metric (7)) after each filter pass;
-   a Rayleigh-Ritz step after every two passes.
+   a Rayleigh-Ritz step after every three passes.
      gamma     [n_edges] per-edge scale in canonical order, or NULL.
      which     TYEE_MODES_LOWEST, or TYEE_MODES_HIGHEST (the paper's order: the largest
                eigenvalue first; the solver then works on lambda_bound - K, whose lowest modes
