@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
+#include <utility>
 #include <vector>
 
 #include "sim.hpp"
@@ -874,6 +875,7 @@ struct ModeSolver {
     double top = 0.0;
     size_t packed_bytes = 0;           // LDS for a packed nb x nb triangle, 0 = does not fit
     hipStream_t st = nullptr;
+    DeviceBuffer arena;                // one allocation that the buffers below are views of
     DeviceBuffer nbr, wt, inv_s, s, canon;
     DeviceBuffer buf[5];               // block-sized buffers
     DeviceBuffer g, m, h, q, work, theta, partial, small_i, rot, order;
@@ -911,26 +913,29 @@ struct ModeSolver {
         const size_t blk = size_t(nt) * nb * sizeof(double);
         rows_per_chunk = int32_t(std::max<int64_t>(256, (nt + 255) / 256));
         chunks = int32_t((nt + rows_per_chunk - 1) / rows_per_chunk);
-        int rc = TYEE_OK;
-        for (int i = 0; i < 5 && !rc; ++i) rc = buf[i].alloc(blk);
-        if (!rc) rc = nbr.alloc(hn.size() * 4);
-        if (!rc) rc = wt.alloc(hw.size() * 8);
-        if (!rc) rc = inv_s.alloc(nt * 8);
-        if (!rc) rc = s.alloc(nt * 8);
-        if (!rc) rc = canon.alloc(nt * 4);
         const size_t sq = size_t(nb) * nb * sizeof(double);
-        if (!rc) rc = g.alloc(sq);
-        if (!rc) rc = m.alloc(sq);
-        if (!rc) rc = h.alloc(sq);
-        if (!rc) rc = q.alloc(sq);
-        if (!rc) rc = work.alloc(sq);
-        if (!rc) rc = theta.alloc(size_t(nb) * 8);
-        if (!rc) rc = partial.alloc(size_t(chunks) * nb * nb * sizeof(double));
-        if (!rc) rc = small_i.alloc(2 * sizeof(int32_t));
         const int np = nb + (nb & 1);
-        if (!rc) rc = rot.alloc(size_t(kJacobiSweeps) * (np - 1) * (np / 2) * sizeof(double2));
-        if (!rc) rc = order.alloc(size_t(nb) * sizeof(int32_t));
+        // every device buffer is a 256-byte aligned view of one allocation
+        const std::pair<DeviceBuffer *, size_t> parts[] = {
+            {&buf[0], blk}, {&buf[1], blk}, {&buf[2], blk}, {&buf[3], blk}, {&buf[4], blk},
+            {&nbr, hn.size() * 4}, {&wt, hw.size() * 8}, {&inv_s, size_t(nt) * 8}, {&s, size_t(nt) * 8},
+            {&canon, size_t(nt) * 4}, {&g, sq}, {&m, sq}, {&h, sq}, {&q, sq}, {&work, sq},
+            {&theta, size_t(nb) * 8}, {&partial, size_t(chunks) * nb * nb * sizeof(double)},
+            {&small_i, 2 * sizeof(int32_t)},
+            {&rot, size_t(kJacobiSweeps) * (np - 1) * (np / 2) * sizeof(double2)},
+            {&order, size_t(nb) * sizeof(int32_t)}};
+        auto aligned = [](size_t b) { return (b + 255) / 256 * 256; };
+        size_t total = 0;
+        for (const auto &pt : parts) total += aligned(pt.second);
+        int rc = arena.alloc(total);
         if (rc) return rc;
+        size_t off = 0;
+        for (const auto &pt : parts) {
+            pt.first->p = static_cast<char *>(arena.p) + off;
+            pt.first->bytes = pt.second;
+            pt.first->owned = false;
+            off += aligned(pt.second);
+        }
         int device = 0, lds_limit = 65536;
         TYEE_HIP(hipGetDevice(&device));
         TYEE_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
