@@ -396,6 +396,14 @@ __global__ void __launch_bounds__(256) k_jacobi(int32_t nb, double *__restrict__
 // Packed upper triangle (row-major) of an nb x nb symmetric matrix: element (i, j), i <= j.
 __device__ __forceinline__ int packed(int nb, int i, int j) { return i * (2 * nb - i - 1) / 2 + j; }
 
+// v as held by lane src (src the same for the whole wave): two v_readlane_b32
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(bits), src);
+    const int hi = __builtin_amdgcn_readlane(int(bits >> 32), src);
+    return __longlong_as_double((long long)(unsigned(lo)) | ((long long)(hi) << 32));
+}
+
 // for e < count: store(e, load(e)), the work-group's items in steps of kStage per work-item
 // with all kStage loads issued before the first store (global memory to LDS staging)
 constexpr int kStage = 8;
@@ -456,7 +464,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
 #pragma unroll
             for (int k = 0; k < kPanel; ++k) {
                 if (k >= pw || failed) continue;
-                const double d = __shfl(pr[k][0], k);  // column j0 + k sits in lane k, slot 0
+                const double d = lane_value(pr[k][0], k);  // column j0 + k sits in lane k, slot 0
                 if (!(d > 0.0) || !std::isfinite(d)) {
                     failed = j0 + k + 1;
                     continue;
@@ -471,7 +479,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
 #pragma unroll
                 for (int r = k + 1; r < kPanel; ++r) {
                     if (r >= pw) continue;
-                    const double mult = __shfl(pr[k][0], r);  // R[j0 + k][j0 + r]
+                    const double mult = lane_value(pr[k][0], r);  // R[j0 + k][j0 + r]
 #pragma unroll
                     for (int sl = 0; sl < kSlots; ++sl) {
                         const int c = j0 + lane + 64 * sl;
@@ -561,10 +569,7 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
 #pragma unroll
         for (int sl = 1; sl < kSlots; ++sl)
             if (sl == sr) xr = x[sl];
-        const long long bits = __double_as_longlong(xr);
-        const int lo = __builtin_amdgcn_readlane(int(bits), r & 63);
-        const int hi = __builtin_amdgcn_readlane(int(bits >> 32), r & 63);
-        const double mr = __longlong_as_double((long long)(unsigned(lo)) | ((long long)(hi) << 32)) * d;
+        const double mr = lane_value(xr, r & 63) * d;
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl) {
             const int k = lane + 64 * sl;
