@@ -585,33 +585,76 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
 }
 
 // Cyclic Jacobi on the symmetric h held in LDS (packed upper triangle of np x np, np = nb
-// rounded up to even, the padding row and column zero; dynamic shared memory), np/2 disjoint
-// rotations per round in round-robin order.  A round: the pairs' rotations (one work-item per
-// pair), a barrier, then every 2 x 2 block of h that two pairs s <= t share becomes
-// J_s^T B J_t, and a barrier.  The blocks are dealt to the work-items once (kJacobiItems at
-// most each, the same (s, t) slots every round; the pairs in a slot change), and a work-item
-// issues the loads of all its blocks before it computes any.  The rotations are written to
-// rot[sweep][round][pair] = (c, s) for k_jacobi_vectors; on return theta holds the
-// eigenvalues ascending, order[i] the diagonal position of the i-th, and sweeps_out the
-// sweeps done.
-constexpr int kJacobiItems = 5;     // blocks per work-item: (98 x 99 / 2) / 1024, rounded up
+// rounded up to even, the padding row and column zero), np/2 disjoint rotations per round in
+// round-robin order: position 0 stays, every other player moves down one position per round,
+// and pair slot t joins positions t and np - 1 - t.  Every 2 x 2 block of h that two pairs
+// s <= t share becomes J_s^T B J_t.  The blocks are dealt to the work-items once (kJacobiItems
+// at most each, the same (s, t) slots every round; the pairs in a slot change), and a
+// work-item issues the loads of a group of its blocks before it computes any.
+// The next round's pairs are known in advance (slot t' joins the players now at positions
+// t' + 1 and np - t', or 0 and 1 for t' = 0), and the off-diagonal entry of each lies in one
+// block of the current round: the work-item updating that block also computes the next
+// round's rotation for it, the two diagonal entries re-derived from the current pairs'
+// entries as their own diagonal blocks derive them.  A round is then one barrier; only a
+// sweep's first round (after the convergence test) computes its rotations in a phase of its
+// own.  The rotations are written to rot[sweep][round][pair] = (c, s) for k_jacobi_vectors; on
+// return theta holds the eigenvalues ascending, order[i] the diagonal position of the i-th,
+// and sweeps_out the sweeps done.
+constexpr int kJacobiItems = 5;     // blocks per work-item: (96 x 95 / 2 - 96) / (1024 - 128), rounded up
 constexpr int kJacobiGroup = 3;     // blocks whose loads are issued together
-constexpr int kJacobiLds = 196 * 197 / 2;   // packed triangle of the largest np that fits LDS
+constexpr int kJacobiNp = 192;      // largest np held in LDS
+constexpr int kJacobiHalf = kJacobiNp / 2;
+constexpr int kJacobiLds = kJacobiNp * (kJacobiNp + 1) / 2;
 
 __device__ __forceinline__ int row_offset(int np, int i) { return i * (2 * np - i - 1) / 2; }
+
+// a pair's entries h[a][a], h[b][b], h[a][b] before its rotation
+struct PairEntries {
+    double x, y, z;
+};
+
+// the rotation that annihilates h[a][b]; skipped (identity) below rounding of the diagonal
+__device__ __forceinline__ bool jacobi_angle(double app, double aqq, double apq, double &c, double &sn) {
+    c = 1.0;
+    sn = 0.0;
+    if (!(std::fabs(apq) > 1e-16 * (std::fabs(app) + std::fabs(aqq)))) return false;
+    const double tau = (aqq - app) / (2.0 * apq);
+    const double tt = tau >= 0.0 ? 1.0 / (tau + std::sqrt(1.0 + tau * tau)) : -1.0 / (-tau + std::sqrt(1.0 + tau * tau));
+    c = 1.0 / std::sqrt(1.0 + tt * tt);
+    sn = tt * c;
+    return true;
+}
+
+// J^T B J of a 2 x 2 block between pairs with rotations (c1, s1) (rows) and (c2, s2) (columns)
+__device__ __forceinline__ void rotate_block(double c1, double s1, double c2, double s2, double h00, double h01,
+                                             double h10, double h11, double &y00, double &y01, double &y10,
+                                             double &y11) {
+    // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
+    const double x00 = std::fma(c1, h00, -s1 * h10), x01 = std::fma(c1, h01, -s1 * h11);
+    const double x10 = std::fma(s1, h00, c1 * h10), x11 = std::fma(s1, h01, c1 * h11);
+    y00 = std::fma(c2, x00, -s2 * x01);
+    y01 = std::fma(s2, x00, c2 * x01);
+    y10 = std::fma(c2, x10, -s2 * x11);
+    y11 = std::fma(s2, x10, c2 * x11);
+}
 
 __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const double *__restrict__ h,
                                                               double2 *__restrict__ rot, double *__restrict__ theta,
                                                               int32_t *__restrict__ order_out, int32_t max_sweeps,
                                                               int32_t *__restrict__ sweeps_out) {
     __shared__ double P[kJacobiLds];  // static, so that its address folds into the LDS offsets
-    __shared__ int4 pr[kMaxBlock / 2];       // pair: a < b, row offsets of a and b
-    __shared__ double2 cs[kMaxBlock / 2];    // pair rotation (c, s)
+    __shared__ int4 pr[2][kJacobiHalf];            // pair: 8 a, 8 b, 8 x row offsets (a < b)
+    __shared__ double2 cs[2][kJacobiHalf];          // pair rotation (c, s)
+    __shared__ PairEntries pe[2][kJacobiHalf];
+    __shared__ unsigned char lowa[2][kJacobiHalf];  // 1: a holds the slot's low position
     __shared__ double red[kSmallThreads / 64][2];
-    __shared__ int order[kMaxBlock];
+    __shared__ int order[kJacobiNp];
     __shared__ int rotated;            // a rotation was applied in the current sweep
     const int tid = threadIdx.x, nt = blockDim.x;
     const int np = nb + (nb & 1), half = np / 2, nblk = half * (half + 1) / 2;
+    // with fewer than 3 pairs two of the next round's pairs can share a block: those sizes
+    // compute every round's rotations in a phase of their own
+    const bool merged = half >= 3;
     if (tid == 0) rotated = 0;
     // h symmetrised; entries of h below the diagonal are read in the transposed order
     staged_copy(
@@ -629,26 +672,80 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
         });
     if (np > nb)
         for (int r = tid; r < np; r += nt) P[row_offset(np, r) + nb] = 0.0;
-    // this work-item's blocks: item k < half is the diagonal block (k, k), item half + m the
-    // m-th block (s, t), s < t, of the strict upper triangle in row-major order; -1 = none
+    // Work split.  The first t0 work-items (whole waves) own the pair slots t < half: the
+    // diagonal block (t, t) and, when merged, the block that holds next-round pair t's
+    // off-diagonal entry, for which they also compute the next rotation.  The other
+    // work-items take the remaining blocks (s, t), s < t, in row-major order, at most
+    // kJacobiItems each, the same slots every round.
+    const int t0 = (half + 63) / 64 * 64;
+    // the block (row r, column c) holding next pair tn's entry, and where its players sit:
+    // bit 0 (1): the row (column) slot gives its high-position player, bit 2: the row slot's
+    // player takes the next pair's low position
+    auto next_block = [&](int tn, int &r, int &c) {
+        if (tn == 0) {
+            r = 0;
+            c = 1;
+            return 4;                                  // low of 0 (next low), low of 1
+        }
+        if (tn <= half - 2) {
+            r = tn - 1;
+            c = tn + 1;
+            return 1;                                  // high of tn - 1, low of tn + 1 (next low)
+        }
+        r = half - 2;
+        c = half - 1;
+        return 3;                                      // high of both, the column's next low
+    };
+    auto designated = [&](int r, int c) {
+        return merged && ((r == 0 && c == 1) || (c == r + 2 && r + 1 <= half - 2) || (r == half - 2 && c == half - 1));
+    };
     int item[kJacobiItems];
+    int n_items = 0;                                   // the most any work-item has (the same for all)
+    {
+        const int rest = half * (half - 1) / 2 - (merged ? half : 0);
+        const int workers = nt - t0;
+        n_items = (rest + workers - 1) / workers;
 #pragma unroll
-    for (int i = 0; i < kJacobiItems; ++i) {
-        const int k = tid + i * nt;
-        item[i] = -1;
-        if (k < half) {
-            item[i] = (k << 16) | k;
-        } else if (k < nblk) {
-            const int m = k - half;
-            // row s holds half - 1 - s blocks and starts at s (2 half - s - 1) / 2
-            const double w = 2.0 * half - 1.0;
-            int r = int((w - std::sqrt(w * w - 8.0 * m)) * 0.5);
-            r = r < 0 ? 0 : (r > half - 2 ? half - 2 : r);
-            while (r > 0 && r * (2 * half - r - 1) / 2 > m) --r;
-            while ((r + 1) * (2 * half - r - 2) / 2 <= m) ++r;
-            item[i] = (r << 16) | (r + 1 + m - r * (2 * half - r - 1) / 2);
+        for (int i = 0; i < kJacobiItems; ++i) {
+            item[i] = -1;
+            const int m = tid - t0 + i * workers;
+            if (tid < t0 || m >= rest) continue;
+            // row r holds half - 1 - r blocks, less the designated ones
+            int r = 0, before = 0;
+            for (;; ++r) {
+                // (a row's designated blocks sit in its first two columns)
+                int cnt = half - 1 - r;
+                for (int c = r + 1; c < half && c <= r + 2; ++c) cnt -= designated(r, c);
+                if (m < before + cnt) break;
+                before += cnt;
+            }
+            int j = m - before, c = r + 1;
+            for (;; ++c)
+                if (!designated(r, c) && j-- == 0) break;
+            item[i] = (r << 16) | c;
         }
     }
+    auto player = [&](int k, int round) {
+        if (k == 0) return 0;
+        const int z = k - 1 + round;
+        return 1 + (z >= np - 1 ? z - (np - 1) : z);
+    };
+    // the rotations of one round in a phase of their own, into table buffer bf
+    auto rotations = [&](int sweep, int round, int bf) {
+        for (int t = tid; t < half; t += nt) {
+            const int u = player(t, round), v = player(np - 1 - t, round);
+            const int a = u < v ? u : v, b = u < v ? v : u;
+            const int oa = row_offset(np, a), ob = row_offset(np, b);
+            const double app = P[oa + a], aqq = P[ob + b], apq = P[oa + b];
+            double c = 1.0, sn = 0.0;
+            if (b < nb && jacobi_angle(app, aqq, apq, c, sn)) rotated = 1;
+            pr[bf][t] = make_int4(8 * a, 8 * b, 8 * oa, 8 * ob);
+            cs[bf][t] = make_double2(c, sn);
+            pe[bf][t] = PairEntries{app, aqq, apq};
+            lowa[bf][t] = u < v;
+            rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, sn);
+        }
+    };
     __syncthreads();
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
@@ -680,84 +777,110 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
         if (off_sum <= 1e-30 * all_sum || all_sum == 0.0 || none_last) break;
         if (tid == 0) rotated = 0;
         __syncthreads();
+        rotations(sweep, 0, 0);
+        __syncthreads();
         for (int round = 0; round < np - 1; ++round) {
-            for (int t = tid; t < half; t += nt) {
-                // round-robin positions: 0 stays, the others shift by one every round
-                auto player = [&](int k) {
-                    if (k == 0) return 0;
-                    const int z = k - 1 + round;
-                    return 1 + (z >= np - 1 ? z - (np - 1) : z);
-                };
-                const int u = player(t), v = player(np - 1 - t);
-                const int a = u < v ? u : v, b = u < v ? v : u;
-                const int oa = row_offset(np, a), ob = row_offset(np, b);
-                double c = 1.0, sn = 0.0;
-                if (b < nb) {
-                    const double apq = P[oa + b], app = P[oa + a], aqq = P[ob + b];
-                    // rotations below rounding of the two diagonal entries are skipped
-                    if (std::fabs(apq) > 1e-16 * (std::fabs(app) + std::fabs(aqq))) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = tau >= 0.0 ? 1.0 / (tau + std::sqrt(1.0 + tau * tau))
-                                                     : -1.0 / (-tau + std::sqrt(1.0 + tau * tau));
-                        c = 1.0 / std::sqrt(1.0 + tt * tt);
-                        sn = tt * c;
-                        rotated = 1;
-                    }
-                }
-                pr[t] = make_int4(8 * a, 8 * b, 8 * oa, 8 * ob);
-                cs[t] = make_double2(c, sn);
-                rot[(size_t(sweep) * (np - 1) + round) * half + t] = make_double2(c, sn);
-            }
-            __syncthreads();
+            const int cb = round & 1, nbf = cb ^ 1;
+            const bool ahead = merged && round + 1 < np - 1;   // this round computes the next one's rotations
             // packed position of (i, j) from the row offsets
             // (byte offsets: the table holds 8 x the indices and row offsets)
             auto at = [](int i, int oi, int j, int oj) { return i <= j ? oi + j : oj + i; };
             auto el = [&](int off) -> double & { return *reinterpret_cast<double *>(reinterpret_cast<char *>(P) + off); };
-            // the items in groups of kJacobiGroup: all loads of a group, then its updates
-#pragma unroll
-            for (int g = 0; g < kJacobiItems; g += kJacobiGroup) {
-                if (g * nt >= nblk) break;           // the same for the whole work-group
-                int idx[kJacobiGroup][4];
-                double hv[kJacobiGroup][4];
-#pragma unroll
-                for (int j = 0; j < kJacobiGroup; ++j) {
-                    const int i = g + j;
-                    if (i >= kJacobiItems || i * nt >= nblk) break;
-                    const int code = item[i] < 0 ? 0 : item[i];
-                    const int4 p1 = pr[code >> 16], p2 = pr[code & 0xffff];
-                    idx[j][0] = at(p1.x, p1.z, p2.x, p2.z);
-                    idx[j][1] = at(p1.x, p1.z, p2.y, p2.w);
-                    idx[j][2] = at(p1.y, p1.w, p2.x, p2.z);
-                    idx[j][3] = at(p1.y, p1.w, p2.y, p2.w);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) hv[j][q] = el(idx[j][q]);
+            if (tid < t0) {
+                if (tid < half) {
+                    const int t = tid;
+                    // the pair's diagonal block: (a, b) is annihilated by its own rotation
+                    const int4 p = pr[cb][t];
+                    const double2 q = cs[cb][t];
+                    const int iaa = p.z + p.x, iab = p.z + p.y, ibb = p.w + p.y;
+                    const double haa = el(iaa), hab = el(iab), hbb = el(ibb);
+                    double y00, y01, y10, y11;
+                    rotate_block(q.x, q.y, q.x, q.y, haa, hab, hab, hbb, y00, y01, y10, y11);
+                    el(iaa) = y00;
+                    el(ibb) = y11;
+                    el(iab) = q.y != 0.0 ? 0.0 : y01;
+                    if (merged) {
+                        int s1i, s2i;
+                        const int bits = next_block(t, s1i, s2i);
+                        const int4 p1 = pr[cb][s1i], p2 = pr[cb][s2i];
+                        const double2 q1 = cs[cb][s1i], q2 = cs[cb][s2i];
+                        const int i00 = at(p1.x, p1.z, p2.x, p2.z), i01 = at(p1.x, p1.z, p2.y, p2.w);
+                        const int i10 = at(p1.y, p1.w, p2.x, p2.z), i11 = at(p1.y, p1.w, p2.y, p2.w);
+                        rotate_block(q1.x, q1.y, q2.x, q2.y, el(i00), el(i01), el(i10), el(i11), y00, y01, y10, y11);
+                        el(i00) = y00;
+                        el(i01) = y01;
+                        el(i10) = y10;
+                        el(i11) = y11;
+                        if (ahead) {
+                            // member index (0: a, 1: b) of the row and column slots' players
+                            const int ir = bool(bits & 1) == bool(lowa[cb][s1i]) ? 1 : 0;
+                            const int ic = bool(bits & 2) == bool(lowa[cb][s2i]) ? 1 : 0;
+                            const double offd = ir ? (ic ? y11 : y10) : (ic ? y01 : y00);
+                            const int id_r = (ir ? p1.y : p1.x) >> 3, id_c = (ic ? p2.y : p2.x) >> 3;
+                            // new diagonal entries, as the pairs' own diagonal blocks compute them
+                            auto diag = [&](const double2 &qq, const PairEntries &e, int im) {
+                                double d00, d01, d10, d11;
+                                rotate_block(qq.x, qq.y, qq.x, qq.y, e.x, e.z, e.z, e.y, d00, d01, d10, d11);
+                                return im ? d11 : d00;
+                            };
+                            const double dr = diag(q1, pe[cb][s1i], ir), dc = diag(q2, pe[cb][s2i], ic);
+                            const bool r_first = id_r < id_c;
+                            const int a = r_first ? id_r : id_c, b = r_first ? id_c : id_r;
+                            const double app = r_first ? dr : dc, aqq = r_first ? dc : dr;
+                            double c = 1.0, sn = 0.0;
+                            if (b < nb && jacobi_angle(app, aqq, offd, c, sn)) rotated = 1;
+                            const int oa = row_offset(np, a), ob = row_offset(np, b);
+                            pr[nbf][t] = make_int4(8 * a, 8 * b, 8 * oa, 8 * ob);
+                            cs[nbf][t] = make_double2(c, sn);
+                            pe[nbf][t] = PairEntries{app, aqq, offd};
+                            const int low_id = (bits & 4) ? id_r : id_c;
+                            lowa[nbf][t] = low_id == a;
+                            rot[(size_t(sweep) * (np - 1) + round + 1) * half + t] = make_double2(c, sn);
+                        }
+                    }
                 }
+            } else {
+                // the remaining blocks in groups of kJacobiGroup: all loads of a group, then
+                // its updates
 #pragma unroll
-                for (int j = 0; j < kJacobiGroup; ++j) {
-                    const int i = g + j;
-                    if (i >= kJacobiItems || i * nt >= nblk) break;
-                    if (item[i] < 0) continue;
-                    const double2 r1 = cs[item[i] >> 16], r2 = cs[item[i] & 0xffff];
-                    const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
-                    const double h00 = hv[j][0], h01 = hv[j][1], h10 = hv[j][2], h11 = hv[j][3];
-                    // J_s^T B: rows mix; then (J_s^T B) J_t: columns mix
-                    const double x00 = std::fma(c1, h00, -s1 * h10), x01 = std::fma(c1, h01, -s1 * h11);
-                    const double x10 = std::fma(s1, h00, c1 * h10), x11 = std::fma(s1, h01, c1 * h11);
-                    const double y00 = std::fma(c2, x00, -s2 * x01), y01 = std::fma(s2, x00, c2 * x01);
-                    const double y10 = std::fma(c2, x10, -s2 * x11), y11 = std::fma(s2, x10, c2 * x11);
-                    el(idx[j][0]) = y00;
-                    el(idx[j][3]) = y11;
-                    if ((item[i] >> 16) == (item[i] & 0xffff)) {
-                        // a diagonal block: (a, b) is the one element idx 1 and 2 both name,
-                        // and the pair's own rotation annihilates it
-                        el(idx[j][1]) = s1 != 0.0 ? 0.0 : y01;
-                    } else {
+                for (int g = 0; g < kJacobiItems; g += kJacobiGroup) {
+                    if (g >= n_items) break;             // the same for the whole work-group
+                    int idx[kJacobiGroup][4];
+                    double hv[kJacobiGroup][4];
+#pragma unroll
+                    for (int j = 0; j < kJacobiGroup; ++j) {
+                        const int i = g + j;
+                        if (i >= kJacobiItems || i >= n_items) break;
+                        const int code = item[i] < 0 ? 1 : item[i];   // (0, 1) is a valid block
+                        const int4 p1 = pr[cb][code >> 16], p2 = pr[cb][code & 0xffff];
+                        idx[j][0] = at(p1.x, p1.z, p2.x, p2.z);
+                        idx[j][1] = at(p1.x, p1.z, p2.y, p2.w);
+                        idx[j][2] = at(p1.y, p1.w, p2.x, p2.z);
+                        idx[j][3] = at(p1.y, p1.w, p2.y, p2.w);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) hv[j][q] = el(idx[j][q]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < kJacobiGroup; ++j) {
+                        const int i = g + j;
+                        if (i >= kJacobiItems || i >= n_items) break;
+                        if (item[i] < 0) continue;
+                        const double2 q1 = cs[cb][item[i] >> 16], q2 = cs[cb][item[i] & 0xffff];
+                        double y00, y01, y10, y11;
+                        rotate_block(q1.x, q1.y, q2.x, q2.y, hv[j][0], hv[j][1], hv[j][2], hv[j][3], y00, y01, y10,
+                                     y11);
+                        el(idx[j][0]) = y00;
                         el(idx[j][1]) = y01;
                         el(idx[j][2]) = y10;
+                        el(idx[j][3]) = y11;
                     }
                 }
             }
             __syncthreads();
+            if (!merged && round + 1 < np - 1) {
+                rotations(sweep, round + 1, nbf);
+                __syncthreads();
+            }
         }
     }
     for (int i = tid; i < nb; i += nt) {
@@ -947,8 +1070,10 @@ struct ModeSolver {
         // the small kernels also hold up to about 7 KB of static shared memory
         // (np: the Jacobi kernel pads an odd nb by one row and column)
         const size_t tri_bytes = size_t(np) * (np + 1) / 2 * sizeof(double);
-        const int jh = np / 2;
-        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) && jh * (jh + 1) / 2 <= kJacobiItems * kSmallThreads &&
+        // (the Jacobi kernel's remaining blocks must fit the work-items beyond the pair slots)
+        const int jh = np / 2, jt0 = (jh + 63) / 64 * 64;
+        const int jrest = jh * (jh - 1) / 2 - (jh >= 3 ? jh : 0);
+        packed_bytes = tri_bytes + 8 * 1024 <= size_t(lds_limit) && jrest <= kJacobiItems * (kSmallThreads - jt0) &&
                                np * (np + 1) / 2 <= kJacobiLds
                            ? tri_bytes
                            : 0;
