@@ -99,6 +99,57 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply(
     }
 }
 
+// The same for an even nb, two columns per work-item (16-byte loads and stores; rows are
+// 16-byte aligned): CH2 chunks of 128 columns per row.
+template <int CH2>               // ceil(nb / 128)
+__global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply2(
+    int32_t n, int32_t nb, const double *__restrict__ y, const double *__restrict__ yp, double *__restrict__ yo,
+    const int32_t *__restrict__ nbr, const double *__restrict__ wt, const double *__restrict__ inv_s, double alpha,
+    double beta, double gam) {
+    const int j = __builtin_amdgcn_readfirstlane(xcd_group(blockIdx.x, gridDim.x) * kApplyWaves +
+                                                 int(threadIdx.x >> 6));
+    if (j >= n) return;
+    const int lane = threadIdx.x & 63, h2 = nb >> 1;
+    int32_t o[3];
+    double w[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        o[q] = nbr[3 * j + q];
+        w[q] = wt[3 * j + q];
+    }
+    const double is = inv_s[j];
+    const double2 *y2 = reinterpret_cast<const double2 *>(y), *p2 = reinterpret_cast<const double2 *>(yp);
+    double2 *o2 = reinterpret_cast<double2 *>(yo);
+    const size_t row = size_t(j) * h2;
+    double2 yv[CH2], g[CH2][3], pv[CH2];
+#pragma unroll
+    for (int k = 0; k < CH2; ++k) {
+        const int c = min(lane + 64 * k, h2 - 1);
+        yv[k] = y2[row + c];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[k][q] = y2[size_t(o[q] >= 0 ? o[q] : j) * h2 + c];
+        pv[k] = yp ? p2[row + c] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < CH2; ++k) {
+        const int c = lane + 64 * k;
+        if (c >= h2) break;
+        double ax = 0.0, ay = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (o[q] >= 0) {
+                ax += w[q] * (yv[k].x - g[k][q].x);
+                ay += w[q] * (yv[k].y - g[k][q].y);
+            }
+        double ox = alpha * (ax * is) + beta * yv[k].x, oy = alpha * (ay * is) + beta * yv[k].y;
+        if (yp) {
+            ox += gam * pv[k].x;
+            oy += gam * pv[k].y;
+        }
+        o2[row + c] = make_double2(ox, oy);
+    }
+}
+
 // partial[chunk][p][q] = sum over the chunk's rows j of S_j x[j][p] z[j][q], on the FP64
 // matrix cores: per step of 4 rows, v_mfma_f64_16x16x4 takes (S x)^T as the 16 x 4 operand
 // (lane l: column p0 + l % 16 of row l / 16) and z as the 4 x 16 one (lane l: row l / 16,
@@ -1096,6 +1147,14 @@ struct ModeSolver {
         const dim3 grid((n + kApplyWaves - 1) / kApplyWaves), threads(64 * kApplyWaves);
         const int32_t *nb_ = nbr.as<int32_t>();
         const double *wt_ = wt.as<double>(), *is_ = inv_s.as<double>();
+        if (nb % 2 == 0 && nb <= 256) {
+            switch ((nb + 127) / 128) {
+            case 1: hipLaunchKernelGGL(k_modes_apply2<1>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+            default: hipLaunchKernelGGL(k_modes_apply2<2>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
+            }
+            TYEE_HIP(hipGetLastError());
+            return TYEE_OK;
+        }
         switch ((nb + 63) / 64) {
         case 1: hipLaunchKernelGGL(k_modes_apply<1>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
         case 2: hipLaunchKernelGGL(k_modes_apply<2>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, alpha, beta, gam); break;
