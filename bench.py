@@ -659,7 +659,7 @@ def bench_modes(args):
                    "modes": MODES_WANTED, "block": nb, "max_degree": args.modes_degree,
                    "iterations": r["iters"],
                    "applies": r["applies"], "lambda_bound": r["lambda_bound"]},
-        "roofline": {"bound": "hbm", "kernel": "k_modes_apply",
+        "roofline": {"bound": "hbm", "kernel": "k_modes_apply2 (two columns per work-item, even block)",
                      "timed_with": "HIP events around the filter launches",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
@@ -681,7 +681,7 @@ def bench_modes(args):
 
 
 def modes_apply_at_scale(ty, stream, nb=MODES_BLOCK):
-    """k_modes_apply where the block cannot stay in the caches: one filtering iteration (degree
+    """The block apply where the block cannot stay in the caches: one filtering iteration (degree
     capped by the solver) on a 700 x 1000 resonator (1.6M triangles, block of 160, 1.64 GB per
     block); HIP-event time per application against its algorithmic bytes."""
     from meshgen import box_tri_mesh
