@@ -141,6 +141,20 @@ def test_odd_block_widths(ty, n_modes, block):
     _check(om, got, lam_ref, V_ref)
 
 
+@pytest.mark.parametrize("block", [2, 3, 4, 5, 6])
+def test_small_blocks(ty, block):
+    # blocks of up to 4 vectors (at most two Jacobi pairs) compute every round's rotations in
+    # a phase of their own; from 5 on the pair-slot waves compute the next round's
+    _note(f"case: 4 x 3 box (24 triangles), {min(block, 2)} lowest modes, block {block}")
+    xy, tri, Lx, Ly = box_mesh(4, 3, 0.1, 1, h=0.5)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam_ref, V_ref = om.modes(om.nt)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    got = m.modes(min(block, 2), block=block, tol=1e-12, max_iter=2000)
+    _note(f"  iters {got['iters']} applies {got['applies']}")
+    _check(om, got, lam_ref, V_ref)
+
+
 def test_whole_spectrum_of_a_tiny_mesh(ty):
     _note("case: 2 x 2 box (8 triangles), every mode, block = n_t")
     xy, tri, Lx, Ly = box_mesh(2, 2, 0.1, 1, h=0.5)
