@@ -26,7 +26,8 @@
 //   * Rayleigh-Ritz: H = V^T S K V is diagonalised (cyclic Jacobi) and V rotated into Ritz
 //     vectors; the largest Ritz value of the block becomes the next a.
 // An outer iteration runs three filter passes, each followed by the orthonormalisation (subspace
-// iteration needs no Rayleigh-Ritz in between), then one Rayleigh-Ritz step.
+// iteration needs no Rayleigh-Ritz in between; before another pass one Cholesky QR, which
+// leaves the block well conditioned, is enough), then one Rayleigh-Ritz step.
 // b is a Gershgorin bound on lambda_max of the symmetric form S^(1/2) K S^(-1/2).
 //
 // Layout: the block is row-major, [n_t][nb] doubles (row = triangle in device numbering), so
