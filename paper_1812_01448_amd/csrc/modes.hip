@@ -334,7 +334,8 @@ __global__ void __launch_bounds__(256) k_chol_inverse(int32_t nb, double *__rest
 // columns; h and work are overwritten.  sweeps_out: sweeps done.
 __global__ void __launch_bounds__(256) k_jacobi(int32_t nb, double *__restrict__ h, double *__restrict__ work,
                                                 double *__restrict__ q, double *__restrict__ theta,
-                                                int32_t max_sweeps, int32_t *__restrict__ sweeps_out) {
+                                                int32_t max_sweeps, double off_floor,
+                                                int32_t *__restrict__ sweeps_out) {
     __shared__ double cs[kMaxBlock / 2 + 1], sn[kMaxBlock / 2 + 1];
     __shared__ int pp[kMaxBlock / 2 + 1], qq[kMaxBlock / 2 + 1];
     __shared__ double red[256];
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(256) k_jacobi(int32_t nb, double *__restrict__
         }
         const double all_sum = red[0];
         __syncthreads();
-        if (off_sum <= 1e-30 * all_sum || all_sum == 0.0) break;
+        if (off_sum <= 1e-30 * all_sum || off_sum <= off_floor || all_sum == 0.0) break;
         for (int round = 0; round < np - 1; ++round) {
             // circle method: player 0 fixed, the others rotate
             for (int t = tid; t < half; t += nt) {
@@ -693,7 +694,7 @@ __device__ __forceinline__ void rotate_block(double c1, double s1, double c2, do
 __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const double *__restrict__ h,
                                                               double2 *__restrict__ rot, double *__restrict__ theta,
                                                               int32_t *__restrict__ order_out, int32_t max_sweeps,
-                                                              int32_t *__restrict__ sweeps_out) {
+                                                              double off_floor, int32_t *__restrict__ sweeps_out) {
     __shared__ double P[kJacobiLds];  // static, so that its address folds into the LDS offsets
     __shared__ int4 pr[2][kJacobiHalf];            // pair: 8 a, 8 b, 8 x row offsets (a < b)
     __shared__ double2 cs[2][kJacobiHalf];          // pair rotation (c, s)
@@ -826,7 +827,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
         }
         const bool none_last = sweep > 0 && !rotated;
         __syncthreads();
-        if (off_sum <= 1e-30 * all_sum || all_sum == 0.0 || none_last) break;
+        if (off_sum <= 1e-30 * all_sum || off_sum <= off_floor || all_sum == 0.0 || none_last) break;
         if (tid == 0) rotated = 0;
         __syncthreads();
         rotations(sweep, 0, 0);
@@ -1260,13 +1261,14 @@ struct ModeSolver {
 
     // Rayleigh-Ritz of the S-orthonormal block in buffer iv (scratch iz): Ritz vectors to
     // buffer ov, K times them to buffer okv (four distinct buffers), Ritz values to host.
-    int rayleigh_ritz(int iv, int iz, int ov, int okv, std::vector<double> &ritz, int max_sweeps = kJacobiSweeps) {
+    // off_floor: the Jacobi also stops once the off-diagonal sum of squares is below it
+    int rayleigh_ritz(int iv, int iz, int ov, int okv, std::vector<double> &ritz, int max_sweeps, double off_floor) {
         int rc = apply(B(iv), nullptr, B(iz), 1.0, 0.0, 0.0);
         if (!rc) rc = gram(B(iv), B(iz), h.as<double>());
         if (rc) return rc;
         if (packed_bytes) {
             hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(kSmallThreads), 0, st, nb, h.as<double>(),
-                               rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), max_sweeps,
+                               rot.as<double2>(), theta.as<double>(), order.as<int32_t>(), max_sweeps, off_floor,
                                small_i.as<int32_t>() + 1);
             TYEE_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_jacobi_vectors, dim3((nb + kVecRows - 1) / kVecRows), dim3(128), 0, st, nb,
@@ -1274,7 +1276,7 @@ struct ModeSolver {
                                small_i.as<int32_t>() + 1, order.as<int32_t>(), q.as<double>());
         } else {
             hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, nb, h.as<double>(), work.as<double>(),
-                               q.as<double>(), theta.as<double>(), max_sweeps, small_i.as<int32_t>() + 1);
+                               q.as<double>(), theta.as<double>(), max_sweeps, off_floor, small_i.as<int32_t>() + 1);
         }
         TYEE_HIP(hipGetLastError());
         rc = rotate(B(iv), q.as<double>(), B(ov), false);
@@ -1375,7 +1377,10 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
         int vb = ModeSolver::pick({ob, 2}), kvb = ModeSolver::pick({ob, 2, vb});  // Ritz vectors, K times them
         // a random block smaller than the space is never converged: a few Jacobi sweeps give
         // Ritz values close enough for the first filter's bounds
-        if (!rc) rc = sv.rayleigh_ritz(ob, 2, vb, kvb, ritz, nb < nt ? kStartSweeps : kJacobiSweeps);
+        // off-diagonal entries of H move Ritz pairs by about their size: below 1e-3 of the
+        // residual tolerance they no longer matter
+        const double off_floor = (1e-3 * tol * b_up) * (1e-3 * tol * b_up);
+        if (!rc) rc = sv.rayleigh_ritz(ob, 2, vb, kvb, ritz, nb < nt ? kStartSweeps : kJacobiSweeps, off_floor);
         if (!rc) rc = sv.residuals(vb, kvb, res);
         applies += 1;
         auto converged = [&]() {
@@ -1419,7 +1424,7 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
             const int spare = ModeSolver::pick({in});
             vb = ModeSolver::pick({in, spare});
             kvb = ModeSolver::pick({in, spare, vb});
-            rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz);
+            rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz, kJacobiSweeps, off_floor);
             if (!rc) rc = sv.residuals(vb, kvb, res);
             if (rc) break;
             applies += 1;                          // the Rayleigh-Ritz product K V
