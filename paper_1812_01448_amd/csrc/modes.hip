@@ -1372,7 +1372,9 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
                            sv.canon.as<int32_t>(), seed, sv.B(0));
         TYEE_HIP(hipGetLastError());
         int ob = 1;
-        rc = sv.orthonormalise(0, 1, &ob);
+        // a tall random block is well conditioned: one Cholesky QR leaves it orthonormal to
+        // rounding
+        rc = sv.orthonormalise(0, 1, &ob, 4 * nb <= nt);
         std::vector<double> ritz, res;
         int vb = ModeSolver::pick({ob, 2}), kvb = ModeSolver::pick({ob, 2, vb});  // Ritz vectors, K times them
         // a random block smaller than the space is never converged: a few Jacobi sweeps give
