@@ -488,6 +488,7 @@ constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kerne
 // (rt[c (c + 1)/2 + k] = R[k][c], k <= c) for k_tri_inverse.  info = 0, or 1 + the failing
 // pivot's index.
 constexpr int kPanel = 8;
+constexpr int kTrail = kMaxBlock / 32;   // columns per lane in the trailing update
 __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const double *__restrict__ g, double shift,
                                                             double *__restrict__ rt, int32_t *__restrict__ info) {
     extern __shared__ double P[];
@@ -506,12 +507,16 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
         const int pw = min(kPanel, nb - j0);
         if (tid < 64) {
             double pr[kPanel][kSlots];
+            // every load from a valid address (the panel's diagonal entry where the element is
+            // outside the panel), so that all of them are in flight together
 #pragma unroll
             for (int r = 0; r < kPanel; ++r)
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
-                    const int c = j0 + lane + 64 * sl;
-                    pr[r][sl] = (r < pw && c < nb && c >= j0 + r) ? P[packed(nb, j0 + r, c)] : 0.0;
+                    const int c = j0 + lane + 64 * sl, rr = j0 + min(r, pw - 1);
+                    const bool in = r < pw && c < nb && c >= j0 + r;
+                    const double v = P[packed(nb, rr, in ? c : rr)];
+                    pr[r][sl] = in ? v : 0.0;
                 }
             int failed = 0;
 #pragma unroll
@@ -551,18 +556,42 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
         }
         __syncthreads();
         if (bad) break;
-        // rows below the panel: P[r][c] -= sum over the panel rows k of R[k][r] R[k][c]
-        for (int r = j0 + pw + (tid >> 5); r < nb; r += nt >> 5) {
+        // rows below the panel: P[r][c] -= sum over the panel rows k of R[k][r] R[k][c], a
+        // group of 32 lanes per row, each lane up to kTrail columns 32 apart whose loads are
+        // issued together (clamped to the row's diagonal where a column is past nb)
+        for (int r0 = j0 + pw + ((tid >> 6) << 1); r0 < nb; r0 += nt >> 5) {
+            const int r = r0 + ((tid >> 5) & 1);        // r0: the wave's first row
+            const int ne = (nb - r0 + 31) >> 5;         // column steps of the wave's longer row
+            const bool row_in = r < nb;
+            const int rs = row_in ? r : r0;
             double rk[kPanel];
 #pragma unroll
-            for (int k = 0; k < kPanel; ++k) rk[k] = k < pw ? P[packed(nb, j0 + k, r)] : 0.0;
-            const int rowr = packed(nb, r, 0);
-            for (int c = r + (tid & 31); c < nb; c += 32) {
-                double acc = P[rowr + c];
+            for (int k = 0; k < kPanel; ++k) rk[k] = k < pw ? P[packed(nb, j0 + k, rs)] : 0.0;
+            const int rowr = packed(nb, rs, 0);
+            double acc[kTrail];
+            int cc[kTrail];
 #pragma unroll
-                for (int k = 0; k < kPanel; ++k)
-                    if (k < pw) acc -= rk[k] * P[packed(nb, j0 + k, c)];
-                P[rowr + c] = acc;
+            for (int e = 0; e < kTrail; ++e) {
+                if (e >= ne) break;
+                const int c = rs + (tid & 31) + 32 * e;
+                cc[e] = c < nb ? c : rs;
+                acc[e] = P[rowr + cc[e]];
+            }
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k) {
+                if (k >= pw) break;
+                const int rowk = packed(nb, j0 + k, 0);
+#pragma unroll
+                for (int e = 0; e < kTrail; ++e) {
+                    if (e >= ne) break;
+                    acc[e] -= rk[k] * P[rowk + cc[e]];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < kTrail; ++e) {
+                if (e >= ne) break;
+                const int c = rs + (tid & 31) + 32 * e;
+                if (row_in && c < nb) P[rowr + c] = acc[e];
             }
         }
         __syncthreads();
