@@ -513,6 +513,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
             for (int r = 0; r < kPanel; ++r)
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
+                    if (j0 + 64 * sl >= nb) break;  // the same for the whole wave
                     const int c = j0 + lane + 64 * sl, rr = j0 + min(r, pw - 1);
                     const bool in = r < pw && c < nb && c >= j0 + r;
                     const double v = P[packed(nb, rr, in ? c : rr)];
@@ -530,6 +531,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
                 const double piv = std::sqrt(d), inv = 1.0 / piv;
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
+                    if (j0 + 64 * sl >= nb) break;  // the same for the whole wave
                     const int c = j0 + lane + 64 * sl;
                     if (c == j0 + k) pr[k][sl] = piv;
                     else if (c > j0 + k) pr[k][sl] *= inv;
@@ -540,6 +542,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
                     const double mult = lane_value(pr[k][0], r);  // R[j0 + k][j0 + r]
 #pragma unroll
                     for (int sl = 0; sl < kSlots; ++sl) {
+                        if (j0 + 64 * sl >= nb) break;  // the same for the whole wave
                         const int c = j0 + lane + 64 * sl;
                         if (c >= j0 + r && c < nb) pr[r][sl] -= mult * pr[k][sl];
                     }
@@ -549,6 +552,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
             for (int r = 0; r < kPanel; ++r)
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
+                    if (j0 + 64 * sl >= nb) break;  // the same for the whole wave
                     const int c = j0 + lane + 64 * sl;
                     if (r < pw && c < nb && c >= j0 + r) P[packed(nb, j0 + r, c)] = pr[r][sl];
                 }
@@ -733,7 +737,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_jacobi_lds(int32_t nb, const 
     __shared__ int order[kJacobiNp];
     __shared__ int rotated;            // a rotation was applied in the current sweep
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int np = nb + (nb & 1), half = np / 2, nblk = half * (half + 1) / 2;
+    const int np = nb + (nb & 1), half = np / 2;
     // with fewer than 3 pairs two of the next round's pairs can share a block: those sizes
     // compute every round's rotations in a phase of their own
     const bool merged = half >= 3;
