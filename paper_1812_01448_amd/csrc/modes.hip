@@ -482,9 +482,9 @@ constexpr int kSmallThreads = 1024;   // threads of the one-work-group LDS kerne
 
 // The Cholesky factor of g + shift I with g held in LDS (packed upper triangle, nb (nb + 1)/2
 // doubles of dynamic shared memory), blocked in panels of kPanel rows: one wave factors a
-// panel in registers (lane l holds columns j0 + l + 64 s), exchanging each pivot and
-// multiplier by a shuffle, with no barrier; then all work-items apply the panel's rank-kPanel
-// update to the rows below it.  g is only read; R goes to rt packed by columns
+// panel in registers (lane l holds columns j0 + l + 64 s), reading each pivot and multiplier
+// from its lane with v_readlane, with no barrier; then all work-items apply the panel's
+// rank-kPanel update to the rows below it (a group of 32 lanes per row).  g is only read; R goes to rt packed by columns
 // (rt[c (c + 1)/2 + k] = R[k][c], k <= c) for k_tri_inverse.  info = 0, or 1 + the failing
 // pivot's index.
 constexpr int kPanel = 8;
