@@ -1125,7 +1125,7 @@ struct ModeSolver {
         }
         *upper = bound;
         const size_t blk = size_t(nt) * nb * sizeof(double);
-        rows_per_chunk = int32_t(std::max<int64_t>(256, (nt + 255) / 256));
+        rows_per_chunk = int32_t(std::max<int64_t>(128, (nt + 511) / 512));
         chunks = int32_t((nt + rows_per_chunk - 1) / rows_per_chunk);
         const size_t sq = size_t(nb) * nb * sizeof(double);
         const int np = nb + (nb & 1);
