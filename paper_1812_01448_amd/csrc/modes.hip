@@ -211,13 +211,23 @@ __global__ void __launch_bounds__(64 * kGramWaves) k_gram(int32_t n, int32_t nb,
             }
 }
 
-// out[k] = sum over chunks c (in order) of partial[c][k]
+// out[k] = sum over chunks c (in order) of partial[c][k]; the loads of kSumAhead chunks are
+// issued before they are added (in order)
+constexpr int kSumAhead = 8;
 __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restrict__ partial,
                              double *__restrict__ out) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= len) return;
     double acc = 0.0;
-    for (int c = 0; c < chunks; ++c) acc += partial[size_t(c) * len + k];
+    int c = 0;
+    for (; c + kSumAhead <= chunks; c += kSumAhead) {
+        double v[kSumAhead];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) v[u] = partial[size_t(c + u) * len + k];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) acc += v[u];
+    }
+    for (; c < chunks; ++c) acc += partial[size_t(c) * len + k];
     out[k] = acc;
 }
 
