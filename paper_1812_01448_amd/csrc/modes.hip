@@ -645,10 +645,14 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
     double x[kSlots];
 #pragma unroll
     for (int sl = 0; sl < kSlots; ++sl) x[sl] = lane + 64 * sl == c ? 1.0 : 0.0;
-    // column r of R (clamped to its length) and 1 / R[r][r], loaded one step ahead
+    // column r of R (clamped to its length) and 1 / R[r][r], loaded one step ahead; slots past
+    // row r hold no row that step r touches and are skipped (r is the same for the whole wave)
     auto load = [&](int r, double *colv, double &d) {
 #pragma unroll
-        for (int sl = 0; sl < kSlots; ++sl) colv[sl] = Rt[r * (r + 1) / 2 + min(lane + 64 * sl, r)];
+        for (int sl = 0; sl < kSlots; ++sl) {
+            if (sl > (r >> 6)) break;
+            colv[sl] = Rt[r * (r + 1) / 2 + min(lane + 64 * sl, r)];
+        }
         d = dinv[r];
     };
     double nxt[kSlots], dnxt;
@@ -660,7 +664,7 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
         const double d = dnxt;
         if (r > 0) load(r - 1, nxt, dnxt);
         const int sr = r >> 6;
-        // x_r from its lane (r is the same for the whole wave)
+        // x_r from its lane
         double xr = x[0];
 #pragma unroll
         for (int sl = 1; sl < kSlots; ++sl)
@@ -668,6 +672,7 @@ __global__ void __launch_bounds__(64 * kInvCols) k_tri_inverse(int32_t nb, const
         const double mr = lane_value(xr, r & 63) * d;
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl) {
+            if (sl > sr) break;
             const int k = lane + 64 * sl;
             const double upd = x[sl] - cur[sl] * mr;
             x[sl] = k < r ? upd : (k == r ? mr : x[sl]);
