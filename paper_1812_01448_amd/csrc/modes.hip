@@ -1069,7 +1069,23 @@ __global__ void k_residual(int32_t n, int32_t nb, int32_t rows_per_chunk, const 
     const int64_t r_end = std::min<int64_t>(n, r_begin + rows_per_chunk);
     const double th = theta[c];
     double acc = 0.0;
-    for (int64_t j = r_begin; j < r_end; ++j) {
+    int64_t j = r_begin;
+    // kSumAhead rows' loads in flight, accumulated in row order
+    for (; j + kSumAhead <= r_end; j += kSumAhead) {
+        double a[kSumAhead], b[kSumAhead], w[kSumAhead];
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            a[u] = kv[(j + u) * nb + c];
+            b[u] = v[(j + u) * nb + c];
+            w[u] = s[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            const double r = a[u] - th * b[u];
+            acc += w[u] * r * r;
+        }
+    }
+    for (; j < r_end; ++j) {
         const double r = kv[j * nb + c] - th * v[j * nb + c];
         acc += s[j] * r * r;
     }
