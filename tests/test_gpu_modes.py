@@ -126,11 +126,11 @@ def test_largest_block_uses_the_global_memory_small_kernels(ty):
     _check(om, got, lam_ref, V_ref)
 
 
-@pytest.mark.parametrize("n_modes,block", [(21, 37), (150, 201)])
-def test_odd_block_widths(ty, n_modes, block):
-    # an odd block gives the round-robin Jacobi a ghost row and column: 37 in LDS, 201 (too
-    # large for LDS) in global memory
-    _note(f"case: box 16 x 24 triangular lattice, {n_modes} modes, odd block {block}")
+@pytest.mark.parametrize("n_modes,block", [(21, 37), (150, 191), (150, 192), (150, 201)])
+def test_odd_and_largest_lds_block_widths(ty, n_modes, block):
+    # an odd block gives the round-robin Jacobi a ghost row and column: 37 and 191 in LDS, 201
+    # (too large for LDS) in global memory; 191 and 192 fill the LDS Jacobi's table and work split
+    _note(f"case: box 16 x 24 triangular lattice, {n_modes} modes, block {block}")
     xy, tri, Lx, Ly = box_tri_mesh(16, 24, 1.0, 0.1, 3)
     om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
     lam_ref, V_ref = om.modes(min(om.nt, block + 40))
