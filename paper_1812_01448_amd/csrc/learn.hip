@@ -127,7 +127,16 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                                                            const float *__restrict__ gamma, double inv_mw,
                                                            double *__restrict__ eps_out,
                                                            float *__restrict__ grad_out, int64_t grad_stride) {
-    __shared__ float xr[kTsMaxTris], xi[kTsMaxTris], vr[kTsMaxTris], vi[kTsMaxTris];
+    // the two sequences' current values, double-buffered: a step reads buffer n & 1 and writes
+    // the other, so one barrier per step separates the reads from the next step's writes
+    __shared__ float lds_state[2][4][kTsMaxTris];
+    float *xr = lds_state[0][0], *xi = lds_state[0][1], *vr = lds_state[0][2], *vi = lds_state[0][3];
+    auto swap_state = [&](int n) {
+        xr = lds_state[n & 1][0];
+        xi = lds_state[n & 1][1];
+        vr = lds_state[n & 1][2];
+        vi = lds_state[n & 1][3];
+    };
     __shared__ double red[kTsThreads / 64][2];
     // work-groups start longest recurrence first (order sorts (mesh, wave) pairs by steps)
     const int b = order[blockIdx.x];
@@ -199,6 +208,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
 
     // pass 1: x and v forward N steps
     for (int n = 0; n < N; ++n) {
+        swap_state(n);
 #pragma unroll
         for (int r = 0; r < kTsTris; ++r) {
             if (tid + r * kTsThreads < M.nt) {
@@ -206,7 +216,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                 TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
             }
         }
-        __syncthreads();
+        swap_state(n + 1);
 #pragma unroll
         for (int r = 0; r < kTsTris; ++r) {
             const int t = tid + r * kTsThreads;
@@ -277,6 +287,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
         }
     }
     __syncthreads();   // everyone has read its z-partials before LDS is rewritten
+    swap_state(0);
 #pragma unroll
     for (int r = 0; r < kTsTris; ++r) {
         const int t = tid + r * kTsThreads;
@@ -297,6 +308,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
     }
     __syncthreads();
     for (int n = 0; n < N; ++n) {
+        swap_state(n);
 #pragma unroll
         for (int r = 0; r < kTsEdges; ++r) {
             if (tid + r * kTsThreads < M.ne) {
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                 TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
             }
         }
-        __syncthreads();
+        swap_state(n + 1);
 #pragma unroll
         for (int r = 0; r < kTsTris; ++r) {
             const int t = tid + r * kTsThreads;
