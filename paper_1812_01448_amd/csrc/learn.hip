@@ -129,13 +129,12 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                                                            float *__restrict__ grad_out, int64_t grad_stride) {
     // the two sequences' current values, double-buffered: a step reads buffer n & 1 and writes
     // the other, so one barrier per step separates the reads from the next step's writes
-    __shared__ float lds_state[2][4][kTsMaxTris];
-    float *xr = lds_state[0][0], *xi = lds_state[0][1], *vr = lds_state[0][2], *vi = lds_state[0][3];
+    // (real, imaginary) pairs, so that one 8-byte access moves a complex value
+    __shared__ float2 lds_state[2][2][kTsMaxTris];
+    float2 *xs = lds_state[0][0], *vs = lds_state[0][1];
     auto swap_state = [&](int n) {
-        xr = lds_state[n & 1][0];
-        xi = lds_state[n & 1][1];
-        vr = lds_state[n & 1][2];
-        vi = lds_state[n & 1][3];
+        xs = lds_state[n & 1][0];
+        vs = lds_state[n & 1][1];
     };
     __shared__ double red[kTsThreads / 64][2];
     // work-groups start longest recurrence first (order sorts (mesh, wave) pairs by steps)
@@ -185,22 +184,20 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
             v_i[r] = bi;
             u_r[r] = br;
             u_i[r] = bi;
-            xr[t] = x_r[r];
-            xi[t] = x_i[r];
-            vr[t] = v_r[r];
-            vi[t] = v_i[r];
+            xs[t] = make_float2(x_r[r], x_i[r]);
+            vs[t] = make_float2(v_r[r], v_i[r]);
         }
     }
     __syncthreads();
 
-    // one step of y <- y - dt^2 K s, s <- s + y for the sequences held in (sr, si) / LDS (lr, li)
-#define TS_STEP(SR, SI, YR, YI, LR, LI)                                                     \
+    // one step of y <- y - dt^2 K s, s <- s + y for the sequences held in (sr, si) / LDS pairs ls
+#define TS_STEP(SR, SI, YR, YI, LS)                                                         \
     {                                                                                       \
         float kr = 0.0f, ki = 0.0f;                                                         \
         _Pragma("unroll") for (int q = 0; q < 3; ++q) {                                     \
-            const int nb = int(word[r][q] & 0xFFFFu);                                       \
-            kr = fmaf(sig[r][q], SR[r] - LR[nb], kr);                                       \
-            ki = fmaf(sig[r][q], SI[r] - LI[nb], ki);                                       \
+            const float2 o = LS[int(word[r][q] & 0xFFFFu)];                                 \
+            kr = fmaf(sig[r][q], SR[r] - o.x, kr);                                          \
+            ki = fmaf(sig[r][q], SI[r] - o.y, ki);                                          \
         }                                                                                   \
         YR[r] += kr;                                                                        \
         YI[r] += ki;                                                                        \
@@ -212,8 +209,8 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
 #pragma unroll
         for (int r = 0; r < kTsTris; ++r) {
             if (tid + r * kTsThreads < M.nt) {
-                TS_STEP(x_r, x_i, y_r, y_i, xr, xi);
-                TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
+                TS_STEP(x_r, x_i, y_r, y_i, xs);
+                TS_STEP(v_r, v_i, u_r, u_i, vs);
             }
         }
         swap_state(n + 1);
@@ -225,10 +222,8 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                 x_i[r] += y_i[r];
                 v_r[r] += u_r[r];
                 v_i[r] += u_i[r];
-                xr[t] = x_r[r];
-                xi[t] = x_i[r];
-                vr[t] = v_r[r];
-                vi[t] = v_i[r];
+                xs[t] = make_float2(x_r[r], x_i[r]);
+                vs[t] = make_float2(v_r[r], v_i[r]);
             }
         }
         __syncthreads();
@@ -292,10 +287,8 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
     for (int r = 0; r < kTsTris; ++r) {
         const int t = tid + r * kTsThreads;
         if (t < M.nt) {
-            xr[t] = x_r[r];
-            xi[t] = x_i[r];
-            vr[t] = v_r[r];
-            vi[t] = v_i[r];
+            xs[t] = make_float2(x_r[r], x_i[r]);
+            vs[t] = make_float2(v_r[r], v_i[r]);
         }
     }
     uint32_t erl[kTsEdges];
@@ -313,8 +306,9 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
         for (int r = 0; r < kTsEdges; ++r) {
             if (tid + r * kTsThreads < M.ne) {
                 const int R = int(erl[r] & 0xFFFFu), L = int(erl[r] >> 16);
-                const float dvr = vr[R] - vr[L], dvi = vi[R] - vi[L];
-                const float dxr = xr[R] - xr[L], dxi = xi[R] - xi[L];
+                const float2 vR = vs[R], vL = vs[L], xR = xs[R], xL = xs[L];
+                const float dvr = vR.x - vL.x, dvi = vR.y - vL.y;
+                const float dxr = xR.x - xL.x, dxi = xR.y - xL.y;
                 acc_r[r] = fmaf(dvr, dxr, fmaf(dvi, dxi, acc_r[r]));   // Re(conj(dv) dx)
                 acc_i[r] = fmaf(dvr, dxi, fmaf(-dvi, dxr, acc_i[r]));  // Im(conj(dv) dx)
             }
@@ -322,8 +316,8 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
 #pragma unroll
         for (int r = 0; r < kTsTris; ++r) {
             if (tid + r * kTsThreads < M.nt) {
-                TS_STEP(x_r, x_i, y_r, y_i, xr, xi);
-                TS_STEP(v_r, v_i, u_r, u_i, vr, vi);
+                TS_STEP(x_r, x_i, y_r, y_i, xs);
+                TS_STEP(v_r, v_i, u_r, u_i, vs);
             }
         }
         swap_state(n + 1);
@@ -335,10 +329,8 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
                 x_i[r] += y_i[r];
                 v_r[r] += u_r[r];
                 v_i[r] += u_i[r];
-                xr[t] = x_r[r];
-                xi[t] = x_i[r];
-                vr[t] = v_r[r];
-                vi[t] = v_i[r];
+                xs[t] = make_float2(x_r[r], x_i[r]);
+                vs[t] = make_float2(v_r[r], v_i[r]);
             }
         }
         __syncthreads();
