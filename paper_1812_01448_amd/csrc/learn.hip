@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_mlp_gamma(int n, const float *__restric
     gamma[i] = 1.0f + kSpan * mlp_edge(sP, x, h1, h2);
 }
 
-constexpr int kTsThreads = 512, kTsTris = 8, kTsEdges = 12;  // per work-item
+constexpr int kTsThreads = 1024, kTsTris = 4, kTsEdges = 6;  // per work-item
 constexpr int kTsMaxTris = kTsThreads * kTsTris, kTsMaxEdges = kTsThreads * kTsEdges;
 
 struct TsMesh {
