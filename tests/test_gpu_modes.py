@@ -155,6 +155,21 @@ def test_small_blocks(ty, block):
     _check(om, got, lam_ref, V_ref)
 
 
+def test_every_block_width_up_to_48(ty):
+    # every block width from 2 to 48 (the Jacobi's work split and pair schedule depend on it),
+    # eigenvalues against the oracle's dense spectrum
+    _note("case: 6 x 4 box (48 triangles), blocks 2 .. 48, half as many modes")
+    xy, tri, Lx, Ly = box_mesh(6, 4, 0.1, 1, h=0.5)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam_ref, _ = om.modes(om.nt)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    for block in range(2, om.nt + 1):
+        k = max(1, block // 2)
+        got = m.modes(k, block=block, tol=1e-11, max_iter=3000)
+        assert got["converged"], block
+        assert np.max(np.abs(got["omega2"] - lam_ref[:k])) <= 1e-9 * got["lambda_bound"], block
+
+
 def test_whole_spectrum_of_a_tiny_mesh(ty):
     _note("case: 2 x 2 box (8 triangles), every mode, block = n_t")
     xy, tri, Lx, Ly = box_mesh(2, 2, 0.1, 1, h=0.5)
