@@ -49,6 +49,8 @@ constexpr int kMaxBlock = 256;
 typedef double double4v __attribute__((ext_vector_type(4)));   // one lane's share of a 16 x 16 FP64 MFMA tile
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 constexpr int kStartSweeps = 3;     // the same for the random starting block
+constexpr int kMidSweeps = 4;       // the same while the residuals are far from the tolerance
+constexpr double kNearTol = 1e4;    // "far": above kNearTol x the tolerance
 constexpr int kFilterPasses = 3;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
 // y_out = alpha * (K y) + beta * y + gam * y_prev   (y_prev may be null).  One wave per row
@@ -1490,7 +1492,14 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
             const int spare = ModeSolver::pick({in});
             vb = ModeSolver::pick({in, spare});
             kvb = ModeSolver::pick({in, spare, vb});
-            rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz, kJacobiSweeps, off_floor);
+            // far from convergence the Rayleigh-Ritz step only has to give the filter its bounds
+            // and an orthonormal basis of the same subspace (any rotation of it will do): a few
+            // Jacobi sweeps suffice.  Once the previous step's residuals are within kNearTol of
+            // the tolerance, the Jacobi runs to its end.
+            double worst = 0.0;
+            for (int64_t c = 0; c < n_modes; ++c) worst = std::max(worst, res[c]);
+            const int sweeps = worst <= kNearTol * tol * b_up ? kJacobiSweeps : kMidSweeps;
+            rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz, sweeps, off_floor);
             if (!rc) rc = sv.residuals(vb, kvb, res);
             if (rc) break;
             applies += 1;                          // the Rayleigh-Ritz product K V
