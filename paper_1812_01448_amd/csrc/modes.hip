@@ -49,7 +49,7 @@ constexpr int kMaxBlock = 256;
 typedef double double4v __attribute__((ext_vector_type(4)));   // one lane's share of a 16 x 16 FP64 MFMA tile
 constexpr int kJacobiSweeps = 40;   // sweep limit of the Rayleigh-Ritz eigensolver
 constexpr int kStartSweeps = 3;     // the same for the random starting block
-constexpr int kMidSweeps = 4;       // the same while the residuals are far from the tolerance
+constexpr int kMidSweeps = 3;       // the same while the residuals are far from the tolerance
 constexpr double kNearTol = 1e4;    // "far": above kNearTol x the tolerance
 constexpr int kFilterPasses = 3;    // filter + Cholesky QR passes per Rayleigh-Ritz step
 
