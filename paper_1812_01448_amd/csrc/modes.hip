@@ -540,7 +540,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_lds(int32_t nb, const do
                     failed = j0 + k + 1;
                     continue;
                 }
-                const double piv = std::sqrt(d), inv = 1.0 / piv;
+                // 1/sqrt(d): the hardware estimate and two Newton steps (each one squares the
+                // relative error), a shorter dependent chain than a square root and a division
+                double inv = __builtin_amdgcn_rsq(d);
+#pragma unroll
+                for (int it = 0; it < 2; ++it) inv = std::fma(0.5 * inv, std::fma(-d * inv, inv, 1.0), inv);
+                const double piv = d * inv;
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
                     if (j0 + 64 * sl >= nb) break;  // the same for the whole wave
