@@ -240,7 +240,7 @@ __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restri
 // per wave) and 16 kRotTiles columns; the rows of m that a step needs are staged in LDS, kRotK
 // at a time, and x is read straight into the operand registers.
 constexpr int kRotWaves = 4;
-constexpr int kRotTiles = 4;
+constexpr int kRotTiles = 2;
 constexpr int kRotK = 32;
 
 __global__ void __launch_bounds__(64 * kRotWaves) k_rotate(int32_t n, int32_t nb, const double *__restrict__ x,
