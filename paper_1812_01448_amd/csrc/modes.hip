@@ -1261,7 +1261,9 @@ struct ModeSolver {
 
     // One Cholesky QR pass: src -> dst (src is left intact when the factorisation fails).
     // *ok = false when a pivot is not positive.
-    int cholqr_pass(int src, int dst, bool shifted, bool *ok) {
+    // With `ahead`, the rotation into dst is launched before the status is read (dst then holds
+    // garbage on failure, so dst must not be a block that a failure needs).
+    int cholqr_pass(int src, int dst, bool shifted, bool *ok, bool ahead = false) {
         int rc = gram(B(src), B(src), g.as<double>());
         if (rc) return rc;
         double shift = 0.0;
@@ -1287,9 +1289,13 @@ struct ModeSolver {
         TYEE_HIP(hipGetLastError());
         int32_t info = 0;
         TYEE_HIP(hipMemcpyAsync(&info, small_i.p, 4, hipMemcpyDeviceToHost, st));
+        if (ahead) {
+            const int rc = rotate(B(src), m.as<double>(), B(dst), true);
+            if (rc) return rc;
+        }
         TYEE_HIP(hipStreamSynchronize(st));
         *ok = info == 0;
-        return *ok ? rotate(B(src), m.as<double>(), B(dst), true) : TYEE_OK;
+        return *ok && !ahead ? rotate(B(src), m.as<double>(), B(dst), true) : TYEE_OK;
     }
 
     // The block in buffer ix made S-orthonormal, using buffer iy as well; *out names the
@@ -1301,7 +1307,7 @@ struct ModeSolver {
     // about u cond^2), which is all a following filter pass needs.
     int orthonormalise(int ix, int iy, int *out, bool once = false) {
         bool ok = false;
-        int rc = cholqr_pass(ix, iy, false, &ok);
+        int rc = cholqr_pass(ix, iy, false, &ok, true);   // iy is scratch if this pass fails
         if (!rc && ok && once) {
             *out = iy;
             return TYEE_OK;
@@ -1312,8 +1318,8 @@ struct ModeSolver {
             *out = ix;
             return TYEE_OK;
         }
-        // ix still holds the block when either pass failed (a pass writes only on success,
-        // and a failed second pass leaves the first pass's input, ix, as it was)
+        // ix still holds the block when either pass failed (the first pass writes only iy, and
+        // the second writes ix only on success)
         rc = cholqr_pass(ix, iy, true, &ok);
         if (!rc && ok) rc = cholqr_pass(iy, ix, false, &ok);
         if (!rc && ok) rc = cholqr_pass(ix, iy, false, &ok);
