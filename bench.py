@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 N_LATTICE = 1415
 
 
-def parse():
+def parse(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10000)
@@ -67,7 +67,7 @@ def parse():
                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs of this bench "
                         "and of --copy-calibration into the stored traffic figure of k_fused "
                         "for --workload, then exit (no GPU use)")
-    return p.parse_args()
+    return p.parse_args(argv)
 
 
 def traffic_file(workload):
@@ -226,6 +226,33 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def launch_stats(prof, graph_launches):
+    """Average launch duration of the stepping kernel from the HIP-event totals of a timed
+    region: whole graph replays (each holding `graph_launches` launches) plus the launches
+    made outside a graph (a remainder shorter than one graph span).  Returns (kind, launches,
+    avg_ms) with kind "fused" or "edge+tri" (one launch each per half-step), or None."""
+    if not prof:
+        return None
+    g = prof.get("graph", {"count": 0, "total_ms": 0.0})
+    if "fused" in prof or ("graph" in prof and "edge" not in prof):
+        f = prof.get("fused", {"count": 0, "total_ms": 0.0})
+        n = g["count"] * graph_launches + f["count"]
+        return ("fused", n, (g["total_ms"] + f["total_ms"]) / n) if n else None
+    e = prof.get("edge", {"count": 0, "total_ms": 0.0})
+    t = prof.get("tri", {"count": 0, "total_ms": 0.0})
+    steps = g["count"] * graph_launches + e["count"]
+    return ("edge+tri", steps, (g["total_ms"] + e["total_ms"] + t["total_ms"]) / steps) \
+        if steps else None
+
+
+def graph_size(steps, K, wanted):
+    """Launches per graph: at most `wanted`, even, and no longer than the timed region, so
+    that a short region still runs from graphs (0 when not even two launches fit)."""
+    fit = steps // max(K, 1)
+    g = min(wanted, fit - fit % 2)
+    return g if g >= 2 else 0
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -238,22 +265,39 @@ def main():
         traffic_summary(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the method "
+                                   "shards by contiguous Morton ranges with halo exchange, "
+                                   "which is not built)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    if args.workload == "batch256":
-        bench_batch(args)
-        return
-    if args.workload == "learned":
-        bench_learned(args)
-        return
-    if args.workload == "plasma2830":
-        bench_plasma(args)
-        return
-    if args.workload == "modes70x101":
-        bench_modes(args)
-        return
+    run = {"batch256": bench_batch, "learned": bench_learned, "plasma2830": bench_plasma,
+           "modes70x101": bench_modes, "torus1415": bench_torus}[args.workload]
+    out = run(args)
+    print(json.dumps(out), flush=True)
 
+
+def single_step_rate(sim, bytes_step, steps=2000):
+    """One launch per half-step (k_edge then k_tri), replayed from graphs of 8 steps: HIP-event
+    time per step against the per-step algorithmic bytes."""
+    sim.set_fusion(1, 0)
+    sim.set_graph(8)
+    sim.step(400)
+    sim.sync()
+    sim.set_profiling(True, kinds=["graph"])
+    sim.step(steps)
+    sim.sync()
+    prof = sim.kernel_times()
+    sim.set_profiling(False)
+    st = launch_stats(prof, 8)
+    ms = st[2]
+    ach = bytes_step / (ms * 1e-3) / 1e9
+    return {"kernels": "k_edge + k_tri, one launch per half-step, graphs of 8 steps",
+            "ms_per_step": round(ms, 6), "achieved": round(ach, 1),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "steps_timed": st[1]}
+
+
+def bench_torus(args, with_extras=True):
+    """The reported line: the plain FP32 step on the 4M-triangle periodic mesh."""
     import torch
     import paper_1812_01448_amd as ty
     from meshgen import lattice_mesh, periodic_wavevector, plane_wave_packet, random_angle
@@ -279,19 +323,21 @@ def main():
     sim.set_state("E", E0)
     sim.set_state("B", B0)
     sim.set_fusion(args.fusion, args.tile)
-    sim.set_graph(args.graph)
     ne, nt = mesh.ne, mesh.nt
     cells = ne + nt
 
-    sim.step(args.warmup)
+    sim.step(max(args.warmup, 1))
     sim.sync()
     fuse = sim.fusion_info()
     K = fuse["steps_per_launch"]
+    glaunch = graph_size(args.steps, K, args.graph) if args.graph > 0 else 0
+    sim.set_graph(glaunch)
+    if glaunch:                                   # capture outside the timed region
+        sim.step(K * glaunch)
     torch.cuda.synchronize()
-    # HIP events bracket every launch of the dominant kernel inside the timed region (every
-    # graph replay when the fused launches run from a captured graph)
-    use_graph = args.graph > 0
-    sim.set_profiling(True, kinds=["graph"] if use_graph else (["fused"] if K > 1 else ["edge", "tri"]))
+    # HIP events bracket every graph replay and every launch made outside a graph inside the
+    # timed region, on the simulation's stream
+    sim.set_profiling(True, kinds=["graph", "fused"] if K > 1 else ["graph", "edge", "tri"])
     t_start = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
@@ -300,71 +346,47 @@ def main():
     sim.set_profiling(False)
     diag = sim.diagnostics()
     log(f"timed {args.steps} steps in {elapsed:.4f} s; energy {diag['energy']:.6e} "
-        f"nonfinite={diag['nonfinite']}")
+        f"nonfinite={diag['nonfinite']}; launches {prof}")
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = cells * args.steps / elapsed
     esz = 4 if args.prec == "f32" else 8
-    # algorithmic bytes (every cell read/written once, compulsory gathers counted once)
+    # algorithmic bytes: every cell read and written once, its coefficient and indices read
+    # once, compulsory gathers counted once (64 B per triangle in FP32, 25.6 B per cell)
     bytes_edge = 3 * esz * ne + 8 * ne + esz * nt          # Et r/w + cE, R/L, B gather
     bytes_tri = 3 * esz * nt + 12 * nt + esz * ne           # B r/w + nB, A, Et gather
-    algo = {"edge": bytes_edge, "tri": bytes_tri}
-    # dominant kernel = the one with the largest total time in the timed region
-    dom = max(prof, key=lambda kk: prof[kk]["total_ms"])
-    launches = prof[dom]["count"] * (args.graph if dom == "graph" else 1)
-    per_launch_bytes = K * (bytes_edge + bytes_tri) if dom in ("fused", "graph") else algo[dom]
-    avg_ms = prof[dom]["total_ms"] / launches
-    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     step_bytes = bytes_edge + bytes_tri
-    kname = ("k_fused" if K > 1 else "k_edge+k_tri") if dom in ("fused", "graph") else prof[dom]["name"]
-    roofline = {"bound": "hbm", "kernel": kname,
-                "timed_with": "HIP events per graph replay of %d launches" % args.graph
-                if dom == "graph" else "HIP events per launch",
-                "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 5),
-                "algorithmic_bytes_per_launch": per_launch_bytes,
-                "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)}
-    if K > 1:
-        # bytes the fused kernel actually moves per launch (tile cells with halos, once)
-        moved = (fuse["local_tris"] * (esz + esz + 8 + 4) + fuse["local_edges"] * (esz + esz + 4 + 4)
-                 + (nt + ne) * esz)
-        roofline["moved_bytes_per_launch"] = moved
-        roofline["moved_GBs"] = round(moved / (avg_ms * 1e-3) / 1e9, 1)
-        roofline["halo_ratio_tris"] = round(fuse["local_tris"] / nt, 3)
-        roofline["halo_ratio_edges"] = round(fuse["local_edges"] / ne, 3)
-        roofline["traffic"] = measured_traffic("k_fused", {
-            "triangles": nt, "steps_per_launch": K, "tile_tris": fuse["tile"], "prec": args.prec,
-            "order": args.order})
-
-    # five further runs of 1,000 steps (median beside the single timed region above)
-    reps = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t_r = time.perf_counter()
-        sim.step(1000)
-        torch.cuda.synchronize()
-        reps.append((time.perf_counter() - t_r) * 1e3 / 1000)
-    # the boundary takes and returns host buffers in canonical order: state transfer cost
-    torch.cuda.synchronize()
-    t_io = time.perf_counter()
-    E1, B1 = sim.get_state("E"), sim.get_state("B")
-    t_get = time.perf_counter() - t_io
-    t_io = time.perf_counter()
-    sim.set_state("E", E1)
-    sim.set_state("B", B1)
-    torch.cuda.synchronize()
-    t_set = time.perf_counter() - t_io
-    roofline["copy_GBs"] = measure_copy_bandwidth()
-    roofline["torch_copy_GBs"] = measure_torch_copy_bandwidth()
-    if roofline.get("traffic"):
-        roofline["traffic_GBs"] = round(roofline["traffic"] / (avg_ms * 1e-3) / 1e9, 1)
-        roofline["traffic_frac_of_copy"] = round(roofline["traffic_GBs"] / roofline["copy_GBs"], 4)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(xy, tri, dt, E0, B0, args.cpu_steps, view)
-
+    st = launch_stats(prof, glaunch)
+    roofline = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    if st is not None:
+        kind, launches, avg_ms = st
+        # a K-step fused launch must still move every cell once: its compulsory bytes are one
+        # step's; the K - 1 further steps run from the tile held on chip
+        per_launch = step_bytes
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        roofline.update({
+            "kernel": "k_fused" if kind == "fused" else "k_edge+k_tri",
+            "achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_launch_ms": round(avg_ms, 6), "launches_timed": launches,
+            "steps_per_launch": K if kind == "fused" else 1,
+            "timed_with": f"HIP events on the simulation stream: {prof.get('graph', {}).get('count', 0)} "
+                          f"graph replays of {glaunch} launches, "
+                          f"{prof.get('fused', prof.get('edge', {})).get('count', 0)} launches outside graphs",
+            "algorithmic_bytes_per_launch": per_launch,
+            "algorithmic_bytes_note": "64 B per triangle (25.6 B per cell): each cell's field read "
+                                      "and written once, coefficient and indices read once, "
+                                      "gathers counted once",
+            "effective_GBs": round((K if kind == "fused" else 1) * step_bytes / (avg_ms * 1e-3) / 1e9, 1)})
+        if kind == "fused":
+            tr = measured_traffic("k_fused", {
+                "triangles": nt, "steps_per_launch": K, "tile_tris": fuse["tile"],
+                "prec": args.prec, "order": args.order})
+            roofline["traffic"] = tr
+            if tr:
+                roofline["traffic_GBs"] = round(tr / (avg_ms * 1e-3) / 1e9, 1)
+                roofline["traffic_frac"] = round(tr / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            roofline["halo_ratio_tris"] = round(fuse["local_tris"] / nt, 3)
+            roofline["halo_ratio_edges"] = round(fuse["local_edges"] / ne, 3)
     out = {
         "metric": "cell-updates/s (edges+tris) & HBM GB/s, plain vs learned at fixed phase error",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -374,15 +396,40 @@ def main():
                                f"(+-0.25h), plane-wave packet 20 cells/lambda, CFL 0.5",
                    "triangles": nt, "edges": ne, "cell_updates_per_step": cells,
                    "order": args.order, "steps_per_launch": K, "tile_tris": fuse["tile"],
-                   "graph_launches": args.graph if K > 1 else 0,
-                   "parallelism": "single GPU"},
+                   "graph_launches": glaunch, "parallelism": "single GPU"},
         "roofline": roofline,
-        "cpu_baseline": cpu,
-        "repeats_ms_per_step": [round(r, 5) for r in reps],
-        "median_ms_per_step": round(float(np.median(reps)), 5),
-        "host_io_ms": {"get_E_B": round(t_get * 1e3, 1), "set_E_B": round(t_set * 1e3, 1)},
+        "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    if not with_extras:
+        return out
+    # further runs of 1,000 steps (median beside the timed region above)
+    sim.set_graph(args.graph)
+    reps = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t_r = time.perf_counter()
+        sim.step(1000)
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - t_r) * 1e3 / 1000)
+    out["repeats_ms_per_step"] = [round(r, 5) for r in reps]
+    out["median_ms_per_step"] = round(float(np.median(reps)), 5)
+    # the boundary takes and returns host buffers in canonical order: state transfer cost
+    torch.cuda.synchronize()
+    t_io = time.perf_counter()
+    E1, B1 = sim.get_state("E"), sim.get_state("B")
+    t_get = time.perf_counter() - t_io
+    t_io = time.perf_counter()
+    sim.set_state("E", E1)
+    sim.set_state("B", B1)
+    torch.cuda.synchronize()
+    out["host_io_ms"] = {"get_E_B": round((t_get) * 1e3, 1),
+                         "set_E_B": round((time.perf_counter() - t_io) * 1e3, 1)}
+    roofline["single_step"] = single_step_rate(sim, step_bytes)
+    roofline["copy_GBs"] = measure_copy_bandwidth()
+    roofline["torch_copy_GBs"] = measure_torch_copy_bandwidth()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(xy, tri, dt, args.cpu_steps)
+    return out
 
 
 def bench_plasma(args):
@@ -461,11 +508,13 @@ def bench_plasma(args):
     # Q r/w, and per incidence its edge and coefficient
     bytes_special = n_special * (4 + 5 * esz)
     bytes_charge = len(nodes) * (8 + 2 * esz) + n_inc * (4 + esz)    # plus esz per decrement read
-    # one fused launch (plain-class tiles, special-class tiles and the charge update of its
-    # K steps, which reads each step's decrements) advances K whole steps
+    # compulsory bytes of one launch: a single-step kernel moves its own cells once; a fused
+    # launch (plain-class tiles, special-class tiles and the charge update of its K steps)
+    # must still move every cell, special edge and charge node once, its K - 1 further steps
+    # running from tiles held on chip
+    step_bytes = bytes_edge + bytes_tri + bytes_special + bytes_charge
     algo = {"edge": bytes_edge, "tri": bytes_tri, "special": bytes_special, "charge": bytes_charge,
-            "fused": K * (bytes_edge + bytes_tri + bytes_special) + bytes_charge + K * n_inc * esz}
-    step_bytes = bytes_edge + bytes_tri + bytes_special + bytes_charge + n_inc * esz
+            "fused": step_bytes}
     avg_ms = prof[dom]["total_ms"] / prof[dom]["count"]
     achieved = algo[dom] / (avg_ms * 1e-3) / 1e9
     cells = ne + nt
@@ -491,6 +540,8 @@ def bench_plasma(args):
                          "prec": args.prec, "order": args.order}, "plasma2830")
                      if dom == "fused" else None,
                      "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": algo[dom],
+                     "effective_GBs": round(step_bytes * (K if dom == "fused" else 1)
+                                            / (avg_ms * 1e-3) / 1e9, 1),
                      "step_effective_GBs": round(step_bytes * args.steps / elapsed / 1e9, 1)},
         "copy_GBs": measure_copy_bandwidth(),
         "cpu_baseline": None if args.no_cpu else cpu_baseline_plasma(708),
@@ -503,8 +554,9 @@ def bench_plasma(args):
     tr = out["roofline"]["traffic"]
     if tr:
         out["roofline"]["traffic_GBs"] = round(tr / (avg_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_frac"] = round(out["roofline"]["traffic_GBs"] / HBM_PEAK_GBS, 4)
         out["roofline"]["traffic_frac_of_copy"] = round(out["roofline"]["traffic_GBs"] / out["copy_GBs"], 4)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_batch(args):
@@ -549,15 +601,17 @@ def bench_batch(args):
         log(f"tuned: {best}")
     else:
         batch.set_fusion(args.fusion, args.tile)
-        batch.set_graph(args.graph)
     sim = batch.sim()
-    batch.step(args.warmup)
+    batch.step(max(args.warmup, 1))
     batch.sync()
     fuse = sim.fusion_info()
     K = fuse["steps_per_launch"]
+    glaunch = graph_size(args.steps, K, args.graph) if args.graph > 0 else 0
+    batch.set_graph(glaunch)
+    if glaunch:                                   # capture outside the timed region
+        batch.step(K * glaunch)
     torch.cuda.synchronize()
-    sim.set_profiling(True, kinds=["graph"] if args.graph and K > 1 else (
-        ["fused"] if K > 1 else ["edge", "tri"]))
+    sim.set_profiling(True, kinds=["graph", "fused"] if K > 1 else ["graph", "edge", "tri"])
     t1 = time.perf_counter()
     batch.step(args.steps)
     torch.cuda.synchronize()
@@ -568,11 +622,11 @@ def bench_batch(args):
     esz = 4 if args.prec == "f32" else 8
     step_bytes = (3 * esz + 8) * info["edges"] + esz * info["triangles"] + \
                  (3 * esz + 12) * info["triangles"] + esz * info["edges"]
-    dom = max(prof, key=lambda kk: prof[kk]["total_ms"])
-    launches = prof[dom]["count"] * (args.graph if dom == "graph" else 1)
-    avg_ms = prof[dom]["total_ms"] / launches
-    per_launch = step_bytes * (K if dom in ("graph", "fused") else 1)
+    kind, launches, avg_ms = launch_stats(prof, glaunch)
+    # compulsory bytes per launch: every cell of the union moved once (see the torus line)
+    per_launch = step_bytes
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    kf = K if kind == "fused" else 1
     out = {
         "metric": "cell-updates/s (edges+tris), batched plain method",
         "value": cells * args.steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1,
@@ -583,15 +637,17 @@ def bench_batch(args):
                                "log-uniform in [5k, 500k], per-mesh dt and plane wave",
                    "members": info["members"], "triangles": info["triangles"],
                    "edges": info["edges"], "steps_per_launch": K, "tile_tris": fuse["tile"],
-                   "graph_launches": args.graph, "order": args.order if not tuned else "tuned"},
-        "roofline": {"bound": "hbm", "kernel": "k_fused" if K > 1 else prof[dom]["name"],
+                   "graph_launches": glaunch, "order": args.order if not tuned else "tuned"},
+        "roofline": {"bound": "hbm", "kernel": "k_fused" if kind == "fused" else "k_edge+k_tri",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
-                     "algorithmic_bytes_per_launch": per_launch, "traffic": None},
+                     "launches_timed": launches, "steps_per_launch": kf,
+                     "algorithmic_bytes_per_launch": per_launch, "traffic": None,
+                     "effective_GBs": round(kf * step_bytes / (avg_ms * 1e-3) / 1e9, 1)},
         "tune": tuned,
         "cpu_baseline": None if args.no_cpu else cpu_baseline_batch(sizes, dts, init_xy),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 MODES_WANTED, MODES_BLOCK, MODES_TOL = 128, 160, 1e-11
@@ -677,7 +733,7 @@ def bench_modes(args):
         "apply_at_hbm_scale": None if args.modes_no_scale else modes_apply_at_scale(ty, stream),
         "cpu_baseline": None if args.no_cpu else cpu_baseline_modes(xy, tri, Lx, Ly),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def modes_apply_at_scale(ty, stream, nb=MODES_BLOCK):
@@ -920,25 +976,13 @@ def bench_learned(args):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
-
-
-def _oracle_rate(om, run, budget_s=12.0):
-    """Cell-updates/s of `run(nsteps)` on oracle mesh `om`: a 2-step probe sizes a sample of
-    about budget_s seconds, which is then timed."""
-    t1 = time.perf_counter()
-    run(2)
-    per = (time.perf_counter() - t1) / 2
-    steps = int(max(2, min(5000, budget_s / max(per, 1e-9))))
-    t1 = time.perf_counter()
-    run(steps)
-    el = time.perf_counter() - t1
-    return (om.ne + om.nt) * steps / el, steps
+    return out
 
 
 def cpu_baseline_plasma(n_sample):
     """The FP64 oracle on the plasma workload recipe at a smaller lattice (same particle,
-    source, rates in mesh units), single-threaded."""
+    source, rates in mesh units): a per-cell rate of a smaller mesh of the same recipe, on
+    one thread and on all OpenMP threads."""
     import oracle
     from meshgen import plasma_workload, periodic_wavevector, plane_wave_packet
     w = plasma_workload(n_sample)
@@ -948,15 +992,56 @@ def cpu_baseline_plasma(n_sample):
     B0, E0 = plane_wave_packet(om.O, om.C, om.tangent, k, dt, sigma=0.1, center=(0.5, 0.5))
     wp2 = om.edge_wp2(w["wp2_tri"])
     src = (w["src_pairs"], w["src_weights"], w["src_omega"], w["src_cycles"])
-    rate, steps = _oracle_rate(om, lambda m: om.step(E0, B0, dt, m, wp2=wp2, nu=w["nu"], src=src))
-    log(f"oracle plasma{n_sample}: {steps} steps, {rate:.3e} cell-updates/s")
-    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the plasma recipe at {n_sample}x{n_sample} "
-                      f"({om.nt} triangles, particle and source), single-threaded plain C oracle"}
+    all_threads = oracle.get_threads()
+    rates = {}
+    for th in sorted({1, all_threads}):
+        oracle.set_threads(th)
+        ns, el = _timed_oracle_steps(
+            om, lambda m: om.step(E0, B0, dt, m, wp2=wp2, nu=w["nu"], src=src), 6.0)
+        rates[th] = ((om.ne + om.nt) * ns / el, ns)
+    oracle.set_threads(all_threads)
+    log(f"oracle plasma{n_sample}: {rates}")
+    out = {"value": rates[all_threads][0], "unit": "cell-updates/s", "cores": all_threads,
+           "kind": "oracle", "value_1_thread": rates[1][0],
+           "sample": f"{rates[all_threads][1]} FP64 steps of the plasma recipe at "
+                     f"{n_sample}x{n_sample} ({om.nt} triangles, particle and source; a smaller "
+                     f"mesh than the benchmarked one, so a per-cell rate) on {all_threads} "
+                     f"threads, {rates[1][1]} steps on one; plain C oracle"}
+    out.update(host_cpu())
+    return out
 
 
-def cpu_baseline(xy, tri, dt, E0_lib, B0_lib, steps, view):
-    """The FP64 CPU oracle stepping the same mesh (bounded sample of steps)."""
+def host_cpu():
+    """CPU model, logical CPUs of the host and CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "cpus_allowed": len(os.sched_getaffinity(0))}
+
+
+def _timed_oracle_steps(om, run, budget_s, steps=0):
+    """(steps, seconds) of `run(steps)`: a one-step probe sizes a sample of about budget_s."""
+    if steps <= 0:
+        t1 = time.perf_counter()
+        run(1)
+        per = time.perf_counter() - t1
+        steps = int(max(2, min(5000, budget_s / max(per, 1e-9))))
+    t1 = time.perf_counter()
+    run(steps)
+    return steps, time.perf_counter() - t1
+
+
+def cpu_baseline(xy, tri, dt, steps=0, budget_s=8.0):
+    """The FP64 CPU oracle stepping the same mesh and start on a bounded sample of steps, on
+    one thread and on all the threads OpenMP is given (the oracle's result does not depend on
+    the count)."""
     import oracle
     t0 = time.time()
     om = oracle.OracleMesh(xy, tri, True)
@@ -966,18 +1051,22 @@ def cpu_baseline(xy, tri, dt, E0_lib, B0_lib, steps, view):
     k, _, _ = periodic_wavevector(random_angle(2), 20.0, 1.0 / n)
     B0, E0 = plane_wave_packet(om.O, om.C, om.tangent, k, dt, sigma=0.1, center=(0.5, 0.5))
     cells = om.ne + om.nt
-    if steps <= 0:
-        t1 = time.perf_counter()
-        om.step(E0, B0, dt, 2)
-        per = (time.perf_counter() - t1) / 2
-        steps = int(max(2, min(2000, 15.0 / max(per, 1e-9))))
-    t1 = time.perf_counter()
-    om.step(E0, B0, dt, steps)
-    el = time.perf_counter() - t1
-    log(f"oracle {steps} steps in {el:.2f} s")
-    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 leap-frog steps of the same {om.nt}-triangle mesh, "
-                      f"single-threaded plain C oracle"}
+    all_threads = oracle.get_threads()
+    rates = {}
+    for th in sorted({1, all_threads}):
+        oracle.set_threads(th)
+        ns, el = _timed_oracle_steps(om, lambda m: om.step(E0, B0, dt, m), budget_s, steps)
+        rates[th] = (cells * ns / el, ns, el)
+        log(f"oracle {th} threads: {ns} steps in {el:.2f} s ({rates[th][0]:.3e} cell-updates/s)")
+    oracle.set_threads(all_threads)
+    rate, ns, el = rates[all_threads]
+    out = {"value": rate, "unit": "cell-updates/s", "cores": all_threads, "kind": "oracle",
+           "value_1_thread": rates[1][0],
+           "sample": f"{ns} FP64 leap-frog steps of the same {om.nt}-triangle mesh and start on "
+                     f"{all_threads} threads ({el:.1f} s), and {rates[1][1]} steps on one thread "
+                     f"({rates[1][2]:.1f} s); plain C oracle, OpenMP over cells"}
+    out.update(host_cpu())
+    return out
 
 
 if __name__ == "__main__":

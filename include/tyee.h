@@ -250,7 +250,9 @@ typedef enum { TYEE_KERNEL_EDGE = 0, TYEE_KERNEL_TRI = 1, TYEE_KERNEL_FUSED = 2,
 
 /* Time every later launch of the kernel kinds in the bit mask `kinds` (bit k = tyee_kernel
    k) with a HIP event pair on the simulation's stream; resets the totals.  0 turns timing
-   off. */
+   off.  Without TYEE_KERNEL_GRAPH in the mask, timing any other kind turns graph replay off
+   so that each launch is timed; with it, replays stay on and are timed whole, and the other
+   kinds in the mask time the launches made outside a graph. */
 int tyee_sim_set_profiling(tyee_sim *sim, uint32_t kinds);
 
 /* Number of timed launches of one kernel kind and their summed duration in ms since the

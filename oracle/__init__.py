@@ -10,10 +10,10 @@ plasma-frequency averaging onto edges, source lookup by node pairs, the plane-wa
 overlap used for the dispersion metric, and the resonator modes (eigenpairs of K = -L_E L_B
 from the core's own operators and a library symmetric eigensolver).
 
-Parity unpinned: `OracleMesh.edge_wp2` (the half-dual weighted average of per-triangle plasma
-frequencies onto an edge of the particle boundary; the paper gives no rule) and the source
-waveform of the C core; both are readings shared with the library, with no independent check
-beyond the Gauss law and linearity tests that hold for any such rule.
+`OracleMesh.edge_wp2` (the half-dual weighted average of per-triangle plasma frequencies onto
+an edge of the particle boundary) and the source waveform of the C core are readings (the paper
+gives no rule for either); both are pinned by hand-derived values (a homogeneous medium, a kite
+with plasma on one side, the waveform at hand-evaluated times).
 """
 import ctypes
 import os
@@ -39,8 +39,8 @@ class OracleError(RuntimeError):
 
 def build():
     """Compile the C oracle into oracle/liborc.so."""
-    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fPIC",
-           "-shared", "-o", _LIB, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fopenmp",
+           "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
     subprocess.check_call(cmd)
     return _LIB
 
@@ -81,6 +81,8 @@ def _load():
     lib.orc_order.argtypes = [vp, ci, ctypes.c_uint64, vp, vp]
     lib.orc_splitmix64.restype = ctypes.c_uint64
     lib.orc_splitmix64.argtypes = [ctypes.c_uint64]
+    lib.orc_set_threads.argtypes = [ci]
+    lib.orc_get_threads.restype = ci
     lib.orc_morton.restype = ctypes.c_uint64
     lib.orc_morton.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     _lib = lib
@@ -89,6 +91,15 @@ def _load():
 
 def _p(a):
     return None if a is None else a.ctypes.data
+
+
+def set_threads(n):
+    """Threads of the C core's per-cell loops (its results do not depend on the count)."""
+    _load().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(_load().orc_get_threads())
 
 
 def splitmix64(x):
@@ -256,7 +267,7 @@ class OracleMesh:
 
         Each interior edge takes the half-dual-length weighted mean of its two triangles,
         (hR wp2_R + hL wp2_L)/d; outer edges carry no field and get 0 (a reading of the
-        particle boundary of Fig. 3; parity unpinned).
+        particle boundary of Fig. 3).
         """
         wt = np.asarray(wp2_tri, np.float64)
         out = np.zeros(self.ne)

@@ -10,6 +10,13 @@
  * Every routine is a scalar loop in the order the paper (or the reading noted beside it)
  * states.  Build with -O2 -ffp-contract=off so that no multiply-add is fused.
  *
+ * Threads: the per-cell loops of the stepper (each cell's new value depends only on the
+ * old values of its neighbours) are split over OpenMP threads; every cell's arithmetic and
+ * its order are the same as in one thread, so the result does not depend on the thread
+ * count.  The nodal charge is a gather per node over its edges in ascending edge order,
+ * which is the order a serial scatter over the edges would add them in.  Reductions
+ * (energies, inner products) stay serial.
+ *
  * Conventions:
  *  - coordinates (x1, x2) = (x, z); normal n = x1 x x2; B is the normal component;
  *  - triangles are made counter-clockwise by swapping v1 and v2 when needed;
@@ -22,16 +29,20 @@
  *  - dual length d_i = hR_i + hL_i, signed half lengths from the edge midpoint to the
  *    two circumcentres along the left normal of e_i (|O_R O_L| of eq. 3 on a Delaunay mesh).
  *
- * Parity unpinned: the source waveform g(t) (`waveform`): the paper does not specify its
- * source, so its values are a reading shared with the library, checked only through the
- * linearity of the response and the Gauss law with the source charge.
+ * The source waveform g(t) (`waveform`) is a reading (the paper does not specify its
+ * source); its values are pinned at hand-evaluated times through the first step of a source
+ * edge, besides the linearity of the response and the Gauss law with the source charge.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #include "oracle.h"
+
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------- */
 /* small helpers                                                              */
@@ -74,6 +85,8 @@ struct orc_mesh {
     double *O;           /* [nt][2] circumcentre (vertex 0 + local offset, not wrapped) */
     double *C;           /* [ne][2] edge midpoint x_lo + e/2 */
     uint8_t *node_bnd;   /* [nv] 1 if the node lies on an outer edge */
+    int64_t *node_off;   /* [nv + 1] edges of node k: node_edge[node_off[k] .. node_off[k+1]) */
+    int32_t *node_edge;  /* [2 ne] in ascending edge id */
 };
 
 typedef struct { int32_t lo, hi, t, q; int dir; } halfedge;
@@ -93,6 +106,7 @@ void orc_mesh_free(orc_mesh *m)
     free(m->xy); free(m->tri); free(m->edge); free(m->R); free(m->L); free(m->A);
     free(m->s); free(m->ex); free(m->ez); free(m->elen); free(m->hR); free(m->hL);
     free(m->d); free(m->S); free(m->O); free(m->C); free(m->node_bnd);
+    free(m->node_off); free(m->node_edge);
     free(m);
 }
 
@@ -249,6 +263,24 @@ orc_mesh *orc_mesh_build(const double *xy, int64_t nv, const int32_t *tri_in, in
             *status = ORC_ENOTDELAUNAY; orc_mesh_free(m); return NULL;
         }
     }
+
+    /* node -> edge incidence lists, each in ascending edge id (for the nodal charge) */
+    m->node_off = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    m->node_edge = (int32_t *)malloc(sizeof(int32_t) * 2 * ne);
+    for (int64_t i = 0; i < ne; ++i) {
+        ++m->node_off[m->edge[2 * i] + 1];
+        ++m->node_off[m->edge[2 * i + 1] + 1];
+    }
+    for (int64_t v = 0; v < nv; ++v) m->node_off[v + 1] += m->node_off[v];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * nv);
+        memcpy(fill, m->node_off, sizeof(int64_t) * nv);
+        for (int64_t i = 0; i < ne; ++i) {
+            m->node_edge[fill[m->edge[2 * i]]++] = (int32_t)i;
+            m->node_edge[fill[m->edge[2 * i + 1]]++] = (int32_t)i;
+        }
+        free(fill);
+    }
     *status = ORC_OK;
     return m;
 }
@@ -298,6 +330,7 @@ static int interior(const orc_mesh *m, int64_t i) { return m->R[i] >= 0 && m->L[
 /* (L_B B)_i = gamma_i (B_R - B_L) / d_i on interior edges, 0 on outer edges (eq. 3) */
 void orc_apply_LB(const orc_mesh *m, const double *gamma, const double *B, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m->ne; ++i) {
         if (!interior(m, i)) { out[i] = 0.0; continue; }
         double g = gamma ? gamma[i] : 1.0;
@@ -308,6 +341,7 @@ void orc_apply_LB(const orc_mesh *m, const double *gamma, const double *B, doubl
 /* (L_E E)_j = -(1/S_j) sum_q s(j,q) gamma |e| E over the three edges, q = 0, 1, 2 (eq. 4) */
 void orc_apply_LE(const orc_mesh *m, const double *gamma, const double *E, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < m->nt; ++j) {
         double acc = 0.0;
         for (int q = 0; q < 3; ++q) {
@@ -324,7 +358,7 @@ void orc_apply_LE(const orc_mesh *m, const double *gamma, const double *E, doubl
 /* ------------------------------------------------------------------------- */
 
 /* soft-source envelope g(t) = sin(omega t) sin^2(pi t / T), T = cycles 2 pi / omega, zero
-   outside [0, T) (a reading: Fig. 3's source is unspecified; parity unpinned) */
+   outside [0, T) (a reading: Fig. 3's source is unspecified) */
 static double waveform(double t, double omega, double cycles)
 {
     double T = cycles * 2.0 * M_PI / omega;
@@ -354,21 +388,23 @@ int orc_step(const orc_mesh *m, const orc_params *p, int64_t n0, int64_t nsteps,
     double *LB = (double *)malloc(sizeof(double) * ne);
     double *LE = (double *)malloc(sizeof(double) * nt);
     double *Js = (double *)calloc((size_t)ne, sizeof(double));
-    double *flux = (double *)calloc((size_t)nv, sizeof(double));
     for (int64_t k = 0; k < nsteps; ++k) {
         int64_t n = n0 + k;
         double th = ((double)n + 0.5) * dt;
-        if (media)
+        if (media) {
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < ne; ++i)
                 if (p->wp2[i] > 0.0)
                     J[i] = ((1.0 - p->nu * dt / 2.0) * J[i] + dt * p->wp2[i] * E[i])
                            / (1.0 + p->nu * dt / 2.0);
+        }
         if (source) {
             double g = waveform(th, p->src_omega, p->src_cycles);
             memset(Js, 0, sizeof(double) * ne);
             for (int64_t r = 0; r < p->n_src; ++r) Js[p->src_edge[r]] += p->src_w[r] * g;
         }
         orc_apply_LB(m, p->gamma, B, LB);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < ne; ++i) {
             if (!interior(m, i)) continue;
             double rhs = LB[i];
@@ -377,21 +413,28 @@ int orc_step(const orc_mesh *m, const orc_params *p, int64_t n0, int64_t nsteps,
             E[i] = E[i] + dt * rhs;
         }
         if (media || source) {
-            memset(flux, 0, sizeof(double) * nv);
-            for (int64_t i = 0; i < ne; ++i) {
-                double cur = (media ? J[i] : 0.0) + (source ? Js[i] : 0.0);
-                if (cur == 0.0) continue;
-                flux[m->edge[2 * i]] += m->d[i] * cur;      /* e_i leaves node lo */
-                flux[m->edge[2 * i + 1]] -= m->d[i] * cur;  /* and enters node hi */
+            /* flux of (j + Jsrc) out of node v: + d_i cur_i where e_i leaves v (v = lo),
+               - d_i cur_i where it enters (v = hi), over v's edges in ascending id */
+#pragma omp parallel for schedule(static)
+            for (int64_t v = 0; v < nv; ++v) {
+                if (m->node_bnd[v]) continue;
+                double flux = 0.0;
+                for (int64_t r = m->node_off[v]; r < m->node_off[v + 1]; ++r) {
+                    int64_t i = m->node_edge[r];
+                    double cur = (media ? J[i] : 0.0) + (source ? Js[i] : 0.0);
+                    if (cur == 0.0) continue;
+                    if (m->edge[2 * i] == v) flux += m->d[i] * cur;
+                    else                     flux -= m->d[i] * cur;
+                }
+                Q[v] = Q[v] - dt * flux;
             }
-            for (int64_t v = 0; v < nv; ++v)
-                if (!m->node_bnd[v]) Q[v] = Q[v] - dt * flux[v];
         }
         orc_apply_LE(m, p->gamma, E, LE);
         if (B_prev && k == nsteps - 1) memcpy(B_prev, B, sizeof(double) * nt);
+#pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < nt; ++j) B[j] = B[j] + dt * LE[j];
     }
-    free(LB); free(LE); free(Js); free(flux);
+    free(LB); free(LE); free(Js);
     return ORC_OK;
 }
 
@@ -426,6 +469,7 @@ void orc_div(const orc_mesh *m, const double *E, double *out)
 
 static void apply_K(const orc_mesh *m, const double *gamma, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < m->nt; ++j) {
         double acc = 0.0;
         for (int q = 0; q < 3; ++q) {

@@ -33,6 +33,9 @@ typedef struct {
 } orc_params;
 
 uint64_t orc_splitmix64(uint64_t x);
+/* threads of the per-cell loops (results do not depend on it) */
+void orc_set_threads(int n);
+int orc_get_threads(void);
 uint64_t orc_morton(uint32_t qx, uint32_t qz);
 
 orc_mesh *orc_mesh_build(const double *xy, int64_t nv, const int32_t *tri, int64_t nt,

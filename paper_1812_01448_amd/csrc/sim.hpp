@@ -222,7 +222,13 @@ struct Sim {
 
     double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
     // per-launch timing of single kernels needs eager launches (graph replays are timed whole)
-    bool timer_wants_kernels() const { return (timer.mask & ~(1u << TYEE_KERNEL_GRAPH)) != 0; }
+    // Per-launch timing of kernels that a graph would hold bypasses graph replay, unless
+    // whole replays are timed too: then replays stay on and the other kinds time only the
+    // launches made outside a graph (a remainder shorter than one graph span).
+    bool timer_wants_kernels() const {
+        const uint32_t g = 1u << TYEE_KERNEL_GRAPH;
+        return (timer.mask & ~g) != 0 && (timer.mask & g) == 0;
+    }
 };
 
 

@@ -140,8 +140,11 @@ def test_autotuner_restores_state_and_picks_a_setting(ty):
 
 @pytest.mark.slow
 def test_batch256_full_size_members(ty):
+    """The batched workload at its stated length: 256 members, 2,000 steps from graphs of 8
+    fused launches; four members bit-identical to their standalone runs and sixteen, spread
+    over the sizes, against the oracle element by element."""
     sizes = batch_lattice_sizes(256, seed=4)
-    _note(f"case: batch256 full size ({int(np.sum(2 * sizes ** 2))} triangles)")
+    _note(f"case: batch256 full size ({int(np.sum(2 * sizes ** 2))} triangles), 2,000 steps")
     mem = _members(ty, sizes, 1000)
     for m in mem:
         m["mesh"].reorder("morton")
@@ -155,18 +158,25 @@ def test_batch256_full_size_members(ty):
         batch.set_state(k, "B", B)
     batch.set_fusion(4, 0)
     batch.set_graph(8)
-    batch.step(200)
+    batch.step(2000)
+    assert batch.sim().diagnostics()["nonfinite"] == 0
     for k in (0, int(np.argmin(sizes)), int(np.argmax(sizes)), 255):
         m = mem[k]
         sim = ty.Sim(m["mesh"], m["dt"], "f32")
         E, B = _initial(m, views[k], k % 7)
         sim.set_state("E", E)
         sim.set_state("B", B)
-        sim.step(200)
+        sim.step(2000)
         assert np.array_equal(batch.get_state(k, "E"), sim.get_state("E")), k
         assert np.array_equal(batch.get_state(k, "B"), sim.get_state("B")), k
-    k = int(np.argmin(sizes))
-    om = oracle.OracleMesh(mem[k]["xy"], mem[k]["tri"], True)
-    E, B = _initial(mem[k], dict(O=om.O, C=om.C, evec=om.evec, elen=om.elen), k % 7)
-    ref = om.step(E, B, mem[k]["dt"], 200)
-    assert rel_l2(batch.get_state(k, "E"), ref["E"]) < 1e-5
+    order = np.argsort(sizes)
+    worst = 0.0
+    for k in order[np.linspace(0, 255, 16).astype(int)]:
+        om = oracle.OracleMesh(mem[k]["xy"], mem[k]["tri"], True)
+        E, B = _initial(mem[k], dict(O=om.O, C=om.C, evec=om.evec, elen=om.elen), k % 7)
+        ref = om.step(E, B, mem[k]["dt"], 2000)
+        eE = rel_l2(batch.get_state(k, "E"), ref["E"])
+        eB = rel_l2(batch.get_state(k, "B"), ref["B"])
+        worst = max(worst, eE, eB)
+        assert eE < 1e-3 and eB < 1e-3, k
+    _note(f"  16 members vs oracle after 2,000 steps: worst rel L2 {worst:.2e}")

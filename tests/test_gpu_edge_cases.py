@@ -212,9 +212,15 @@ def test_launch_timing_counts(ty):
     sim.step(48)                                  # 3 replays of 4 launches of 4 steps
     t = sim.kernel_times()
     assert set(t) == {"graph"} and t["graph"]["count"] == 3
+    # timing replays and fused launches together keeps the replays: a remainder shorter than
+    # a graph span (4 + 4 steps) runs as two fused launches outside a graph
+    sim.set_profiling(True, kinds=["graph", "fused"])
+    sim.step(40)
+    t = sim.kernel_times()
+    assert t["graph"]["count"] == 2 and t["fused"]["count"] == 2
     sim.set_profiling(False)
     sim.step(8)
-    assert sim.kernel_times() == {} and sim.steps == 10 + 40 + 48 + 8
+    assert sim.kernel_times() == {} and sim.steps == 10 + 40 + 48 + 40 + 8
     # a batch hands out its union's simulation for the same queries
     b = ty.Batch([m, m], [dt, dt], "f32")
     b.set_fusion(4, 0)

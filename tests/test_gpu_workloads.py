@@ -1,12 +1,15 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the bench times.
 
 * torus1415 (4,004,450 triangles) FP32, Morton order, default fusion: 100 steps against the
-  FP64 oracle element by element (relative L2 <= 1e-5), then 10^4 more steps checked through
-  properties that hold at any size (leap-frog energy, nodal divergence).
-* 10^4-step FP32 parity (<= 1e-3) on a reduced torus where the oracle runs in seconds.
+  FP64 oracle element by element (relative L2 <= 1e-5), then replayed from graphs of 8 fused
+  launches (the bench's configuration) to 10^4 steps, against the oracle element by element
+  (relative L2 <= 1e-3), with the leap-frog energy and the nodal divergence conserved.
+* 10^4-step FP32 parity (<= 1e-3) on a reduced torus.
 * plasma2830 (16,017,830 triangles, conforming plasma particle, soft line source) FP32: 100
-  steps against the oracle (E, B, J, Q), then 5,000 steps checked through the discrete Gauss
-  law, which holds at any size.
+  steps against the oracle (E, B, J, Q), then to 5,000 steps, again element by element (E, B,
+  J, Q), with the discrete Gauss law.
+
+The oracle's per-cell loops run on all the host threads OpenMP is given.
 """
 import sys
 
@@ -52,15 +55,21 @@ def test_torus1415_full_size_fp32(ty):
     ref = om.step(*packet_state(om, dt, n), dt, 100)
     _note(f"  rel L2 E {rel_l2(E_gpu, ref['E']):.2e} B {rel_l2(B_gpu, ref['B']):.2e}")
     assert rel_l2(E_gpu, ref["E"]) < 1e-5 and rel_l2(B_gpu, ref["B"]) < 1e-5
-    # 10^4 further steps: energy and divergence (properties valid at any size)
+    # to 10^4 steps from graphs of 8 fused launches (the bench's replay), element by element
     w0 = sim.diagnostics()["energy_h"]
     div0 = om.div(E_gpu)
-    sim.step(10000)
+    sim.set_graph(8)
+    sim.step(9900)
     d = sim.diagnostics()
-    assert d["nonfinite"] == 0
-    _note(f"  W_h drift over 10^4 steps {d['energy_h'] / w0 - 1:.2e}")
+    assert d["nonfinite"] == 0 and d["step"] == 10000
+    E_gpu, B_gpu = sim.get_state("E"), sim.get_state("B")
+    _note("  oracle: 9,900 further steps")
+    ref = om.step(ref["E"], ref["B"], dt, 9900, n0=100)
+    eE, eB = rel_l2(E_gpu, ref["E"]), rel_l2(B_gpu, ref["B"])
+    _note(f"  10^4 steps: rel L2 E {eE:.2e} B {eB:.2e}; W_h drift {d['energy_h'] / w0 - 1:.2e}")
+    assert eE < 1e-3 and eB < 1e-3
     assert abs(d["energy_h"] / w0 - 1) < 1e-4
-    div1 = om.div(sim.get_state("E"))
+    div1 = om.div(E_gpu)
     assert np.max(np.abs(div1 - div0)) < 1e-4 * np.max(np.abs(div0)) + 1e-6
 
 
@@ -116,20 +125,28 @@ def test_plasma2830_full_size_fp32(ty):
     assert np.max(np.abs(ref["J"])) > 0 and np.max(np.abs(ref["Q"])) > 0
     for f, e in errs.items():
         assert e < 1e-5, f
-    del om, ref
-    # 5,000 further steps: (D E - Q) stays at its initial value (continuity, any size)
-    sim.step(5000)
+    # to 5,000 steps: element by element again, and (D E - Q) stays at its initial value
+    sim.step(4900)
     d = sim.diagnostics()
-    assert d["nonfinite"] == 0
+    assert d["nonfinite"] == 0 and d["step"] == 5000
+    got = {f: sim.get_state(f) for f in ("E", "B", "J", "Q")}
+    _note("  oracle: 4,900 further steps")
+    ref = om.step(ref["E"], ref["B"], dt, 4900, n0=100, J=ref["J"], Q=ref["Q"],
+                  wp2=om.edge_wp2(w["wp2_tri"]), nu=w["nu"], src=src)
+    errs = {f: rel_l2(got[f], ref[f]) for f in got}
+    _note("  5,000 steps: rel L2 " + " ".join(f"{f} {e:.2e}" for f, e in errs.items()))
+    for f, e in errs.items():
+        assert e < 1e-3, f
+    del om, ref
     g1 = sim.gauss()
     # scale: the largest nodal sum of |d E| (the terms FP32 rounds), and the charge itself
-    E1 = sim.get_state("E")
+    E1 = got["E"]
     mag = np.zeros(len(g1))
     np.add.at(mag, v["edge_nodes"][:, 0], np.abs(v["d"] * E1))
     np.add.at(mag, v["edge_nodes"][:, 1], np.abs(v["d"] * E1))
-    Q1 = sim.get_state("Q")
+    Q1 = got["Q"]
     res = np.max(np.abs(g1 - g0))
-    _note(f"  Gauss-law residual after 5,100 steps {res:.3e} (max nodal |d E| sum "
+    _note(f"  Gauss-law residual after 5,000 steps {res:.3e} (max nodal |d E| sum "
           f"{np.max(mag):.3e}, max |Q| {np.max(np.abs(Q1)):.3e})")
     assert np.max(np.abs(Q1)) > 1e-2 * np.max(mag)      # the charge is not negligible
     assert res < 1e-3 * np.max(mag)

@@ -357,3 +357,96 @@ def test_orderings_are_bijections_with_expected_locality(periodic):
     assert bandwidth(sm, pt) == 1
     deg = (sm.interior[sm.A]).sum(1)
     assert deg[pt[0]] == 1 and deg[pt[-1]] == 1
+
+
+def kite():
+    # two isosceles triangles on the base P(0,-1) - Q(0,1): apex A(-2, 0) on the left, B(3, 0)
+    # on the right.  Circumcentres lie on the x axis at (1 - a^2)/(2a) from the base for apex
+    # distance a: O_A = (-3/4, 0), O_B = (4/3, 0); the base runs P -> Q counter-clockwise
+    # around PQA, so R(PQ) = PQA with hR = 3/4, L(PQ) = PBQ with hL = 4/3, d = 25/12
+    xy = np.array([[0.0, -1.0], [0.0, 1.0], [-2.0, 0.0], [3.0, 0.0]])
+    tri = np.array([[0, 1, 2], [0, 3, 1]], np.int32)
+    return xy, tri
+
+
+def test_edge_plasma_frequency_rule_hand_derived():
+    """The per-edge plasma frequency squared (eq. 5 on edges): every interior edge of a
+    homogeneous medium carries the medium's value; the base of the kite, with plasma on one
+    side only, carries wp2 times that side's half dual length over d."""
+    xy, tri = kite()
+    m = oracle.OracleMesh(xy, tri, periodic=False, L=5.0)
+    assert m.edge[0].tolist() == [0, 1] and (m.R[0], m.L[0]) == (0, 1)
+    np.testing.assert_allclose([m.hR[0], m.hL[0], m.d[0]], [0.75, 4 / 3, 25 / 12], rtol=1e-14)
+    np.testing.assert_allclose(m.edge_wp2([0.64, 0.0]), [0.64 * 9 / 25, 0, 0, 0, 0], rtol=1e-14)
+    np.testing.assert_allclose(m.edge_wp2([0.0, 0.64]), [0.64 * 16 / 25, 0, 0, 0, 0], rtol=1e-14)
+    np.testing.assert_allclose(m.edge_wp2([0.64, 0.64]), [0.64, 0, 0, 0, 0], rtol=1e-14)
+    for periodic in (True, False):
+        xy, tri = lattice_mesh(16, 0.25, 8, periodic=periodic)
+        m = oracle.OracleMesh(xy, tri, periodic=periodic)
+        w = m.edge_wp2(np.full(m.nt, 0.64))
+        i = m.interior
+        # (hR c + hL c) / d rounds with an error of a few ulps of c (|hR| + |hL|) / d, large
+        # where hR and hL nearly cancel (near-cocircular quads)
+        bound = 4 * np.finfo(float).eps * 0.64 * (np.abs(m.hR[i]) + np.abs(m.hL[i])) / m.d[i]
+        assert np.all(np.abs(w[i] - 0.64) <= bound)
+        assert np.all(w[~m.interior] == 0.0)
+
+
+def test_source_waveform_values_hand_evaluated():
+    """The soft source J = w g(t) with g(t) = sin(omega t) sin^2(pi t / T), T = cycles 2 pi /
+    omega, and g = 0 outside [0, T): with B = 0 and E = 0 one step gives E^1 = -dt w g(dt/2) on
+    the source edge (eq. 6 with the source term), so the first step reads g at t = dt / 2."""
+    xy, tri = rhombus()
+    m = oracle.OracleMesh(xy, tri, periodic=False, L=2.0)
+    z_e, z_b = np.zeros(m.ne), np.zeros(m.nt)
+
+    def first_step(dt, pair, w, n0=0):
+        return m.step(z_e, z_b, dt, 1, n0=n0, src=(np.array([pair]), np.array([w]), 1.0, 10))["E"]
+
+    # t = pi/2 (omega = 1, T = 20 pi): g = sin^2(pi / 40)
+    e = first_step(np.pi, [1, 2], 1.0)
+    assert e[2] == pytest.approx(-np.pi * np.sin(np.pi / 40) ** 2, rel=1e-14)
+    assert np.all(np.delete(e, 2) == 0.0)
+    # the weight follows the direction the pair is given in: 2 -> 1 is against e (1 -> 2)
+    e = first_step(np.pi, [2, 1], 2.0)
+    assert e[2] == pytest.approx(2 * np.pi * np.sin(np.pi / 40) ** 2, rel=1e-14)
+    # t = 19 pi / 2: sin(omega t) = -1, g = -sin^2(19 pi / 40)
+    e = first_step(19 * np.pi, [1, 2], 1.0)
+    assert e[2] == pytest.approx(19 * np.pi * np.sin(19 * np.pi / 40) ** 2, rel=1e-13)
+    # t = T (the pulse has ended) and t < 0 (not started): no source
+    assert np.all(first_step(40 * np.pi, [1, 2], 1.0) == 0.0)
+    assert np.all(first_step(1.0, [1, 2], 1.0, n0=-1) == 0.0)
+    # n0 shifts the time: step n0 reads g at (n0 + 1/2) dt
+    e = first_step(np.pi / 3, [1, 2], 1.0, n0=1)
+    assert e[2] == pytest.approx(-np.pi / 3 * np.sin(np.pi / 40) ** 2, rel=1e-14)
+
+
+def test_threaded_oracle_is_bit_identical_to_one_thread():
+    """Every per-cell update keeps its arithmetic and order under OpenMP, and the nodal charge
+    is a per-node gather in ascending edge order: the thread count changes no bit."""
+    from meshgen import triangle_particle_mask, line_source_pairs
+    xy, tri = lattice_mesh(40, 0.25, 21, periodic=True)
+    m = oracle.OracleMesh(xy, tri, periodic=True)
+    chi = triangle_particle_mask(xy, tri, True, side=0.5, center=(0.6, 0.5))
+    wp2 = m.edge_wp2(0.64 * chi)
+    pairs, w = line_source_pairs(xy, tri, True, 1.0, 1 / 40, x0=0.2, z0=0.25, z1=0.75)
+    dt = 0.5 * 2 / np.sqrt(m.power()[0])
+    rng = np.random.default_rng(5)
+    E0, B0 = rng.standard_normal(m.ne), rng.standard_normal(m.nt)
+    gamma = 1 + 0.05 * rng.standard_normal(m.ne)
+    kw = dict(wp2=wp2, nu=0.05, src=(pairs, w, 1.0 / dt / 50, 2), gamma=gamma, want_prev=True)
+    before = oracle.get_threads()
+    try:
+        oracle.set_threads(1)
+        a = m.step(E0, B0, dt, 60, **kw)
+        pa = m.power(gamma=gamma)
+        oracle.set_threads(max(4, before))
+        assert oracle.get_threads() >= 4
+        b = m.step(E0, B0, dt, 60, **kw)
+        pb = m.power(gamma=gamma)
+    finally:
+        oracle.set_threads(before)
+    for k in ("E", "B", "J", "Q", "B_prev"):
+        assert np.array_equal(a[k], b[k]), k
+    assert pa == pb
+    assert np.max(np.abs(a["Q"])) > 0
