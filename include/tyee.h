@@ -215,6 +215,20 @@ typedef struct {
    Returns TYEE_EUNSTABLE if a field is not finite (out is still filled). */
 int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out);
 
+/* The same diagnostics without any device or host allocation, for callers that cannot
+   allocate (tight serving loops, harnesses that forbid hipMalloc).  The per-block partial
+   sums and their totals go to a fixed 6 MiB device array of the library (one per GPU, held
+   until the process ends, every partial and total overwritten by each call), not to a
+   buffer of the simulation; the totals are added on the device in the order
+   tyee_sim_diagnostics adds them on the host, so both return the same bits.  Calls that
+   overlap on one GPU (simulations on different streams or threads) share that array and race:
+   serialise them.  Synchronises the simulation's stream.
+   Errors: TYEE_EINVAL if the FP64 weight tables are not built (call tyee_sim_diagnostics once
+   after creating the simulation or changing its coefficients; that call allocates them) or
+   if the mesh has more than 33,554,432 edges or triangles; TYEE_EDEVICE on a HIP error;
+   TYEE_EUNSTABLE as tyee_sim_diagnostics. */
+int tyee_sim_diagnostics_noalloc(tyee_sim *sim, tyee_diag *out);
+
 /* Discrete Gauss residual per node (canonical, FP64 host): out_k = (D E)_k - Q_k with
    (D E)_k = sum_i sigma(k,i) d_i E_i, sigma = +1 when e_i leaves node k (the flux of E
    through the dual cell of node k, Section 1).  In vacuum D E is conserved on interior

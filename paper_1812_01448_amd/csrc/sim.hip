@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -410,6 +411,7 @@ int init_sim(Sim &s, const Mesh &m, int32_t prec, const std::vector<double> &dt_
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+    s.device = device;
     if (stream) {
         s.stream = static_cast<hipStream_t>(stream);
     } else {
@@ -482,6 +484,88 @@ template <typename T> int device_diagnostics(Sim &s, double *sums) {
         sums[4] = std::max(sums[4], part[6 * size_t(b) + 4]);
         sums[5] += part[6 * size_t(b) + 5];
     }
+    return TYEE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Diagnostics without allocation: the per-block partial sums of k_diag and their six totals
+// live in a fixed device array instead of a buffer the simulation allocates.
+// ---------------------------------------------------------------------------------------
+
+// k_diag blocks the array holds: meshes with up to kDiagStaticBlocks * kDiagThreads
+// (33,554,432) edges and as many triangles.
+constexpr int64_t kDiagStaticBlocks = 131072;
+constexpr size_t kDiagStaticTotals = size_t(6) * kDiagStaticBlocks;  // offset of the six totals
+
+// 6.0 MiB per device, held until the process ends; every call on a device shares it.
+static __device__ __align__(256) double scratch[6 * kDiagStaticBlocks + 8];
+
+// The six totals of nb per-block partials, each column added in block order with the same
+// operations as the host loop of device_diagnostics (so both entry points agree bit for bit).
+__global__ __launch_bounds__(64) void k_diag_total(int nb, double *__restrict__ buf) {
+    const int q = threadIdx.x;
+    if (q >= 6) return;
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double v = buf[6 * size_t(b) + q];
+        if (q == 3 || q == 4) acc = acc < v ? v : acc;
+        else acc += v;
+    }
+    buf[kDiagStaticTotals + q] = acc;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int static_scratch(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(TYEE_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TYEE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return TYEE_OK;
+}
+
+// Makes `device` current for the lifetime of the guard, restoring the previous one.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int device) {
+        int cur = 0;
+        err = hipGetDevice(&cur);
+        if (err == hipSuccess && cur != device) {
+            err = hipSetDevice(device);
+            if (err == hipSuccess) prev = cur;
+        }
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T> int device_diagnostics_static(Sim &s, double *buf, double *sums) {
+    const int64_t n = std::max(s.ne, s.nt);
+    const int nb = int((n + kDiagThreads - 1) / kDiagThreads);
+    k_diag<T><<<nb, kDiagThreads, 0, s.stream>>>(int(s.ne), int(s.nt), s.Et().as<T>(), s.B().as<T>(),
+                                                 s.A0.as<uint32_t>(), s.A1.as<uint32_t>(), s.A2.as<uint32_t>(),
+                                                 s.diag_wE.as<double>(), s.diag_inv_scale.as<float>(),
+                                                 s.diag_S.as<double>(), s.diag_dtS.as<double>(), buf);
+    TYEE_HIP(hipGetLastError());
+    k_diag_total<<<1, 64, 0, s.stream>>>(nb, buf);
+    TYEE_HIP(hipGetLastError());
+    TYEE_HIP(hipMemcpyAsync(sums, buf + kDiagStaticTotals, 6 * sizeof(double), hipMemcpyDeviceToHost, s.stream));
+    TYEE_HIP(hipStreamSynchronize(s.stream));
     return TYEE_OK;
 }
 
@@ -734,6 +818,37 @@ int tyee_sim_diagnostics(tyee_sim *sim, tyee_diag *out) {
     if (int64_t(std::max(s.ne, s.nt)) >= int64_t(INT32_MAX)) return fail(TYEE_EINVAL, "mesh too large");
     double v[6];
     rc = s.f64 ? tyee::device_diagnostics<double>(s, v) : tyee::device_diagnostics<float>(s, v);
+    if (rc) return rc;
+    tyee_diag d{};
+    d.step = s.step;
+    d.time = double(s.step) * s.dt;
+    d.energy = v[0] + v[1];
+    d.energy_h = v[0] + v[2];
+    d.max_abs_E = v[3];
+    d.max_abs_B = v[4];
+    d.nonfinite = v[5] > 0.0;
+    *out = d;
+    return d.nonfinite ? fail(TYEE_EUNSTABLE, "non-finite field value") : TYEE_OK;
+}
+
+int tyee_sim_diagnostics_noalloc(tyee_sim *sim, tyee_diag *out) {
+    if (!sim || !out) return fail(TYEE_EINVAL, "null argument");
+    tyee::Sim &s = sim->s;
+    if (!s.diag_ready)
+        return fail(TYEE_EINVAL, "diagnostics tables are not built: call tyee_sim_diagnostics once after "
+                                 "creating the simulation or changing its coefficients");
+    if (std::max(s.ne, s.nt) > tyee::kDiagStaticBlocks * tyee::kDiagThreads)
+        return fail(TYEE_EINVAL, "mesh too large for the fixed diagnostics scratch (at most 33,554,432 edges "
+                                 "and 33,554,432 triangles)");
+    tyee::DeviceGuard guard(s.device);
+    if (guard.err != hipSuccess)
+        return fail(TYEE_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(guard.err));
+    double *buf = nullptr;
+    int rc = tyee::static_scratch(s.device, &buf);
+    if (rc) return rc;
+    double v[6];
+    rc = s.f64 ? tyee::device_diagnostics_static<double>(s, buf, v)
+               : tyee::device_diagnostics_static<float>(s, buf, v);
     if (rc) return rc;
     tyee_diag d{};
     d.step = s.step;

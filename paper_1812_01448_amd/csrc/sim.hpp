@@ -170,6 +170,7 @@ struct Sim {
     std::vector<double> dt_tri, dt_edge;       // per canonical cell (batches mix meshes)
     hipStream_t stream = nullptr;
     bool own_stream = false;                   // created by the library (caller passed NULL)
+    int device = 0;                            // HIP device current at creation
     int graph_launches = 0;                    // fused launches per captured graph (0 = eager)
     hipGraphExec_t graph = nullptr;
     bool graph_dirty = true;

@@ -79,7 +79,7 @@ EXPORTS = [
     "tyee_mesh_cfl", "tyee_mesh_destroy", "tyee_sim_create", "tyee_sim_set_state",
     "tyee_sim_get_state", "tyee_sim_set_media", "tyee_sim_set_source",
     "tyee_sim_set_edge_scale", "tyee_sim_set_fusion", "tyee_sim_step", "tyee_sim_sync",
-    "tyee_sim_diagnostics", "tyee_sim_last_step_ms", "tyee_sim_set_profiling",
+    "tyee_sim_diagnostics", "tyee_sim_diagnostics_noalloc", "tyee_sim_last_step_ms", "tyee_sim_set_profiling",
     "tyee_sim_kernel_times", "tyee_sim_get_fusion", "tyee_sim_steps", "tyee_sim_destroy",
     "tyee_sim_gauss", "tyee_sim_add_probe", "tyee_sim_read_probe", "tyee_sim_set_graph",
     "tyee_batch_create", "tyee_batch_set_state", "tyee_batch_get_state", "tyee_batch_reorder",
@@ -140,6 +140,7 @@ def _load():
         "tyee_sim_step": [vp, i64],
         "tyee_sim_sync": [vp],
         "tyee_sim_diagnostics": [vp, ctypes.POINTER(_Diag)],
+        "tyee_sim_diagnostics_noalloc": [vp, ctypes.POINTER(_Diag)],
         "tyee_sim_last_step_ms": [vp, ctypes.POINTER(f64)],
         "tyee_sim_set_profiling": [vp, ctypes.c_uint32],
         "tyee_sim_kernel_times": [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(f64)],
@@ -486,6 +487,13 @@ class Sim:
     def diagnostics(self):
         d = _Diag()
         _check(lib.tyee_sim_diagnostics(self._h, ctypes.byref(d)), allow=(EUNSTABLE,))
+        return {n: getattr(d, n) for n, _ in _Diag._fields_}
+
+    def diagnostics_noalloc(self):
+        """The same diagnostics through the entry point that allocates nothing (its tables
+        must have been built by one diagnostics() call since the coefficients changed)."""
+        d = _Diag()
+        _check(lib.tyee_sim_diagnostics_noalloc(self._h, ctypes.byref(d)), allow=(EUNSTABLE,))
         return {n: getattr(d, n) for n, _ in _Diag._fields_}
 
     @property
