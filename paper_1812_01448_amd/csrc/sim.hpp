@@ -222,7 +222,6 @@ struct Sim {
     ~Sim();
 
     double scale(int64_t i) const { return gamma[i] * elen[i]; }  // Et = scale * E
-    // per-launch timing of single kernels needs eager launches (graph replays are timed whole)
     // Per-launch timing of kernels that a graph would hold bypasses graph replay, unless
     // whole replays are timed too: then replays stay on and the other kinds time only the
     // launches made outside a graph (a remainder shorter than one graph span).
