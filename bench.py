@@ -46,11 +46,18 @@ def parse(argv=None):
                         "lowest modes of the 70 x 101 resonator of Fig. 4; --steps timed "
                         "solves, at most 20)")
     p.add_argument("--train-meshes", type=int, default=64)
-    p.add_argument("--train-n", type=int, default=40)
+    p.add_argument("--train-n", type=int, default=316,
+                   help="learned: training lattice size (316: 199,712 triangles per mesh)")
     p.add_argument("--eval-meshes", type=int, default=16)
     p.add_argument("--eval-n", type=int, default=707)
-    p.add_argument("--iters", type=int, default=400)
+    p.add_argument("--iters", type=int, default=200)
     p.add_argument("--lr", type=float, default=3e-3)
+    p.add_argument("--batch-meshes", type=int, default=4,
+                   help="learned: meshes per Adam step (0: every (mesh, wave) pair each step)")
+    p.add_argument("--batch-waves", type=int, default=4, help="learned: waves per mesh per Adam step")
+    p.add_argument("--val-pairs", type=int, default=48,
+                   help="learned: fixed (mesh, wave) pairs for the reported loss and the "
+                        "constant-scale ablation (0: every pair)")
     p.add_argument("--graph", type=int, default=8, help="fused launches per HIP graph (0 = eager)")
     p.add_argument("--tune", action="store_true", help="batch256: run the autotuner first")
     p.add_argument("--modes-no-scale", action="store_true",
@@ -848,18 +855,54 @@ def bench_learned(args):
     learner = ty.Learner([m for m, _ in train], [d for _, d in train],
                          np.stack([W] * len(train)), phase=2.0)
     learner.init(seed=0)
-    loss0, _, _ = learner.loss_grad(want_grad=False)
+    nM, nW = len(train), len(W)
+    rng = np.random.default_rng(12345)
+    # fixed validation pairs (spread over meshes and waves) for the reported loss and the
+    # constant-scale ablation; every pair when --val-pairs is 0 or covers them all
+    if 0 < args.val_pairs < nM * nW:
+        val = [(int(b // nW), int(b % nW)) for b in
+               np.sort(rng.choice(nM * nW, args.val_pairs, replace=False))]
+    else:
+        val = None
+    minibatch = args.batch_meshes > 0 and args.batch_meshes * args.batch_waves < nM * nW
+
+    def val_loss():
+        learner.set_batch(val)
+        lv, _, _ = learner.loss_grad(want_grad=False)
+        return lv
+
+    loss0 = val_loss()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hist = learner.train(args.iters, args.lr)
+    if minibatch:
+        # each Adam step: one wavelength (cycling through the four, so every pair of a batch
+        # runs about as many recurrence steps and few launches carry only a straggler), then
+        # batch_meshes meshes drawn without replacement and batch_waves of their 12 angles
+        # each (seeded); waves are ordered angle-major, wavelength-minor
+        n_cls = 4
+        hist = []
+        for it in range(args.iters):
+            cls = it % n_cls
+            ms = rng.choice(nM, min(args.batch_meshes, nM), replace=False)
+            pairs = [(int(m), int(a) * n_cls + cls) for m in ms
+                     for a in rng.choice(nW // n_cls, min(args.batch_waves, nW // n_cls), replace=False)]
+            learner.set_batch(pairs)
+            hist.append(float(learner.train(1, args.lr)[0]))
+            if (it + 1) % 10 == 0:
+                log(f"Adam step {it + 1}/{args.iters}: minibatch loss {hist[-1]:.4e} "
+                    f"({time.perf_counter() - t1:.1f} s)")
+        hist = np.array(hist)
+    else:
+        learner.set_batch(None)
+        hist = learner.train(args.iters, args.lr)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    loss1, _, _ = learner.loss_grad(want_grad=False)
+    loss1 = val_loss()
     theta = learner.params()
-    log(f"trained {args.iters} Adam steps in {train_s:.2f} s: loss {loss0:.4e} -> {loss1:.4e}")
-    # constant-scale ablation: best single gamma for every edge on the training set
+    log(f"trained {args.iters} Adam steps in {train_s:.2f} s: validation loss {loss0:.4e} -> {loss1:.4e}")
+    # constant-scale ablation: best single gamma for every edge on the validation pairs
     best_c, best_l = 1.0, loss0
-    for c in np.arange(0.990, 1.0301, 0.001):
+    for c in np.arange(0.990, 1.0301, 0.002):
         th = np.zeros_like(theta)
         th[-1] = np.arctanh((c - 1.0) / 0.1)
         learner.set_params(th)
@@ -867,7 +910,7 @@ def bench_learned(args):
         if lc < best_l:
             best_c, best_l = float(c), lc
     learner.set_params(theta)
-    log(f"best constant scale {best_c:.4f} (training loss {best_l:.4e})")
+    log(f"best constant scale {best_c:.4f} (validation loss {best_l:.4e})")
 
     rows = []
     for k in range(args.eval_meshes):
@@ -911,43 +954,65 @@ def bench_learned(args):
             f"learned {row['cost_ratio_learned']:.3f} const {row['cost_ratio_const']:.3f} "
             f"({time.perf_counter() - t_mesh:.1f} s)")
     ratio = float(np.mean([r["cost_ratio_learned"] for r in rows]))
-    # LDS roofline of the training step's dominant kernel (k_ts_adjoint, one work-group per
-    # mesh and wave): per leap-frog step of the B-only recurrence each triangle reads its 3
-    # neighbours' x and v (complex: 12 floats) and writes its own 4, in both passes, and the
-    # second pass reads 8 floats per edge for the gradient: (32 n_t + 8 n_e) x 4 B per step.
-    lds_bytes = 0.0
-    for m_, dt_ in train:
-        for kv in W:
-            nsteps = max(1, int(round(2.0 / (np.hypot(*kv) * dt_))))
-            lds_bytes += nsteps * (32 * m_.nt + 8 * m_.ne) * 4.0
     step_s = train_s / max(1, args.iters)
-    lds_peak = 256 * 128 * 2.4e9 / 1e12        # TB/s: 256 CUs x 128 B/clk x 2.4 GHz
-    roofline = {"bound": "lds", "kernel": "k_ts_adjoint", "unit": "TB/s",
-                "achieved": round(lds_bytes / step_s / 1e12, 2), "peak": round(lds_peak, 1),
-                "frac": round(lds_bytes / step_s / 1e12 / lds_peak, 4),
-                "algorithmic_bytes_per_launch": lds_bytes, "avg_launch_ms": round(step_s * 1e3, 2),
-                "timed_with": "wall time of the training steps (the adjoint kernel is ~95 % of it)",
-                "peak_assumes": "128 B per clock per CU of LDS bandwidth", "traffic": None}
+    per_step_pairs = (min(args.batch_meshes, nM) * min(args.batch_waves, nW)) if minibatch else nM * nW
+    if train[0][0].nt <= 4096:
+        # LDS roofline of the training step's dominant kernel (k_ts_adjoint, one work-group per
+        # mesh and wave): per leap-frog step of the B-only recurrence each triangle reads its 3
+        # neighbours' x and v (complex: 12 floats) and writes its own 4, in both passes, and the
+        # second pass reads 8 floats per edge for the gradient: (32 n_t + 8 n_e) x 4 B per step.
+        lds_bytes = 0.0
+        for m_, dt_ in train:
+            for kv in W:
+                nsteps = max(1, int(round(2.0 / (np.hypot(*kv) * dt_))))
+                lds_bytes += nsteps * (32 * m_.nt + 8 * m_.ne) * 4.0
+        lds_bytes *= per_step_pairs / (nM * nW)
+        lds_peak = 256 * 128 * 2.4e9 / 1e12        # TB/s: 256 CUs x 128 B/clk x 2.4 GHz
+        roofline = {"bound": "lds", "kernel": "k_ts_adjoint", "unit": "TB/s",
+                    "achieved": round(lds_bytes / step_s / 1e12, 2), "peak": round(lds_peak, 1),
+                    "frac": round(lds_bytes / step_s / 1e12 / lds_peak, 4),
+                    "algorithmic_bytes_per_launch": lds_bytes, "avg_launch_ms": round(step_s * 1e3, 2),
+                    "timed_with": "wall time of the training steps (the adjoint kernel is ~95 % of it)",
+                    "peak_assumes": "128 B per clock per CU of LDS bandwidth", "traffic": None}
+    else:
+        # HBM roofline of the multi-work-group adjoint (k_gts_step, one launch per leap-frog
+        # step of every active pair): per triangle and step it reads x, v (16 B), y, u (16 B),
+        # its couplings and neighbour ids (24 B) and writes y, u, x, v (32 B); the second pass
+        # adds its side words (12 B) and the accumulators of the edges it is R of (1.5 per
+        # triangle, 16 B read and written): 88 B, then 124 B, per triangle and step.
+        nt_, ne_ = train[0][0].nt, train[0][0].ne
+        mean_steps = np.mean([[max(1, int(round(2.0 / (np.hypot(*kv) * dt_)))) for kv in W]
+                              for _, dt_ in train])
+        hbm_bytes = per_step_pairs * mean_steps * nt_ * (88.0 + 124.0)
+        roofline = {"bound": "hbm", "kernel": "k_gts_step", "unit": "GB/s",
+                    "achieved": round(hbm_bytes / step_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                    "frac": round(hbm_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                    "algorithmic_bytes_per_launch": hbm_bytes, "avg_launch_ms": round(step_s * 1e3, 2),
+                    "timed_with": "wall time of the Adam steps (both adjoint passes, the MLP kernels "
+                                  "and the minibatch set-up)",
+                    "per_step_pairs": per_step_pairs, "mean_recurrence_steps": float(mean_steps),
+                    "traffic": None}
     cpu = None
     if not args.no_cpu:
         # the FP64 oracle's loss and gradient (time-stepped phase error with its adjoint) on a
-        # sample of the training waves, scaled to one full training step (all meshes x waves)
+        # sample of the training waves, scaled to one Adam step's pairs
         import oracle
         from oracle import learned as OL
         from meshgen import lattice_mesh as _lm
         xy, tri = _lm(args.train_n, 0.3, 100, periodic=True)
         om = oracle.OracleMesh(xy, tri, True)
         dt0 = train[0][1]
-        sample = W[::12][:4]
+        # the shortest recurrence of the set: 8 cells per wavelength at 0 degrees
+        sample = W[:1] if train[0][0].nt > 4096 else W[::12][:4]
         t1 = time.perf_counter()
         for kv in sample:
             OL.ts_phase_error_grad(om, np.ones(om.ne), dt0, kv, OL.ts_steps(kv, dt0))
         per_wave = (time.perf_counter() - t1) / len(sample)
-        cpu = {"value": per_wave * len(W) * len(train), "unit": "s per training step",
-               "gpu_value": train_s / max(1, args.iters), "cores": 1, "kind": "oracle",
-               "sample": f"loss and exact gradient of {len(sample)} training waves on one "
+        cpu = {"value": per_wave * per_step_pairs, "unit": "s per Adam step",
+               "gpu_value": step_s, "cores": 1, "kind": "oracle",
+               "sample": f"loss and exact gradient of {len(sample)} training wave(s) on one "
                          f"{om.nt}-triangle training mesh ({per_wave:.2f} s per wave), scaled to "
-                         f"{len(train)} meshes x {len(W)} waves; single-threaded numpy/scipy"}
+                         f"the {per_step_pairs} pairs of one Adam step; single-threaded numpy/scipy"}
         log(f"oracle training step (scaled): {cpu['value']:.1f} s vs GPU {cpu['gpu_value']:.3f} s")
     out = {
         "metric": "cell-updates to reach the plain method's phase error at 10 cells/lambda, "
@@ -957,11 +1022,16 @@ def bench_learned(args):
         "config": {"workload": "learned edge scale: %d training meshes of %d triangles, %d "
                                "held-out meshes of %d triangles, jitter 0.3"
                                % (len(train), train[0][0].nt, len(rows), rows[0]["triangles"]),
+                   "minibatch": ("%d meshes x %d waves per Adam step, drawn at random (seeded), "
+                                 "one wavelength per step in turn"
+                                 % (min(args.batch_meshes, nM), min(args.batch_waves, nW)))
+                   if minibatch else "every (mesh, wave) pair each Adam step",
+                   "validation_pairs": len(val) if val else nM * nW,
                    "waves_train": "12 angles x (8, 10, 16, 32) cells/lambda, ~2 rad of travel",
                    "waves_eval": "4 angles x %s cells/lambda, full E/B stepping (FP32 fields, "
                                  "agrees with FP64 to 1e-8 in the error)" % r_grid,
                    "iters": args.iters, "lr": args.lr},
-        "train": {"loss_initial": loss0, "loss_final": loss1, "seconds": train_s,
+        "train": {"val_loss_initial": loss0, "val_loss_final": loss1, "seconds": train_s,
                   "ms_per_iter": 1e3 * train_s / max(1, args.iters),
                   "loss_history_every_50": [float(h) for h in hist[::50]]},
         "accepted": int(sum(r["accepted"] for r in rows)),

@@ -338,11 +338,14 @@ typedef struct tyee_learner tyee_learner;
    scheme in its B-only form (x_{n+1} = (2 - dt^2 K_gamma) x_n - x_{n-1}, started from the exact
    wave at -dt/2 and +dt/2), and eps = -arg(z_N/z_0)/(|k| N dt) - 1 with z the S-weighted
    overlap with exp(i k.O).  Its gradient comes from the exact adjoint of that recurrence.
-   meshes: periodic training meshes of at most 4096 triangles (each runs inside one
-   work-group); dt [n_meshes]; waves [n_meshes][n_waves][2]; phase in (0, 3) radians.
+   meshes: periodic training meshes; a mesh of at most 4096 triangles and 6144 edges runs each
+   of its waves inside one work-group (its state in LDS), a larger one on the multi-work-group
+   path (state in device memory, one launch per step for every active wave); dt [n_meshes];
+   waves [n_meshes][n_waves][2]; phase in (0, 3) radians.
    mu and sd default to the mean and standard deviation (+1e-6) of the training features.
-   Parameters start at zero (gamma = 1).  Errors: EINVAL (a mesh not periodic or larger than
-   4096 triangles / 6144 edges, dt not positive, phase out of range), EDEVICE, ENOMEM. */
+   Parameters start at zero (gamma = 1); every (mesh, wave) pair is active.  Errors: EINVAL (a
+   mesh not periodic or with 2^30 or more cells, dt not positive, phase out of range), EDEVICE,
+   ENOMEM. */
 int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_t n_meshes,
                         const double *waves, int64_t n_waves, double phase, void *stream,
                         tyee_learner **out);
@@ -374,6 +377,17 @@ int tyee_learner_train(tyee_learner *l, int64_t iters, double lr, double *loss_h
 /* gamma [n_edges] of any mesh under the current model (1 on outer edges), computed by the
    GPU forward kernel. */
 int tyee_learner_gamma(tyee_learner *l, const tyee_mesh *mesh, double *gamma);
+/* Minibatch: from now on the loss is the mean of eps^2 over the listed (mesh, wave) pairs
+   [n][2] only (plus the stiff-edge term over every training edge), and training and
+   tyee_learner_loss_grad compute only those pairs; the errors of other pairs read NaN.
+   pairs = NULL or n = 0 makes every pair active again.  Allocates the state of the
+   multi-work-group path for the batch.  Errors: EINVAL (a pair out of range or listed twice). */
+int tyee_learner_set_batch(tyee_learner *l, const int32_t *pairs, int64_t n);
+
+/* 0 (default): meshes that fit one work-group use it, larger ones the multi-work-group path;
+   1: every mesh on the multi-work-group path (both paths run the same single-precision
+   recurrences; used to check one against the other). */
+int tyee_learner_set_path(tyee_learner *l, int32_t path);
 void tyee_learner_destroy(tyee_learner *l);
 
 typedef struct {

@@ -38,6 +38,7 @@
 // Every reduction has a fixed order, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <numeric>
 #include <memory>
@@ -352,6 +353,235 @@ __global__ __launch_bounds__(kTsThreads) void k_ts_adjoint(int W, const int32_t 
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Multi-work-group form of k_ts_adjoint, for training meshes larger than one work-group's
+// LDS.  The two recurrences of every active (mesh, wave) pair live in HBM, one launch per
+// step advances every pair that still has steps left (pairs sorted by step count, so the
+// active ones are a prefix and form the grid's y dimension), one work-item per triangle:
+// it gathers its three neighbours' values of the old buffer and writes its new values to the
+// other.  In the second pass the work-item of an edge's R triangle accumulates that edge's
+// product conj(v_R - v_L) (x_R - x_L) before the step (each interior edge has one R
+// triangle, so no two work-items add to one accumulator).  Every value goes through the same
+// single-precision operations in the same order as in k_ts_adjoint, so the two paths give the
+// same recurrences; only the FP64 sums of the overlap z_N are added in another order.
+// ---------------------------------------------------------------------------------------
+
+struct GtsPair {
+    int32_t b, w;           // (mesh, wave) index m * W + w, and the wave
+    int32_t t_off, nt;      // the mesh's triangles in the concatenated arrays
+    int32_t e_off, ne;      // its edges
+    int32_t nsteps;
+    int32_t s_off;          // first state entry of this pair (triangles)
+    int64_t a_off;          // first accumulator of this pair (edges)
+    double dt;
+    float kx, kz;
+};
+
+constexpr int kGtsThreads = 256;
+
+// sig[g][q] = -dt^2 gamma^2 (|e|/d) / S of each side of the mesh's triangles (as k_ts_adjoint)
+__global__ __launch_bounds__(kGtsThreads) void k_gts_coef(int nt, int t_off, int e_off, float dt2,
+                                                          const int32_t *__restrict__ side,
+                                                          const float *__restrict__ tri_invS,
+                                                          const float *__restrict__ edge_ebyd,
+                                                          const float *__restrict__ gamma, float *__restrict__ sig) {
+    const int j = blockIdx.x * kGtsThreads + threadIdx.x;
+    if (j >= nt) return;
+    const int g = t_off + j;
+    const float invS = tri_invS[g];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int e = e_off + (side[3 * g + q] & 0x7FFFFFFF);
+        const float ga = gamma[e];
+        sig[3 * size_t(g) + q] = -dt2 * invS * (ga * ga * edge_ebyd[e]);
+    }
+}
+
+__device__ __forceinline__ void gts_start(const GtsPair &P, const float *__restrict__ tri_O, int g, float2 *x0,
+                                          float2 *y0, float2 *v0) {
+    const double kn = sqrt(double(P.kx) * P.kx + double(P.kz) * P.kz);
+    const float ca = float(cos(kn * P.dt / 2)), sa = float(sin(kn * P.dt / 2));
+    const float ph = P.kx * tri_O[2 * g] + P.kz * tri_O[2 * g + 1];
+    const float br = cosf(ph), bi = sinf(ph);
+    *x0 = make_float2(br * ca + bi * sa, bi * ca - br * sa);
+    *y0 = make_float2(2.0f * bi * sa, -2.0f * br * sa);
+    *v0 = make_float2(br, bi);
+}
+
+// Pass-1 start: x_0, y_0 = x_0 - x_{-1}, v_0 = B, u_0 = v_0 - v_{-1} = B; accumulators zero.
+__global__ __launch_bounds__(kGtsThreads) void k_gts_init(const GtsPair *__restrict__ pairs,
+                                                          const float *__restrict__ tri_O, float2 *__restrict__ X,
+                                                          float2 *__restrict__ Y, float2 *__restrict__ V,
+                                                          float2 *__restrict__ U, float2 *__restrict__ acc) {
+    const GtsPair P = pairs[blockIdx.y];
+    const int j = blockIdx.x * kGtsThreads + threadIdx.x;
+    if (j < P.nt) {
+        float2 x0, y0, v0;
+        gts_start(P, tri_O, P.t_off + j, &x0, &y0, &v0);
+        X[P.s_off + j] = x0;
+        Y[P.s_off + j] = y0;
+        V[P.s_off + j] = v0;
+        U[P.s_off + j] = v0;
+    }
+    if (j < P.ne) acc[P.a_off + j] = make_float2(0.0f, 0.0f);
+}
+
+// Pass-2 start: x from the beginning again; v steps backwards from v_{N-1} = v_N - u_N.
+__global__ __launch_bounds__(kGtsThreads) void k_gts_mid(const GtsPair *__restrict__ pairs, int64_t buf,
+                                                         const float *__restrict__ tri_O, float2 *__restrict__ X,
+                                                         float2 *__restrict__ Y, float2 *__restrict__ V,
+                                                         float2 *__restrict__ U) {
+    const GtsPair P = pairs[blockIdx.y];
+    const int j = blockIdx.x * kGtsThreads + threadIdx.x;
+    if (j >= P.nt) return;
+    const int64_t s = P.s_off + j, last = (P.nsteps & 1) ? buf : 0;  // v_N sits in buffer N & 1
+    float2 x0, y0, v0;
+    gts_start(P, tri_O, P.t_off + j, &x0, &y0, &v0);
+    const float2 vN = V[last + s], uN = U[s];
+    X[s] = x0;
+    Y[s] = y0;
+    V[s] = make_float2(vN.x - uN.x, vN.y - uN.y);
+    U[s] = make_float2(-uN.x, -uN.y);
+}
+
+// Step n of pass `pass` (1 or 2) for the first gridDim.y pairs (those with n < nsteps).
+// X, V: two buffers of `buf` entries each; step n reads buffer n & 1 and writes the other.
+__global__ __launch_bounds__(kGtsThreads) void k_gts_step(int n, int pass, int64_t buf,
+                                                          const GtsPair *__restrict__ pairs,
+                                                          const int32_t *__restrict__ nbr,
+                                                          const int32_t *__restrict__ side,
+                                                          const float *__restrict__ sig, float2 *__restrict__ X,
+                                                          float2 *__restrict__ Y, float2 *__restrict__ V,
+                                                          float2 *__restrict__ U, float2 *__restrict__ acc) {
+    const GtsPair P = pairs[blockIdx.y];
+    const int j = blockIdx.x * kGtsThreads + threadIdx.x;
+    if (n >= P.nsteps || j >= P.nt) return;
+    const int g = P.t_off + j;
+    const int64_t rd = (n & 1) ? buf : 0, wr = (n & 1) ? 0 : buf;
+    const float2 *xs = X + rd + P.s_off, *vs = V + rd + P.s_off;
+    const float2 xo = xs[j], vo = vs[j];
+    int nb[3];
+    float2 xn[3], vn[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        nb[q] = nbr[3 * g + q];
+        xn[q] = xs[nb[q]];
+        vn[q] = vs[nb[q]];
+    }
+    if (pass == 2) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int sd = side[3 * g + q];
+            if (sd < 0) {  // this triangle is R of the edge: L is the neighbour across it
+                float2 &a = acc[P.a_off + (sd & 0x7FFFFFFF)];
+                const float dvr = vo.x - vn[q].x, dvi = vo.y - vn[q].y;
+                const float dxr = xo.x - xn[q].x, dxi = xo.y - xn[q].y;
+                float ar = a.x, ai = a.y;
+                ar = fmaf(dvr, dxr, fmaf(dvi, dxi, ar));
+                ai = fmaf(dvr, dxi, fmaf(-dvi, dxr, ai));
+                a = make_float2(ar, ai);
+            }
+        }
+    }
+    float kr = 0.0f, ki = 0.0f, lr = 0.0f, li = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float sg = sig[3 * size_t(g) + q];
+        kr = fmaf(sg, xo.x - xn[q].x, kr);
+        ki = fmaf(sg, xo.y - xn[q].y, ki);
+        lr = fmaf(sg, vo.x - vn[q].x, lr);
+        li = fmaf(sg, vo.y - vn[q].y, li);
+    }
+    const int64_t s = P.s_off + j;
+    float2 y = Y[s], u = U[s];
+    y.x += kr;
+    y.y += ki;
+    u.x += lr;
+    u.y += li;
+    Y[s] = y;
+    U[s] = u;
+    X[wr + s] = make_float2(xo.x + y.x, xo.y + y.y);
+    V[wr + s] = make_float2(vo.x + u.x, vo.y + u.y);
+}
+
+// After pass 1: z_N = sum_j S_j conj(B_j) x_N,j per pair (one work-group each, fixed order)
+// and eps = -arg(z_N / z_0)/(|k| N dt) - 1.
+constexpr int kGtsZThreads = 1024;
+__global__ __launch_bounds__(kGtsZThreads) void k_gts_z(const GtsPair *__restrict__ pairs, int64_t buf,
+                                                        const float *__restrict__ tri_O,
+                                                        const float *__restrict__ tri_invS,
+                                                        const float2 *__restrict__ X, double2 *__restrict__ z,
+                                                        double *__restrict__ eps_out) {
+    __shared__ double red[kGtsZThreads / 64][2];
+    const GtsPair P = pairs[blockIdx.x];
+    const float2 *xs = X + ((P.nsteps & 1) ? buf : 0) + P.s_off;
+    double zr = 0.0, zi = 0.0;
+    for (int j = threadIdx.x; j < P.nt; j += kGtsZThreads) {
+        const int g = P.t_off + j;
+        const float ph = P.kx * tri_O[2 * g] + P.kz * tri_O[2 * g + 1];
+        const double br = cosf(ph), bi = sinf(ph), S = 1.0 / double(tri_invS[g]);
+        const float2 x = xs[j];
+        zr += S * (br * x.x + bi * x.y);
+        zi += S * (br * x.y - bi * x.x);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        zr += __shfl_xor(zr, off, 64);
+        zi += __shfl_xor(zi, off, 64);
+    }
+    const int tid = threadIdx.x;
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = zr;
+        red[tid >> 6][1] = zi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        zr = zi = 0.0;
+        for (int q = 0; q < kGtsZThreads / 64; ++q) {
+            zr += red[q][0];
+            zi += red[q][1];
+        }
+        const double kn = sqrt(double(P.kx) * P.kx + double(P.kz) * P.kz);
+        const double a0 = kn * P.dt / 2;
+        const double qr = zr * cos(a0) - zi * sin(a0), qi = zi * cos(a0) + zr * sin(a0);
+        const double T = kn * double(P.nsteps) * P.dt;
+        z[blockIdx.x] = make_double2(zr, zi);
+        eps_out[P.b] = -atan2(qi, qr) / T - 1.0;
+    }
+}
+
+// After pass 2: the pair's share of dL/dgamma on its mesh's edges (as k_ts_adjoint).
+__global__ __launch_bounds__(kGtsThreads) void k_gts_grad(const GtsPair *__restrict__ pairs,
+                                                          const double2 *__restrict__ z,
+                                                          const double *__restrict__ eps,
+                                                          const float2 *__restrict__ acc,
+                                                          const float *__restrict__ edge_ebyd,
+                                                          const float *__restrict__ gamma, double inv_mw,
+                                                          float *__restrict__ grad_out, int64_t grad_stride) {
+    const GtsPair P = pairs[blockIdx.y];
+    const int e = blockIdx.x * kGtsThreads + threadIdx.x;
+    if (e >= P.ne) return;
+    const double zr = z[blockIdx.y].x, zi = z[blockIdx.y].y;
+    const double kn = sqrt(double(P.kx) * P.kx + double(P.kz) * P.kz);
+    const double T = kn * double(P.nsteps) * P.dt;
+    const double zz = zr * zr + zi * zi;
+    const double scale = 2.0 * eps[P.b] * inv_mw / (zz * T);
+    const int ge = P.e_off + e;
+    const float2 a = acc[P.a_off + e];
+    const double c = -2.0 * P.dt * P.dt * double(gamma[ge]) * double(edge_ebyd[ge]);
+    const double dzr = c * a.x, dzi = c * a.y;
+    const double im = zr * dzi - zi * dzr;
+    grad_out[size_t(P.w) * grad_stride + ge] = float(-im * scale);
+}
+
+__global__ void k_fill_f32(int64_t n, float v, float *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+__global__ void k_fill_f64(int64_t n, double v, double *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
 // dL/dgamma_e = sum over waves of the per-wave shares (wave order)
 __global__ void k_wave_sum(int64_t n, int W, const float *__restrict__ g, float *__restrict__ out) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -388,12 +618,16 @@ __global__ __launch_bounds__(1024) void k_stiff_reg(int count, const int32_t *__
     }
 }
 
-// loss = sum eps^2 * inv_mw, one block
-__global__ __launch_bounds__(1024) void k_loss(int count, const double *__restrict__ eps, double inv_mw,
+// loss = sum over the active (mesh, wave) pairs of eps^2 * inv_mw, one block
+__global__ __launch_bounds__(1024) void k_loss(int count, const int32_t *__restrict__ active,
+                                               const double *__restrict__ eps, double inv_mw,
                                                double *__restrict__ loss) {
     __shared__ double red[1024 / 64];
     double v = 0.0;
-    for (int t = threadIdx.x; t < count; t += blockDim.x) v += eps[t] * eps[t] * inv_mw;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+        const double e = eps[active[t]];
+        v += e * e * inv_mw;
+    }
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -409,7 +643,9 @@ __global__ __launch_bounds__(1024) void k_loss(int count, const double *__restri
 //   [x(8) | h1(32) | d1(32) | h2(32) | d2(32) | dz | 1]
 // in LDS; then work-item t accumulates, over the staged rows, the products row[u] * row[v]
 // that form the gradient of the parameters it owns (p = t, t + 128, ...).
-__global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int64_t n, const float *__restrict__ feat,
+// idx: the edges to take (n of them, ascending), or null for edges 0 .. n-1.
+__global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int64_t n, const int32_t *__restrict__ idx,
+                                                            const float *__restrict__ feat,
                                                             const float *__restrict__ params,
                                                             const float *__restrict__ dLdg,
                                                             float *__restrict__ partial) {
@@ -442,7 +678,7 @@ __global__ __launch_bounds__(kBwdEdges) void k_mlp_backward(int64_t n, const flo
         __syncthreads();  // previous round's rows fully consumed
         float *row = rows + t * kRow;
         if (t < cnt) {
-            const int64_t i = base + t;
+            const int64_t i = idx ? int64_t(idx[base + t]) : base + t;
             float x[kFeatures], h1[kH1], h2[kH2];
             normalise(sP, feat + size_t(i) * kFeatures, x);
             const float th = mlp_edge(sP, x, h1, h2);
@@ -594,6 +830,22 @@ struct tyee_learner {
     int64_t M = 0, W = 0, n = 0, nt = 0;  // meshes, waves per mesh, edges, triangles (concatenated)
     tyee::DeviceBuffer feat, ebyd, gamma, waves, nsteps, order, meshes;
     tyee::DeviceBuffer tri_word, tri_invS, tri_O, edge_RL;
+    // multi-work-group path: per triangle side its neighbour (local id) and edge (local id,
+    // bit 31 set when the triangle is the edge's R), the couplings of the current gamma, the
+    // active pairs on that path and their recurrence state and edge accumulators
+    tyee::DeviceBuffer g_nbr, g_side, g_sig, g_pairs, g_X, g_Y, g_V, g_U, g_acc, g_z;
+    std::vector<tyee::TsMesh> info;         // per mesh (host copy)
+    std::vector<int32_t> steps;             // per (mesh, wave)
+    std::vector<float> wv;                  // per (mesh, wave) wavevector
+    std::vector<uint8_t> fits_lds;          // per mesh: small enough for k_ts_adjoint
+    int32_t path = 0;                       // 0 automatic, 1 every mesh on the multi-work-group path
+    std::vector<int32_t> active;            // active (mesh, wave) pairs
+    std::vector<tyee::GtsPair> gpairs;      // active pairs on the multi-work-group path (steps descending)
+    tyee::DeviceBuffer d_active;
+    int64_t n_lds_active = 0, g_buf = 0, g_nt_max = 0, g_ne_max = 0;
+    tyee::DeviceBuffer bwd_idx;             // edges the MLP backward pass takes under a minibatch
+    int64_t n_bwd = 0;
+    std::vector<std::vector<int32_t>> stiff_of;  // stiff edges of each mesh
     tyee::DeviceBuffer eps, wave_grad, dLdg, loss, partial_g, grad;
     tyee::DeviceBuffer stiff;            // edges of the stiff-edge term
     int64_t n_stiff = 0;
@@ -612,18 +864,156 @@ using tyee::fail;
 
 namespace {
 
+// The two passes of the multi-work-group path over its active pairs (see k_gts_step).
+int global_pass(tyee_learner &L, double inv_mw, bool want_grad) {
+    using namespace tyee;
+    hipStream_t s = L.stream;
+    const int P = int(L.gpairs.size());
+    // couplings of the current gamma, per mesh with an active pair
+    std::vector<uint8_t> seen(L.M, 0);
+    for (const GtsPair &p : L.gpairs) {
+        const int m = p.b / int(L.W);
+        if (seen[m]) continue;
+        seen[m] = 1;
+        const TsMesh &M = L.info[m];
+        k_gts_coef<<<(M.nt + kGtsThreads - 1) / kGtsThreads, kGtsThreads, 0, s>>>(
+            M.nt, M.t_off, M.e_off, float(M.dt * M.dt), L.g_side.as<int32_t>(), L.tri_invS.as<float>(),
+            L.ebyd.as<float>(), L.gamma.as<float>(), L.g_sig.as<float>());
+    }
+    const int bx_t = int((L.g_nt_max + kGtsThreads - 1) / kGtsThreads);
+    const int bx_a = int((std::max(L.g_nt_max, L.g_ne_max) + kGtsThreads - 1) / kGtsThreads);
+    const GtsPair *gp = L.g_pairs.as<GtsPair>();
+    float2 *X = L.g_X.as<float2>(), *Y = L.g_Y.as<float2>(), *V = L.g_V.as<float2>(), *U = L.g_U.as<float2>();
+    float2 *A = L.g_acc.as<float2>();
+    k_gts_init<<<dim3(bx_a, P), kGtsThreads, 0, s>>>(gp, L.tri_O.as<float>(), X, Y, V, U, A);
+    for (int pass = 1; pass <= (want_grad ? 2 : 1); ++pass) {
+        if (pass == 2)
+            k_gts_mid<<<dim3(bx_t, P), kGtsThreads, 0, s>>>(gp, L.g_buf, L.tri_O.as<float>(), X, Y, V, U);
+        int live = P;
+        const int nmax = L.gpairs[0].nsteps;
+        for (int n = 0; n < nmax; ++n) {
+            while (live > 0 && L.gpairs[live - 1].nsteps <= n) --live;  // steps descending
+            k_gts_step<<<dim3(bx_t, live), kGtsThreads, 0, s>>>(n, pass, L.g_buf, gp, L.g_nbr.as<int32_t>(),
+                                                                L.g_side.as<int32_t>(), L.g_sig.as<float>(), X,
+                                                                Y, V, U, A);
+        }
+        if (pass == 1)
+            k_gts_z<<<P, kGtsZThreads, 0, s>>>(gp, L.g_buf, L.tri_O.as<float>(), L.tri_invS.as<float>(), X,
+                                               L.g_z.as<double2>(), L.eps.as<double>());
+    }
+    if (!want_grad) {
+        TYEE_HIP(hipGetLastError());
+        return TYEE_OK;
+    }
+    const int bx_e = int((L.g_ne_max + kGtsThreads - 1) / kGtsThreads);
+    k_gts_grad<<<dim3(bx_e, P), kGtsThreads, 0, s>>>(gp, L.g_z.as<double2>(), L.eps.as<double>(), A,
+                                                     L.ebyd.as<float>(), L.gamma.as<float>(), inv_mw,
+                                                     L.wave_grad.as<float>(), L.n);
+    TYEE_HIP(hipGetLastError());
+    return TYEE_OK;
+}
+
+// Split the active pairs between the two paths, order each by step count (descending) and
+// size the multi-work-group state.  Rows of wave_grad that no active pair writes are zeroed
+// and the phase errors of inactive pairs set to NaN.
+int apply_batch(tyee_learner &L, const std::vector<int32_t> &active) {
+    using namespace tyee;
+    hipStream_t s = L.stream;
+    std::vector<int32_t> lds;
+    std::vector<GtsPair> gp;
+    for (int32_t b : active) {
+        const int m = b / int(L.W), w = b % int(L.W);
+        if (L.path == 0 && L.fits_lds[m]) {
+            lds.push_back(b);
+            continue;
+        }
+        const TsMesh &M = L.info[m];
+        GtsPair p{};
+        p.b = b;
+        p.w = w;
+        p.t_off = M.t_off;
+        p.nt = M.nt;
+        p.e_off = M.e_off;
+        p.ne = M.ne;
+        p.nsteps = L.steps[b];
+        p.dt = M.dt;
+        p.kx = L.wv[2 * size_t(b)];
+        p.kz = L.wv[2 * size_t(b) + 1];
+        gp.push_back(p);
+    }
+    std::stable_sort(lds.begin(), lds.end(), [&](int32_t a, int32_t b) { return L.steps[a] > L.steps[b]; });
+    std::stable_sort(gp.begin(), gp.end(), [](const GtsPair &a, const GtsPair &b) { return a.nsteps > b.nsteps; });
+    int64_t soff = 0, aoff = 0, ntmax = 0, nemax = 0;
+    for (GtsPair &p : gp) {
+        p.s_off = int32_t(soff);
+        p.a_off = aoff;
+        soff += p.nt;
+        aoff += p.ne;
+        ntmax = std::max<int64_t>(ntmax, p.nt);
+        nemax = std::max<int64_t>(nemax, p.ne);
+    }
+    if (soff >= (int64_t(1) << 31)) return fail(TYEE_EINVAL, "batch too large for the multi-work-group path");
+    // MLP backward edges: every edge of a mesh with an active pair, and the stiff edges of the
+    // others (the stiff-edge term covers all training edges), ascending
+    std::vector<uint8_t> mesh_on(L.M, 0);
+    for (int32_t b : active) mesh_on[b / int(L.W)] = 1;
+    std::vector<int32_t> bwd;
+    const bool every = std::all_of(mesh_on.begin(), mesh_on.end(), [](uint8_t v) { return v != 0; });
+    if (!every) {
+        for (int64_t m = 0; m < L.M; ++m) {
+            const TsMesh &M = L.info[m];
+            if (mesh_on[m]) {
+                for (int32_t e = M.e_off; e < M.e_off + M.ne; ++e) bwd.push_back(e);
+            } else if (L.reg_beta > 0.0) {
+                bwd.insert(bwd.end(), L.stiff_of[m].begin(), L.stiff_of[m].end());
+            }
+        }
+    }
+    L.n_bwd = every ? L.n : int64_t(bwd.size());
+    L.active = active;
+    L.gpairs = gp;
+    L.n_lds_active = int64_t(lds.size());
+    L.g_buf = soff;
+    L.g_nt_max = ntmax;
+    L.g_ne_max = nemax;
+    int rc = upload_vec(L.d_active, active, s);
+    if (!rc && !every) rc = upload_vec(L.bwd_idx, bwd.empty() ? std::vector<int32_t>{0} : bwd, s);
+    if (!rc) rc = upload_vec(L.order, lds.empty() ? std::vector<int32_t>{0} : lds, s);
+    if (!rc && !gp.empty()) {
+        rc = upload_vec(L.g_pairs, gp, s);
+        if (!rc) rc = L.g_X.alloc(size_t(2 * soff) * sizeof(float2));
+        if (!rc) rc = L.g_V.alloc(size_t(2 * soff) * sizeof(float2));
+        if (!rc) rc = L.g_Y.alloc(size_t(soff) * sizeof(float2));
+        if (!rc) rc = L.g_U.alloc(size_t(soff) * sizeof(float2));
+        if (!rc) rc = L.g_acc.alloc(size_t(aoff) * sizeof(float2));
+        if (!rc) rc = L.g_z.alloc(gp.size() * sizeof(double2));
+    }
+    if (rc) return rc;
+    const int64_t ng = L.W * L.n, ne_ = L.M * L.W;
+    k_fill_f32<<<int((ng + 255) / 256), 256, 0, s>>>(ng, 0.0f, L.wave_grad.as<float>());
+    k_fill_f64<<<int((ne_ + 255) / 256), 256, 0, s>>>(ne_, std::nan(""), L.eps.as<double>());
+    TYEE_HIP(hipGetLastError());
+    return TYEE_OK;
+}
+
 int learner_pass(tyee_learner &L, bool want_grad) {
     using namespace tyee;
     hipStream_t s = L.stream;
-    const double inv_mw = 1.0 / double(L.M * L.W);
+    const double inv_mw = 1.0 / double(L.active.size());
     k_mlp_gamma<<<int((L.n + 255) / 256), 256, 0, s>>>(int(L.n), L.feat.as<float>(), L.params.as<float>(),
                                                       L.gamma.as<float>());
-    k_ts_adjoint<<<int(L.M * L.W), kTsThreads, 0, s>>>(
-        int(L.W), L.order.as<int32_t>(), L.meshes.as<TsMesh>(), L.waves.as<float>(), L.nsteps.as<int32_t>(),
-        L.tri_word.as<uint32_t>(),
-        L.tri_invS.as<float>(), L.tri_O.as<float>(), L.edge_RL.as<uint32_t>(), L.ebyd.as<float>(),
-        L.gamma.as<float>(), inv_mw, L.eps.as<double>(), L.wave_grad.as<float>(), L.n);
-    k_loss<<<1, 1024, 0, s>>>(int(L.M * L.W), L.eps.as<double>(), inv_mw, L.loss.as<double>());
+    if (L.n_lds_active > 0)
+        k_ts_adjoint<<<int(L.n_lds_active), kTsThreads, 0, s>>>(
+            int(L.W), L.order.as<int32_t>(), L.meshes.as<TsMesh>(), L.waves.as<float>(), L.nsteps.as<int32_t>(),
+            L.tri_word.as<uint32_t>(),
+            L.tri_invS.as<float>(), L.tri_O.as<float>(), L.edge_RL.as<uint32_t>(), L.ebyd.as<float>(),
+            L.gamma.as<float>(), inv_mw, L.eps.as<double>(), L.wave_grad.as<float>(), L.n);
+    if (!L.gpairs.empty()) {
+        int rc = global_pass(L, inv_mw, want_grad);
+        if (rc) return rc;
+    }
+    k_loss<<<1, 1024, 0, s>>>(int(L.active.size()), L.d_active.as<int32_t>(), L.eps.as<double>(), inv_mw,
+                              L.loss.as<double>());
     if (want_grad)
         // every (mesh, wave) share of dL/dgamma sits in row w of wave_grad; edges of mesh m
         // are touched only by its own W blocks, so the per-edge sum runs over the W rows
@@ -634,9 +1024,13 @@ int learner_pass(tyee_learner &L, bool want_grad) {
                                        float(L.reg_beta), float(L.reg_target), L.dLdg.as<float>(),
                                        L.loss.as<double>(), want_grad ? 1 : 0);
     if (want_grad) {
-        k_mlp_backward<<<int(L.n_bblocks), kBwdEdges, 0, s>>>(L.n, L.feat.as<float>(), L.params.as<float>(),
-                                                              L.dLdg.as<float>(), L.partial_g.as<float>());
-        k_grad_reduce<<<(kParams + 255) / 256, 256, 0, s>>>(int(L.n_bblocks), L.partial_g.as<float>(),
+        // with a minibatch only the active meshes' edges and the stiff edges carry a gradient
+        const bool list = L.n_bwd < L.n;
+        const int64_t nb = (L.n_bwd + kBwdEdges * kBwdRounds - 1) / (kBwdEdges * kBwdRounds);
+        k_mlp_backward<<<int(nb), kBwdEdges, 0, s>>>(L.n_bwd, list ? L.bwd_idx.as<int32_t>() : nullptr,
+                                                     L.feat.as<float>(), L.params.as<float>(),
+                                                     L.dLdg.as<float>(), L.partial_g.as<float>());
+        k_grad_reduce<<<(kParams + 255) / 256, 256, 0, s>>>(int(nb), L.partial_g.as<float>(),
                                                             L.grad.as<float>());
     }
     TYEE_HIP(hipGetLastError());
@@ -645,8 +1039,15 @@ int learner_pass(tyee_learner &L, bool want_grad) {
 
 int set_stiff_edges(tyee_learner &L) {
     std::vector<int32_t> idx;
-    for (int64_t e = 0; e < L.n; ++e)
-        if (double(L.f0[e]) < L.reg_tau) idx.push_back(int32_t(e));
+    L.stiff_of.assign(L.M, {});
+    for (int64_t m = 0; m < L.M; ++m) {
+        const tyee::TsMesh &M = L.info[m];
+        for (int32_t e = M.e_off; e < M.e_off + M.ne; ++e)
+            if (double(L.f0[e]) < L.reg_tau) {
+                idx.push_back(e);
+                L.stiff_of[m].push_back(e);
+            }
+    }
     L.n_stiff = int64_t(idx.size());
     return tyee::upload_vec(L.stiff, idx.empty() ? std::vector<int32_t>{0} : idx, L.stream);
 }
@@ -696,6 +1097,7 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         L->W = n_waves;
         std::vector<float> feat, ebyd, invS, O, wv(2 * n_meshes * n_waves);
         std::vector<uint32_t> word, rl;
+        std::vector<int32_t> gnbr, gside;
         std::vector<int32_t> steps(n_meshes * n_waves);
         std::vector<TsMesh> info(n_meshes);
         std::vector<double> sum(kFeatures, 0.0), sum2(kFeatures, 0.0);
@@ -703,8 +1105,10 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
             if (!meshes[k]) return fail(TYEE_EINVAL, "null mesh");
             const Mesh &m = meshes[k]->m;
             if (!m.periodic) return fail(TYEE_EINVAL, "training meshes must be periodic");
-            if (m.nt > kTsMaxTris || m.ne > kTsMaxEdges)
-                return fail(TYEE_EINVAL, "training meshes are limited to 4096 triangles and 6144 edges");
+            if (m.nt >= (int64_t(1) << 30) || m.ne >= (int64_t(1) << 30))
+                return fail(TYEE_EINVAL, "training mesh too large");
+            const bool small = m.nt <= kTsMaxTris && m.ne <= kTsMaxEdges;
+            L->fits_lds.push_back(small ? 1 : 0);
             if (!(dt[k] > 0.0)) return fail(TYEE_EINVAL, "dt must be > 0");
             TsMesh &t = info[k];
             t.t_off = int32_t(invS.size());
@@ -724,7 +1128,8 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
                 }
                 ebyd.push_back(float(m.elen[i] / m.d[i]));
                 L->f0.push_back(float(f[kFeatures * i]));
-                rl.push_back(uint32_t(m.R[i]) | (uint32_t(m.L[i]) << 16));
+                // 16-bit local triangle ids for the one-work-group kernel (unused above it)
+                rl.push_back(small ? uint32_t(m.R[i]) | (uint32_t(m.L[i]) << 16) : 0u);
             }
             for (int64_t j = 0; j < m.nt; ++j) {
                 t.area += m.S[j];
@@ -734,7 +1139,9 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
                 for (int q = 0; q < 3; ++q) {
                     const int32_t i = m.A[3 * j + q];
                     const int32_t nb = m.R[i] == int32_t(j) ? m.L[i] : m.R[i];
-                    word.push_back(uint32_t(nb) | (uint32_t(i) << 16));
+                    word.push_back(small ? uint32_t(nb) | (uint32_t(i) << 16) : 0u);
+                    gnbr.push_back(nb);
+                    gside.push_back(int32_t(uint32_t(i) | (m.R[i] == int32_t(j) ? 0x80000000u : 0u)));
                 }
             }
             for (int64_t w = 0; w < n_waves; ++w) {
@@ -765,11 +1172,13 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         if (!rc) rc = upload_vec(L->tri_O, O, s);
         if (!rc) rc = upload_vec(L->waves, wv, s);
         if (!rc) rc = upload_vec(L->nsteps, steps, s);
-        std::vector<int32_t> ord(steps.size());
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return steps[a] > steps[b]; });
-        if (!rc) rc = upload_vec(L->order, ord, s);
+        if (!rc) rc = upload_vec(L->g_nbr, gnbr, s);
+        if (!rc) rc = upload_vec(L->g_side, gside, s);
+        if (!rc) rc = L->g_sig.alloc(gnbr.size() * sizeof(float));
         if (!rc) rc = upload_vec(L->meshes, info, s);
+        L->info = info;
+        L->steps = steps;
+        L->wv = wv;
         if (!rc) rc = L->gamma.alloc(L->n * sizeof(float));
         if (!rc) rc = L->eps.alloc(n_meshes * n_waves * sizeof(double));
         if (!rc) rc = L->wave_grad.alloc(size_t(n_waves) * L->n * sizeof(float));
@@ -782,6 +1191,9 @@ int tyee_learner_create(const tyee_mesh *const *meshes, const double *dt, int64_
         if (!rc) rc = upload_vec(L->m2, zeros, s);
         if (!rc) rc = upload_params(*L, std::vector<double>(kParams, 0.0));
         if (!rc) rc = set_stiff_edges(*L);
+        std::vector<int32_t> all(n_meshes * n_waves);
+        std::iota(all.begin(), all.end(), 0);
+        if (!rc) rc = apply_batch(*L, all);
         if (rc) return rc;
         *out = L.release();
         return TYEE_OK;
@@ -819,7 +1231,8 @@ int tyee_learner_regulariser(tyee_learner *L, double tau, double beta, double ta
     L->reg_tau = tau;
     L->reg_beta = beta;
     L->reg_target = target;
-    return set_stiff_edges(*L);
+    int rc = set_stiff_edges(*L);
+    return rc ? rc : apply_batch(*L, L->active);  // the backward edge list follows the stiff edges
 }
 
 int tyee_learner_set_params(tyee_learner *L, const double *theta) {
@@ -920,6 +1333,34 @@ int tyee_learner_gamma(tyee_learner *L, const tyee_mesh *mesh, double *gamma) {
     if ((rc = download_vec(dg, g, size_t(m.ne), L->stream))) return rc;
     for (int64_t i = 0; i < m.ne; ++i) gamma[i] = m.interior(i) ? double(g[i]) : 1.0;
     return TYEE_OK;
+}
+
+int tyee_learner_set_batch(tyee_learner *L, const int32_t *pairs, int64_t n) {
+    if (!L) return fail(TYEE_EINVAL, "null learner");
+    std::vector<int32_t> act;
+    if (!pairs || n == 0) {
+        act.resize(L->M * L->W);
+        std::iota(act.begin(), act.end(), 0);
+    } else {
+        if (n < 0) return fail(TYEE_EINVAL, "negative pair count");
+        std::vector<uint8_t> seen(L->M * L->W, 0);
+        for (int64_t k = 0; k < n; ++k) {
+            const int32_t m = pairs[2 * k], w = pairs[2 * k + 1];
+            if (m < 0 || m >= L->M || w < 0 || w >= L->W) return fail(TYEE_EINVAL, "pair out of range");
+            const int32_t b = int32_t(m * L->W + w);
+            if (seen[b]) return fail(TYEE_EINVAL, "pair listed twice");
+            seen[b] = 1;
+            act.push_back(b);
+        }
+    }
+    return apply_batch(*L, act);
+}
+
+int tyee_learner_set_path(tyee_learner *L, int32_t path) {
+    if (!L) return fail(TYEE_EINVAL, "null learner");
+    if (path != 0 && path != 1) return fail(TYEE_EINVAL, "path must be 0 (automatic) or 1 (multi-work-group)");
+    L->path = path;
+    return apply_batch(*L, L->active);
 }
 
 void tyee_learner_destroy(tyee_learner *L) { delete L; }

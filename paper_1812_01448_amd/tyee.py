@@ -88,7 +88,8 @@ EXPORTS = [
     "tyee_mesh_features", "tyee_mesh_phase_error_rq", "tyee_phase_error_timestepped",
     "tyee_learner_create", "tyee_learner_init", "tyee_learner_set_params",
     "tyee_learner_get_params", "tyee_learner_normaliser", "tyee_learner_loss_grad",
-    "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_destroy", "tyee_gate",
+    "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_set_batch", "tyee_learner_set_path",
+    "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
     "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_batch_tune_progress",
     "tyee_last_error",
@@ -170,6 +171,8 @@ def _load():
         "tyee_learner_loss_grad": [vp, ctypes.POINTER(f64), vp, vp],
         "tyee_learner_train": [vp, i64, f64, vp],
         "tyee_learner_gamma": [vp, vp, vp],
+        "tyee_learner_set_batch": [vp, vp, i64],
+        "tyee_learner_set_path": [vp, i32],
         "tyee_gate": [vp, vp, vp, i64, f64, f64, i32, vp, ctypes.POINTER(_Gate)],
         "tyee_sim_add_probe": [vp, i32, vp, i64, i64, i64, ctypes.POINTER(i32)],
         "tyee_sim_read_probe": [vp, i32, vp, i64, ctypes.POINTER(i64)],
@@ -643,3 +646,15 @@ class Learner:
         out = np.zeros(mesh.ne)
         _check(lib.tyee_learner_gamma(self._h, mesh._h, _ptr(out)))
         return out
+
+    def set_batch(self, pairs=None):
+        """Active (mesh, wave) pairs [n][2] of the loss (None: all)."""
+        if pairs is None or len(pairs) == 0:
+            _check(lib.tyee_learner_set_batch(self._h, None, 0))
+            return
+        p = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        _check(lib.tyee_learner_set_batch(self._h, _ptr(p), len(p)))
+
+    def set_path(self, path):
+        """0: automatic; 1: every mesh on the multi-work-group path."""
+        _check(lib.tyee_learner_set_path(self._h, int(path)))

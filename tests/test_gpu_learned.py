@@ -83,9 +83,14 @@ def test_learner_matches_oracle(ty):
         ref_e = [OL.ts_phase_error_grad(t["om"], gam, t["dt"], k, OL.ts_steps(k, t["dt"]))[0]
                  for k in t["waves"]]
         assert np.max(np.abs(e_row - ref_e)) < 2e-6, np.max(np.abs(e_row - ref_e))
-    _note(f"  loss {loss:.6e} ref {ref_loss:.6e}; grad rel L2 {rel_l2(grad, ref_grad):.2e}")
+    # per parameter: the FP32 recurrences (N <= 2,500 steps, worst-case linear growth of the
+    # rounding, N 2^-24 < 1.5e-4) bound every component by 3e-4 of the largest one
+    err = np.abs(grad - ref_grad)
+    bound = 3e-4 * np.max(np.abs(ref_grad))
+    _note(f"  loss {loss:.6e} ref {ref_loss:.6e}; grad rel L2 {rel_l2(grad, ref_grad):.2e}, "
+          f"worst parameter {np.max(err) / bound:.3f} of the bound")
     assert abs(loss / ref_loss - 1) < 1e-3
-    assert rel_l2(grad, ref_grad) < 1e-2
+    assert np.all(err <= bound)
 
 
 def test_identity_model_is_plain_and_training_lowers_loss(ty):
