@@ -407,6 +407,60 @@ typedef struct {
 int tyee_gate(const tyee_mesh *mesh, const double *gamma, const double *waves, int64_t n_waves,
               double cfl, double phase, int32_t prec, void *stream, tyee_gate_result *out);
 
+/* Lawson flips of a triangulation (Section 3: the flip operation of Fig. 5a): while an
+   interior edge fails the empty-circle test (the apex of its second triangle strictly inside
+   the circumcircle of the first, beyond a relative tolerance of 1e-12 that leaves cocircular
+   quads alone), replace it by the other diagonal of its quad.  xy [n_nodes][2]; tri
+   [n_tris][3] is rewritten in place (counter-clockwise) only on success; dom gives the kind and
+   the periods (minimum image on a torus).  flips (NULL to skip) receives the count.  Host
+   only.  Errors: TYEE_EINVAL (ids out of range), TYEE_EDEGENERATE (a zero-area triangle),
+   TYEE_EUNSTABLE (no end within 50 n_tris flips). */
+int tyee_mesh_flip(const double *xy, int64_t n_nodes, int32_t *tri, int64_t n_tris,
+                   const tyee_domain *dom, int64_t *flips);
+
+/* ---------------------------------------------------------- relaxation ---- */
+
+typedef struct {
+    int32_t rounds;       /* remesh rounds: each runs `iters` Euler steps, Lawson flips, omega_max */
+    int32_t iters;        /* Euler steps per round */
+    double step;          /* Euler step tau: a node moves by tau times its net spring force */
+    double k_edge;        /* spring constant along edges */
+    double k_height;      /* spring constant along triangle heights */
+    double rest;          /* rest length of the edge springs; 0: the side of the equilateral
+                             triangle that covers the domain with n_tris triangles (heights rest
+                             at rest sqrt(3)/2) */
+    int32_t keep_best;    /* 1: return the iterate (input included) with the smallest omega_max;
+                             0: return the last round's */
+} tyee_relax_params;
+
+typedef struct {
+    double omega_initial;  /* omega_max of the input mesh */
+    double omega_best;     /* omega_max of the returned mesh */
+    int32_t best_round;    /* 0 when the input mesh is returned */
+    int64_t flips;         /* Lawson flips over all rounds */
+    double energy_initial, energy_final;  /* spring energy of the input and returned node sets */
+    double step_used;      /* Euler step after any halving (a triangle that turns over makes the
+                              round start again at half the step, up to 5 times) */
+} tyee_relax_stats;
+
+/* Jello relaxation of the mesh's nodes (Section 3, mesh generation, Fig. 5b): nodes joined by
+   springs along every triangle edge and every triangle height, at the rest lengths of a perfect
+   equilateral mesh, move along their net force (heavily damped motion without its second time
+   derivative: x <- x + step F, Euler steps on the GPU, FP64); after every round of `iters`
+   steps the triangulation is remeshed by Lawson flips and omega_max of the result is measured
+   by power iteration (eq. 20: dt = C 2/omega_max).  Nodes on the outline of a closed
+   resonator and the n_anchors node ids in `anchors` (seeds of the geometry) do not move.
+   Outputs (caller buffers, canonical node ids, node and triangle counts unchanged): xy_out
+   [n_nodes][2], tri_out [n_tris][3] (counter-clockwise) of the returned iterate, for
+   tyee_mesh_create with the input's domain; omega_rounds [rounds + 1] (NULL to skip):
+   omega_max of the input and after each round (+infinity when a round's mesh is not Delaunay);
+   stats (NULL to skip).  stream: HIP stream for the steps (NULL = default).
+   Errors: TYEE_EINVAL (bad parameters or anchors), TYEE_EUNSTABLE (triangles fold even at 1/32
+   of the step), TYEE_EDEVICE, TYEE_ENOMEM. */
+int tyee_mesh_relax(const tyee_mesh *mesh, const tyee_relax_params *p, const int32_t *anchors,
+                    int64_t n_anchors, void *stream, double *xy_out, int32_t *tri_out,
+                    double *omega_rounds, tyee_relax_stats *stats);
+
 /* ---------------------------------------------------------------- batch ---- */
 
 typedef struct tyee_batch tyee_batch;

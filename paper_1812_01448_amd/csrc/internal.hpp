@@ -43,6 +43,11 @@ int reorder_mesh(Mesh &m, int32_t kind, uint64_t seed);
 int power_iteration(const Mesh &m, const double *gamma, int64_t max_iter, double rtol,
                     uint64_t seed, double *lambda, int64_t *iters);
 uint64_t splitmix64(uint64_t x);
+// Lawson flips (Section 3, Fig. 5a) until every interior edge of the counter-clockwise
+// triangles passes the empty-circle test; n_flips receives the count.  TYEE_EUNSTABLE when
+// max_flips is reached first.
+int lawson_flip(const std::vector<double> &xy, std::vector<int32_t> &tri, bool periodic, double Lx, double Ly,
+                int64_t nv, int64_t max_flips, int64_t *n_flips);
 // Disjoint union of meshes: node, edge and triangle ids of part p are offset by the totals
 // of parts 0..p-1, and so are their device numberings (each part keeps its own order).
 int merge_meshes(const std::vector<const Mesh *> &parts, Mesh &out);

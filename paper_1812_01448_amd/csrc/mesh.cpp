@@ -9,6 +9,7 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
 
 #include "internal.hpp"
 
@@ -600,6 +601,89 @@ int power_iteration(const Mesh &m, const double *gamma, int64_t max_iter, double
     return fail(TYEE_ENOTCONVERGED, "power iteration did not converge");
 }
 
+namespace {
+double flip_mi(double d, double L, bool periodic) { return periodic ? d - L * std::nearbyint(d / L) : d; }
+}  // namespace
+
+// Lawson flips until every interior edge passes the empty-circle test (with a relative
+// tolerance, so that cocircular quads are left alone).  Triangles stay counter-clockwise.
+int lawson_flip(const std::vector<double> &xy, std::vector<int32_t> &tri, bool periodic, double Lx, double Ly,
+                int64_t nv, int64_t max_flips, int64_t *n_flips) {
+    const int64_t nt = int64_t(tri.size()) / 3;
+    auto key = [nv](int64_t a, int64_t b) { return a < b ? a * nv + b : b * nv + a; };
+    std::unordered_map<int64_t, std::pair<int64_t, int64_t>> sides;  // edge -> (3 t + q, 3 t' + q')
+    sides.reserve(size_t(3 * nt));
+    for (int64_t j = 0; j < nt; ++j)
+        for (int q = 0; q < 3; ++q) {
+            const int64_t k = key(tri[3 * j + q], tri[3 * j + (q + 1) % 3]);
+            auto it = sides.find(k);
+            if (it == sides.end()) sides.emplace(k, std::make_pair(3 * j + q, int64_t(-1)));
+            else it->second.second = 3 * j + q;
+        }
+    std::vector<int64_t> stack;
+    stack.reserve(sides.size());
+    for (auto &kv : sides)
+        if (kv.second.second >= 0) stack.push_back(kv.first);
+    std::sort(stack.begin(), stack.end());  // a fixed order, whatever the hash map's
+    auto rel = [&](int32_t from, int32_t to, double &dx, double &dy) {
+        dx = flip_mi(xy[2 * to] - xy[2 * from], Lx, periodic);
+        dy = flip_mi(xy[2 * to + 1] - xy[2 * from + 1], Ly, periodic);
+    };
+    auto replace = [&](int64_t k, int64_t old_s, int64_t new_s) {
+        auto &pr = sides[k];
+        if (pr.first == old_s) pr.first = new_s;
+        else if (pr.second == old_s) pr.second = new_s;
+    };
+    int64_t flips = 0;
+    while (!stack.empty() && flips < max_flips) {
+        const int64_t k = stack.back();
+        stack.pop_back();
+        auto it = sides.find(k);
+        if (it == sides.end() || it->second.second < 0) continue;
+        const int64_t s1 = it->second.first, s2 = it->second.second;
+        const int64_t t1 = s1 / 3, q1 = s1 % 3, t2 = s2 / 3, q2 = s2 % 3;
+        const int32_t u = tri[3 * t1 + q1], v = tri[3 * t1 + (q1 + 1) % 3], o1 = tri[3 * t1 + (q1 + 2) % 3];
+        const int32_t o2 = tri[3 * t2 + (q2 + 2) % 3];
+        if (o1 == o2 || sides.count(key(o1, o2))) continue;  // the new diagonal exists already
+        // in-circle test of o2 against the circle through u, v, o1 (counter-clockwise)
+        double bx, by, cx, cy, dx, dy;
+        rel(u, v, bx, by);
+        rel(u, o1, cx, cy);
+        rel(u, o2, dx, dy);
+        // with u at the origin: incircle = -| b |b|^2 ; c |c|^2 ; d |d|^2 | (rows x, y, x^2 + y^2),
+        // positive when o2 is inside the circle
+        const double b2 = bx * bx + by * by, c2 = cx * cx + cy * cy, d2 = dx * dx + dy * dy;
+        const double incircle =
+            -(bx * (cy * d2 - c2 * dy) - by * (cx * d2 - c2 * dx) + b2 * (cx * dy - cy * dx));
+        const double scale = std::max(b2, std::max(c2, d2));
+        if (!(incircle > 1e-12 * scale * scale)) continue;
+        // flip u-v to o1-o2: t1 = (o1, u, o2), t2 = (o2, v, o1)
+        const int64_t k_uo2 = key(u, o2), k_vo1 = key(v, o1), k_o1u = key(o1, u), k_o2v = key(o2, v);
+        // sides before: t1: (u,v) q1, (v,o1) q1+1, (o1,u) q1+2; t2: (v,u) q2, (u,o2) q2+1, (o2,v) q2+2
+        const int64_t s_vo1 = 3 * t1 + (q1 + 1) % 3, s_o1u = 3 * t1 + (q1 + 2) % 3;
+        const int64_t s_uo2 = 3 * t2 + (q2 + 1) % 3, s_o2v = 3 * t2 + (q2 + 2) % 3;
+        tri[3 * t1] = o1;
+        tri[3 * t1 + 1] = u;
+        tri[3 * t1 + 2] = o2;
+        tri[3 * t2] = o2;
+        tri[3 * t2 + 1] = v;
+        tri[3 * t2 + 2] = o1;
+        // sides after: t1: (o1,u) 0, (u,o2) 1, (o2,o1) 2; t2: (o2,v) 0, (v,o1) 1, (o1,o2) 2
+        replace(k_o1u, s_o1u, 3 * t1 + 0);
+        replace(k_uo2, s_uo2, 3 * t1 + 1);
+        replace(k_o2v, s_o2v, 3 * t2 + 0);
+        replace(k_vo1, s_vo1, 3 * t2 + 1);
+        sides.erase(it);
+        sides.emplace(key(o1, o2), std::make_pair(3 * t1 + 2, 3 * t2 + 2));
+        for (int64_t kk : {k_uo2, k_vo1, k_o1u, k_o2v}) stack.push_back(kk);
+        ++flips;
+    }
+    *n_flips = flips;
+    if (!stack.empty()) return fail(TYEE_EUNSTABLE, "Lawson flips did not finish within the flip limit");
+    return TYEE_OK;
+}
+
+
 }  // namespace tyee
 
 // ---------------------------------------------------------------------------------------
@@ -721,3 +805,29 @@ int tyee_mesh_phase_error_rq(const tyee_mesh *mesh, const double *gamma, double 
 void tyee_mesh_destroy(tyee_mesh *mesh) { delete mesh; }
 
 }  // extern "C"
+
+extern "C" int tyee_mesh_flip(const double *xy, int64_t n_nodes, int32_t *tri, int64_t n_tris,
+                              const tyee_domain *dom, int64_t *flips) {
+    using namespace tyee;
+    if (!xy || !tri || !dom || n_nodes <= 0 || n_tris <= 0) return fail(TYEE_EINVAL, "null or empty argument");
+    if (n_nodes > INT32_MAX || 3 * n_tris > INT32_MAX) return fail(TYEE_EINVAL, "mesh too large for int32 ids");
+    const bool periodic = dom->kind == TYEE_PERIODIC;
+    std::vector<double> p(xy, xy + 2 * n_nodes);
+    std::vector<int32_t> t(tri, tri + 3 * n_tris);
+    for (int64_t j = 0; j < n_tris; ++j) {
+        for (int q = 0; q < 3; ++q)
+            if (t[3 * j + q] < 0 || t[3 * j + q] >= n_nodes) return fail(TYEE_EINVAL, "node id out of range");
+        const int32_t a = t[3 * j], b = t[3 * j + 1], c = t[3 * j + 2];
+        const double bx = flip_mi(p[2 * b] - p[2 * a], dom->Lx, periodic), by = flip_mi(p[2 * b + 1] - p[2 * a + 1], dom->Ly, periodic);
+        const double cx = flip_mi(p[2 * c] - p[2 * a], dom->Lx, periodic), cy = flip_mi(p[2 * c + 1] - p[2 * a + 1], dom->Ly, periodic);
+        const double o = bx * cy - by * cx;
+        if (o == 0.0) return fail(TYEE_EDEGENERATE, "degenerate triangle");
+        if (o < 0.0) std::swap(t[3 * j + 1], t[3 * j + 2]);  // counter-clockwise
+    }
+    int64_t n = 0;
+    const int rc = lawson_flip(p, t, periodic, dom->Lx, dom->Ly, n_nodes, 50 * n_tris, &n);
+    if (flips) *flips = n;
+    if (rc) return rc;
+    std::copy(t.begin(), t.end(), tri);
+    return TYEE_OK;
+}

@@ -68,6 +68,19 @@ class _ModesStats(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class _RelaxParams(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("iters", ctypes.c_int32), ("step", ctypes.c_double),
+                ("k_edge", ctypes.c_double), ("k_height", ctypes.c_double), ("rest", ctypes.c_double),
+                ("keep_best", ctypes.c_int32)]
+
+
+class _RelaxStats(ctypes.Structure):
+    _fields_ = [("omega_initial", ctypes.c_double), ("omega_best", ctypes.c_double),
+                ("best_round", ctypes.c_int32), ("flips", ctypes.c_int64),
+                ("energy_initial", ctypes.c_double), ("energy_final", ctypes.c_double),
+                ("step_used", ctypes.c_double)]
+
+
 class _Diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("time", ctypes.c_double), ("energy", ctypes.c_double),
                 ("energy_h", ctypes.c_double), ("max_abs_E", ctypes.c_double),
@@ -91,7 +104,8 @@ EXPORTS = [
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_set_batch", "tyee_learner_set_path",
     "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
-    "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_batch_tune_progress",
+    "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_relax", "tyee_mesh_flip",
+    "tyee_batch_tune_progress",
     "tyee_last_error",
 ]
 N_PARAMS = 1377
@@ -179,6 +193,9 @@ def _load():
         "tyee_copy_bandwidth": [i64, i32, ctypes.POINTER(f64)],
         "tyee_sim_bind_external": [vp, i32, vp, vp],
         "tyee_sim_current_buffer": [vp, ctypes.POINTER(i32)],
+        "tyee_mesh_flip": [vp, i64, vp, i64, ctypes.POINTER(_Domain), ctypes.POINTER(i64)],
+        "tyee_mesh_relax": [vp, ctypes.POINTER(_RelaxParams), vp, i64, vp, vp, vp, vp,
+                            ctypes.POINTER(_RelaxStats)],
         "tyee_mesh_modes": [vp, vp, i32, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
                             ctypes.POINTER(_ModesStats)],
         "tyee_batch_tune_progress": [vp, i64, vp, i64, ctypes.POINTER(i64), _TUNE_PROGRESS, vp],
@@ -222,6 +239,16 @@ def _f64(a, n=None):
     return a
 
 
+def flip(xy, tri, periodic, L=1.0, Ly=None):
+    """Lawson flips (tyee_mesh_flip): returns (counter-clockwise Delaunay tri, number of flips)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    t = np.array(tri, dtype=np.int32, copy=True, order="C")
+    dom = _Domain(PERIODIC if periodic else PEC_BOX, float(L), float(L if Ly is None else Ly), 0.0)
+    n = ctypes.c_int64()
+    _check(lib.tyee_mesh_flip(_ptr(xy), len(xy), _ptr(t), len(t), ctypes.byref(dom), ctypes.byref(n)))
+    return t, n.value
+
+
 class Mesh:
     """Connectivity, FP64 geometry and locality numbering of a triangle mesh."""
 
@@ -244,6 +271,22 @@ class Mesh:
         if h is not None and h.value:
             lib.tyee_mesh_destroy(h)
             self._h = None
+
+    def relax(self, rounds=10, iters=100, step=0.05, k_edge=1.0, k_height=1.0, rest=0.0,
+              keep_best=True, anchors=None, stream=None):
+        """Jello relaxation (tyee_mesh_relax): returns (xy, tri, omega per round, stats); build
+        the relaxed mesh with Mesh(xy, tri, ...) on the same domain."""
+        prm = _RelaxParams(int(rounds), int(iters), float(step), float(k_edge), float(k_height),
+                           float(rest), 1 if keep_best else 0)
+        anc = None if anchors is None else np.ascontiguousarray(anchors, np.int32)
+        xy = np.zeros((self.nv, 2))
+        tri = np.zeros((self.nt, 3), np.int32)
+        om = np.zeros(int(rounds) + 1)
+        st = _RelaxStats()
+        _check(lib.tyee_mesh_relax(self._h, ctypes.byref(prm), _ptr(anc), 0 if anc is None else len(anc),
+                                   None if stream is None else int(stream), _ptr(xy), _ptr(tri),
+                                   _ptr(om), ctypes.byref(st)))
+        return xy, tri, om, {n: getattr(st, n) for n, _ in _RelaxStats._fields_}
 
     def reorder(self, kind, seed=0):
         _check(lib.tyee_mesh_reorder(self._h, ORDER[kind] if isinstance(kind, str) else int(kind),

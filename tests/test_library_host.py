@@ -170,3 +170,66 @@ def test_rayleigh_quotient_diagnostic_matches_oracle(ty):
     w2 = 4.0 * (3.0 - np.sum(np.cos(delta @ k)))
     expect = 2 / 0.1 * np.arcsin(np.sqrt(w2) * 0.1 / 2) / np.hypot(*k) - 1
     assert abs(m.phase_error_rq(0.1, k)[0] - expect) < 1e-12
+
+
+def _scramble_diagonals(xy, tri, periodic, seed, frac=0.3):
+    """Flip a random set of interior edges (triangle-disjoint, convex quads only): a
+    non-Delaunay triangulation of the same nodes."""
+    from meshgen.lattice import _interior_pairs
+    tri = np.array(tri, np.int32, copy=True)
+    h1, h2 = _interior_pairs(tri, len(xy))
+    rng = np.random.default_rng(seed)
+    used = set()
+
+    def rel(a, b):
+        d = xy[b] - xy[a]
+        return d - np.round(d) if periodic else d
+
+    n = 0
+    for k in rng.permutation(len(h1))[: int(frac * len(h1))]:
+        t1, q1, t2, q2 = h1[k] // 3, h1[k] % 3, h2[k] // 3, h2[k] % 3
+        if t1 in used or t2 in used:
+            continue
+        u, v, o1 = tri[t1, q1], tri[t1, (q1 + 1) % 3], tri[t1, (q1 + 2) % 3]
+        o2 = tri[t2, (q2 + 2) % 3]
+        # convex quad u, o2, v, o1: both new triangles counter-clockwise
+        cross = lambda a, b: a[0] * b[1] - a[1] * b[0]
+        c1 = cross(rel(o1, u), rel(o1, o2))
+        c2 = cross(rel(o2, v), rel(o2, o1))
+        if c1 <= 0 or c2 <= 0:
+            continue
+        tri[t1] = (o1, u, o2)
+        tri[t2] = (o2, v, o1)
+        used.update((t1, t2))
+        n += 1
+    return tri, n
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_lawson_flips_restore_the_delaunay_triangulation(ty, periodic):
+    # the Delaunay triangulation of points in general position is unique: flipping a random
+    # set of diagonals and handing the result to the library's flips must give it back
+    from meshgen import count_non_delaunay
+    xy, tri = lattice_mesh(20, 0.25, 9, periodic=periodic)
+    bad, n = _scramble_diagonals(xy, tri, periodic, 3)
+    assert n > 50 and count_non_delaunay(xy, bad, periodic) > 0
+    fixed, flips = ty.flip(xy, bad, periodic)
+    assert flips >= n and count_non_delaunay(xy, fixed, periodic) == 0
+    key = lambda t: sorted(tuple(sorted(r)) for r in np.asarray(t).tolist())
+    assert key(fixed) == key(tri)
+    # counter-clockwise output (the oracle keeps counter-clockwise rows as given), accepted by
+    # the oracle's strict Delaunay check
+    om = oracle.OracleMesh(xy, fixed, periodic)
+    assert np.array_equal(om.tri, fixed) and om.nt == len(tri)
+    again, none = ty.flip(xy, fixed, periodic)
+    assert none == 0 and np.array_equal(again, fixed)
+
+
+def test_lawson_flip_errors(ty):
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0], [0.0, 1.0]])
+    with pytest.raises(ty.TyeeError) as e:
+        ty.flip(xy, np.array([[0, 1, 2]]), False, L=2.0)
+    assert e.value.code == -3                      # degenerate
+    with pytest.raises(ty.TyeeError) as e:
+        ty.flip(xy, np.array([[0, 1, 7]]), False, L=2.0)
+    assert e.value.code == -1                      # node id out of range
