@@ -193,7 +193,7 @@ def traffic_summary(args):
     total = fetch * 1024 * fetch_scale + write * 1024 * write_scale
     cfg = {"torus1415": {"triangles": 4004450, "steps_per_launch": 4, "tile_tris": 2048,
                          "prec": "f32", "order": "morton"},
-           "plasma2830": {"triangles": 16017830, "steps_per_launch": 4, "tile_tris": 2048,
+           "plasma2830": {"triangles": 16017830, "steps_per_launch": 8, "tile_tris": 1024,
                           "prec": "f32", "order": "morton"}}[args.workload]
     out = {"kernel": "k_fused", "workload": args.workload, "source_hash": kernel_source_hash(),
            "config": cfg, "copy_fetch_kib": cf, "copy_write_kib": cw,

@@ -241,7 +241,7 @@ template <typename T> int upload_vec(Sim &s, DeviceBuffer &buf, const std::vecto
 
 int default_tile(bool f64, int K) {
     if (f64) return K >= 4 ? 1024 : 2048;
-    return K >= 8 ? 3072 : 2048;
+    return K >= 8 ? 1024 : 2048;
 }
 
 }  // namespace
