@@ -585,6 +585,71 @@ int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32_t which, i
                     void *stream, double *omega2, double *modes, double *residual,
                     tyee_modes_stats *stats);
 
+/* Work done by one tyee_mesh_spectrum call. */
+typedef struct {
+    int32_t windows;       /* spectral windows solved */
+    int32_t iters;         /* Rayleigh-Ritz steps after filter passes, over all windows */
+    int64_t found;         /* pairs accepted (n_triangles on success) */
+    int64_t applies;       /* applications of K to the whole block */
+    int64_t below;         /* converged Ritz pairs below a window's boundary, already found and
+                              discarded */
+    double lambda_bound;   /* Gershgorin bound on lambda_max */
+    double filter_ms;      /* HIP-event time of the filter launches on the stream */
+    double total_ms;       /* host wall time of the call, uploads and readback included */
+    double max_residual;   /* largest residual / lambda_bound of an accepted pair */
+    double min_gap;        /* smallest eigenvalue gap at a window boundary / lambda_bound */
+} tyee_spectrum_stats;
+
+/* Every eigenmode of the resonator: all n_triangles eigenpairs of K = -L_E L_B (the operator of
+   tyee_mesh_modes), the whole spectrum of Fig. 4 (Section 2: as many eigenvalues as B
+   components, the constant field the static one).  The paper finds the modes one after another
+   by the "complex time" iteration, withdrawing the modes already found from the start vector
+   by orthogonality in metric (7); here the same filter, deflation and Rayleigh-Ritz run window
+   by window over the spectrum in FP64 on the device:
+     window 0     the lowest modes (the low-pass filter of tyee_mesh_modes);
+     windows 1..  beta = the boundary below which every mode is found; the filter runs on
+                  (K - sigma)^2 with sigma a quarter of the block's reach above beta, whose
+                  lowest modes are K's modes nearest sigma; the start block (the last window's
+                  Ritz vectors above its boundary, the other columns random) is S-orthogonalised
+                  against the modes of the last three windows;
+     last window  the remaining top modes (the filter of lambda_bound - K).
+   Each filter pass is followed by the orthonormalisation and a Rayleigh-Ritz step.  A window
+   trusts its converged Ritz pairs taken in order of ||(K - sigma) v|| up to the first one that
+   has not converged (every mode closer to sigma than that one is among them), and accepts those
+   at or above beta up to a boundary placed in the widest gap (>= 16 tol lambda_bound) of their
+   top fifth, once 0.6 x block of them are trusted (or the trusted set stops growing).  Modes
+   found before that grow back below beta are set aside (stats->below).  The cost of a window
+   grows with the spread of the spectrum over the window's width: meshes with nearly cocircular
+   quads (very large lambda_bound) need high filter degrees.  n_triangles <= block: one exact
+   Rayleigh-Ritz step.
+     gamma     [n_edges] per-edge scale in canonical order, or NULL.
+     block     vectors iterated, min(n_triangles, 16) .. min(n_triangles, 256); 0 chooses
+               min(n_triangles, 192).  n_triangles x block < 2^31.
+     degree    largest filter degree per pass in applications of K, 2 .. 100000; 0 = no limit
+               beyond the conditioning cap of tyee_mesh_modes (growth from the bottom of the
+               filter interval to the cut at most 2e7).
+     tol       a pair is converged when ||K v - lambda v||_S <= tol * lambda_bound (v
+               S-normalised); an eigenvalue is then within tol * lambda_bound of lambda.  Modes
+               of different windows are S-orthogonal to about tol * lambda_bound / (their gap).
+     max_iter  Rayleigh-Ritz steps allowed per window (>= 1).
+     seed      window w starts its random columns as in tyee_mesh_modes with seed
+               seed + w n_triangles block.
+     stream    HIP stream, or NULL for the default stream.
+     omega2    [n_triangles] host out: lambda ascending.
+     modes     [n_triangles][n_triangles] host out (mode-major, canonical triangle order,
+               S-normalised), or NULL.
+     residual  [n_triangles] host out: residual / lambda_bound, or NULL.
+     stats     host out, or NULL.
+   Allocates about 8 (9 with modes) x n_triangles x block doubles of device memory for the call
+   and frees it; blocks on the stream.  Set TYEE_SPECTRUM_TRACE in the environment for one line
+   per Rayleigh-Ritz step on stderr.  Errors: EINVAL (arguments; a mesh with no interior edge),
+   ENOMEM, EDEVICE, EUNSTABLE (the block lost rank; more converged modes above the last boundary
+   than remain), ENOTCONVERGED (a window did not converge within max_iter; the first
+   stats->found outputs are written). */
+int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, int32_t block, int32_t degree,
+                       double tol, int32_t max_iter, uint64_t seed, void *stream, double *omega2,
+                       double *modes, double *residual, tyee_spectrum_stats *stats);
+
 const char *tyee_last_error(void);
 
 #ifdef __cplusplus

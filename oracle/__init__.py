@@ -226,29 +226,29 @@ class OracleMesh:
                            shape=(self.nt, self.ne))
         return LB, LE
 
-    def modes(self, count, gamma=None, which="lowest"):
-        """Lowest (or highest) `count` eigenpairs of K = -L_E L_B, the operator that eqs. 3-4
-        give for B once E is eliminated (Section 2, eigenvectors and the "complex time" method).
+    def modes(self, count, gamma=None, which="lowest", sigma=0.0):
+        """Lowest (or highest, or with which="nearest" nearest to sigma) `count` eigenpairs of
+        K = -L_E L_B, the operator that eqs. 3-4 give for B once E is eliminated (Section 2,
+        eigenvectors and the "complex time" method).
 
         K is self-adjoint and non-negative in the B part of metric (7) (weights S_j), so
         S^(1/2) K S^(-1/2) is symmetric; its eigenpairs come from a library symmetric solver
         (dense for up to 4,000 triangles, else sparse: shift-invert about a point just below
-        zero for the lowest, the largest algebraic ones directly for the highest). Returns
-        (lam [count], V [n_t, count]) with sum_j S_j V_jc V_jd = delta_cd, lam ascending for
-        "lowest" and descending for "highest"; omega = sqrt(lam). The constant B is the static
-        mode (lam = 0).
+        zero for the lowest, the largest algebraic ones directly for the highest; "nearest" is
+        always sparse shift-invert about sigma). Returns (lam [count], V [n_t, count]) with
+        sum_j S_j V_jc V_jd = delta_cd, lam ascending for "lowest" and "nearest" and descending
+        for "highest"; omega = sqrt(lam). The constant B is the static mode (lam = 0).
         """
         import scipy.linalg
-        import scipy.sparse as sp
         import scipy.sparse.linalg as sla
         count = int(count)
-        if not 1 <= count <= self.nt or which not in ("lowest", "highest"):
+        if not 1 <= count <= self.nt or which not in ("lowest", "highest", "nearest"):
             raise OracleError(EINVAL, "modes count or which")
-        LB, LE = self.sparse_ops(gamma)
-        K = -(LE @ LB)
-        rs, irs = np.sqrt(self.S), 1.0 / np.sqrt(self.S)
-        A = sp.diags(rs) @ K @ sp.diags(irs)
-        A = 0.5 * (A + A.T)
+        A, irs = self._symmetric_k(gamma)
+        if which == "nearest":
+            lam, U = sla.eigsh(A.tocsc(), k=count, sigma=float(sigma), which="LM", tol=1e-14)
+            order = np.argsort(lam)
+            return lam[order], irs[:, None] * U[:, order]
         if self.nt <= 4000:
             lo = 0 if which == "lowest" else self.nt - count
             lam, U = scipy.linalg.eigh(A.toarray(), subset_by_index=[lo, lo + count - 1])
@@ -259,6 +259,31 @@ class OracleMesh:
             lam, U = sla.eigsh(A.tocsc(), k=count, which="LA", tol=1e-14)
         order = np.argsort(lam) if which == "lowest" else np.argsort(-lam)
         lam, U = lam[order], U[:, order]
+        return lam, irs[:, None] * U
+
+    def _symmetric_k(self, gamma=None):
+        """S^(1/2) K S^(-1/2) (sparse, symmetrised) and S^(-1/2)."""
+        import scipy.sparse as sp
+        LB, LE = self.sparse_ops(gamma)
+        K = -(LE @ LB)
+        rs, irs = np.sqrt(self.S), 1.0 / np.sqrt(self.S)
+        A = sp.diags(rs) @ K @ sp.diags(irs)
+        return 0.5 * (A + A.T), irs
+
+    def spectrum(self, gamma=None, vectors=True):
+        """Every eigenpair of K = -L_E L_B (Section 2, Fig. 4: as many eigenvalues as B
+        components, counted with the static constant field).
+
+        The symmetric S^(1/2) K S^(-1/2) is formed densely and handed to a library dense
+        symmetric eigensolver (divide and conquer): n_t^2 doubles of memory and O(n_t^3) work,
+        about two minutes at 16,500 triangles without vectors.  Returns (lam [n_t] ascending,
+        V [n_t, n_t] with S-orthonormal columns, or None).
+        """
+        import scipy.linalg
+        A, irs = self._symmetric_k(gamma)
+        if not vectors:
+            return scipy.linalg.eigh(A.toarray(), eigvals_only=True, driver="evd"), None
+        lam, U = scipy.linalg.eigh(A.toarray(), driver="evd")
         return lam, irs[:, None] * U
 
     # -- media and sources defined on the input ----------------------------------------

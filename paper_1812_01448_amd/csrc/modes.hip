@@ -153,6 +153,74 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply2(
     }
 }
 
+// y_out = alpha * ((K - sigma)^2 y) + beta * y + gam * y_prev (y_prev may be null), in one pass:
+// row j of (K - sigma)^2 y needs (K - sigma) y at j and at its neighbours k, and those need the
+// neighbours of k, so a wave (one row) reads up to ten rows of y (the two-ring of j, mostly
+// from the caches: neighbouring rows are close in the locality numbering).  The weights,
+// neighbour slots and 1/S of the ring are wave-uniform.  Columns in chunks of 64.
+template <int CH>                // 64-column chunks per row: ceil(nb / 64)
+__global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply_sq(
+    int32_t n, int32_t nb, const double *__restrict__ y, const double *__restrict__ yp, double *__restrict__ yo,
+    const int32_t *__restrict__ nbr, const double *__restrict__ wt, const double *__restrict__ inv_s, double sigma,
+    double alpha, double beta, double gam) {
+    const int j = __builtin_amdgcn_readfirstlane(xcd_group(blockIdx.x, gridDim.x) * kApplyWaves +
+                                                 int(threadIdx.x >> 6));
+    if (j >= n) return;
+    const int lane = threadIdx.x & 63;
+    int32_t o[3], oo[3][3];
+    double w[3], ww[3][3], isk[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        o[q] = nbr[3 * j + q];
+        w[q] = wt[3 * j + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int k = o[q] >= 0 ? o[q] : j;   // a missing neighbour reads row j (not used)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            oo[q][p] = nbr[3 * k + p];
+            ww[q][p] = wt[3 * k + p];
+        }
+        isk[q] = inv_s[k];
+    }
+    const double isj = inv_s[j];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int c = min(lane + 64 * ch, nb - 1);
+        const double yj = y[size_t(j) * nb + c];
+        double yk[3], ykk[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int k = o[q] >= 0 ? o[q] : j;
+            yk[q] = y[size_t(k) * nb + c];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) ykk[q][p] = y[size_t(oo[q][p] >= 0 ? oo[q][p] : k) * nb + c];
+        }
+        const double pv = yp ? yp[size_t(j) * nb + c] : 0.0;
+        // t = (K - sigma) y at j and at the neighbours
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (o[q] >= 0) acc += w[q] * (yj - yk[q]);
+        const double tj = acc * isj - sigma * yj;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (o[q] < 0) continue;
+            double ak = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                if (oo[q][p] >= 0) ak += ww[q][p] * (yk[q] - ykk[q][p]);
+            const double tk = ak * isk[q] - sigma * yk[q];
+            s += w[q] * (tj - tk);
+        }
+        double out = alpha * (s * isj - sigma * tj) + beta * yj;
+        if (yp) out += gam * pv;
+        if (lane + 64 * ch < nb) yo[size_t(j) * nb + c] = out;
+    }
+}
+
 // partial[chunk][p][q] = sum over the chunk's rows j of S_j x[j][p] z[j][q], on the FP64
 // matrix cores: per step of 4 rows, v_mfma_f64_16x16x4 takes (S x)^T as the 16 x 4 operand
 // (lane l: column p0 + l % 16 of row l / 16) and z as the 4 x 16 one (lane l: row l / 16,
@@ -233,7 +301,8 @@ __global__ void k_sum_chunks(int32_t chunks, int32_t len, const double *__restri
     out[k] = acc;
 }
 
-// y[j][c] = sum_k x[j][k] m[k][c]  (m upper triangular when upper != 0), on the FP64 matrix
+// y[j][c] = sum_k x[j][k] m[k][c]  (m upper triangular when upper != 0), or with `sub` given,
+// y[j][c] = sub[j][c] - sum_k x[j][k] m[k][c] (sub may be y itself), on the FP64 matrix
 // cores: v_mfma_f64_16x16x4 multiplies a 16 x 4 tile of x (lane l holds row l % 16, k l / 16)
 // by a 4 x 16 tile of m (lane l holds k l / 16, column l % 16) into a 16 x 16 tile of y (lane l
 // holds rows 4 i + l / 16, i < 4, column l % 16).  A work-group takes 16 kRotWaves rows (16
@@ -244,8 +313,8 @@ constexpr int kRotTiles = 2;
 constexpr int kRotK = 32;
 
 __global__ void __launch_bounds__(64 * kRotWaves) k_rotate(int32_t n, int32_t nb, const double *__restrict__ x,
-                                                           const double *__restrict__ m, double *__restrict__ y,
-                                                           int32_t upper) {
+                                                           const double *__restrict__ m, double *y,
+                                                           int32_t upper, const double *sub) {
     constexpr int kCols = 16 * kRotTiles;
     __shared__ double ms[kRotK][kCols + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -293,7 +362,7 @@ __global__ void __launch_bounds__(64 * kRotWaves) k_rotate(int32_t n, int32_t nb
         for (int i = 0; i < 4; ++i) {
             const int64_t row = r0 + 16 * w + 4 * i + (lane >> 4);
             const int col = c0 + 16 * t + (lane & 15);
-            if (row < n && col < nb) y[row * nb + col] = acc[t][i];
+            if (row < n && col < nb) y[row * nb + col] = sub ? sub[row * nb + col] - acc[t][i] : acc[t][i];
         }
 }
 
@@ -1099,17 +1168,52 @@ __global__ void k_residual(int32_t n, int32_t nb, int32_t rows_per_chunk, const 
     partial[size_t(blockIdx.x) * nb + c] = acc;
 }
 
-// x[j][c] = 2 u - 1 with u = (splitmix64(seed + j nb + c) >> 11) 2^-53 (canonical j)
+// x[j][c] = 2 u - 1 with u = (splitmix64(seed + j nb + c) >> 11) 2^-53 (canonical j), for the
+// columns c with flags[c] != 0 (every column when flags is null; the others are left as they are)
 __global__ void k_random_block(int32_t n, int32_t nb, const int32_t *__restrict__ canon, uint64_t seed,
-                               double *__restrict__ x) {
+                               double *__restrict__ x, const int32_t *__restrict__ flags) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= uint32_t(n) * uint32_t(nb)) return;
     const uint32_t j = g / uint32_t(nb), c = g - j * uint32_t(nb);
+    if (flags && !flags[c]) return;
     uint64_t z = seed + uint64_t(canon[j]) * uint64_t(nb) + c + 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     x[g] = 2.0 * (double(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+// x[j][c] = 0 for the columns with flags[c] == 0
+__global__ void k_keep_columns(int32_t n, int32_t nb, const int32_t *__restrict__ flags, double *__restrict__ x) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= uint32_t(n) * uint32_t(nb)) return;
+    if (!flags[g % uint32_t(nb)]) x[g] = 0.0;
+}
+
+// out[i][canon[j]] = x[j][cols[i]] for i < count: block columns transposed into canonical
+// triangle order.  A work-group moves a 64-row x 16-column tile through LDS (reads along the
+// row, writes along the triangles).
+constexpr int kExportRows = 64, kExportCols = 16;
+__global__ void __launch_bounds__(256) k_export_columns(int32_t n, int32_t nb, const double *__restrict__ x,
+                                                        const int32_t *__restrict__ canon,
+                                                        const int32_t *__restrict__ cols, int32_t count,
+                                                        double *__restrict__ out) {
+    __shared__ double tile[kExportCols][kExportRows + 1];
+    const int tid = threadIdx.x;
+    const int64_t j0 = int64_t(blockIdx.x) * kExportRows;
+    const int i0 = int(blockIdx.y) * kExportCols;
+    for (int e = tid; e < kExportRows * kExportCols; e += blockDim.x) {
+        const int r = e / kExportCols, c = e % kExportCols;
+        const int64_t j = j0 + r;
+        tile[c][r] = j < n && i0 + c < count ? x[j * nb + cols[i0 + c]] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < kExportRows * kExportCols; e += blockDim.x) {
+        const int c = e / kExportRows, r = e % kExportRows;
+        const int64_t j = j0 + r;
+        const int i = i0 + c;
+        if (j < n && i < count) out[int64_t(i) * n + canon[j]] = tile[c][r];
+    }
 }
 
 struct EventPair {
@@ -1130,11 +1234,14 @@ struct ModeSolver {
     DeviceBuffer arena;                // one allocation that the buffers below are views of
     DeviceBuffer nbr, wt, inv_s, s, canon;
     DeviceBuffer buf[5];               // block-sized buffers
+    DeviceBuffer xb[4];                // further block-sized buffers (the spectrum's locked windows)
     DeviceBuffer g, m, h, q, work, theta, partial, small_i, rot, order;
+    DeviceBuffer cols;                 // 3 nb int32: a column list and two column flag arrays
 
     double *B(int i) const { return buf[i].as<double>(); }
 
-    int alloc(const Mesh &mesh, const double *gamma, int32_t nblock, double *upper) {
+    // `extra` (<= 4) further block-sized buffers in xb
+    int alloc(const Mesh &mesh, const double *gamma, int32_t nblock, double *upper, int extra = 0) {
         n = int32_t(mesh.nt);
         nb = nblock;
         const int64_t nt = mesh.nt;
@@ -1168,14 +1275,15 @@ struct ModeSolver {
         const size_t sq = size_t(nb) * nb * sizeof(double);
         const int np = nb + (nb & 1);
         // every device buffer is a 256-byte aligned view of one allocation
-        const std::pair<DeviceBuffer *, size_t> parts[] = {
+        std::vector<std::pair<DeviceBuffer *, size_t>> parts = {
             {&buf[0], blk}, {&buf[1], blk}, {&buf[2], blk}, {&buf[3], blk}, {&buf[4], blk},
             {&nbr, hn.size() * 4}, {&wt, hw.size() * 8}, {&inv_s, size_t(nt) * 8}, {&s, size_t(nt) * 8},
             {&canon, size_t(nt) * 4}, {&g, sq}, {&m, sq}, {&h, sq}, {&q, sq}, {&work, sq},
             {&theta, size_t(nb) * 8}, {&partial, size_t(chunks) * nb * nb * sizeof(double)},
             {&small_i, 2 * sizeof(int32_t)},
             {&rot, size_t(kJacobiSweeps) * (np - 1) * (np / 2) * sizeof(double2)},
-            {&order, size_t(nb) * sizeof(int32_t)}};
+            {&order, size_t(nb) * sizeof(int32_t)}, {&cols, size_t(3) * nb * sizeof(int32_t)}};
+        for (int i = 0; i < std::min(extra, 4); ++i) parts.push_back({&xb[i], blk});
         auto aligned = [](size_t b) { return (b + 255) / 256 * 256; };
         size_t total = 0;
         for (const auto &pt : parts) total += aligned(pt.second);
@@ -1238,6 +1346,21 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
+    // yo = alpha (K - sigma)^2 y + beta y + gam yp, one launch
+    int apply_sq(const double *y, const double *yp, double *yo, double sigma, double alpha, double beta, double gam) {
+        const dim3 grid((n + kApplyWaves - 1) / kApplyWaves), threads(64 * kApplyWaves);
+        const int32_t *nb_ = nbr.as<int32_t>();
+        const double *wt_ = wt.as<double>(), *is_ = inv_s.as<double>();
+        switch ((nb + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_modes_apply_sq<1>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, sigma, alpha, beta, gam); break;
+        case 2: hipLaunchKernelGGL(k_modes_apply_sq<2>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, sigma, alpha, beta, gam); break;
+        case 3: hipLaunchKernelGGL(k_modes_apply_sq<3>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, sigma, alpha, beta, gam); break;
+        default: hipLaunchKernelGGL(k_modes_apply_sq<4>, grid, threads, 0, st, n, nb, y, yp, yo, nb_, wt_, is_, sigma, alpha, beta, gam); break;
+        }
+        TYEE_HIP(hipGetLastError());
+        return TYEE_OK;
+    }
+
     // out (nb x nb) = x^T S z
     int gram(const double *x, const double *z, double *out) {
         const int bt = (nb + 31) / 32;
@@ -1251,10 +1374,10 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
-    int rotate(const double *x, const double *mat, double *y, bool upper) {
+    int rotate(const double *x, const double *mat, double *y, bool upper, const double *sub = nullptr) {
         const int rows = 16 * kRotWaves, cols = 16 * kRotTiles;
         hipLaunchKernelGGL(k_rotate, dim3(((n + rows - 1) / rows) * ((nb + cols - 1) / cols)), dim3(64 * kRotWaves), 0,
-                           st, n, nb, x, mat, y, int32_t(upper));
+                           st, n, nb, x, mat, y, int32_t(upper), sub);
         TYEE_HIP(hipGetLastError());
         return TYEE_OK;
     }
@@ -1379,6 +1502,44 @@ struct ModeSolver {
         return TYEE_OK;
     }
 
+    // Deflation in metric (7): x <- x - V (V^T S x) for each locked block V in xb (S-orthonormal
+    // columns, the unused ones zero), in place in buffer ix.
+    int project(int ix, const std::vector<int> &locked) {
+        for (int l : locked) {
+            int rc = gram(xb[l].as<double>(), B(ix), g.as<double>());
+            if (!rc) rc = rotate(xb[l].as<double>(), g.as<double>(), B(ix), false, B(ix));
+            if (rc) return rc;
+        }
+        return TYEE_OK;
+    }
+
+    // The filter below run on (K - sigma)^2, whose spectrum lies in [0, mu_max] and whose lowest
+    // modes are the modes of K nearest sigma: degree-k Chebyshev damping of [a, mu_max] with
+    // growth measured from mu = 0, each step one launch of the fused (K - sigma)^2 apply.  Reads
+    // buffer `in`, rotates through three others; the result lands in buffer *out.
+    int filter_sq(int in, int degree, double a, double mu_max, double sigma, int *out) {
+        const double e = 0.5 * (mu_max - a), c = 0.5 * (mu_max + a);
+        const double sigma1 = -e / c;
+        double sg = sigma1;
+        const int w0 = pick({in}), w1 = pick({in, w0}), w2 = pick({in, w0, w1});
+        // y1 = (sigma1 / e) ((K - sigma)^2 - c) y0
+        int rc = apply_sq(B(in), nullptr, B(w0), sigma, sigma1 / e, -sigma1 * c / e, 0.0);
+        if (rc) return rc;
+        int prev = in, cur = w0;
+        for (int k = 2; k <= degree; ++k) {
+            const double sn = 1.0 / (2.0 / sigma1 - sg);
+            const int nxt = (w0 != cur && w0 != prev) ? w0 : (w1 != cur && w1 != prev) ? w1 : w2;
+            // y_k = (2 sn / e) ((K - sigma)^2 - c) y_{k-1} - sg sn y_{k-2}
+            rc = apply_sq(B(cur), B(prev), B(nxt), sigma, 2.0 * sn / e, -2.0 * sn * c / e, -sg * sn);
+            if (rc) return rc;
+            prev = cur;
+            cur = nxt;
+            sg = sn;
+        }
+        *out = cur;
+        return TYEE_OK;
+    }
+
     // Degree-k filter of the block in buffer `in` damping [a, b_up] with a0 the estimate of
     // the lowest eigenvalue; it rotates through three other buffers (`in` is only read) and
     // the result lands in buffer *out.
@@ -1446,7 +1607,7 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
         sv.top = b_up;  // top - K has its spectrum in [0, b_up] too
         // random start, S-orthonormalised, then a first Rayleigh-Ritz for the bounds
         hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
-                           sv.canon.as<int32_t>(), seed, sv.B(0));
+                           sv.canon.as<int32_t>(), seed, sv.B(0), nullptr);
         TYEE_HIP(hipGetLastError());
         int ob = 1;
         // a tall random block is well conditioned: one Cholesky QR leaves it orthonormal to
@@ -1539,6 +1700,401 @@ extern "C" int tyee_mesh_modes(const tyee_mesh *mesh, const double *gamma, int32
             }
         }
         return done ? TYEE_OK : fail(TYEE_ENOTCONVERGED, "mode residuals above tol after max_iter iterations");
+    } catch (const std::bad_alloc &) {
+        return fail(TYEE_ENOMEM, "host allocation failed");
+    }
+}
+
+
+namespace tyee {
+namespace {
+
+constexpr int64_t kSpectrumBlock = 192;   // default block of the whole-spectrum solver
+constexpr int kLocked = 3;                // windows kept for deflation (xb[0..2]; xb[3] stages exports)
+
+// Rows row0.. of the host matrix modes[n_t][n_t] (canonical triangle order) from the block
+// columns listed first in sv.cols (count of them, in that order), through xb[3].
+int export_modes(ModeSolver &sv, int vb, int64_t count, double *modes, int64_t row0) {
+    if (!modes || count <= 0) return TYEE_OK;
+    const dim3 grid((sv.n + kExportRows - 1) / kExportRows, unsigned((count + kExportCols - 1) / kExportCols));
+    hipLaunchKernelGGL(k_export_columns, grid, dim3(256), 0, sv.st, sv.n, sv.nb, sv.B(vb), sv.canon.as<int32_t>(),
+                       sv.cols.as<int32_t>(), int32_t(count), sv.xb[3].as<double>());
+    TYEE_HIP(hipGetLastError());
+    TYEE_HIP(hipMemcpyAsync(modes + row0 * sv.n, sv.xb[3].p, size_t(count) * sv.n * sizeof(double),
+                            hipMemcpyDeviceToHost, sv.st));
+    TYEE_HIP(hipStreamSynchronize(sv.st));
+    return TYEE_OK;
+}
+
+bool spectrum_trace() {
+    static const bool on = std::getenv("TYEE_SPECTRUM_TRACE") != nullptr;
+    return on;
+}
+
+}  // namespace
+}  // namespace tyee
+
+extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, int32_t block, int32_t degree,
+                                  double tol, int32_t max_iter, uint64_t seed, void *stream, double *omega2,
+                                  double *modes, double *residual, tyee_spectrum_stats *stats) {
+    using namespace tyee;
+    if (!mesh || !omega2) return fail(TYEE_EINVAL, "null argument");
+    const Mesh &msh = mesh->m;
+    const int64_t nt = msh.nt;
+    int64_t nb = block;
+    if (nb == 0) nb = std::min<int64_t>(nt, kSpectrumBlock);
+    if (nb < std::min<int64_t>(nt, 16) || nb > std::min<int64_t>(nt, kMaxBlock))
+        return fail(TYEE_EINVAL, "block must be in min(n_triangles, 16) .. min(n_triangles, 256)");
+    if (nt * nb >= (int64_t(1) << 31)) return fail(TYEE_EINVAL, "n_triangles x block must be below 2^31");
+    if (degree == 0) degree = 100000;
+    if (degree < 2 || degree > 100000) return fail(TYEE_EINVAL, "degree must be in 2 .. 100000");
+    if (!(tol > 0.0) || max_iter < 1) return fail(TYEE_EINVAL, "tol > 0 and max_iter >= 1 required");
+    const auto t_start = std::chrono::steady_clock::now();
+    tyee_spectrum_stats st{};
+    auto finish = [&](int rc) {
+        st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        if (stats) *stats = st;
+        return rc;
+    };
+    try {
+        ModeSolver sv;
+        sv.st = static_cast<hipStream_t>(stream);
+        EventPair ev;
+        TYEE_HIP(hipEventCreate(&ev.a));
+        TYEE_HIP(hipEventCreate(&ev.b));
+        double b_up = 0.0;
+        int rc = sv.alloc(msh, gamma, int32_t(nb), &b_up, modes ? kLocked + 1 : kLocked);
+        if (rc) return rc;
+        if (!(b_up > 0.0)) return fail(TYEE_EINVAL, "mesh has no interior edge");
+        st.lambda_bound = b_up;
+        sv.top = b_up;  // lambda_bound - K has its spectrum in [0, b_up] too
+        const double res_tol = tol * b_up;
+        const double off_floor = (1e-3 * res_tol) * (1e-3 * res_tol);
+        std::vector<double> ritz, res;
+        // host copy of sv.cols: the accepted columns in output order, the columns to keep in the
+        // locked copy, the columns to restart at random in the next window
+        std::vector<int32_t> hcols(size_t(3) * nb, 0);
+        auto upload_cols = [&]() -> int {
+            TYEE_HIP(hipMemcpyAsync(sv.cols.p, hcols.data(), hcols.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    sv.st));
+            TYEE_HIP(hipStreamSynchronize(sv.st));
+            return TYEE_OK;
+        };
+        auto accept_outputs = [&](const std::vector<int64_t> &acc, const std::vector<double> &val, int64_t row0,
+                                  int vb) -> int {
+            for (size_t i = 0; i < acc.size(); ++i) {
+                omega2[row0 + int64_t(i)] = val[i];
+                st.max_residual = std::max(st.max_residual, res[acc[i]] / b_up);
+                if (residual) residual[row0 + int64_t(i)] = res[acc[i]] / b_up;
+                hcols[i] = int32_t(acc[i]);
+            }
+            int rc2 = upload_cols();
+            if (!rc2) rc2 = export_modes(sv, vb, int64_t(acc.size()), modes, row0);
+            return rc2;
+        };
+
+        if (nb == nt) {
+            // the block spans the whole space: one Rayleigh-Ritz step is exact
+            hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
+                               sv.canon.as<int32_t>(), seed, sv.B(0), nullptr);
+            TYEE_HIP(hipGetLastError());
+            int ob = 0;
+            rc = sv.orthonormalise(0, 1, &ob);
+            const int spare = ModeSolver::pick({ob}), vb = ModeSolver::pick({ob, spare}),
+                      kvb = ModeSolver::pick({ob, spare, vb});
+            if (!rc) rc = sv.rayleigh_ritz(ob, spare, vb, kvb, ritz, kJacobiSweeps, off_floor);
+            if (!rc) rc = sv.residuals(vb, kvb, res);
+            if (rc) return finish(rc);
+            std::vector<int64_t> acc(nt);
+            for (int64_t c = 0; c < nt; ++c) acc[c] = c;
+            rc = accept_outputs(acc, ritz, 0, vb);
+            if (rc) return finish(rc);
+            st.windows = 1;
+            st.applies = 1;
+            st.found = nt;
+            for (int64_t c = 0; c < nt; ++c)
+                if (!(res[c] <= res_tol)) return finish(fail(TYEE_ENOTCONVERGED, "mode residuals above tol"));
+            return finish(TYEE_OK);
+        }
+
+        // Spectrum slicing.  Window 0 takes the lowest modes with the low-pass filter of K; each
+        // further window filters with (K - sigma)^2, beta being the boundary below which every
+        // mode is already found; the last window takes the remaining top modes with the low-pass
+        // filter of lambda_bound - K.  A window's start block is S-orthogonalised against the
+        // modes of the last windows (deflation in metric (7), as the paper withdraws the found
+        // eigenvectors from the initial vector), and the filter passes then run without
+        // projections: a projection in every pass would hold the block exactly orthogonal to
+        // modes that are themselves only accurate to the tolerance, and that error would pass on
+        // from window to window.  Found modes that grow back are recognised below beta and set
+        // aside.  sigma sits a quarter of the block's reach R above beta (R^2 = the largest mu of
+        // the block, below), so that the ball of radius R about sigma reaches down past beta;
+        // sigma moves down when the reach shrinks (the spectrum gets denser).
+        //
+        // Which Ritz pairs a window may accept: the filter favours the block's directions by
+        // mu = ||(K - z) v||^2 = res^2 + (theta - z)^2 (z = sigma, or the bottom of the filtered
+        // operator's spectrum), so every mode with a smaller mu than a converged Ritz vector is
+        // in the block and converged before it.  The trusted set is the block's converged Ritz
+        // pairs taken in order of mu up to the first one that has not converged, and it holds
+        // every mode with (lambda - z)^2 below that one's mu; unconverged vectors (mixtures from
+        // both sides of sigma) may have Ritz values anywhere and are passed over.  A window is
+        // accepted once that ball reaches down to beta, with its boundary in the widest gap
+        // among the trusted Ritz values, so that each eigenvalue is accepted exactly once.
+        enum { kLinear, kSquared, kTop };
+        const int64_t target = (3 * nb + 4) / 5;     // pairs a window aims to accept
+        const double gap_min = 16.0 * res_tol;      // a boundary gap the Ritz errors cannot cross
+        constexpr double kSigmaAt = 0.25, kSigmaMax = 0.35;   // sigma - beta in units of the reach
+        int64_t accepted = 0;
+        double beta = -HUGE_VAL, sigma = 0.0, a_hint = 0.0, min_gap = HUGE_VAL;
+        std::vector<int> locked;                    // xb indices of the windows deflated against
+        int next_slot = 0;
+        int vb = -1, kvb = -1;                      // Ritz vectors of the last window, K times them
+        std::vector<double> mu(nb);
+        std::vector<int64_t> by_mu(nb);
+        // the block's reach in mu: its largest mu (the pass band of the filter then holds at
+        // least as many modes as the block has vectors)
+        auto reach_of = [&](const std::vector<double> &m) { return *std::max_element(m.begin(), m.end()); };
+        for (int32_t win = 0; accepted < nt; ++win) {
+            const int64_t remaining = nt - accepted;
+            const int mode = win == 0 ? kLinear : remaining <= target ? kTop : kSquared;
+            sv.reversed = mode == kTop;
+            // start: the last window's block with its accepted and stale columns restarted at random
+            int x0 = 0;
+            if (vb >= 0) {
+                x0 = ModeSolver::pick({vb});
+                TYEE_HIP(hipMemcpyAsync(sv.B(x0), sv.B(vb), size_t(nt) * nb * sizeof(double),
+                                        hipMemcpyDeviceToDevice, sv.st));
+            }
+            hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
+                               sv.canon.as<int32_t>(), seed + uint64_t(win) * uint64_t(nt) * uint64_t(nb), sv.B(x0),
+                               vb >= 0 ? sv.cols.as<int32_t>() + 2 * nb : nullptr);
+            TYEE_HIP(hipGetLastError());
+            rc = sv.project(x0, locked);
+            int ob = x0;
+            if (!rc) rc = sv.orthonormalise(x0, ModeSolver::pick({x0}), &ob);
+            if (rc == TYEE_EUNSTABLE && vb >= 0) {
+                // the kept columns were too close to the deflated modes: all columns at random
+                hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
+                                   sv.canon.as<int32_t>(), seed + uint64_t(win) * uint64_t(nt) * uint64_t(nb),
+                                   sv.B(x0), nullptr);
+                TYEE_HIP(hipGetLastError());
+                rc = sv.project(x0, locked);
+                if (!rc) rc = sv.orthonormalise(x0, ModeSolver::pick({x0}), &ob);
+            }
+            int spare = ModeSolver::pick({ob});
+            vb = ModeSolver::pick({ob, spare});
+            kvb = ModeSolver::pick({ob, spare, vb});
+            if (!rc) rc = sv.rayleigh_ritz(ob, spare, vb, kvb, ritz, kStartSweeps, off_floor);
+            if (!rc) rc = sv.residuals(vb, kvb, res);
+            if (rc) return finish(rc);
+            st.applies += 1;
+            std::vector<int64_t> acc, below_cols, warm;
+            std::vector<double> acc_val;
+            double new_beta = beta, worst_wanted = HUGE_VAL;
+            int64_t prev_trusted = -1;
+            int stalled = 0;                       // iterations without more trusted pairs
+            for (int32_t it = 0;; ++it) {
+                const bool last_try = it >= max_iter;
+                // trusted set: converged pairs in order of mu up to the first unconverged one
+                for (int64_t c = 0; c < nb; ++c) {
+                    const double z = mode == kSquared ? ritz[c] - sigma : ritz[c];
+                    mu[c] = res[c] * res[c] + z * z;
+                    by_mu[c] = c;
+                }
+                std::stable_sort(by_mu.begin(), by_mu.end(), [&](int64_t x, int64_t y) { return mu[x] < mu[y]; });
+                std::vector<int64_t> good;                 // trusted, at or above beta, by K-value
+                below_cols.clear();
+                int64_t trusted = 0;
+                for (; trusted < nb && res[by_mu[trusted]] <= res_tol; ++trusted) {
+                    const int64_t c = by_mu[trusted];
+                    const double lam = mode == kTop ? b_up - ritz[c] : ritz[c];
+                    if (lam >= beta) good.push_back(c);
+                    else below_cols.push_back(c);
+                }
+                // the trusted ball holds every mode with (lambda - sigma)^2 below mu_stop
+                const double mu_stop = trusted < nb ? mu[by_mu[trusted]] : HUGE_VAL;
+                const bool covers_beta = mode != kSquared || (sigma - beta) * (sigma - beta) < mu_stop;
+                auto lam_of = [&](int64_t c) { return mode == kTop ? b_up - ritz[c] : ritz[c]; };
+                std::sort(good.begin(), good.end(), [&](int64_t x, int64_t y) { return lam_of(x) < lam_of(y); });
+                // the residuals still to come down: the wanted pairs not yet trusted
+                const int64_t wanted = mode == kTop ? remaining : std::min(target, remaining - 1) + 1;
+                worst_wanted = 0.0;
+                for (int64_t k = 0; k < std::min<int64_t>(nb, wanted); ++k) worst_wanted = std::max(worst_wanted, res[by_mu[k]]);
+                bool done = false;
+                if (mode == kTop) {
+                    if (int64_t(good.size()) > remaining)
+                        return finish(fail(TYEE_EUNSTABLE, "more converged modes above the boundary than remain"));
+                    if (int64_t(good.size()) == remaining) {
+                        acc = good;
+                        done = true;
+                    }
+                } else {
+                    // a block that holds no more trusted pairs than before (its ball cannot grow:
+                    // a sparse part of the spectrum, the rest of the block below beta) settles
+                    // for what it has
+                    stalled = trusted > 0 && trusted <= prev_trusted ? stalled + 1 : 0;
+                    prev_trusted = trusted;
+                    const int64_t g = int64_t(good.size());
+                    const bool settle = last_try || trusted == nb || stalled >= 2;
+                    // once target pairs are trusted (or the block has settled), take all but the
+                    // last of them, cut in the widest gap of the top fifth, else anywhere
+                    const int64_t want = std::min(g - 1, remaining - 1);
+                    if (covers_beta && want >= 1 && (g >= target + 1 || settle)) {
+                        double best = -1.0;
+                        int64_t cut = -1;
+                        for (int pass = 0; pass < 2 && best < gap_min; ++pass)
+                            for (int64_t k = pass == 0 ? (4 * want) / 5 : 0; k < want; ++k) {
+                                const double gap = lam_of(good[k + 1]) - lam_of(good[k]);
+                                if (gap > best) {
+                                    best = gap;
+                                    cut = k;
+                                }
+                            }
+                        if (best >= gap_min) {
+                            acc.assign(good.begin(), good.begin() + cut + 1);
+                            warm.assign(good.begin() + cut + 1, good.end());
+                            new_beta = 0.5 * (lam_of(good[cut]) + lam_of(good[cut + 1]));
+                            min_gap = std::min(min_gap, best / b_up);
+                            done = true;
+                        }
+                    }
+                }
+                if (spectrum_trace()) {
+                    std::fprintf(stderr,
+                                 "[spectrum] win %d mode %d it %d beta %.9g sigma %.9g trusted %lld good %lld below %zu "
+                                 "covers %d worst %.2e%s |",
+                                 win, mode, it, beta, sigma, (long long)trusted, (long long)good.size(), below_cols.size(),
+                                 int(covers_beta), worst_wanted / b_up, done ? " accept" : "");
+                    for (int64_t k = 0; k < std::min<int64_t>(nb, 4); ++k)
+                        std::fprintf(stderr, " (%.4g %.1e)", lam_of(by_mu[k]) - (mode == kSquared ? sigma : 0.0),
+                                     res[by_mu[k]] / b_up);
+                    std::fprintf(stderr, "\n");
+                }
+                if (done) {
+                    st.iters += it;
+                    st.below += int64_t(below_cols.size());
+                    break;
+                }
+                if (last_try) {
+                    st.iters += it;
+                    return finish(fail(TYEE_ENOTCONVERGED, "a spectral window did not converge within max_iter"));
+                }
+                // filter passes, each followed by deflation and the orthonormalisation
+                bool filtered = false;
+                int deg = 1;
+                double a = 0.0, a0 = 0.0, mu_max = 0.0;
+                if (mode == kSquared) {
+                    a = reach_of(mu);
+                    if (it == 0 && a_hint > 0.0) a = std::min(a, a_hint);
+                    // keep sigma within reach of beta
+                    if (sigma - beta > kSigmaMax * std::sqrt(a)) {
+                        const double moved = beta + kSigmaAt * std::sqrt(a);
+                        for (int64_t c = 0; c < nb; ++c) {   // the block's mu about the new sigma
+                            const double z = ritz[c] - moved;
+                            mu[c] = res[c] * res[c] + z * z;
+                        }
+                        sigma = moved;
+                        a = reach_of(mu);
+                        if (it == 0 && a_hint > 0.0) a = std::min(a, a_hint);
+                    }
+                    mu_max = std::max(sigma, b_up - sigma);
+                    mu_max *= mu_max;
+                    filtered = a > 0.0 && a < mu_max * (1.0 - 1e-12);
+                    if (filtered) {
+                        // growth from mu = 0 to the cut at most 2e7
+                        const double x0m = (mu_max + a) / (mu_max - a);
+                        deg = int(std::max(1.0, std::min(double(degree / 2), std::floor(std::log(2e7) / std::acosh(x0m)))));
+                    }
+                } else {
+                    // the growth is capped from the bottom of the filtered operator's spectrum
+                    // (K, and lambda_bound - K, are non-negative), below which no mode lies
+                    a = ritz[nb - 1];
+                    a0 = 0.0;
+                    filtered = a < b_up * (1.0 - 1e-12) && a0 < a;
+                    const double x0 = (0.5 * (b_up + a) - a0) / (0.5 * (b_up - a));
+                    deg = degree;
+                    if (x0 > 1.0)
+                        deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e7) / std::acosh(x0)))));
+                }
+                if (spectrum_trace())
+                    std::fprintf(stderr, "[spectrum]   filter a %.6g mu_max %.6g deg %d\n", a, mu_max, deg);
+                // interior windows: one pass per Rayleigh-Ritz step, which costs little beside a
+                // pass at these degrees and lets the window stop as soon as it has converged
+                const int passes = !filtered ? 1 : mode == kSquared ? 1 : kFilterPasses;
+                int in = vb;
+                for (int pass = 0; pass < passes && !rc; ++pass) {
+                    int fo = in;
+                    if (filtered) {
+                        TYEE_HIP(hipEventRecord(ev.a, sv.st));
+                        if (mode == kSquared) {
+                            rc = sv.filter_sq(in, deg, a, mu_max, sigma, &fo);
+                            st.applies += 2 * deg;
+                        } else {
+                            rc = sv.filter(in, deg, a, b_up, a0, &fo);
+                            st.applies += deg;
+                        }
+                        TYEE_HIP(hipEventRecord(ev.b, sv.st));
+                    }
+                    const bool last = pass + 1 == passes;
+                    if (!rc) rc = sv.orthonormalise(fo, ModeSolver::pick({fo}), &in, !last);
+                    if (!rc && filtered) {
+                        float ms = 0.0f;
+                        TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                        st.filter_ms += ms;
+                    }
+                }
+                if (rc) return finish(rc);
+                spare = ModeSolver::pick({in});
+                vb = ModeSolver::pick({in, spare});
+                kvb = ModeSolver::pick({in, spare, vb});
+                // the Jacobi runs to its end once the best pair is near the tolerance (junk vectors
+                // of the block never converge, so the worst cannot decide this)
+                double best_res = HUGE_VAL;
+                for (int64_t c = 0; c < nb; ++c) best_res = std::min(best_res, res[c]);
+                const int sweeps = best_res <= kNearTol * res_tol ? kJacobiSweeps : kMidSweeps;
+                rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz, sweeps, off_floor);
+                if (!rc) rc = sv.residuals(vb, kvb, res);
+                if (rc) return finish(rc);
+                st.applies += 1;
+            }
+            // accept the window's pairs (ascending)
+            acc_val.resize(acc.size());
+            for (size_t i = 0; i < acc.size(); ++i) acc_val[i] = mode == kTop ? b_up - ritz[acc[i]] : ritz[acc[i]];
+            // locked: the accepted columns; kept for the next window's start: the trusted pairs
+            // above the boundary (every other column restarts at random: an unconverged column
+            // may lie almost in the span of the deflated modes)
+            std::fill(hcols.begin() + nb, hcols.begin() + 2 * nb, 0);
+            std::fill(hcols.begin() + 2 * nb, hcols.end(), 1);
+            for (int64_t c : acc) hcols[nb + c] = 1;
+            for (int64_t c : warm) hcols[2 * nb + c] = 0;
+            rc = accept_outputs(acc, acc_val, accepted, vb);
+            if (rc) return finish(rc);
+            if (mode != kTop) {
+                beta = new_beta;
+                for (int64_t c = 0; c < nb; ++c) {        // the block's reach at its end
+                    const double z = mode == kSquared ? ritz[c] - sigma : ritz[c];
+                    mu[c] = res[c] * res[c] + z * z;
+                }
+                double reach2 = reach_of(mu);
+                // window 0's block spans [0, R0]; a ball about sigma = beta + R/4 holds as many
+                // modes above beta when 1.25 R = R0
+                if (mode == kLinear) reach2 *= 0.64;
+                sigma = beta + kSigmaAt * std::sqrt(reach2);
+                a_hint = reach2;
+                // lock the accepted columns for deflation, in the ring of kLocked windows
+                TYEE_HIP(hipMemcpyAsync(sv.xb[next_slot].p, sv.B(vb), size_t(nt) * nb * sizeof(double),
+                                        hipMemcpyDeviceToDevice, sv.st));
+                hipLaunchKernelGGL(k_keep_columns, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
+                                   sv.cols.as<int32_t>() + nb, sv.xb[next_slot].as<double>());
+                TYEE_HIP(hipGetLastError());
+                if (std::find(locked.begin(), locked.end(), next_slot) == locked.end()) locked.push_back(next_slot);
+                next_slot = (next_slot + 1) % kLocked;
+            }
+            accepted += int64_t(acc.size());
+            st.found = accepted;
+            st.windows = win + 1;
+            st.min_gap = std::isfinite(min_gap) ? min_gap : 0.0;
+        }
+        return finish(TYEE_OK);
     } catch (const std::bad_alloc &) {
         return fail(TYEE_ENOMEM, "host allocation failed");
     }

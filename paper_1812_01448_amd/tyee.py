@@ -68,6 +68,14 @@ class _ModesStats(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class _SpectrumStats(ctypes.Structure):
+    _fields_ = [("windows", ctypes.c_int32), ("iters", ctypes.c_int32), ("found", ctypes.c_int64),
+                ("applies", ctypes.c_int64), ("below", ctypes.c_int64),
+                ("lambda_bound", ctypes.c_double), ("filter_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("max_residual", ctypes.c_double),
+                ("min_gap", ctypes.c_double)]
+
+
 class _RelaxParams(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("iters", ctypes.c_int32), ("step", ctypes.c_double),
                 ("k_edge", ctypes.c_double), ("k_height", ctypes.c_double), ("rest", ctypes.c_double),
@@ -104,7 +112,8 @@ EXPORTS = [
     "tyee_learner_train", "tyee_learner_gamma", "tyee_learner_set_batch", "tyee_learner_set_path",
     "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
-    "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_relax", "tyee_mesh_flip",
+    "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_spectrum", "tyee_mesh_relax",
+    "tyee_mesh_flip",
     "tyee_batch_tune_progress",
     "tyee_last_error",
 ]
@@ -198,6 +207,8 @@ def _load():
                             ctypes.POINTER(_RelaxStats)],
         "tyee_mesh_modes": [vp, vp, i32, i64, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
                             ctypes.POINTER(_ModesStats)],
+        "tyee_mesh_spectrum": [vp, vp, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
+                               ctypes.POINTER(_SpectrumStats)],
         "tyee_batch_tune_progress": [vp, i64, vp, i64, ctypes.POINTER(i64), _TUNE_PROGRESS, vp],
     }
     for name, args in sig.items():
@@ -386,6 +397,29 @@ class Mesh:
                     allow=(ENOTCONVERGED,))
         out = {"omega2": om2, "modes": vec, "residual": res, "converged": rc == OK}
         out.update({n: getattr(st, n) for n, _ in _ModesStats._fields_})
+        return out
+
+
+    def spectrum(self, gamma=None, block=0, degree=0, tol=1e-10, max_iter=50, seed=0, stream=None,
+                 want_vectors=True):
+        """Every eigenpair of K = -L_E L_B on the device (FP64), window by window.
+
+        Returns a dict: omega2 [n_t] ascending, modes [n_t, n_t] (mode-major, canonical
+        triangle order, S-orthonormal; None unless want_vectors), residual [n_t] (relative to the
+        Gershgorin bound), converged, and the call's stats (windows, iters, found, applies,
+        below, lambda_bound, filter_ms, total_ms, max_residual, min_gap)."""
+        om2 = np.zeros(self.nt)
+        vec = np.zeros((self.nt, self.nt)) if want_vectors else None
+        res = np.zeros(self.nt)
+        st = _SpectrumStats()
+        g = None if gamma is None else _f64(gamma, self.ne)
+        rc = _check(lib.tyee_mesh_spectrum(self._h, _ptr(g), int(block), int(degree), float(tol),
+                                           int(max_iter), int(seed),
+                                           None if stream is None else int(stream), _ptr(om2),
+                                           _ptr(vec), _ptr(res), ctypes.byref(st)),
+                    allow=(ENOTCONVERGED,))
+        out = {"omega2": om2, "modes": vec, "residual": res, "converged": rc == OK}
+        out.update({n: getattr(st, n) for n, _ in _SpectrumStats._fields_})
         return out
 
 

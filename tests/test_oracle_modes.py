@@ -9,6 +9,12 @@
   gamma^2;
 * every pair is an eigenpair of the C core's matrix-free operator, S-orthonormal, with one
   static (zero) mode on a connected mesh.
+
+Pins of the whole spectrum (``OracleMesh.spectrum``): the honeycomb closed form on the
+equilateral torus; the sums of the eigenvalues and of their squares equal the traces of K and
+K^2 written out from the weights gamma^2 |e|/d and the areas S (K's definition from eqs. 3-4);
+on a tiny mesh, the eigenvalues of the non-symmetric K built column by column from the C core
+(a general eigenvalue routine); S-orthonormal eigenpairs of the matrix-free operator.
 """
 import numpy as np
 import pytest
@@ -101,3 +107,76 @@ def test_modes_are_s_orthonormal_eigenpairs_of_the_matrix_free_operator(periodic
     # the static mode is the constant field
     v0 = V[:, 0] / V[np.argmax(np.abs(V[:, 0])), 0]
     assert np.max(np.abs(v0 - 1.0)) < 1e-9
+
+
+def test_whole_spectrum_of_the_equilateral_torus_is_the_honeycomb_closed_form():
+    nx, ny, a = 8, 6, 1.0
+    xy, tri, Lx, Ly = equilateral_torus(nx, ny, a)
+    m = oracle.OracleMesh(xy, tri, True, Lx, Ly)
+    lam, V = m.spectrum()
+    delta = np.array([[0.0, -a / SQ3], [a / 2, a / (2 * SQ3)], [-a / 2, a / (2 * SQ3)]])
+    ex = []
+    for m1 in range(nx):
+        for m2 in range(ny):
+            k = 2 * np.pi * np.array([m1 / Lx, m2 / Ly])
+            f = np.abs(np.exp(1j * delta @ k).sum())
+            ex += [4 / a ** 2 * (3 - f), 4 / a ** 2 * (3 + f)]
+    assert len(lam) == m.nt == len(ex)
+    np.testing.assert_allclose(lam, np.sort(ex), atol=1e-12)
+    assert np.max(np.abs(V.T @ (m.S[:, None] * V) - np.eye(m.nt))) < 1e-12
+    lam_only, none = m.spectrum(vectors=False)
+    assert none is None and np.max(np.abs(lam_only - lam)) < 1e-12
+
+
+def _traces(m, gamma):
+    """trace K and trace K^2 from K's entries: (K B)_j = (1/S_j) sum over interior edges i of j
+    of w_i (B_j - B_other), w_i = gamma_i^2 |e_i| / d_i."""
+    w = np.where(m.interior, gamma ** 2 * m.elen / np.where(m.d != 0, m.d, 1.0), 0.0)
+    diag = np.zeros(m.nt)
+    i = np.nonzero(m.interior)[0]
+    np.add.at(diag, m.R[i], w[i] / m.S[m.R[i]])
+    np.add.at(diag, m.L[i], w[i] / m.S[m.L[i]])
+    # K_RL K_LR = w^2 / (S_R S_L); a pair of triangles sharing two edges (periodic strips) is
+    # not made here
+    off2 = 2.0 * np.sum(w[i] ** 2 / (m.S[m.R[i]] * m.S[m.L[i]]))
+    return diag.sum(), np.sum(diag ** 2) + off2
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_whole_spectrum_sums_are_the_traces_of_k_and_k_squared(periodic):
+    xy, tri = lattice_mesh(12, 0.25, 11, periodic=periodic)
+    m = oracle.OracleMesh(xy, tri, periodic)
+    gamma = 1.0 + 0.1 * np.cos(np.arange(m.ne) * 1.3)
+    lam, V = m.spectrum(gamma)
+    t1, t2 = _traces(m, gamma)
+    assert abs(lam.sum() - t1) < 1e-11 * t1
+    assert abs(np.sum(lam ** 2) - t2) < 1e-11 * t2
+    top = lam[-1]
+    for c in range(0, m.nt, 7):
+        kv = -m.apply_LE(m.apply_LB(V[:, c], gamma), gamma)
+        assert np.sqrt(np.sum(m.S * (kv - lam[c] * V[:, c]) ** 2)) < 1e-11 * top
+    assert np.max(np.abs(V.T @ (m.S[:, None] * V) - np.eye(m.nt))) < 1e-11
+
+
+def test_whole_spectrum_of_a_tiny_mesh_is_the_general_eigenvalues_of_k():
+    xy, tri, Lx, Ly = box_mesh(3, 3, 0.15, 2, h=0.5)
+    m = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    K = np.stack([-m.apply_LE(m.apply_LB(np.eye(m.nt)[j])) for j in range(m.nt)], axis=1)
+    ev = np.linalg.eigvals(K)                      # K itself is not symmetric (S differs)
+    assert np.max(np.abs(ev.imag)) < 1e-10 * np.max(np.abs(ev.real))
+    lam, _ = m.spectrum()
+    np.testing.assert_allclose(lam, np.sort(ev.real), atol=1e-11 * lam[-1])
+
+
+def test_nearest_modes_are_the_middle_of_the_whole_spectrum():
+    xy, tri, Lx, Ly = box_mesh(16, 24, 0.15, 4, h=0.25)
+    m = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    lam, V = m.spectrum()
+    k = m.nt // 2
+    sigma = 0.5 * (lam[k] + lam[k + 1])
+    near, W = m.modes(10, which="nearest", sigma=sigma)
+    idx = np.argsort(np.abs(lam - sigma))[:10]
+    np.testing.assert_allclose(near, np.sort(lam[idx]), atol=1e-11 * lam[-1])
+    # the same eigenvectors (simple eigenvalues here), up to sign
+    for c, j in enumerate(np.sort(idx)):
+        assert abs(abs(np.sum(m.S * W[:, c] * V[:, j])) - 1.0) < 1e-8
