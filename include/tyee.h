@@ -591,8 +591,9 @@ typedef struct {
     int32_t iters;         /* Rayleigh-Ritz steps after filter passes, over all windows */
     int64_t found;         /* pairs accepted (n_triangles on success) */
     int64_t applies;       /* applications of K to the whole block */
-    int64_t below;         /* converged Ritz pairs below a window's boundary, already found and
-                              discarded */
+    int64_t below;         /* converged Ritz pairs outside a window (found before), set aside */
+    int64_t retries;       /* interior filter passes redone at a lower growth (the block was too
+                              ill-conditioned for the shifted Cholesky QR) */
     double lambda_bound;   /* Gershgorin bound on lambda_max */
     double filter_ms;      /* HIP-event time of the filter launches on the stream */
     double total_ms;       /* host wall time of the call, uploads and readback included */

@@ -1428,9 +1428,21 @@ struct ModeSolver {
     // Sci. Comput. 2020) from the same block.  TYEE_EUNSTABLE when that fails too.
     // With `once`, a single Cholesky QR: the block comes out well conditioned (orthonormal to
     // about u cond^2), which is all a following filter pass needs.
-    int orthonormalise(int ix, int iy, int *out, bool once = false) {
+    // With `shifted`, the shifted Cholesky QR three times straight away: for a block filtered
+    // with a growth beyond what Cholesky QR twice can take (condition numbers up to about u^-1).
+    int orthonormalise(int ix, int iy, int *out, bool once = false, bool shifted = false) {
         bool ok = false;
-        int rc = cholqr_pass(ix, iy, false, &ok, true);   // iy is scratch if this pass fails
+        int rc = TYEE_OK;
+        if (shifted) {
+            rc = cholqr_pass(ix, iy, true, &ok);
+            if (!rc && ok) rc = cholqr_pass(iy, ix, false, &ok);
+            if (!rc && ok) rc = cholqr_pass(ix, iy, false, &ok);
+            if (rc) return rc;
+            if (!ok) return fail(TYEE_EUNSTABLE, "mode block lost rank");
+            *out = iy;
+            return TYEE_OK;
+        }
+        rc = cholqr_pass(ix, iy, false, &ok, true);   // iy is scratch if this pass fails
         if (!rc && ok && once) {
             *out = iy;
             return TYEE_OK;
@@ -1817,18 +1829,20 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
             return finish(TYEE_OK);
         }
 
-        // Spectrum slicing.  Window 0 takes the lowest modes with the low-pass filter of K; each
+        // Spectrum slicing.  Window 0 takes the top modes with the low-pass filter of
+        // lambda_bound - K (which also gives lambda_max, the top of the spectrum the other
+        // filters have to damp); window 1 the lowest modes with the low-pass filter of K; each
         // further window filters with (K - sigma)^2, beta being the boundary below which every
-        // mode is already found; the last window takes the remaining top modes with the low-pass
-        // filter of lambda_bound - K.  A window's start block is S-orthogonalised against the
-        // modes of the last windows (deflation in metric (7), as the paper withdraws the found
-        // eigenvectors from the initial vector), and the filter passes then run without
-        // projections: a projection in every pass would hold the block exactly orthogonal to
-        // modes that are themselves only accurate to the tolerance, and that error would pass on
-        // from window to window.  Found modes that grow back are recognised below beta and set
-        // aside.  sigma sits a quarter of the block's reach R above beta (R^2 = the largest mu of
-        // the block, below), so that the ball of radius R about sigma reaches down past beta;
-        // sigma moves down when the reach shrinks (the spectrum gets denser).
+        // mode is found, and runs up to the top window's boundary.  A window's start block is
+        // S-orthogonalised against the modes of the last windows (deflation in metric (7), as the
+        // paper withdraws the found eigenvectors from the initial vector), and the filter passes
+        // then run without projections: a projection in every pass would hold the block exactly
+        // orthogonal to modes that are themselves only accurate to the tolerance, and that error
+        // would pass on from window to window.  Found modes that grow back are recognised outside
+        // the window and set aside.  sigma sits a quarter of the block's reach R above beta
+        // (R^2 = the largest mu of the block, below), so that the ball of radius R about sigma
+        // reaches down past beta; sigma moves down when the reach shrinks (the spectrum gets
+        // denser).
         //
         // Which Ritz pairs a window may accept: the filter favours the block's directions by
         // mu = ||(K - z) v||^2 = res^2 + (theta - z)^2 (z = sigma, or the bottom of the filtered
@@ -1840,42 +1854,61 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
         // accepted once that ball reaches down to beta, with its boundary in the widest gap
         // among the trusted Ritz values, so that each eigenvalue is accepted exactly once.
         enum { kLinear, kSquared, kTop };
-        const int64_t target = (3 * nb + 4) / 5;     // pairs a window aims to accept
+        const int64_t target = (2 * nb + 4) / 5;     // trusted pairs a window waits for
         const double gap_min = 16.0 * res_tol;      // a boundary gap the Ritz errors cannot cross
         constexpr double kSigmaAt = 0.25, kSigmaMax = 0.35;   // sigma - beta in units of the reach
-        int64_t accepted = 0;
-        double beta = -HUGE_VAL, sigma = 0.0, a_hint = 0.0, min_gap = HUGE_VAL;
+        constexpr double kSqGrowth = 1e10;                     // filter growth per interior pass
+        int64_t low = 0, high = 0;                  // pairs found from the bottom, from the top
+        double beta = -HUGE_VAL, beta_top = HUGE_VAL;   // the window runs over [beta, beta_top)
+        double lam_hi = b_up;                       // the top of the spectrum (lambda_max once known)
+        double sigma = 0.0, a_hint = 0.0, min_gap = HUGE_VAL;
         std::vector<int> locked;                    // xb indices of the windows deflated against
         int next_slot = 0;
         int vb = -1, kvb = -1;                      // Ritz vectors of the last window, K times them
         std::vector<double> mu(nb);
         std::vector<int64_t> by_mu(nb);
-        // the block's reach in mu: its largest mu (the pass band of the filter then holds at
-        // least as many modes as the block has vectors)
-        auto reach_of = [&](const std::vector<double> &m) { return *std::max_element(m.begin(), m.end()); };
-        for (int32_t win = 0; accepted < nt; ++win) {
-            const int64_t remaining = nt - accepted;
-            const int mode = win == 0 ? kLinear : remaining <= target ? kTop : kSquared;
+        // The block's reach in mu, for the filter's pass band [0, a]: its largest mu.  After a
+        // pass whose band held fewer modes than the block has vectors, the spare vectors come
+        // out of the orthonormalisation as unfiltered noise with a huge mu; they do not measure
+        // the reach: the band is then widened in the ratio of all vectors to the filtered ones
+        // (at a constant density of modes, their count grows with the radius sqrt(a)).
+        auto reach_of = [&](const std::vector<double> &m, double a_used) {
+            double top = 0.0, top_kept = 0.0;
+            int64_t spare = 0;
+            for (double v : m) {
+                top = std::max(top, v);
+                if (a_used > 0.0 && v > 4.0 * a_used) ++spare;
+                else top_kept = std::max(top_kept, v);
+            }
+            if (spare == 0 || spare == nb) return top;
+            const double grow = double(nb) / double(nb - spare);
+            return std::min(top, top_kept * grow * grow);
+        };
+        for (int32_t win = 0; low + high < nt; ++win) {
+            const int64_t remaining = nt - low - high;
+            const int mode = win == 0 ? kTop : win == 1 ? kLinear : kSquared;
             sv.reversed = mode == kTop;
-            // start: the last window's block with its accepted and stale columns restarted at random
+            // start: the last window's block with its accepted and stale columns restarted at
+            // random (the window after the top one starts afresh)
+            const bool warm_start = vb >= 0 && mode == kSquared;
             int x0 = 0;
-            if (vb >= 0) {
+            if (warm_start) {
                 x0 = ModeSolver::pick({vb});
                 TYEE_HIP(hipMemcpyAsync(sv.B(x0), sv.B(vb), size_t(nt) * nb * sizeof(double),
                                         hipMemcpyDeviceToDevice, sv.st));
             }
+            const uint64_t wseed = seed + uint64_t(win) * uint64_t(nt) * uint64_t(nb);
             hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
-                               sv.canon.as<int32_t>(), seed + uint64_t(win) * uint64_t(nt) * uint64_t(nb), sv.B(x0),
-                               vb >= 0 ? sv.cols.as<int32_t>() + 2 * nb : nullptr);
+                               sv.canon.as<int32_t>(), wseed, sv.B(x0),
+                               warm_start ? sv.cols.as<int32_t>() + 2 * nb : nullptr);
             TYEE_HIP(hipGetLastError());
             rc = sv.project(x0, locked);
             int ob = x0;
             if (!rc) rc = sv.orthonormalise(x0, ModeSolver::pick({x0}), &ob);
-            if (rc == TYEE_EUNSTABLE && vb >= 0) {
+            if (rc == TYEE_EUNSTABLE && warm_start) {
                 // the kept columns were too close to the deflated modes: all columns at random
                 hipLaunchKernelGGL(k_random_block, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
-                                   sv.canon.as<int32_t>(), seed + uint64_t(win) * uint64_t(nt) * uint64_t(nb),
-                                   sv.B(x0), nullptr);
+                                   sv.canon.as<int32_t>(), wseed, sv.B(x0), nullptr);
                 TYEE_HIP(hipGetLastError());
                 rc = sv.project(x0, locked);
                 if (!rc) rc = sv.orthonormalise(x0, ModeSolver::pick({x0}), &ob);
@@ -1887,11 +1920,12 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
             if (!rc) rc = sv.residuals(vb, kvb, res);
             if (rc) return finish(rc);
             st.applies += 1;
-            std::vector<int64_t> acc, below_cols, warm;
-            std::vector<double> acc_val;
-            double new_beta = beta, worst_wanted = HUGE_VAL;
-            int64_t prev_trusted = -1;
+            auto lam_of = [&](int64_t c) { return mode == kTop ? b_up - ritz[c] : ritz[c]; };
+            std::vector<int64_t> acc, aside, warm;  // accepted (ascending), found before, kept
+            double new_bound = 0.0;                 // the window's new boundary
+            int64_t prev_good = -1;
             int stalled = 0;                       // iterations without more trusted pairs
+            double a_used = 0.0;                   // the pass band of the last filter pass
             for (int32_t it = 0;; ++it) {
                 const bool last_try = it >= max_iter;
                 // trusted set: converged pairs in order of mu up to the first unconverged one
@@ -1901,69 +1935,72 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
                     by_mu[c] = c;
                 }
                 std::stable_sort(by_mu.begin(), by_mu.end(), [&](int64_t x, int64_t y) { return mu[x] < mu[y]; });
-                std::vector<int64_t> good;                 // trusted, at or above beta, by K-value
-                below_cols.clear();
+                std::vector<int64_t> good;          // trusted and inside [beta, beta_top)
+                aside.clear();
                 int64_t trusted = 0;
                 for (; trusted < nb && res[by_mu[trusted]] <= res_tol; ++trusted) {
                     const int64_t c = by_mu[trusted];
-                    const double lam = mode == kTop ? b_up - ritz[c] : ritz[c];
-                    if (lam >= beta) good.push_back(c);
-                    else below_cols.push_back(c);
+                    const double lam = lam_of(c);
+                    if (lam >= beta && lam < beta_top) good.push_back(c);
+                    else aside.push_back(c);
                 }
                 // the trusted ball holds every mode with (lambda - sigma)^2 below mu_stop
                 const double mu_stop = trusted < nb ? mu[by_mu[trusted]] : HUGE_VAL;
-                const bool covers_beta = mode != kSquared || (sigma - beta) * (sigma - beta) < mu_stop;
-                auto lam_of = [&](int64_t c) { return mode == kTop ? b_up - ritz[c] : ritz[c]; };
+                const bool covers = mode != kSquared || (sigma - beta) * (sigma - beta) < mu_stop;
                 std::sort(good.begin(), good.end(), [&](int64_t x, int64_t y) { return lam_of(x) < lam_of(y); });
-                // the residuals still to come down: the wanted pairs not yet trusted
-                const int64_t wanted = mode == kTop ? remaining : std::min(target, remaining - 1) + 1;
-                worst_wanted = 0.0;
-                for (int64_t k = 0; k < std::min<int64_t>(nb, wanted); ++k) worst_wanted = std::max(worst_wanted, res[by_mu[k]]);
+                const int64_t g = int64_t(good.size());
+                // a window whose trusted pairs no longer grow in number (its ball cannot grow: a
+                // sparse part of the spectrum, the rest of the block outside the window) settles
+                // for what it has
+                stalled = covers && g >= 2 && g <= prev_good + 1 ? stalled + 1 : 0;
+                prev_good = g;
+                const bool settle = last_try || trusted == nb || stalled >= 1;
                 bool done = false;
-                if (mode == kTop) {
-                    if (int64_t(good.size()) > remaining)
-                        return finish(fail(TYEE_EUNSTABLE, "more converged modes above the boundary than remain"));
-                    if (int64_t(good.size()) == remaining) {
-                        acc = good;
-                        done = true;
-                    }
-                } else {
-                    // a block that holds no more trusted pairs than before (its ball cannot grow:
-                    // a sparse part of the spectrum, the rest of the block below beta) settles
-                    // for what it has
-                    stalled = trusted > 0 && trusted <= prev_trusted ? stalled + 1 : 0;
-                    prev_trusted = trusted;
-                    const int64_t g = int64_t(good.size());
-                    const bool settle = last_try || trusted == nb || stalled >= 2;
-                    // once target pairs are trusted (or the block has settled), take all but the
-                    // last of them, cut in the widest gap of the top fifth, else anywhere
-                    const int64_t want = std::min(g - 1, remaining - 1);
-                    if (covers_beta && want >= 1 && (g >= target + 1 || settle)) {
-                        double best = -1.0;
-                        int64_t cut = -1;
-                        for (int pass = 0; pass < 2 && best < gap_min; ++pass)
-                            for (int64_t k = pass == 0 ? (4 * want) / 5 : 0; k < want; ++k) {
-                                const double gap = lam_of(good[k + 1]) - lam_of(good[k]);
-                                if (gap > best) {
-                                    best = gap;
-                                    cut = k;
-                                }
+                if (covers && g == remaining) {
+                    acc = good;                     // every mode left: no boundary needed
+                    warm.clear();
+                    done = true;
+                } else if (covers && g > remaining) {
+                    return finish(fail(TYEE_EUNSTABLE, "more converged modes in the window than remain"));
+                } else if (covers && g >= 2 && (g >= target + 1 || settle)) {
+                    // take all but the last of them (from the window's own end: the bottom for
+                    // the top window), cut in the widest gap of the far fifth, else anywhere
+                    const int64_t want = g - 1;
+                    double best = -1.0;
+                    int64_t cut = -1;               // boundary between good[cut] and good[cut + 1]
+                    for (int pass = 0; pass < 2 && best < gap_min; ++pass) {
+                        int64_t k0 = 0, k1 = want;
+                        if (pass == 0) {
+                            if (mode == kTop) k1 = std::max<int64_t>(1, want / 5);
+                            else k0 = (4 * want) / 5;
+                        }
+                        for (int64_t k = k0; k < k1; ++k) {
+                            const double gap = lam_of(good[k + 1]) - lam_of(good[k]);
+                            if (gap > best) {
+                                best = gap;
+                                cut = k;
                             }
-                        if (best >= gap_min) {
+                        }
+                    }
+                    if (best >= gap_min) {
+                        new_bound = 0.5 * (lam_of(good[cut]) + lam_of(good[cut + 1]));
+                        if (mode == kTop) {
+                            acc.assign(good.begin() + cut + 1, good.end());
+                            warm.clear();
+                        } else {
                             acc.assign(good.begin(), good.begin() + cut + 1);
                             warm.assign(good.begin() + cut + 1, good.end());
-                            new_beta = 0.5 * (lam_of(good[cut]) + lam_of(good[cut + 1]));
-                            min_gap = std::min(min_gap, best / b_up);
-                            done = true;
                         }
+                        min_gap = std::min(min_gap, best / b_up);
+                        done = true;
                     }
                 }
                 if (spectrum_trace()) {
                     std::fprintf(stderr,
-                                 "[spectrum] win %d mode %d it %d beta %.9g sigma %.9g trusted %lld good %lld below %zu "
-                                 "covers %d worst %.2e%s |",
-                                 win, mode, it, beta, sigma, (long long)trusted, (long long)good.size(), below_cols.size(),
-                                 int(covers_beta), worst_wanted / b_up, done ? " accept" : "");
+                                 "[spectrum] win %d mode %d it %d beta %.9g sigma %.9g trusted %lld good %lld aside %zu "
+                                 "covers %d%s |",
+                                 win, mode, it, beta, sigma, (long long)trusted, (long long)g, aside.size(),
+                                 int(covers), done ? " accept" : "");
                     for (int64_t k = 0; k < std::min<int64_t>(nb, 4); ++k)
                         std::fprintf(stderr, " (%.4g %.1e)", lam_of(by_mu[k]) - (mode == kSquared ? sigma : 0.0),
                                      res[by_mu[k]] / b_up);
@@ -1971,19 +2008,19 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
                 }
                 if (done) {
                     st.iters += it;
-                    st.below += int64_t(below_cols.size());
+                    st.below += int64_t(aside.size());
                     break;
                 }
                 if (last_try) {
                     st.iters += it;
                     return finish(fail(TYEE_ENOTCONVERGED, "a spectral window did not converge within max_iter"));
                 }
-                // filter passes, each followed by deflation and the orthonormalisation
+                // a filter pass, the orthonormalisation, Rayleigh-Ritz
                 bool filtered = false;
                 int deg = 1;
-                double a = 0.0, a0 = 0.0, mu_max = 0.0;
+                double a = 0.0, a0 = 0.0, mu_max = 0.0, upper = 0.0;
                 if (mode == kSquared) {
-                    a = reach_of(mu);
+                    a = reach_of(mu, a_used);
                     if (it == 0 && a_hint > 0.0) a = std::min(a, a_hint);
                     // keep sigma within reach of beta
                     if (sigma - beta > kSigmaMax * std::sqrt(a)) {
@@ -1993,104 +2030,142 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
                             mu[c] = res[c] * res[c] + z * z;
                         }
                         sigma = moved;
-                        a = reach_of(mu);
+                        a = reach_of(mu, a_used);
                         if (it == 0 && a_hint > 0.0) a = std::min(a, a_hint);
                     }
-                    mu_max = std::max(sigma, b_up - sigma);
+                    a_used = a;
+                    mu_max = std::max(sigma, lam_hi - sigma);
                     mu_max *= mu_max;
                     filtered = a > 0.0 && a < mu_max * (1.0 - 1e-12);
                     if (filtered) {
-                        // growth from mu = 0 to the cut at most 2e7
+                        // growth from mu = 0 to the cut at most kSqGrowth: one pass then converges
+                        // the modes near sigma (the block is orthonormalised by the shifted
+                        // Cholesky QR, which takes such condition numbers)
                         const double x0m = (mu_max + a) / (mu_max - a);
-                        deg = int(std::max(1.0, std::min(double(degree / 2), std::floor(std::log(2e7) / std::acosh(x0m)))));
+                        deg = int(std::max(1.0, std::min(double(degree / 2), std::floor(std::log(kSqGrowth) / std::acosh(x0m)))));
                     }
                 } else {
                     // the growth is capped from the bottom of the filtered operator's spectrum
-                    // (K, and lambda_bound - K, are non-negative), below which no mode lies
+                    // (K, and lambda_bound - K, are non-negative), below which no mode lies; the
+                    // damped interval ends at the top of that spectrum
+                    upper = mode == kTop ? b_up : lam_hi;
                     a = ritz[nb - 1];
                     a0 = 0.0;
-                    filtered = a < b_up * (1.0 - 1e-12) && a0 < a;
-                    const double x0 = (0.5 * (b_up + a) - a0) / (0.5 * (b_up - a));
+                    filtered = a < upper * (1.0 - 1e-12) && a0 < a;
+                    const double x0 = (0.5 * (upper + a) - a0) / (0.5 * (upper - a));
                     deg = degree;
-                    if (x0 > 1.0)
+                    if (filtered && x0 > 1.0)
                         deg = int(std::max(1.0, std::min(double(degree), std::floor(std::log(2e7) / std::acosh(x0)))));
                 }
                 if (spectrum_trace())
-                    std::fprintf(stderr, "[spectrum]   filter a %.6g mu_max %.6g deg %d\n", a, mu_max, deg);
+                    std::fprintf(stderr, "[spectrum]   filter a %g mu_max %g deg %d\n", a, mu_max, deg);
                 // interior windows: one pass per Rayleigh-Ritz step, which costs little beside a
                 // pass at these degrees and lets the window stop as soon as it has converged
                 const int passes = !filtered ? 1 : mode == kSquared ? 1 : kFilterPasses;
                 int in = vb;
                 for (int pass = 0; pass < passes && !rc; ++pass) {
-                    int fo = in;
-                    if (filtered) {
-                        TYEE_HIP(hipEventRecord(ev.a, sv.st));
-                        if (mode == kSquared) {
-                            rc = sv.filter_sq(in, deg, a, mu_max, sigma, &fo);
-                            st.applies += 2 * deg;
-                        } else {
-                            rc = sv.filter(in, deg, a, b_up, a0, &fo);
-                            st.applies += deg;
-                        }
-                        TYEE_HIP(hipEventRecord(ev.b, sv.st));
-                    }
                     const bool last = pass + 1 == passes;
-                    if (!rc) rc = sv.orthonormalise(fo, ModeSolver::pick({fo}), &in, !last);
-                    if (!rc && filtered) {
-                        float ms = 0.0f;
-                        TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
-                        st.filter_ms += ms;
+                    auto run_pass = [&](int d, bool high_growth) -> int {
+                        int fo = in;
+                        if (filtered) {
+                            TYEE_HIP(hipEventRecord(ev.a, sv.st));
+                            int rc2;
+                            if (mode == kSquared) {
+                                rc2 = sv.filter_sq(in, d, a, mu_max, sigma, &fo);
+                                st.applies += 2 * d;
+                            } else {
+                                rc2 = sv.filter(in, d, a, upper, a0, &fo);
+                                st.applies += d;
+                            }
+                            TYEE_HIP(hipEventRecord(ev.b, sv.st));
+                            if (rc2) return rc2;
+                        }
+                        // the scratch buffer spares `in`, so that a failed pass can be redone
+                        int out = in;
+                        const int rc2 = sv.orthonormalise(fo, ModeSolver::pick({fo, in}), &out, !last, high_growth);
+                        if (filtered) {   // the orthonormalisation has waited for the stream
+                            TYEE_HIP(hipEventSynchronize(ev.b));
+                            float ms = 0.0f;
+                            TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+                            st.filter_ms += ms;
+                        }
+                        if (!rc2) in = out;
+                        return rc2;
+                    };
+                    const bool high_growth = mode == kSquared && filtered;
+                    rc = run_pass(deg, high_growth);
+                    if (rc == TYEE_EUNSTABLE && high_growth) {
+                        // the block was worse conditioned than the shifted Cholesky QR takes:
+                        // the pass again at the growth that Cholesky QR twice handles
+                        ++st.retries;
+                        if (spectrum_trace()) std::fprintf(stderr, "[spectrum]   pass redone at low growth\n");
+                        const double x0m = (mu_max + a) / (mu_max - a);
+                        const int safe = int(std::max(1.0, std::min(double(deg), std::floor(std::log(2e7) / std::acosh(x0m)))));
+                        rc = run_pass(safe, false);
                     }
                 }
                 if (rc) return finish(rc);
                 spare = ModeSolver::pick({in});
                 vb = ModeSolver::pick({in, spare});
                 kvb = ModeSolver::pick({in, spare, vb});
-                // the Jacobi runs to its end once the best pair is near the tolerance (junk vectors
-                // of the block never converge, so the worst cannot decide this)
+                // The Jacobi runs to its end (it stops early once the off-diagonal mass is below
+                // off_floor) in the interior windows: there a few sweeps leave every Ritz vector a
+                // mixture with a large residual even when the block's subspace has converged, and
+                // the residuals would never come down to tell.  At the ends of the spectrum, as in
+                // tyee_mesh_modes, once the best pair is near the tolerance.
                 double best_res = HUGE_VAL;
                 for (int64_t c = 0; c < nb; ++c) best_res = std::min(best_res, res[c]);
-                const int sweeps = best_res <= kNearTol * res_tol ? kJacobiSweeps : kMidSweeps;
+                const int sweeps = mode == kSquared || best_res <= kNearTol * res_tol ? kJacobiSweeps : kMidSweeps;
                 rc = sv.rayleigh_ritz(in, spare, vb, kvb, ritz, sweeps, off_floor);
                 if (!rc) rc = sv.residuals(vb, kvb, res);
                 if (rc) return finish(rc);
                 st.applies += 1;
             }
-            // accept the window's pairs (ascending)
-            acc_val.resize(acc.size());
-            for (size_t i = 0; i < acc.size(); ++i) acc_val[i] = mode == kTop ? b_up - ritz[acc[i]] : ritz[acc[i]];
+            // the window's pairs, ascending, to their places in the outputs
+            std::vector<double> acc_val(acc.size());
+            for (size_t i = 0; i < acc.size(); ++i) acc_val[i] = lam_of(acc[i]);
             // locked: the accepted columns; kept for the next window's start: the trusted pairs
-            // above the boundary (every other column restarts at random: an unconverged column
+            // beyond the boundary (every other column restarts at random: an unconverged column
             // may lie almost in the span of the deflated modes)
             std::fill(hcols.begin() + nb, hcols.begin() + 2 * nb, 0);
             std::fill(hcols.begin() + 2 * nb, hcols.end(), 1);
             for (int64_t c : acc) hcols[nb + c] = 1;
             for (int64_t c : warm) hcols[2 * nb + c] = 0;
-            rc = accept_outputs(acc, acc_val, accepted, vb);
+            const bool finished = low + high + int64_t(acc.size()) == nt;
+            const int64_t row0 = mode == kTop ? nt - int64_t(acc.size()) : low;
+            rc = accept_outputs(acc, acc_val, row0, vb);
             if (rc) return finish(rc);
-            if (mode != kTop) {
-                beta = new_beta;
-                for (int64_t c = 0; c < nb; ++c) {        // the block's reach at its end
-                    const double z = mode == kSquared ? ritz[c] - sigma : ritz[c];
-                    mu[c] = res[c] * res[c] + z * z;
+            if (mode == kTop) {
+                high = int64_t(acc.size());
+                lam_hi = acc_val.back() + 2.0 * res_tol;   // lambda_max, and the Ritz error above it
+                beta_top = finished ? HUGE_VAL : new_bound;
+            } else {
+                low += int64_t(acc.size());
+                if (!finished) {
+                    beta = new_bound;
+                    for (int64_t c = 0; c < nb; ++c) {        // the block's reach at its end
+                        const double z = mode == kSquared ? ritz[c] - sigma : ritz[c];
+                        mu[c] = res[c] * res[c] + z * z;
+                    }
+                    double reach2 = reach_of(mu, a_used);
+                    // window 1's block spans [0, R0]; a ball about sigma = beta + R/4 holds as
+                    // many modes above beta when 1.25 R = R0.  A later window's ball held some
+                    // modes below its beta that the next start block has deflated: the next ball
+                    // reaches further.
+                    reach2 *= mode == kLinear ? 0.64 : 1.5;
+                    sigma = beta + kSigmaAt * std::sqrt(reach2);
+                    a_hint = reach2;
+                    // lock the accepted columns for deflation, in the ring of kLocked windows
+                    TYEE_HIP(hipMemcpyAsync(sv.xb[next_slot].p, sv.B(vb), size_t(nt) * nb * sizeof(double),
+                                            hipMemcpyDeviceToDevice, sv.st));
+                    hipLaunchKernelGGL(k_keep_columns, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
+                                       sv.cols.as<int32_t>() + nb, sv.xb[next_slot].as<double>());
+                    TYEE_HIP(hipGetLastError());
+                    if (std::find(locked.begin(), locked.end(), next_slot) == locked.end()) locked.push_back(next_slot);
+                    next_slot = (next_slot + 1) % kLocked;
                 }
-                double reach2 = reach_of(mu);
-                // window 0's block spans [0, R0]; a ball about sigma = beta + R/4 holds as many
-                // modes above beta when 1.25 R = R0
-                if (mode == kLinear) reach2 *= 0.64;
-                sigma = beta + kSigmaAt * std::sqrt(reach2);
-                a_hint = reach2;
-                // lock the accepted columns for deflation, in the ring of kLocked windows
-                TYEE_HIP(hipMemcpyAsync(sv.xb[next_slot].p, sv.B(vb), size_t(nt) * nb * sizeof(double),
-                                        hipMemcpyDeviceToDevice, sv.st));
-                hipLaunchKernelGGL(k_keep_columns, dim3(sv.grid_items()), dim3(kBlock), 0, sv.st, sv.n, sv.nb,
-                                   sv.cols.as<int32_t>() + nb, sv.xb[next_slot].as<double>());
-                TYEE_HIP(hipGetLastError());
-                if (std::find(locked.begin(), locked.end(), next_slot) == locked.end()) locked.push_back(next_slot);
-                next_slot = (next_slot + 1) % kLocked;
             }
-            accepted += int64_t(acc.size());
-            st.found = accepted;
+            st.found = low + high;
             st.windows = win + 1;
             st.min_gap = std::isfinite(min_gap) ? min_gap : 0.0;
         }

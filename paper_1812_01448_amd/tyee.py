@@ -70,7 +70,7 @@ class _ModesStats(ctypes.Structure):
 
 class _SpectrumStats(ctypes.Structure):
     _fields_ = [("windows", ctypes.c_int32), ("iters", ctypes.c_int32), ("found", ctypes.c_int64),
-                ("applies", ctypes.c_int64), ("below", ctypes.c_int64),
+                ("applies", ctypes.c_int64), ("below", ctypes.c_int64), ("retries", ctypes.c_int64),
                 ("lambda_bound", ctypes.c_double), ("filter_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("max_residual", ctypes.c_double),
                 ("min_gap", ctypes.c_double)]
@@ -407,7 +407,7 @@ class Mesh:
         Returns a dict: omega2 [n_t] ascending, modes [n_t, n_t] (mode-major, canonical
         triangle order, S-orthonormal; None unless want_vectors), residual [n_t] (relative to the
         Gershgorin bound), converged, and the call's stats (windows, iters, found, applies,
-        below, lambda_bound, filter_ms, total_ms, max_residual, min_gap)."""
+        below, retries, lambda_bound, filter_ms, total_ms, max_residual, min_gap)."""
         om2 = np.zeros(self.nt)
         vec = np.zeros((self.nt, self.nt)) if want_vectors else None
         res = np.zeros(self.nt)
