@@ -39,12 +39,14 @@ def parse(argv=None):
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
     p.add_argument("--workload", default="torus1415",
-                   choices=["torus1415", "plasma2830", "batch256", "learned", "modes70x101", "relax"],
+                   choices=["torus1415", "plasma2830", "batch256", "learned", "modes70x101", "spectrum70x101",
+                            "relax"],
                    help="torus1415 (the reported line), plasma2830 (16M triangles with a plasma "
                         "particle and a line source), batch256 (256 uneven meshes), learned "
                         "(train and evaluate the learned edge scale) or modes70x101 (the 128 "
                         "lowest modes of the 70 x 101 resonator of Fig. 4; --steps timed "
-                        "solves, at most 20) or relax (jello relaxation of the 45 x 45 cavity and "
+                        "solves, at most 20), spectrum70x101 (every mode of that resonator, one "
+                        "solve) or relax (jello relaxation of the 45 x 45 cavity and "
                         "the 1415 x 1415 torus: omega_max and so dt before and after)")
     p.add_argument("--relax-rounds", type=int, default=8)
     p.add_argument("--relax-iters", type=int, default=100)
@@ -282,7 +284,8 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     run = {"batch256": bench_batch, "learned": bench_learned, "plasma2830": bench_plasma,
-           "modes70x101": bench_modes, "torus1415": bench_torus, "relax": bench_relax}[args.workload]
+           "modes70x101": bench_modes, "spectrum70x101": bench_spectrum, "torus1415": bench_torus,
+           "relax": bench_relax}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -745,6 +748,91 @@ def bench_modes(args):
         "cpu_baseline": None if args.no_cpu else cpu_baseline_modes(xy, tri, Lx, Ly),
     }
     return out
+
+
+SPECTRUM_TOL = 1e-10
+
+
+def bench_spectrum(args):
+    """Every mode of the Fig. 4 resonator (16,497 eigenpairs, FP64) on the device, vectors
+    included (copied to the host in canonical order)."""
+    import torch
+    import paper_1812_01448_amd as ty
+
+    xy, tri, Lx, Ly = fig4_mesh()
+    mesh = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    mesh.reorder("morton")
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    nt = len(tri)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = mesh.spectrum(tol=SPECTRUM_TOL, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert r["converged"] and r["found"] == nt
+    nb = 192
+    avg_ms = r["sq_ms"] / r["sq_launches"]
+    # per fused (K - sigma)^2 launch: the block read once, the older block read, one block
+    # written (24 nb B per row) and the row's tables (44 B); the two-ring gathers of the block
+    # come from the caches and are not counted again
+    per_launch = nt * (24 * nb + 44)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    om2 = r["omega2"]
+    # Fig. 4's three curves against the mode index: the unstructured mesh (all n_t modes), the
+    # structured square Yee grid (70 x 101 cells, 7,070 modes) and the continuum
+    nq = 70 * 101
+    exact, quad = fig4_reference_curves(nq, Lx, Ly)
+    idx = list(range(0, nq, 256)) + [nq - 1]
+    log(f"whole spectrum: {r['windows']} windows, {r['iters']} Rayleigh-Ritz steps, {r['applies']} "
+        f"applies, filter {r['filter_ms']:.0f} ms of {r['total_ms']:.0f} ms")
+    out = {
+        "metric": "resonator modes/s (every eigenpair with its vector, residual <= 1e-10 of the "
+                  "lambda bound)",
+        "value": nt / elapsed, "unit": "modes/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "whole spectrum of the Fig. 4 closed resonator 70 x 101, h = 1, "
+                               "jittered (+-0.1h) triangular-lattice Delaunay mesh",
+                   "triangles": nt, "modes": nt, "block": nb, "windows": r["windows"],
+                   "rayleigh_ritz_steps": r["iters"], "applies": r["applies"],
+                   "set_aside": r["below"], "retries": r["retries"],
+                   "lambda_bound": r["lambda_bound"], "lambda_max": float(om2[-1]),
+                   "max_residual": r["max_residual"], "min_boundary_gap": r["min_gap"]},
+        "roofline": {"bound": "hbm", "kernel": "k_modes_apply_sq (fused (K - sigma)^2 block apply)",
+                     "timed_with": "HIP events around the interior windows' filter passes",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg_ms, 5),
+                     "launches": r["sq_launches"], "algorithmic_bytes_per_launch": per_launch,
+                     "traffic": None,
+                     "filter_share_of_solve": round(r["filter_ms"] / r["total_ms"], 4)},
+        "fig4_curves": {"index_every_256": idx,
+                        "omega_unstructured": [float(np.sqrt(max(om2[k], 0.0))) for k in idx],
+                        "omega_structured_quad": [float(np.sqrt(quad[k])) for k in idx],
+                        "omega_analytic": [float(np.sqrt(exact[k])) for k in idx],
+                        "omega_unstructured_top": float(np.sqrt(om2[-1]))},
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_spectrum(nt),
+    }
+    return out
+
+
+def cpu_baseline_spectrum(nt_full):
+    """The oracle's whole spectrum (dense library eigensolver, eigenvalues only, every host
+    core) on the 40 x 58 box (5,427 triangles): the full-size solve takes minutes, so the
+    sample is timed and scaled by the solver's n^3 work to the Fig. 4 size."""
+    import oracle
+    from meshgen import box_tri_mesh
+    xy, tri, Lx, Ly = box_tri_mesh(40.0, 58.0, 1.0, 0.1, 3)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    t0 = time.perf_counter()
+    om.spectrum(vectors=False)
+    el = time.perf_counter() - t0
+    scaled = el * (nt_full / om.nt) ** 3
+    from threadpoolctl import threadpool_info
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": nt_full / scaled, "unit": "modes/s", "cores": threads, "kind": "oracle",
+            "sample": f"eigenvalues (no vectors) of the 40 x 58 box, {om.nt} triangles, in {el:.1f} s, "
+                      f"scaled by (n/{om.nt})^3 to {nt_full} triangles ({scaled:.0f} s)"}
 
 
 def modes_apply_at_scale(ty, stream, nb=MODES_BLOCK):

@@ -599,6 +599,9 @@ typedef struct {
     double total_ms;       /* host wall time of the call, uploads and readback included */
     double max_residual;   /* largest residual / lambda_bound of an accepted pair */
     double min_gap;        /* smallest eigenvalue gap at a window boundary / lambda_bound */
+    int64_t sq_launches;   /* launches of the fused (K - sigma)^2 block apply */
+    double sq_ms;          /* HIP-event time of the interior windows' filter passes (those
+                              launches only) */
 } tyee_spectrum_stats;
 
 /* Every eigenmode of the resonator: all n_triangles eigenpairs of K = -L_E L_B (the operator of

@@ -156,14 +156,16 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply2(
 // y_out = alpha * ((K - sigma)^2 y) + beta * y + gam * y_prev (y_prev may be null), in one pass:
 // row j of (K - sigma)^2 y needs (K - sigma) y at j and at its neighbours k, and those need the
 // neighbours of k, so a wave (one row) reads up to ten rows of y (the two-ring of j, mostly
-// from the caches: neighbouring rows are close in the locality numbering).  The weights,
+// from the caches: neighbouring rows are close in the locality numbering; row j, which is in
+// each neighbour's ring, is read once).  The weights,
 // neighbour slots and 1/S of the ring are wave-uniform.  Columns in chunks of 64.
+constexpr int kSqWaves = 4;      // rows per work-group of the fused apply (8 measured slower)
 template <int CH>                // 64-column chunks per row: ceil(nb / 64)
-__global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply_sq(
+__global__ void __launch_bounds__(64 * kSqWaves) k_modes_apply_sq(
     int32_t n, int32_t nb, const double *__restrict__ y, const double *__restrict__ yp, double *__restrict__ yo,
     const int32_t *__restrict__ nbr, const double *__restrict__ wt, const double *__restrict__ inv_s, double sigma,
     double alpha, double beta, double gam) {
-    const int j = __builtin_amdgcn_readfirstlane(xcd_group(blockIdx.x, gridDim.x) * kApplyWaves +
+    const int j = __builtin_amdgcn_readfirstlane(xcd_group(blockIdx.x, gridDim.x) * kSqWaves +
                                                  int(threadIdx.x >> 6));
     if (j >= n) return;
     const int lane = threadIdx.x & 63;
@@ -195,7 +197,11 @@ __global__ void __launch_bounds__(64 * kApplyWaves) k_modes_apply_sq(
             const int k = o[q] >= 0 ? o[q] : j;
             yk[q] = y[size_t(k) * nb + c];
 #pragma unroll
-            for (int p = 0; p < 3; ++p) ykk[q][p] = y[size_t(oo[q][p] >= 0 ? oo[q][p] : k) * nb + c];
+            for (int p = 0; p < 3; ++p) {
+                const int l = oo[q][p];
+                // row j is at hand; a missing neighbour reads row k (not used)
+                ykk[q][p] = l == j ? yj : y[size_t(l >= 0 ? l : k) * nb + c];
+            }
         }
         const double pv = yp ? yp[size_t(j) * nb + c] : 0.0;
         // t = (K - sigma) y at j and at the neighbours
@@ -1348,7 +1354,7 @@ struct ModeSolver {
 
     // yo = alpha (K - sigma)^2 y + beta y + gam yp, one launch
     int apply_sq(const double *y, const double *yp, double *yo, double sigma, double alpha, double beta, double gam) {
-        const dim3 grid((n + kApplyWaves - 1) / kApplyWaves), threads(64 * kApplyWaves);
+        const dim3 grid((n + kSqWaves - 1) / kSqWaves), threads(64 * kSqWaves);
         const int32_t *nb_ = nbr.as<int32_t>();
         const double *wt_ = wt.as<double>(), *is_ = inv_s.as<double>();
         switch ((nb + 63) / 64) {
@@ -2073,6 +2079,7 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
                             if (mode == kSquared) {
                                 rc2 = sv.filter_sq(in, d, a, mu_max, sigma, &fo);
                                 st.applies += 2 * d;
+                                st.sq_launches += d;
                             } else {
                                 rc2 = sv.filter(in, d, a, upper, a0, &fo);
                                 st.applies += d;
@@ -2088,6 +2095,7 @@ extern "C" int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, in
                             float ms = 0.0f;
                             TYEE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
                             st.filter_ms += ms;
+                            if (mode == kSquared) st.sq_ms += ms;
                         }
                         if (!rc2) in = out;
                         return rc2;

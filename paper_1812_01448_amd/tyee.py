@@ -73,7 +73,8 @@ class _SpectrumStats(ctypes.Structure):
                 ("applies", ctypes.c_int64), ("below", ctypes.c_int64), ("retries", ctypes.c_int64),
                 ("lambda_bound", ctypes.c_double), ("filter_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("max_residual", ctypes.c_double),
-                ("min_gap", ctypes.c_double)]
+                ("min_gap", ctypes.c_double), ("sq_launches", ctypes.c_int64),
+                ("sq_ms", ctypes.c_double)]
 
 
 class _RelaxParams(ctypes.Structure):
@@ -407,7 +408,8 @@ class Mesh:
         Returns a dict: omega2 [n_t] ascending, modes [n_t, n_t] (mode-major, canonical
         triangle order, S-orthonormal; None unless want_vectors), residual [n_t] (relative to the
         Gershgorin bound), converged, and the call's stats (windows, iters, found, applies,
-        below, retries, lambda_bound, filter_ms, total_ms, max_residual, min_gap)."""
+        below, retries, lambda_bound, filter_ms, total_ms, max_residual, min_gap, sq_launches,
+        sq_ms)."""
         om2 = np.zeros(self.nt)
         vec = np.zeros((self.nt, self.nt)) if want_vectors else None
         res = np.zeros(self.nt)
