@@ -654,6 +654,82 @@ int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, int32_t block
                        double tol, int32_t max_iter, uint64_t seed, void *stream, double *omega2,
                        double *modes, double *residual, tyee_spectrum_stats *stats);
 
+/* ---------------------------------------------------------------------------------------
+   Open boundary: the triangle mesh of a closed box tied to a rectangular frame of PML layers.
+   The paper's Conclusion: the scheme works on mixed meshes (triangles plus quads), so a mesh
+   with rectangular boundaries can be joined to a structured frame that carries PML layers.
+   A rectangle's circumcentre is its centre, on the perpendicular bisector of each side as a
+   triangle's circumcentre is, so eqs. 3-4 hold on the mixed mesh unchanged.
+
+   The frame: the mesh must fill the box [0, Lx] x [0, Ly] (a TYEE_PEC_BOX mesh whose outer edges
+   lie on the box sides, with nodes exactly on the side lines).  Each side is continued outwards
+   by `layers` rows of rectangles `width` deep whose columns (rows) are bounded by that side's
+   boundary nodes; each corner by layers x layers squares.  The frame's outer wall is a perfect
+   conductor (E = 0).  Damping: sigma(rho) = sigma_max (rho / (layers width))^grading, rho the
+   distance beyond the box in x (sigma_x) or y (sigma_y).  A frame cell's B is split into Bx
+   (driven by its two sides parallel to y, decaying with its sigma_x) and By (its two sides
+   parallel to x, sigma_y); an edge parallel to x decays with sigma_y at its midpoint, one
+   parallel to y with sigma_x; triangles and edges inside the box do not decay.  Each damping
+   term is taken at the half step: X <- (1 - sigma dt/2)/(1 + sigma dt/2) X + dt/(1 + sigma dt/2)
+   (drive).  A step updates E (eq. 3, B_left - B_right over the centre distance d, edges
+   oriented from the lower node id to the higher, "left" the cell on the left of that tangent),
+   then B (eq. 4, -(1/S) sum over the cell's edges of s |e| E, s = +1 where the edge runs
+   counter-clockwise around the cell), one launch each.
+
+   Canonical numbering of the mixed mesh: the triangle mesh's nodes, edges and triangles keep
+   their ids; the frame's new nodes follow ordered by (y, x), its edges follow the mesh's
+   ordered by (lower, higher) node id, its rectangles follow the triangles ordered by the (y, x)
+   of their centres.  Device arrays are in the same order. */
+typedef struct tyee_open tyee_open;
+
+typedef struct {
+    int32_t layers;        /* rows of rectangles around each side, 1 .. 4096 */
+    double width;          /* depth of one row (> 0) */
+    double sigma_max;      /* damping rate at the outer wall (>= 0; 0 gives a reflecting frame) */
+    double grading;        /* exponent of the profile (>= 0) */
+} tyee_pml_params;
+
+/* Fields of the open simulation.  E: [n_edges] (the frame's outer wall stays 0); BX: [n_cells],
+   B of a triangle and the Bx part of a frame cell; BY: [n_cells] with the By part of frame
+   cells (entries of triangles are ignored on set and returned as 0).  B = BX + BY. */
+typedef enum { TYEE_OPEN_E = 0, TYEE_OPEN_BX = 1, TYEE_OPEN_BY = 2 } tyee_open_field;
+
+/* Build the frame (host, FP64), upload the coefficients (prec TYEE_F32 or TYEE_F64) for the time
+   step dt, zero state.  stream: HIP stream, or NULL for one of the library's own.  Errors:
+   EINVAL (a periodic mesh, a mesh that does not fill the box, bad parameters), ENOTDELAUNAY (a
+   centre distance across an edge is not positive), ENOMEM, EDEVICE.  *out gets the handle. */
+int tyee_open_create(const tyee_mesh *mesh, const tyee_pml_params *pml, int32_t prec, double dt, void *stream,
+                     tyee_open **out);
+/* out = {n_nodes, n_edges, n_cells, n_frame_cells, n_inner_edges} of the mixed mesh. */
+int tyee_open_sizes(const tyee_open *o, int64_t out[5]);
+/* The mixed mesh that tyee_open_create builds, built on the host alone (no device): sizes =
+   {n_nodes, n_edges, n_cells, n_frame_cells, n_inner_edges}; the arrays, in canonical order, may
+   each be NULL (a first call with all of them NULL gives the sizes): xy [n_nodes][2], edge
+   [n_edges][2] (lower, higher node id), cell_edge [n_cells][4] (a rectangle: its sides parallel
+   to y, then those parallel to x; a triangle's fourth entry -1), elen, d (centre distance across
+   the edge, 0 on the outer wall), sigma_e [n_edges]; S, sigma_x, sigma_y [n_cells] (0 on
+   triangles); O [n_cells][2] circumcentres.  Errors as tyee_open_create's, ENOMEM. */
+int tyee_open_frame(const tyee_mesh *mesh, const tyee_pml_params *pml, int64_t sizes[5], double *xy,
+                    int32_t *edge, int32_t *cell_edge, double *elen, double *d, double *S, double *O,
+                    double *sigma_e, double *sigma_x, double *sigma_y);
+/* Largest eigenvalue lambda of K = -L_E L_B on the mixed mesh without damping (FP64 power
+   iteration on the host); omega_max = sqrt(lambda) sets dt < 2/omega_max (eq. 20).  Errors:
+   EINVAL, ENOTCONVERGED (*lambda still set). */
+int tyee_open_cfl(const tyee_open *o, int64_t max_iter, double rtol, uint64_t seed, double *lambda,
+                  int64_t *iters);
+/* Host values (FP64, canonical order) to or from the device; both wait for the stream. */
+int tyee_open_set_state(tyee_open *o, int32_t field, const double *values);
+int tyee_open_get_state(tyee_open *o, int32_t field, double *values);
+/* Enqueue nsteps steps on the stream (returns without waiting unless timing is on). */
+int tyee_open_step(tyee_open *o, int64_t nsteps);
+int tyee_open_sync(tyee_open *o);
+/* With timing on, each step records HIP events around its two launches (and waits for them);
+   tyee_open_kernel_ms gives the summed milliseconds {E update, B update} and the steps timed
+   since timing was set. */
+int tyee_open_set_timing(tyee_open *o, int32_t on);
+int tyee_open_kernel_ms(const tyee_open *o, double out[2], int64_t *steps);
+int tyee_open_destroy(tyee_open *o);
+
 const char *tyee_last_error(void);
 
 #ifdef __cplusplus

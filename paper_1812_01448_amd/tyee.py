@@ -77,6 +77,11 @@ class _SpectrumStats(ctypes.Structure):
                 ("sq_ms", ctypes.c_double)]
 
 
+class _PmlParams(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int32), ("width", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("grading", ctypes.c_double)]
+
+
 class _RelaxParams(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("iters", ctypes.c_int32), ("step", ctypes.c_double),
                 ("k_edge", ctypes.c_double), ("k_height", ctypes.c_double), ("rest", ctypes.c_double),
@@ -114,7 +119,9 @@ EXPORTS = [
     "tyee_learner_destroy", "tyee_gate",
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
     "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_spectrum", "tyee_mesh_relax",
-    "tyee_mesh_flip",
+    "tyee_mesh_flip", "tyee_open_create", "tyee_open_sizes", "tyee_open_frame", "tyee_open_cfl",
+    "tyee_open_set_state", "tyee_open_get_state", "tyee_open_step", "tyee_open_sync",
+    "tyee_open_set_timing", "tyee_open_kernel_ms", "tyee_open_destroy",
     "tyee_batch_tune_progress",
     "tyee_last_error",
 ]
@@ -211,6 +218,17 @@ def _load():
         "tyee_mesh_spectrum": [vp, vp, i32, i32, f64, i32, ctypes.c_uint64, vp, vp, vp, vp,
                                ctypes.POINTER(_SpectrumStats)],
         "tyee_batch_tune_progress": [vp, i64, vp, i64, ctypes.POINTER(i64), _TUNE_PROGRESS, vp],
+        "tyee_open_create": [vp, ctypes.POINTER(_PmlParams), i32, f64, vp, ctypes.POINTER(vp)],
+        "tyee_open_sizes": [vp, vp],
+        "tyee_open_frame": [vp, ctypes.POINTER(_PmlParams), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "tyee_open_cfl": [vp, i64, f64, ctypes.c_uint64, ctypes.POINTER(f64), ctypes.POINTER(i64)],
+        "tyee_open_set_state": [vp, i32, vp],
+        "tyee_open_get_state": [vp, i32, vp],
+        "tyee_open_step": [vp, i64],
+        "tyee_open_sync": [vp],
+        "tyee_open_set_timing": [vp, i32],
+        "tyee_open_kernel_ms": [vp, vp, ctypes.POINTER(i64)],
+        "tyee_open_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -423,6 +441,85 @@ class Mesh:
         out = {"omega2": om2, "modes": vec, "residual": res, "converged": rc == OK}
         out.update({n: getattr(st, n) for n, _ in _SpectrumStats._fields_})
         return out
+
+
+OPEN_FIELD = {"E": 0, "BX": 1, "BY": 2}
+
+
+def pml(layers, width, sigma_max, grading=3.0):
+    """PML frame parameters (tyee_pml_params)."""
+    return _PmlParams(int(layers), float(width), float(sigma_max), float(grading))
+
+
+def open_frame(mesh, params):
+    """The mixed mesh (triangles plus the PML frame) built on the host (tyee_open_frame): a dict
+    of numpy arrays in canonical order and the sizes."""
+    sizes = np.zeros(5, np.int64)
+    _check(lib.tyee_open_frame(mesh._h, ctypes.byref(params), _ptr(sizes), *([None] * 10)))
+    nv, ne, nc = (int(v) for v in sizes[:3])
+    out = {"xy": np.zeros((nv, 2)), "edge": np.zeros((ne, 2), np.int32), "cell_edge": np.zeros((nc, 4), np.int32),
+           "elen": np.zeros(ne), "d": np.zeros(ne), "S": np.zeros(nc), "O": np.zeros((nc, 2)),
+           "sigma_e": np.zeros(ne), "sigma_x": np.zeros(nc), "sigma_y": np.zeros(nc)}
+    _check(lib.tyee_open_frame(mesh._h, ctypes.byref(params), _ptr(sizes),
+                               *[_ptr(out[k]) for k in ("xy", "edge", "cell_edge", "elen", "d", "S", "O",
+                                                        "sigma_e", "sigma_x", "sigma_y")]))
+    out.update({"n_nodes": nv, "n_edges": ne, "n_cells": nc, "n_frame_cells": int(sizes[3]),
+                "n_inner_edges": int(sizes[4])})
+    return out
+
+
+class Open:
+    """The triangle mesh of a closed box tied to a PML frame, stepped on the device
+    (tyee_open_*)."""
+
+    def __init__(self, mesh, params, dt, prec="f32", stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.tyee_open_create(mesh._h, ctypes.byref(params), PREC[prec], float(dt),
+                                    None if stream is None else int(stream), ctypes.byref(h)))
+        self._h = h
+        sizes = np.zeros(5, np.int64)
+        _check(lib.tyee_open_sizes(h, _ptr(sizes)))
+        self.nv, self.ne, self.ncell, self.nf, self.n_inner = (int(v) for v in sizes)
+        self.nt = self.ncell - self.nf
+        self.dt, self.prec = float(dt), prec
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_open_destroy(h)
+            self._h = None
+
+    def _n(self, field):
+        return self.ne if field == "E" else self.ncell
+
+    def set_state(self, field, values):
+        a = _f64(values, self._n(field))
+        _check(lib.tyee_open_set_state(self._h, OPEN_FIELD[field], _ptr(a)))
+
+    def get_state(self, field):
+        out = np.zeros(self._n(field))
+        _check(lib.tyee_open_get_state(self._h, OPEN_FIELD[field], _ptr(out)))
+        return out
+
+    def step(self, n=1):
+        _check(lib.tyee_open_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib.tyee_open_sync(self._h))
+
+    def cfl(self, max_iter=200000, rtol=1e-12, seed=0):
+        lam, it = ctypes.c_double(), ctypes.c_int64()
+        rc = _check(lib.tyee_open_cfl(self._h, int(max_iter), float(rtol), int(seed), ctypes.byref(lam),
+                                      ctypes.byref(it)), allow=(ENOTCONVERGED,))
+        return lam.value, it.value, rc == OK
+
+    def set_timing(self, on=True):
+        _check(lib.tyee_open_set_timing(self._h, 1 if on else 0))
+
+    def kernel_ms(self):
+        out, n = np.zeros(2), ctypes.c_int64()
+        _check(lib.tyee_open_kernel_ms(self._h, _ptr(out), ctypes.byref(n)))
+        return {"edge_ms": float(out[0]), "cell_ms": float(out[1]), "steps": n.value}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

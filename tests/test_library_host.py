@@ -233,3 +233,53 @@ def test_lawson_flip_errors(ty):
     with pytest.raises(ty.TyeeError) as e:
         ty.flip(xy, np.array([[0, 1, 7]]), False, L=2.0)
     assert e.value.code == -1                      # node id out of range
+
+
+@pytest.mark.parametrize("kind,layers,width,smax,grading",
+                         [("tri", 3, 0.5, 0.0, 3.0), ("tri", 4, 0.7, 2.0, 3.0), ("square", 2, 1.25, 1.5, 2.0)])
+def test_open_frame_matches_oracle(ty, kind, layers, width, smax, grading):
+    """The library's PML frame (built on the host) against the oracle's own builder: the same
+    canonical numbering, coordinates, edges, cell-edge sets, lengths, centre distances, areas,
+    centres and damping profiles."""
+    from meshgen import box_mesh, box_tri_mesh
+    from oracle.open import OpenMesh
+    if kind == "tri":
+        xy, tri, Lx, Ly = box_tri_mesh(8, 6, 1.0, 0.1, 1)
+    else:
+        xy, tri, Lx, Ly = box_mesh(6, 5, 0.15, 2, h=1.0)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    ref = OpenMesh(om, layers, width, smax, grading)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    g = ty.open_frame(m, ty.pml(layers, width, smax, grading))
+    assert (g["n_nodes"], g["n_edges"], g["n_cells"], g["n_frame_cells"]) == (ref.nv, ref.ne, ref.ncell, ref.nf)
+    assert g["n_inner_edges"] == int(ref.inner.sum())
+    assert np.array_equal(g["xy"], ref.xy) and np.array_equal(g["edge"], ref.edge)
+    for j in range(ref.ncell):
+        got = g["cell_edge"][j]
+        assert sorted(got[got >= 0].tolist()) == sorted(ref.cell_edges[j]), j
+    # a rectangle lists its sides parallel to y first
+    vert = np.abs(np.diff(g["xy"][g["edge"]], axis=1)[:, 0, 0]) == 0.0
+    assert np.all(vert[g["cell_edge"][ref.nt:, :2]]) and not np.any(vert[g["cell_edge"][ref.nt:, 2:]])
+    for k, v in (("elen", ref.elen), ("d", ref.d), ("S", ref.S), ("O", ref.O), ("sigma_e", ref.sigma_e),
+                 ("sigma_x", ref.sigma_x), ("sigma_y", ref.sigma_y)):
+        assert np.max(np.abs(g[k] - v)) <= 1e-14 * max(1.0, np.max(np.abs(v))), k
+
+
+def test_open_frame_errors(ty):
+    from meshgen import box_tri_mesh
+    xy, tri, Lx, Ly = box_tri_mesh(8, 6, 1.0, 0.1, 1)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    for bad in (ty.pml(0, 1.0, 1.0), ty.pml(2, 0.0, 1.0), ty.pml(2, 1.0, -1.0), ty.pml(2, 1.0, 1.0, -1.0)):
+        with pytest.raises(ty.TyeeError) as e:
+            ty.open_frame(m, bad)
+        assert e.value.code == -1
+    # the mesh must fill the box it is declared on
+    wide = ty.Mesh(xy, tri, False, L=Lx + 1.0, Ly=Ly)
+    with pytest.raises(ty.TyeeError) as e:
+        ty.open_frame(wide, ty.pml(2, 1.0, 1.0))
+    assert e.value.code == -1
+    xt, tt = lattice_mesh(8, 0.2, 3, periodic=True)
+    torus = ty.Mesh(xt, tt, True)
+    with pytest.raises(ty.TyeeError) as e:
+        ty.open_frame(torus, ty.pml(2, 0.1, 1.0))
+    assert e.value.code == -1
