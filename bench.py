@@ -40,13 +40,14 @@ def parse(argv=None):
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
     p.add_argument("--workload", default="torus1415",
                    choices=["torus1415", "plasma2830", "batch256", "learned", "modes70x101", "spectrum70x101",
-                            "relax"],
+                            "relax", "open1415"],
                    help="torus1415 (the reported line), plasma2830 (16M triangles with a plasma "
                         "particle and a line source), batch256 (256 uneven meshes), learned "
                         "(train and evaluate the learned edge scale) or modes70x101 (the 128 "
                         "lowest modes of the 70 x 101 resonator of Fig. 4; --steps timed "
                         "solves, at most 20), spectrum70x101 (every mode of that resonator, one "
-                        "solve) or relax (jello relaxation of the 45 x 45 cavity and "
+                        "solve), open1415 (the 1415 x 1415 box tied to a 16-layer PML frame) or relax "
+                        "(jello relaxation of the 45 x 45 cavity and "
                         "the 1415 x 1415 torus: omega_max and so dt before and after)")
     p.add_argument("--relax-rounds", type=int, default=8)
     p.add_argument("--relax-iters", type=int, default=100)
@@ -285,7 +286,7 @@ def main():
         sys.exit(2)
     run = {"batch256": bench_batch, "learned": bench_learned, "plasma2830": bench_plasma,
            "modes70x101": bench_modes, "spectrum70x101": bench_spectrum, "torus1415": bench_torus,
-           "relax": bench_relax}[args.workload]
+           "relax": bench_relax, "open1415": bench_open}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -748,6 +749,118 @@ def bench_modes(args):
         "cpu_baseline": None if args.no_cpu else cpu_baseline_modes(xy, tri, Lx, Ly),
     }
     return out
+
+
+def bench_open(args):
+    """The 1415 x 1415 box (4.6M triangles, a jittered triangular lattice) tied to a 16-layer PML
+    frame (the paper's Conclusion), FP32, two launches per step (E, then B); a centred pulse
+    leaves through the frame."""
+    import torch
+    import paper_1812_01448_amd as ty
+    from meshgen import box_tri_mesh
+
+    t0 = time.perf_counter()
+    xy, tri, Lx, Ly = box_tri_mesh(1415.0, 1415.0, 1.0, 0.1, 11)
+    mesh = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    prm = ty.pml(16, 1.0, 1.0, 3.0)
+    torch.cuda.init()
+    stream = torch.cuda.Stream()          # a stream of our own: graphs are captured on it
+    probe = ty.Open(mesh, prm, 1.0, "f32", stream.cuda_stream)
+    lam, iters, ok = probe.cfl(rtol=1e-6)
+    del probe
+    dt = 0.5 * 2 / np.sqrt(lam)
+    sim = ty.Open(mesh, prm, dt, "f32", stream.cuda_stream)
+    log(f"open1415: mesh, frame and omega_max (lambda {lam:.4g}, {iters} iterations) in "
+        f"{time.perf_counter() - t0:.1f} s; {sim.nt} triangles, {sim.nf} frame cells, {sim.ne} edges")
+    g = ty.open_frame(mesh, prm)
+    r2 = np.sum((g["O"] - [Lx / 2, Ly / 2]) ** 2, axis=1)
+    B0 = np.where(np.arange(sim.ncell) < sim.nt, np.exp(-r2 / (2 * 40.0 ** 2)), 0.0)
+    sim.set_state("BX", B0)
+    steps, warmup = args.steps, args.warmup
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    cells = sim.ne + sim.ncell
+    B = sim.get_state("BX") + sim.get_state("BY")
+    left = float(np.sum(g["S"][:sim.nt] * B[:sim.nt] ** 2) / np.sum(g["S"][:sim.nt] * B0[:sim.nt] ** 2))
+    step_ms = open_step_ms(sim, steps, stream)
+    ne, nc, nf, nt = sim.ne, sim.ncell, sim.nf, sim.nt
+    wall = ne - sim.n_inner                     # the frame's outer edges (one cell)
+    frame_inner = ne - mesh.ne - wall           # the frame's own edges between two cells
+    # algorithmic bytes (FP32), each array read or written once: E update: per inner edge the
+    # line integral r/w, two cell ids and one coefficient, a decay factor per inner frame edge,
+    # the ids of a wall edge; B of every cell and By of every frame cell read once.  B update:
+    # per triangle three signed edge ids, dt/S and B r/w; per frame cell four ids, four
+    # coefficients and Bx, By r/w; every edge's line integral read once
+    edge_bytes = 20 * sim.n_inner + 8 * wall + 4 * frame_inner + 4 * nc + 4 * nf
+    cell_bytes = 24 * nt + 48 * nf + 4 * ne
+    step_bytes = edge_bytes + cell_bytes
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
+    out = {
+        "metric": "cell-updates/s (edges + cells of the mixed mesh per step)",
+        "value": cells * steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "open boundary: 1415 x 1415 box, jittered (+-0.1h) triangular-lattice Delaunay "
+                               "mesh, tied to a 16-layer PML frame of width 1 (sigma_max 1, cubic grading)",
+                   "triangles": sim.nt, "frame_cells": nf, "edges": ne, "dt": dt, "omega_max": float(np.sqrt(lam)),
+                   "pulse_energy_left_in_box": left},
+        "roofline": {"bound": "hbm", "kernel": "k_open_edge + k_open_cell (one step: the E and the B update)",
+                     "timed_with": "HIP events on the launch stream around segments of 256 steps (graphs of 8 steps)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "launches_per_step": 2, "avg_step_ms": round(step_ms, 5),
+                     "algorithmic_bytes_per_step": step_bytes, "traffic": None,
+                     "per_kernel_bytes": {"k_open_edge": edge_bytes, "k_open_cell": cell_bytes}},
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_open(),
+    }
+    return out
+
+
+def open_step_ms(sim, steps, stream, segment=256):
+    """Steady-state GPU time of one open-boundary step (two launches) from HIP events on the
+    launch stream: one event pair per segment of 256 steps (32 graph replays), the stream
+    drained between segments. A pair around thousands of queued launches reads short on this
+    runtime (its first timestamp is taken late), so the region is cut into segments; their
+    event times agree with the wall clock of the same segments."""
+    import torch
+    total, done = 0.0, 0
+    while done < steps:
+        n = min(segment, steps - done)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(n)
+        e1.record(stream)
+        e1.synchronize()
+        total += e0.elapsed_time(e1)
+        done += n
+    return total / steps
+
+
+def cpu_baseline_open():
+    """The open-boundary oracle (numpy, FP64) stepping a 192 x 192 box with the same frame
+    recipe: a per-cell rate."""
+    import oracle
+    from oracle.open import OpenMesh
+    from meshgen import box_tri_mesh
+    from threadpoolctl import threadpool_info
+    xy, tri, Lx, Ly = box_tri_mesh(192.0, 192.0, 1.0, 0.1, 11)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    m = OpenMesh(om, 16, 1.0, 1.0)
+    E, Bx, By = np.zeros(m.ne), np.ones(m.ncell), np.zeros(m.ncell)
+    m.step(E, Bx, By, 0.1, 2)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < 10.0:
+        E, Bx, By = m.step(E, Bx, By, 0.1, 10)
+        n += 10
+    el = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": (m.ne + m.ncell) * n / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the 192 x 192 box with the frame ({m.nt} triangles, {m.nf} frame cells), "
+                      f"numpy on one process"}
 
 
 SPECTRUM_TOL = 1e-10

@@ -679,7 +679,9 @@ int tyee_mesh_spectrum(const tyee_mesh *mesh, const double *gamma, int32_t block
    Canonical numbering of the mixed mesh: the triangle mesh's nodes, edges and triangles keep
    their ids; the frame's new nodes follow ordered by (y, x), its edges follow the mesh's
    ordered by (lower, higher) node id, its rectangles follow the triangles ordered by the (y, x)
-   of their centres.  Device arrays are in the same order. */
+   of their centres.  Device arrays are in the same order; the device holds each edge's line
+   integral |e| E (converted on set and get), so that a cell's update reads only the sign of
+   each side. */
 typedef struct tyee_open tyee_open;
 
 typedef struct {
@@ -720,10 +722,17 @@ int tyee_open_cfl(const tyee_open *o, int64_t max_iter, double rtol, uint64_t se
 /* Host values (FP64, canonical order) to or from the device; both wait for the stream. */
 int tyee_open_set_state(tyee_open *o, int32_t field, const double *values);
 int tyee_open_get_state(tyee_open *o, int32_t field, double *values);
-/* Enqueue nsteps steps on the stream (returns without waiting unless timing is on). */
+/* Enqueue nsteps steps on the stream (returns without waiting unless timing is on): whole
+   groups of the graph size replay one captured HIP graph (the stream must allow capture: a
+   caller's stream other than the legacy default one), the rest are launched one by one. */
 int tyee_open_step(tyee_open *o, int64_t nsteps);
+/* Steps per captured graph, 0 .. 1024 (0: every launch eager; default 8).  Waits for the stream
+   if a graph exists (it is discarded).  Errors: EINVAL. */
+int tyee_open_set_graph(tyee_open *o, int32_t steps);
 int tyee_open_sync(tyee_open *o);
-/* With timing on, each step records HIP events around its two launches (and waits for them);
+/* With timing on, steps are launched one by one, each with HIP events around its two launches
+   (read after every 256 steps, so a timed call waits for its steps; the events add a few us to
+   each launch's reading);
    tyee_open_kernel_ms gives the summed milliseconds {E update, B update} and the steps timed
    since timing was set. */
 int tyee_open_set_timing(tyee_open *o, int32_t on);

@@ -33,6 +33,7 @@ namespace {
 // by the (y, x) of their centres.
 struct Frame {
     int64_t nv = 0, ne = 0, ncell = 0, nt = 0, nf = 0, n_inner = 0;
+    int64_t ne_mesh = 0;                       // the triangle mesh's edges, ids 0 .. ne_mesh-1
     std::vector<double> xy;                    // [nv][2]
     std::vector<int32_t> edge;                 // [ne][2]
     std::vector<int32_t> left, right;          // [ne], -1 on the frame's outer wall
@@ -136,9 +137,11 @@ int build_frame(const Mesh &m, const tyee_pml_params &p, Frame &f) {
     f.nt = m.nt;
     f.nf = int64_t(rects.size());
     f.ncell = f.nt + f.nf;
-    // edges: the mesh's ids, then the frame's by node pair
+    // edges: the mesh's ids (only its outer edges can be sides of a rectangle), then the
+    // frame's by node pair
     std::map<std::pair<int32_t, int32_t>, int32_t> eid;
-    for (int64_t i = 0; i < m.ne; ++i) eid[{m.edge[2 * i], m.edge[2 * i + 1]}] = int32_t(i);
+    for (int64_t i = 0; i < m.ne; ++i)
+        if (!m.interior(i)) eid[{m.edge[2 * i], m.edge[2 * i + 1]}] = int32_t(i);
     auto key = [](int32_t a, int32_t b) { return std::make_pair(std::min(a, b), std::max(a, b)); };
     std::vector<std::array<int32_t, 4>> corner(rects.size());
     std::set<std::pair<int32_t, int32_t>> fresh_edges;
@@ -150,6 +153,7 @@ int build_frame(const Mesh &m, const tyee_pml_params &p, Frame &f) {
             if (!eid.count(k2)) fresh_edges.insert(k2);
         }
     }
+    f.ne_mesh = m.ne;
     f.ne = m.ne + int64_t(fresh_edges.size());
     f.edge.assign(m.edge.begin(), m.edge.end());
     {
@@ -242,39 +246,53 @@ int build_frame(const Mesh &m, const tyee_pml_params &p, Frame &f) {
     return TYEE_OK;
 }
 
-// E_i = ca_i E_i + cbd_i (B_left - B_right), B of a frame cell the sum of its two parts; the
-// frame's outer edges (no second cell) stay at zero.
+// The device holds each edge's line integral e_i = |e_i| E_i, so that a cell's update needs
+// only the sign of each of its sides, carried in the sign of the stored edge id (id or ~id).
+//
+// E update: e_i = ca_i e_i + k_i (B_left - B_right), k_i = |e_i| dt / ((1 + sigma_i dt/2) d_i).
+// The triangle mesh's edges lie in the box, where sigma is zero (ca = 1); only the frame's own
+// edges (ids from nem up) read a decay factor.  A frame cell's B is the sum of its two parts.
+// The frame's outer edges (one cell) keep their value.
 template <typename T>
-__global__ void k_open_edge(int32_t ne, int32_t nt, const int2 *__restrict__ lr, const T *__restrict__ ca,
-                            const T *__restrict__ cbd, const T *__restrict__ B, const T *__restrict__ By,
-                            T *__restrict__ E) {
+__global__ void k_open_edge(int32_t ne, int32_t nem, int32_t nt, const int2 *__restrict__ lr,
+                            const T *__restrict__ k, const T *__restrict__ caf, const T *__restrict__ B,
+                            const T *__restrict__ By, T *__restrict__ E) {
     const int i = xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= ne) return;
     const int2 c = lr[i];
     if (c.x < 0 || c.y < 0) return;
     const T bl = B[c.x] + (c.x >= nt ? By[c.x - nt] : T(0));
     const T br = B[c.y] + (c.y >= nt ? By[c.y - nt] : T(0));
-    E[i] = ca[i] * E[i] + cbd[i] * (bl - br);
+    const T e = i >= nem ? caf[i - nem] * E[i] : E[i];
+    E[i] = e + k[i] * (bl - br);
 }
 
-// Triangles: B -= (dt/S) sum_q s|e| E.  Frame cells: Bx = ax Bx - bx (its vertical sides' terms),
-// By = ay By - by (its horizontal sides' terms), bx and by holding the 1/S.
+// s e_i for a signed id: id >= 0 reads +e_id, ~id reads -e_id.
 template <typename T>
-__global__ void k_open_cell(int32_t ncell, int32_t nt, const int4 *__restrict__ ce, const T *__restrict__ sl,
-                            const T *__restrict__ ax, const T *__restrict__ bx, const T *__restrict__ ay,
-                            const T *__restrict__ by, const T *__restrict__ E, T *__restrict__ B,
-                            T *__restrict__ By) {
+__device__ __forceinline__ T side(const T *__restrict__ E, int32_t id) {
+    const T v = E[id ^ (id >> 31)];
+    return id < 0 ? -v : v;
+}
+
+// B update.  Triangles (j < nt): B -= (dt/S) sum of s e over the three sides (ids t0, t1, t2).
+// Frame cells: Bx = ax Bx - bx (left and right sides), By = ay By - by (bottom and top sides),
+// fc = {ax, bx, ay, by} per cell with bx and by holding dt/S.
+template <typename T>
+__global__ void k_open_cell(int32_t ncell, int32_t nt, const int32_t *__restrict__ t0,
+                            const int32_t *__restrict__ t1, const int32_t *__restrict__ t2,
+                            const T *__restrict__ g, const int4 *__restrict__ fe, const T *__restrict__ fc,
+                            const T *__restrict__ E, T *__restrict__ B, T *__restrict__ By) {
     const int j = xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (j >= ncell) return;
-    const int4 e = ce[j];
-    const T c0 = sl[4 * j] * E[e.x], c1 = sl[4 * j + 1] * E[e.y], c2 = sl[4 * j + 2] * E[e.z];
     if (j < nt) {
-        B[j] = B[j] - bx[j] * (c0 + c1 + c2);
+        const T c = side(E, t0[j]) + side(E, t1[j]) + side(E, t2[j]);
+        B[j] = B[j] - g[j] * c;
     } else {
-        const T c3 = sl[4 * j + 3] * E[e.w];
-        B[j] = ax[j] * B[j] - bx[j] * (c0 + c1);
         const int f = j - nt;
-        By[f] = ay[f] * By[f] - by[f] * (c2 + c3);
+        const int4 q = fe[f];
+        const T ax = fc[4 * f], bx = fc[4 * f + 1], ay = fc[4 * f + 2], by = fc[4 * f + 3];
+        B[j] = ax * B[j] - bx * (side(E, q.x) + side(E, q.y));
+        By[f] = ay * By[f] - by * (side(E, q.z) + side(E, q.w));
     }
 }
 
@@ -288,12 +306,19 @@ struct tyee_open {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    tyee::DeviceBuffer E, B, By, lr, ca, cbd, ce, sl, ax, bx, ay, by;
+    // state: E (line integrals), B (triangles' B, frame cells' Bx), By (frame cells)
+    tyee::DeviceBuffer E, B, By;
+    // E update: lr, k per edge, caf per frame edge; B update: t0, t1, t2, g per triangle, fe, fc
+    // per frame cell
+    tyee::DeviceBuffer lr, k, caf, t0, t1, t2, g, fe, fc;
+    int32_t graph_steps = 8;          // steps per captured graph (0: eager launches)
+    hipGraphExec_t graph = nullptr;
     bool timing = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> ev;   // timing: three events per step of a chunk of steps
     double ms_edge = 0.0, ms_cell = 0.0;
     int64_t timed = 0;
     ~tyee_open() {
+        if (graph) (void)hipGraphExecDestroy(graph);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -303,36 +328,46 @@ struct tyee_open {
 namespace tyee {
 namespace {
 
+int32_t signed_id(int32_t i, bool positive) { return positive ? i : ~i; }
+
 template <typename T>
 int upload_open(tyee_open &o) {
     const Frame &f = o.f;
     const double dt = o.dt;
     const size_t ts = sizeof(T);
+    const int64_t nem = f.ne_mesh, nfe = f.ne - f.ne_mesh;
     std::vector<int2> lr(f.ne);
-    std::vector<T> ca(f.ne), cbd(f.ne);
+    std::vector<T> k(f.ne), caf(nfe);
     for (int64_t i = 0; i < f.ne; ++i) {
         lr[i] = make_int2(f.left[i], f.right[i]);
         const double s = 0.5 * f.sigma_e[i] * dt;
-        ca[i] = T((1.0 - s) / (1.0 + s));
-        cbd[i] = f.left[i] >= 0 && f.right[i] >= 0 ? T(dt / (1.0 + s) / f.d[i]) : T(0);
+        if (i < nem && s != 0.0) return fail(TYEE_EINVAL, "a damped edge inside the box");
+        if (i >= nem) caf[i - nem] = T((1.0 - s) / (1.0 + s));
+        k[i] = f.left[i] >= 0 && f.right[i] >= 0 ? T(f.elen[i] * dt / (1.0 + s) / f.d[i]) : T(0);
     }
-    std::vector<int4> ce(f.ncell);
-    std::vector<T> sl(4 * f.ncell), ax(f.ncell), bx(f.ncell), ay(f.nf), by(f.nf);
+    std::vector<int32_t> t0(f.nt), t1(f.nt), t2(f.nt);
+    std::vector<T> g(f.nt);
+    std::vector<int4> fe(f.nf);
+    std::vector<T> fc(4 * f.nf);
     for (int64_t j = 0; j < f.ncell; ++j) {
         const int32_t *e = &f.cell_edge[4 * j];
-        // a triangle's missing fourth side reads its first edge (a valid address, not used)
-        ce[j] = make_int4(e[0], e[1], e[2], e[3] >= 0 ? e[3] : e[0]);
-        for (int q = 0; q < 4; ++q) sl[4 * j + q] = T(f.cell_sl[4 * j + q]);
-        const double sx = 0.5 * f.sigma_x[j] * dt;
-        ax[j] = T((1.0 - sx) / (1.0 + sx));
-        bx[j] = T(dt / (1.0 + sx) / f.S[j]);
-        if (j >= f.nt) {
-            const double sy = 0.5 * f.sigma_y[j] * dt;
-            ay[j - f.nt] = T((1.0 - sy) / (1.0 + sy));
-            by[j - f.nt] = T(dt / (1.0 + sy) / f.S[j]);
+        int32_t id[4];
+        for (int q = 0; q < 4; ++q) id[q] = e[q] >= 0 ? signed_id(e[q], f.cell_sl[4 * j + q] > 0.0) : 0;
+        if (j < f.nt) {
+            t0[j] = id[0];
+            t1[j] = id[1];
+            t2[j] = id[2];
+            g[j] = T(dt / f.S[j]);
+        } else {
+            const int64_t q = j - f.nt;
+            fe[q] = make_int4(id[0], id[1], id[2], id[3]);
+            const double sx = 0.5 * f.sigma_x[j] * dt, sy = 0.5 * f.sigma_y[j] * dt;
+            fc[4 * q] = T((1.0 - sx) / (1.0 + sx));
+            fc[4 * q + 1] = T(dt / (1.0 + sx) / f.S[j]);
+            fc[4 * q + 2] = T((1.0 - sy) / (1.0 + sy));
+            fc[4 * q + 3] = T(dt / (1.0 + sy) / f.S[j]);
         }
     }
-    int rc = 0;
     auto put = [&](DeviceBuffer &b, const void *src, size_t bytes) -> int {
         int r = b.alloc(std::max<size_t>(bytes, 16));
         if (r) return r;
@@ -340,43 +375,96 @@ int upload_open(tyee_open &o) {
         else TYEE_HIP(hipMemsetAsync(b.p, 0, bytes, o.stream));
         return TYEE_OK;
     };
+    int rc = 0;
     if ((rc = put(o.E, nullptr, f.ne * ts)) || (rc = put(o.B, nullptr, f.ncell * ts)) ||
         (rc = put(o.By, nullptr, f.nf * ts)) || (rc = put(o.lr, lr.data(), f.ne * sizeof(int2))) ||
-        (rc = put(o.ca, ca.data(), f.ne * ts)) || (rc = put(o.cbd, cbd.data(), f.ne * ts)) ||
-        (rc = put(o.ce, ce.data(), f.ncell * sizeof(int4))) || (rc = put(o.sl, sl.data(), 4 * f.ncell * ts)) ||
-        (rc = put(o.ax, ax.data(), f.ncell * ts)) || (rc = put(o.bx, bx.data(), f.ncell * ts)) ||
-        (rc = put(o.ay, ay.data(), f.nf * ts)) || (rc = put(o.by, by.data(), f.nf * ts)))
+        (rc = put(o.k, k.data(), f.ne * ts)) || (rc = put(o.caf, caf.data(), nfe * ts)) ||
+        (rc = put(o.t0, t0.data(), f.nt * 4)) || (rc = put(o.t1, t1.data(), f.nt * 4)) ||
+        (rc = put(o.t2, t2.data(), f.nt * 4)) || (rc = put(o.g, g.data(), f.nt * ts)) ||
+        (rc = put(o.fe, fe.data(), f.nf * sizeof(int4))) || (rc = put(o.fc, fc.data(), 4 * f.nf * ts)))
         return rc;
     TYEE_HIP(hipStreamSynchronize(o.stream));
     return TYEE_OK;
 }
 
 template <typename T>
-int launch_open(tyee_open &o, int64_t nsteps) {
-    const Frame &f = o.f;
-    const int32_t ne = int32_t(f.ne), nc = int32_t(f.ncell), nt = int32_t(f.nt);
-    const dim3 ge(unsigned((ne + kBlock - 1) / kBlock)), gc(unsigned((nc + kBlock - 1) / kBlock));
-    for (int64_t s = 0; s < nsteps; ++s) {
-        if (o.timing) TYEE_HIP(hipEventRecord(o.ev[0], o.stream));
-        hipLaunchKernelGGL(k_open_edge<T>, ge, dim3(kBlock), 0, o.stream, ne, nt, o.lr.as<int2>(), o.ca.as<T>(),
-                           o.cbd.as<T>(), o.B.as<T>(), o.By.as<T>(), o.E.as<T>());
-        TYEE_HIP(hipGetLastError());
-        if (o.timing) TYEE_HIP(hipEventRecord(o.ev[1], o.stream));
-        hipLaunchKernelGGL(k_open_cell<T>, gc, dim3(kBlock), 0, o.stream, nc, nt, o.ce.as<int4>(), o.sl.as<T>(),
-                           o.ax.as<T>(), o.bx.as<T>(), o.ay.as<T>(), o.by.as<T>(), o.E.as<T>(), o.B.as<T>(),
-                           o.By.as<T>());
-        TYEE_HIP(hipGetLastError());
-        if (o.timing) {
-            TYEE_HIP(hipEventRecord(o.ev[2], o.stream));
-            TYEE_HIP(hipEventSynchronize(o.ev[2]));
+void enqueue_edge(tyee_open &o) {
+    const int32_t ne = int32_t(o.f.ne);
+    hipLaunchKernelGGL(k_open_edge<T>, dim3(unsigned(blocks_for(ne))), dim3(kBlock), 0, o.stream, ne,
+                       int32_t(o.f.ne_mesh), int32_t(o.f.nt), o.lr.as<int2>(), o.k.as<T>(), o.caf.as<T>(),
+                       o.B.as<T>(), o.By.as<T>(), o.E.as<T>());
+}
+
+template <typename T>
+void enqueue_cell(tyee_open &o) {
+    const int32_t nc = int32_t(o.f.ncell);
+    hipLaunchKernelGGL(k_open_cell<T>, dim3(unsigned(blocks_for(nc))), dim3(kBlock), 0, o.stream, nc,
+                       int32_t(o.f.nt), o.t0.as<int32_t>(), o.t1.as<int32_t>(), o.t2.as<int32_t>(), o.g.as<T>(),
+                       o.fe.as<int4>(), o.fc.as<T>(), o.E.as<T>(), o.B.as<T>(), o.By.as<T>());
+}
+
+constexpr int64_t kTimedChunk = 256;   // steps whose events are recorded before any is read
+
+// Per-launch HIP events around each E and B update (eager launches).
+template <typename T>
+int launch_timed(tyee_open &o, int64_t nsteps) {
+    if (o.ev.empty()) {
+        o.ev.assign(3 * kTimedChunk, nullptr);
+        for (hipEvent_t &e : o.ev) TYEE_HIP(hipEventCreate(&e));
+    }
+    for (int64_t s0 = 0; s0 < nsteps; s0 += kTimedChunk) {
+        const int64_t chunk = std::min(kTimedChunk, nsteps - s0);
+        for (int64_t s = 0; s < chunk; ++s) {
+            TYEE_HIP(hipEventRecord(o.ev[3 * s], o.stream));
+            enqueue_edge<T>(o);
+            TYEE_HIP(hipGetLastError());
+            TYEE_HIP(hipEventRecord(o.ev[3 * s + 1], o.stream));
+            enqueue_cell<T>(o);
+            TYEE_HIP(hipGetLastError());
+            TYEE_HIP(hipEventRecord(o.ev[3 * s + 2], o.stream));
+        }
+        TYEE_HIP(hipEventSynchronize(o.ev[3 * (chunk - 1) + 2]));
+        for (int64_t s = 0; s < chunk; ++s) {
             float a = 0.0f, b = 0.0f;
-            TYEE_HIP(hipEventElapsedTime(&a, o.ev[0], o.ev[1]));
-            TYEE_HIP(hipEventElapsedTime(&b, o.ev[1], o.ev[2]));
+            TYEE_HIP(hipEventElapsedTime(&a, o.ev[3 * s], o.ev[3 * s + 1]));
+            TYEE_HIP(hipEventElapsedTime(&b, o.ev[3 * s + 1], o.ev[3 * s + 2]));
             o.ms_edge += a;
             o.ms_cell += b;
-            ++o.timed;
         }
+        o.timed += chunk;
     }
+    return TYEE_OK;
+}
+
+// Whole graphs of graph_steps steps (captured once: the buffers never move), the rest eager.
+template <typename T>
+int launch_open(tyee_open &o, int64_t nsteps) {
+    if (o.timing) return launch_timed<T>(o, nsteps);
+    int64_t done = 0;
+    if (o.graph_steps > 0 && nsteps >= o.graph_steps) {
+        if (!o.graph) {
+            TYEE_HIP(hipStreamBeginCapture(o.stream, hipStreamCaptureModeThreadLocal));
+            for (int32_t s = 0; s < o.graph_steps; ++s) {
+                enqueue_edge<T>(o);
+                enqueue_cell<T>(o);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(o.stream, &graph);
+            if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&o.graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                o.graph = nullptr;
+                return fail(TYEE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+        }
+        for (; nsteps - done >= o.graph_steps; done += o.graph_steps) TYEE_HIP(hipGraphLaunch(o.graph, o.stream));
+    }
+    for (; done < nsteps; ++done) {
+        enqueue_edge<T>(o);
+        enqueue_cell<T>(o);
+    }
+    TYEE_HIP(hipGetLastError());
     return TYEE_OK;
 }
 
@@ -387,26 +475,45 @@ int open_power(const Frame &f, int64_t max_iter, double rtol, uint64_t seed, dou
     for (int64_t j = 0; j < f.ncell; ++j) x[j] = 2.0 * (double(splitmix64(seed + uint64_t(j)) >> 11) * 0x1.0p-53) - 1.0;
     double lam = 0.0;
     int64_t it = 1;
+    constexpr int64_t kChunks = 256;
+    std::vector<double> part(3 * kChunks);
     for (; it <= max_iter; ++it) {
-        // g = L_B x (per inner edge), y = -L_E g
-        for (int64_t i = 0; i < f.ne; ++i)
-            g[i] = f.left[i] >= 0 && f.right[i] >= 0 ? (x[f.left[i]] - x[f.right[i]]) / f.d[i] : 0.0;
-        double sxy = 0.0, sxx = 0.0, syy = 0.0;
-        for (int64_t j = 0; j < f.ncell; ++j) {
-            double acc = 0.0;
-            for (int q = 0; q < 4; ++q) {
-                const int32_t i = f.cell_edge[4 * j + q];
-                if (i >= 0) acc += f.cell_sl[4 * j + q] * g[i];
+        // g = L_B x (per inner edge), y = -L_E g; per-chunk sums added in chunk order
+        parallel_for(f.ne, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i)
+                g[i] = f.left[i] >= 0 && f.right[i] >= 0 ? (x[f.left[i]] - x[f.right[i]]) / f.d[i] : 0.0;
+        });
+        parallel_for(kChunks, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                double sxy = 0.0, sxx = 0.0, syy = 0.0;
+                for (int64_t j = f.ncell * c / kChunks; j < f.ncell * (c + 1) / kChunks; ++j) {
+                    double acc = 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int32_t i = f.cell_edge[4 * j + q];
+                        if (i >= 0) acc += f.cell_sl[4 * j + q] * g[i];
+                    }
+                    y[j] = acc / f.S[j];
+                    sxy += f.S[j] * x[j] * y[j];
+                    sxx += f.S[j] * x[j] * x[j];
+                    syy += f.S[j] * y[j] * y[j];
+                }
+                part[3 * c] = sxy;
+                part[3 * c + 1] = sxx;
+                part[3 * c + 2] = syy;
             }
-            y[j] = acc / f.S[j];
-            sxy += f.S[j] * x[j] * y[j];
-            sxx += f.S[j] * x[j] * x[j];
-            syy += f.S[j] * y[j] * y[j];
+        }, f.ncell);
+        double sxy = 0.0, sxx = 0.0, syy = 0.0;
+        for (int64_t c = 0; c < kChunks; ++c) {
+            sxy += part[3 * c];
+            sxx += part[3 * c + 1];
+            syy += part[3 * c + 2];
         }
         const double next = sxy / sxx;
         const double nrm = std::sqrt(syy);
         if (!(nrm > 0.0)) break;
-        for (int64_t j = 0; j < f.ncell; ++j) x[j] = y[j] / nrm;
+        parallel_for(f.ncell, [&](int64_t j0, int64_t j1) {
+            for (int64_t j = j0; j < j1; ++j) x[j] = y[j] / nrm;
+        });
         const bool done = it > 1 && std::fabs(next - lam) <= rtol * std::fabs(next);
         lam = next;
         if (done) break;
@@ -441,7 +548,6 @@ extern "C" int tyee_open_create(const tyee_mesh *mesh, const tyee_pml_params *pm
             TYEE_HIP(hipStreamCreateWithFlags(&o->stream, hipStreamNonBlocking));
             o->own_stream = true;
         }
-        for (hipEvent_t &e : o->ev) TYEE_HIP(hipEventCreate(&e));
         rc = o->f64 ? upload_open<double>(*o) : upload_open<float>(*o);
         if (rc) return rc;
         *out = o.release();
@@ -523,11 +629,17 @@ extern "C" int tyee_open_set_state(tyee_open *o, int32_t field, const double *va
     DeviceBuffer *b = nullptr;
     int rc = open_field(o, field, &n, &b, &off);
     if (rc) return rc;
+    // E is held as the line integral |e| E
+    const bool line = field == TYEE_OPEN_E;
     TYEE_HIP(hipStreamSynchronize(o->stream));
     if (o->f64) {
-        TYEE_HIP(hipMemcpy(b->p, values + off, size_t(n) * 8, hipMemcpyHostToDevice));
+        std::vector<double> tmp(values + off, values + off + n);
+        if (line)
+            for (int64_t i = 0; i < n; ++i) tmp[i] *= o->f.elen[i];
+        TYEE_HIP(hipMemcpy(b->p, tmp.data(), size_t(n) * 8, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> tmp(values + off, values + off + n);
+        std::vector<float> tmp(n);
+        for (int64_t i = 0; i < n; ++i) tmp[i] = float(line ? values[off + i] * o->f.elen[i] : values[off + i]);
         TYEE_HIP(hipMemcpy(b->p, tmp.data(), size_t(n) * 4, hipMemcpyHostToDevice));
     }
     return TYEE_OK;
@@ -540,6 +652,7 @@ extern "C" int tyee_open_get_state(tyee_open *o, int32_t field, double *values) 
     DeviceBuffer *b = nullptr;
     int rc = open_field(o, field, &n, &b, &off);
     if (rc) return rc;
+    const bool line = field == TYEE_OPEN_E;
     TYEE_HIP(hipStreamSynchronize(o->stream));
     if (field == TYEE_OPEN_BY) std::fill(values, values + o->f.nt, 0.0);
     if (o->f64) {
@@ -549,6 +662,8 @@ extern "C" int tyee_open_get_state(tyee_open *o, int32_t field, double *values) 
         TYEE_HIP(hipMemcpy(tmp.data(), b->p, size_t(n) * 4, hipMemcpyDeviceToHost));
         std::copy(tmp.begin(), tmp.end(), values + off);
     }
+    if (line)
+        for (int64_t i = 0; i < n; ++i) values[off + i] /= o->f.elen[i];
     return TYEE_OK;
 }
 
@@ -556,6 +671,18 @@ extern "C" int tyee_open_step(tyee_open *o, int64_t nsteps) {
     using namespace tyee;
     if (!o || nsteps < 0) return fail(TYEE_EINVAL, "null handle or negative step count");
     return o->f64 ? launch_open<double>(*o, nsteps) : launch_open<float>(*o, nsteps);
+}
+
+extern "C" int tyee_open_set_graph(tyee_open *o, int32_t steps) {
+    if (!o) return tyee::fail(TYEE_EINVAL, "null argument");
+    if (steps < 0 || steps > 1024) return tyee::fail(TYEE_EINVAL, "steps per graph must be in 0 .. 1024");
+    if (o->graph) {
+        if (hipStreamSynchronize(o->stream) != hipSuccess) return tyee::fail(TYEE_EDEVICE, "hipStreamSynchronize failed");
+        (void)hipGraphExecDestroy(o->graph);
+        o->graph = nullptr;
+    }
+    o->graph_steps = steps;
+    return TYEE_OK;
 }
 
 extern "C" int tyee_open_sync(tyee_open *o) {

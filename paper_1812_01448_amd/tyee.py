@@ -120,7 +120,8 @@ EXPORTS = [
     "tyee_learner_regulariser", "tyee_copy_bandwidth", "tyee_sim_bind_external",
     "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_spectrum", "tyee_mesh_relax",
     "tyee_mesh_flip", "tyee_open_create", "tyee_open_sizes", "tyee_open_frame", "tyee_open_cfl",
-    "tyee_open_set_state", "tyee_open_get_state", "tyee_open_step", "tyee_open_sync",
+    "tyee_open_set_state", "tyee_open_get_state", "tyee_open_step", "tyee_open_set_graph",
+    "tyee_open_sync",
     "tyee_open_set_timing", "tyee_open_kernel_ms", "tyee_open_destroy",
     "tyee_batch_tune_progress",
     "tyee_last_error",
@@ -225,6 +226,7 @@ def _load():
         "tyee_open_set_state": [vp, i32, vp],
         "tyee_open_get_state": [vp, i32, vp],
         "tyee_open_step": [vp, i64],
+        "tyee_open_set_graph": [vp, i32],
         "tyee_open_sync": [vp],
         "tyee_open_set_timing": [vp, i32],
         "tyee_open_kernel_ms": [vp, vp, ctypes.POINTER(i64)],
@@ -503,6 +505,10 @@ class Open:
 
     def step(self, n=1):
         _check(lib.tyee_open_step(self._h, int(n)))
+
+    def set_graph(self, steps):
+        """Steps per captured HIP graph (0: eager launches; the library's default is 8)."""
+        _check(lib.tyee_open_set_graph(self._h, int(steps)))
 
     def sync(self):
         _check(lib.tyee_open_sync(self._h))

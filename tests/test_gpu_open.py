@@ -75,6 +75,34 @@ def test_stepping_matches_oracle(ty, kind, prec, steps, tol):
     assert np.all(np.isfinite(e)) and np.all(np.isfinite(bx))
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_graph_replay_matches_eager_launches(ty, prec):
+    """Whole graphs of 8 steps and a remainder of eager steps give the same bits as eager
+    launches alone (the same kernels in the same order), and a state set and read back is
+    unchanged up to the |e| scaling of E."""
+    _note(f"case: open tri box, graph replay against eager launches, {prec}, 203 steps")
+    xy, tri, Lx, Ly = _case("tri")
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    ref = OpenMesh(om, 4, 0.7, 2.0)
+    dt = 0.6 * 2 / ref.omega_max()
+    E, Bx, By = _random_state(ref, 5)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    out = []
+    for graph in (8, 0):
+        sim = ty.Open(m, ty.pml(4, 0.7, 2.0), dt, prec)
+        sim.set_graph(graph)
+        sim.set_state("E", E)
+        sim.set_state("BX", Bx)
+        sim.set_state("BY", By)
+        e0 = sim.get_state("E")
+        rt = 1e-15 if prec == "f64" else 1e-7
+        assert np.all(np.abs(e0 - E) <= rt * np.abs(E) + 1e-300)
+        sim.step(203)
+        out.append([sim.get_state(f) for f in ("E", "BX", "BY")])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_cfl_matches_oracle(ty):
     xy, tri, Lx, Ly = _case("tri")
     om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
@@ -145,3 +173,7 @@ def test_timing_and_errors(ty):
         ty.Open(m, ty.pml(2, 1.0, 1.0), -1.0, "f32")
     with pytest.raises(ty.TyeeError):
         ty.Open(m, ty.pml(0, 1.0, 1.0), 0.05, "f32")
+    with pytest.raises(ty.TyeeError):
+        sim.set_graph(-1)
+    with pytest.raises(ty.TyeeError):
+        sim.set_graph(2000)
