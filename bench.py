@@ -40,13 +40,14 @@ def parse(argv=None):
     p.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0 = auto)")
     p.add_argument("--workload", default="torus1415",
                    choices=["torus1415", "plasma2830", "batch256", "learned", "modes70x101", "spectrum70x101",
-                            "relax", "open1415"],
+                            "relax", "open1415", "tet100"],
                    help="torus1415 (the reported line), plasma2830 (16M triangles with a plasma "
                         "particle and a line source), batch256 (256 uneven meshes), learned "
                         "(train and evaluate the learned edge scale) or modes70x101 (the 128 "
                         "lowest modes of the 70 x 101 resonator of Fig. 4; --steps timed "
                         "solves, at most 20), spectrum70x101 (every mode of that resonator, one "
-                        "solve), open1415 (the 1415 x 1415 box tied to a 16-layer PML frame) or relax "
+                        "solve), open1415 (the 1415 x 1415 box tied to a 16-layer PML frame), tet100 (12M "
+                        "tetrahedra of a 100^3 BCC box, E on edges and B on faces) or relax "
                         "(jello relaxation of the 45 x 45 cavity and "
                         "the 1415 x 1415 torus: omega_max and so dt before and after)")
     p.add_argument("--relax-rounds", type=int, default=8)
@@ -286,7 +287,7 @@ def main():
         sys.exit(2)
     run = {"batch256": bench_batch, "learned": bench_learned, "plasma2830": bench_plasma,
            "modes70x101": bench_modes, "spectrum70x101": bench_spectrum, "torus1415": bench_torus,
-           "relax": bench_relax, "open1415": bench_open}[args.workload]
+           "relax": bench_relax, "open1415": bench_open, "tet100": bench_tet}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
@@ -817,6 +818,93 @@ def bench_open(args):
         "cpu_baseline": None if args.no_cpu else cpu_baseline_open(),
     }
     return out
+
+
+def bench_tet(args):
+    """The three-dimensional scheme (the Conclusion: tetrahedra, E on edges, B on faces): the
+    Delaunay tetrahedralisation of a jittered (+-0.05 h) BCC lattice of 100^3 cubes (12M
+    tetrahedra) with conducting walls, FP32, two launches per step (E, then B); a Gaussian B
+    pulse at the centre."""
+    import torch
+    import paper_1812_01448_amd as ty
+    from meshgen.tet import bcc_box
+
+    t0 = time.perf_counter()
+    xyz, tets, L = bcc_box(100, 100, 100, 1.0, 0.05, 0)
+    t1 = time.perf_counter()
+    T = ty.Tet(xyz, tets)
+    t2 = time.perf_counter()
+    lam, iters, ok = T.cfl(max_iter=5000, rtol=1e-6)
+    dt = 0.5 * 2 / np.sqrt(lam)
+    log(f"tet100: {T.nt} tetrahedra, {T.ne} edges, {T.nf} faces; input {t1 - t0:.1f} s, mesh {t2 - t1:.1f} s, "
+        f"omega_max {np.sqrt(lam):.4g} ({iters} iterations) {time.perf_counter() - t2:.1f} s")
+    v = T.view()
+    face = v["face"]
+    fa = xyz[face[:, 0]]
+    nrm = np.cross(xyz[face[:, 1]] - fa, xyz[face[:, 2]] - fa)
+    nz = nrm[:, 2] / np.linalg.norm(nrm, axis=1)
+    r2 = np.sum((xyz[face].mean(axis=1) - 50.0) ** 2, axis=1)
+    B0 = np.where(v["d"] > 0, np.exp(-r2 / (2 * 8.0 ** 2)) * nz, 0.0)
+    del v, face, fa, nrm, nz, r2
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    sim = ty.TetSim(T, dt, "f32", stream.cuda_stream)
+    sim.set_state("B", B0)
+    steps, warmup = args.steps, args.warmup
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t3
+    step_ms = open_step_ms(sim, steps, stream)
+    ne, nf, ninc = T.ne, T.nf, T.n_incidences
+    # algorithmic bytes (FP32), each array read or written once: E update: per edge its line
+    # integral r/w, coefficient and row offset, per incidence one signed face id, every face's
+    # h once; B update: per face h r/w, three edge ids and one coefficient, every edge's line
+    # integral once
+    edge_bytes = 16 * ne + 4 * ninc + 4 * nf
+    face_bytes = 24 * nf + 4 * ne
+    step_bytes = edge_bytes + face_bytes
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
+    return {
+        "metric": "cell-updates/s (edges + faces of the tetrahedral mesh per step)",
+        "value": (ne + nf) * steps / elapsed, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tetrahedra: 100 x 100 x 100 BCC box (h = 1, jitter 0.05 h, seed 0), Delaunay, "
+                               "conducting walls",
+                   "tetrahedra": T.nt, "edges": ne, "faces": nf, "incidences": ninc, "dt": dt,
+                   "omega_max": float(np.sqrt(lam))},
+        "roofline": {"bound": "hbm", "kernel": "k_tet_edge + k_tet_face (one step: the E and the B update)",
+                     "timed_with": "HIP events on the launch stream around segments of 256 steps (graphs of 8 steps)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "launches_per_step": 2,
+                     "avg_step_ms": round(step_ms, 5), "algorithmic_bytes_per_step": step_bytes, "traffic": None,
+                     "per_kernel_bytes": {"k_tet_edge": edge_bytes, "k_tet_face": face_bytes}},
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_tet(),
+    }
+
+
+def cpu_baseline_tet():
+    """The tetrahedral oracle (numpy, FP64) stepping a 20^3 BCC box of the same recipe: a
+    per-cell rate."""
+    from meshgen.tet import bcc_box
+    from oracle.tet import TetMesh
+    from threadpoolctl import threadpool_info
+    xyz, tets, L = bcc_box(20, 20, 20, 1.0, 0.05, 0)
+    m = TetMesh(xyz, tets, L)
+    E, B = np.zeros(m.ne), np.where(m.inner_face, 1.0, 0.0)
+    m.step(E, B, 0.05, 2)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < 10.0:
+        E, B = m.step(E, B, 0.05, 10)
+        n += 10
+    el = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": (m.ne + m.nf) * n / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps of the 20^3 BCC box ({m.nt} tetrahedra), numpy on one process"}
 
 
 def open_step_ms(sim, steps, stream, segment=256):

@@ -54,8 +54,9 @@ typedef enum {
     TYEE_OK = 0,
     TYEE_EINVAL = -1,        /* bad argument, size or state */
     TYEE_ENOTDELAUNAY = -2,  /* an interior edge has d_i <= dual_tol * |e_i| */
-    TYEE_EDEGENERATE = -3,   /* a triangle with |2 S| <= 1e-14 Lx Ly */
-    TYEE_ENONMANIFOLD = -4,  /* an edge in more than two triangles, or twice in one direction */
+    TYEE_EDEGENERATE = -3,   /* a triangle with |2 S| <= 1e-14 Lx Ly; a tetrahedron with no volume */
+    TYEE_ENONMANIFOLD = -4,  /* an edge in more than two triangles, or twice in one direction; a
+                                face in more than two tetrahedra, or two on one of its sides */
     TYEE_EPERIODIC = -5,     /* periodic mesh with an edge that has only one triangle */
     TYEE_ENOMEM = -6,        /* host or device allocation failed */
     TYEE_EDEVICE = -7,       /* a HIP runtime call failed */
@@ -738,6 +739,70 @@ int tyee_open_sync(tyee_open *o);
 int tyee_open_set_timing(tyee_open *o, int32_t on);
 int tyee_open_kernel_ms(const tyee_open *o, double out[2], int64_t *steps);
 int tyee_open_destroy(tyee_open *o);
+
+/* ---------------------------------------------------------------------------------------
+   Three dimensions: tetrahedra (the paper's Conclusion: E and j on edges, B on faces, n on
+   nodes).  The dual is the Voronoi diagram of the nodes (the circumcentres of the
+   tetrahedra), as the triangles' circumcentres are in two dimensions.  Faraday on a face and
+   Ampere on an edge's Voronoi polygon (the 3-D form of eqs. 3-4):
+     A_f dB_f/dt = -sum over the face's edges of s |e| E_e,
+     A*_e dE_e/dt = sum over the faces around the edge of s d_f B_f,
+   with d_f = (C_front - C_back) . n_f the distance between the circumcentres on either side of
+   face f along its unit normal, A*_e the area of the edge's Voronoi polygon, s = +1 where the
+   face's circuit runs along the edge.  Leap-frog, E then B; dt < 2/omega_max (eq. 20).  The
+   mesh fills a box whose walls are perfect conductors: a face with one tetrahedron is a wall
+   face, every edge of a wall face a wall edge (E = 0 there, B of wall faces never changes).
+
+   Canonical numbering: nodes as given; edges by (lower, higher) node id, tangent from the lower
+   to the higher; faces by their sorted node triples (a, b, c), unit normal by the right-hand
+   rule of a -> b -> c, whose circuit runs along (a, b) and (b, c) and against (a, c);
+   tetrahedra as given.  The device holds the line integrals |e| E and d_f B (B itself on wall
+   faces), converted on set and get. */
+typedef struct tyee_tet tyee_tet;
+typedef struct tyee_tet_sim tyee_tet_sim;
+typedef enum { TYEE_TET_E = 0, TYEE_TET_B = 1 } tyee_tet_field;
+
+/* Build the mesh on the host (FP64): xyz [nv][3], tets [nt][4] node ids (any orientation; each
+   is reoriented to positive volume).  Errors: EINVAL (null, sizes, an index out of range),
+   EDEGENERATE (a tetrahedron with no volume), ENONMANIFOLD (a face shared by more than two
+   tetrahedra, or two tetrahedra on one side of a face), ENOTDELAUNAY (d_f <= 0 across an inner face or an inner edge's Voronoi
+   polygon without positive area: the mesh is not a Delaunay tetrahedralisation), ENOMEM.
+   *out gets the handle; the arrays are copied. */
+int tyee_tet_create(const double *xyz, int64_t nv, const int32_t *tets, int64_t nt, tyee_tet **out);
+/* out = {n_nodes, n_edges, n_faces, n_tets, n_inner_edges, n_inner_faces, n_incidences} with
+   n_incidences the (inner edge, face around it) pairs the E update reads. */
+int tyee_tet_sizes(const tyee_tet *m, int64_t out[7]);
+/* Canonical arrays, each may be NULL: edge [n_edges][2], face [n_faces][3], face_edge
+   [n_faces][3] (its (a,b), (b,c), (a,c) edges), elen and dual_area [n_edges] (0 on wall edges),
+   farea and d [n_faces] (d 0 on wall faces), C [n_tets][3] circumcentres. */
+int tyee_tet_view(const tyee_tet *m, int32_t *edge, int32_t *face, int32_t *face_edge, double *elen,
+                  double *dual_area, double *farea, double *d, double *C);
+/* Largest eigenvalue lambda of K = -curl_B curl_E on the inner edges (FP64 power iteration on
+   the host in the energy weights A*_e |e|); omega_max = sqrt(lambda).  Errors: EINVAL,
+   ENOTCONVERGED (*lambda still set). */
+int tyee_tet_cfl(const tyee_tet *m, int64_t max_iter, double rtol, uint64_t seed, double *lambda, int64_t *iters);
+int tyee_tet_destroy(tyee_tet *m);
+
+/* Upload the coefficients (prec TYEE_F32 or TYEE_F64) for the time step dt, zero state.
+   stream: HIP stream, or NULL for one of the library's own.  The mesh may be destroyed
+   afterwards.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int tyee_tet_sim_create(const tyee_tet *m, int32_t prec, double dt, void *stream, tyee_tet_sim **out);
+/* E [n_edges] or B [n_faces], FP64 host values in canonical order; both wait for the stream. */
+int tyee_tet_sim_set_state(tyee_tet_sim *s, int32_t field, const double *values);
+int tyee_tet_sim_get_state(tyee_tet_sim *s, int32_t field, double *values);
+/* Enqueue nsteps steps (two launches each: the E update over the edges, then the B update over
+   the faces); whole groups of the graph size replay one captured HIP graph (the stream must
+   allow capture), the rest are launched one by one. */
+int tyee_tet_sim_step(tyee_tet_sim *s, int64_t nsteps);
+/* Steps per captured graph, 0 .. 1024 (0: eager launches; default 8).  Errors: EINVAL. */
+int tyee_tet_sim_set_graph(tyee_tet_sim *s, int32_t steps);
+int tyee_tet_sim_sync(tyee_tet_sim *s);
+/* With timing on, steps are launched one by one with HIP events around both launches (read
+   every 256 steps); tyee_tet_sim_kernel_ms gives the summed milliseconds {E update, B update}
+   and the steps timed since timing was set. */
+int tyee_tet_sim_set_timing(tyee_tet_sim *s, int32_t on);
+int tyee_tet_sim_kernel_ms(const tyee_tet_sim *s, double out[2], int64_t *steps);
+int tyee_tet_sim_destroy(tyee_tet_sim *s);
 
 const char *tyee_last_error(void);
 

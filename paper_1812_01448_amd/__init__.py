@@ -4,7 +4,7 @@ The solver lives in the native library libtyee.so (C ABI in include/tyee.h); thi
 is its Python binding.  Importing it fails loudly when the library has not been built.
 """
 from .tyee import (Mesh, Sim, Batch, Learner, TyeeError, ORDER, PREC, FIELD, EXPORTS, LIB_PATH,  # noqa: F401
-                   copy_bandwidth, flip, Open, open_frame, pml)
+                   copy_bandwidth, flip, Open, open_frame, pml, Tet, TetSim)
 
 __all__ = ["Mesh", "Sim", "Batch", "Learner", "TyeeError", "ORDER", "PREC", "FIELD", "EXPORTS", "LIB_PATH",
-           "copy_bandwidth", "flip", "Open", "open_frame", "pml"]
+           "copy_bandwidth", "flip", "Open", "open_frame", "pml", "Tet", "TetSim"]

@@ -123,6 +123,10 @@ EXPORTS = [
     "tyee_open_set_state", "tyee_open_get_state", "tyee_open_step", "tyee_open_set_graph",
     "tyee_open_sync",
     "tyee_open_set_timing", "tyee_open_kernel_ms", "tyee_open_destroy",
+    "tyee_tet_create", "tyee_tet_sizes", "tyee_tet_view", "tyee_tet_cfl", "tyee_tet_destroy",
+    "tyee_tet_sim_create", "tyee_tet_sim_set_state", "tyee_tet_sim_get_state", "tyee_tet_sim_step",
+    "tyee_tet_sim_set_graph", "tyee_tet_sim_sync", "tyee_tet_sim_set_timing", "tyee_tet_sim_kernel_ms",
+    "tyee_tet_sim_destroy",
     "tyee_batch_tune_progress",
     "tyee_last_error",
 ]
@@ -231,6 +235,20 @@ def _load():
         "tyee_open_set_timing": [vp, i32],
         "tyee_open_kernel_ms": [vp, vp, ctypes.POINTER(i64)],
         "tyee_open_destroy": [vp],
+        "tyee_tet_create": [vp, i64, vp, i64, ctypes.POINTER(vp)],
+        "tyee_tet_sizes": [vp, vp],
+        "tyee_tet_view": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "tyee_tet_cfl": [vp, i64, f64, ctypes.c_uint64, ctypes.POINTER(f64), ctypes.POINTER(i64)],
+        "tyee_tet_destroy": [vp],
+        "tyee_tet_sim_create": [vp, i32, f64, vp, ctypes.POINTER(vp)],
+        "tyee_tet_sim_set_state": [vp, i32, vp],
+        "tyee_tet_sim_get_state": [vp, i32, vp],
+        "tyee_tet_sim_step": [vp, i64],
+        "tyee_tet_sim_set_graph": [vp, i32],
+        "tyee_tet_sim_sync": [vp],
+        "tyee_tet_sim_set_timing": [vp, i32],
+        "tyee_tet_sim_kernel_ms": [vp, vp, ctypes.POINTER(i64)],
+        "tyee_tet_sim_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -534,6 +552,94 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     g = ctypes.c_double()
     _check(lib.tyee_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)))
     return g.value
+
+
+TET_FIELD = {"E": 0, "B": 1}
+
+
+class Tet:
+    """A tetrahedral mesh of a box with conducting walls (tyee_tet_*): canonical edges and
+    faces, FP64 geometry and the Voronoi dual, built on the host."""
+
+    def __init__(self, xyz, tets):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        t = np.ascontiguousarray(tets, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 4:
+            raise ValueError("xyz must be [n, 3] and tets [n, 4]")
+        h = ctypes.c_void_p()
+        _check(lib.tyee_tet_create(_ptr(xyz), len(xyz), _ptr(t), len(t), ctypes.byref(h)))
+        self._h = h
+        sizes = np.zeros(7, np.int64)
+        _check(lib.tyee_tet_sizes(h, _ptr(sizes)))
+        (self.nv, self.ne, self.nf, self.nt, self.n_inner_edge, self.n_inner_face,
+         self.n_incidences) = (int(v) for v in sizes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_tet_destroy(h)
+            self._h = None
+
+    def view(self):
+        """Canonical arrays: edge, face, face_edge, elen, dual_area, farea, d, C."""
+        out = {"edge": np.zeros((self.ne, 2), np.int32), "face": np.zeros((self.nf, 3), np.int32),
+               "face_edge": np.zeros((self.nf, 3), np.int32), "elen": np.zeros(self.ne),
+               "dual_area": np.zeros(self.ne), "farea": np.zeros(self.nf), "d": np.zeros(self.nf),
+               "C": np.zeros((self.nt, 3))}
+        _check(lib.tyee_tet_view(self._h, *(_ptr(out[k]) for k in ("edge", "face", "face_edge", "elen",
+                                                                  "dual_area", "farea", "d", "C"))))
+        return out
+
+    def cfl(self, max_iter=200000, rtol=1e-12, seed=0):
+        """(lambda = omega_max^2, iterations, converged)."""
+        lam, it = ctypes.c_double(), ctypes.c_int64()
+        rc = _check(lib.tyee_tet_cfl(self._h, int(max_iter), float(rtol), int(seed), ctypes.byref(lam),
+                                     ctypes.byref(it)), allow=(ENOTCONVERGED,))
+        return lam.value, it.value, rc == OK
+
+
+class TetSim:
+    """Leap-frog stepping of E on the edges and B on the faces of a tetrahedral mesh on the
+    device (tyee_tet_sim_*)."""
+
+    def __init__(self, tet, dt, prec="f32", stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.tyee_tet_sim_create(tet._h, PREC[prec], float(dt), None if stream is None else int(stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        self.ne, self.nf, self.dt, self.prec = tet.ne, tet.nf, float(dt), prec
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.tyee_tet_sim_destroy(h)
+            self._h = None
+
+    def set_state(self, field, values):
+        a = _f64(values, self.ne if field == "E" else self.nf)
+        _check(lib.tyee_tet_sim_set_state(self._h, TET_FIELD[field], _ptr(a)))
+
+    def get_state(self, field):
+        out = np.zeros(self.ne if field == "E" else self.nf)
+        _check(lib.tyee_tet_sim_get_state(self._h, TET_FIELD[field], _ptr(out)))
+        return out
+
+    def step(self, n=1):
+        _check(lib.tyee_tet_sim_step(self._h, int(n)))
+
+    def set_graph(self, steps):
+        _check(lib.tyee_tet_sim_set_graph(self._h, int(steps)))
+
+    def sync(self):
+        _check(lib.tyee_tet_sim_sync(self._h))
+
+    def set_timing(self, on=True):
+        _check(lib.tyee_tet_sim_set_timing(self._h, 1 if on else 0))
+
+    def kernel_ms(self):
+        out, n = np.zeros(2), ctypes.c_int64()
+        _check(lib.tyee_tet_sim_kernel_ms(self._h, _ptr(out), ctypes.byref(n)))
+        return {"edge_ms": float(out[0]), "face_ms": float(out[1]), "steps": n.value}
 
 
 class Sim:

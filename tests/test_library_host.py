@@ -283,3 +283,44 @@ def test_open_frame_errors(ty):
     with pytest.raises(ty.TyeeError) as e:
         ty.open_frame(torus, ty.pml(2, 0.1, 1.0))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("dims,jitter,method", [((3, 4, 2), 0.05, "direct"), ((4, 3, 3), 0.25, "qhull")])
+def test_tet_mesh_matches_oracle(ty, dims, jitter, method):
+    """The tetrahedral builder against the oracle's: canonical edges, faces and face edges bit
+    for bit, geometry and the Voronoi dual to 1e-12, omega_max to 1e-10. The Qhull mesh at
+    jitter 0.25 is an irregular Delaunay mesh (edges in 3 to 9 faces)."""
+    from meshgen.tet import bcc_box
+    from oracle.tet import TetMesh
+    xyz, tets, L = bcc_box(*dims, 1.0, jitter, 2, method=method)
+    # hand the library the tetrahedra in scrambled vertex order: it reorients them
+    rng = np.random.default_rng(0)
+    scr = np.array([t[rng.permutation(4)] for t in tets], np.int32)
+    T = ty.Tet(xyz, scr)
+    m = TetMesh(xyz, tets, L)
+    v = T.view()
+    assert (T.ne, T.nf, T.nt, T.n_inner_edge, T.n_inner_face) == (m.ne, m.nf, m.nt, m.inner_edge.sum(),
+                                                                    m.inner_face.sum())
+    assert np.array_equal(v["edge"], m.edge) and np.array_equal(v["face"], m.face)
+    assert np.array_equal(v["face_edge"], m.face_edge)
+    for k, ref in (("elen", m.elen), ("dual_area", m.dual_area), ("farea", m.farea), ("d", m.d)):
+        assert np.max(np.abs(v[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+    lam, it, ok = T.cfl(rtol=1e-14)
+    assert ok and abs(np.sqrt(lam) - m.omega_max()) <= 1e-10 * np.sqrt(lam)
+
+
+def test_tet_mesh_errors(ty):
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0.3, 0.3, 1.0], [0.3, 0.3, -0.05], [0.2, 0.2, 0.5]])
+    cases = [
+        (np.array([[0, 1, 2, 7]]), -1),                        # index out of range
+        (np.array([[0, 1, 2, 2]]), -3),                        # no volume
+        (np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]]), -4),   # face in three tetrahedra
+        (np.array([[0, 1, 2, 3], [0, 1, 2, 5]]), -4),          # both on one side of (a, b, c)
+        (np.array([[0, 1, 2, 3], [0, 1, 2, 4]]), -2),          # q inside the sphere of (a, b, c, p)
+    ]
+    for tets, code in cases:
+        with pytest.raises(ty.TyeeError) as e:
+            ty.Tet(xyz, tets)
+        assert e.value.code == code, tets
+    with pytest.raises(ValueError):
+        ty.Tet(xyz[:, :2], [[0, 1, 2, 3]])
