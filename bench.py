@@ -860,10 +860,10 @@ def bench_tet(args):
     step_ms = open_step_ms(sim, steps, stream)
     ne, nf, ninc = T.ne, T.nf, T.n_incidences
     # algorithmic bytes (FP32), each array read or written once: E update: per edge its line
-    # integral r/w, coefficient and row offset, per incidence one signed face id, every face's
-    # h once; B update: per face h r/w, three edge ids and one coefficient, every edge's line
-    # integral once
-    edge_bytes = 16 * ne + 4 * ninc + 4 * nf
+    # integral r/w and coefficient, per incidence one signed face id (the slices' padding is not
+    # counted), every face's h once, a width and a start per slice of 64 edges; B update: per
+    # face h r/w, three edge ids and one coefficient, every edge's line integral once
+    edge_bytes = 12 * ne + 4 * ninc + 4 * nf + 8 * ((ne + 63) // 64)
     face_bytes = 24 * nf + 4 * ne
     step_bytes = edge_bytes + face_bytes
     achieved = step_bytes / (step_ms * 1e-3) / 1e9

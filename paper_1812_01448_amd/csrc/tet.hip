@@ -31,22 +31,57 @@ __global__ void k_tet_face(int32_t nf, const int32_t *__restrict__ eab, const in
     h[f] = h[f] - g[f] * (e[eab[f]] + e[ebc[f]] - e[eac[f]]);
 }
 
-// Ampere: every edge with a non-empty row of faces (f or ~f for a circuit against the edge).
+// Ampere.  The faces around the edges are held in slices of kSlice = 64 edges (one wavefront):
+// slice s has width w_s (its longest row) and its entries slot-major at so_s + k kSlice + lane,
+// so every load of a wave is one contiguous run; each entry is f or ~f (a circuit against the
+// edge), padding and wall edges read the zero kept at h[nf].
+constexpr int kSlice = 64;
+
+template <typename T, int W>
+__device__ __forceinline__ T slice_row(const int32_t *__restrict__ r, const T *__restrict__ h, int lane) {
+    int32_t id[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) id[k] = r[k * kSlice + lane];
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const T v = h[id[k] ^ (id[k] >> 31)];
+        acc += id[k] < 0 ? -v : v;
+    }
+    return acc;
+}
+
 template <typename T>
-__global__ void k_tet_edge(int32_t ne, const int32_t *__restrict__ off, const int32_t *__restrict__ ef,
-                           const T *__restrict__ a, const T *__restrict__ h, T *__restrict__ e) {
+__global__ void k_tet_edge(int32_t ne, const int32_t *__restrict__ sw, const int32_t *__restrict__ so,
+                           const int32_t *__restrict__ ids, const T *__restrict__ a, const T *__restrict__ h,
+                           T *__restrict__ e) {
     const int i = xcd_group(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= ne) return;
-    const int32_t k0 = off[i], k1 = off[i + 1];
-    if (k0 == k1) return;
-    T acc = T(0);
-    for (int32_t k = k0; k < k1; ++k) {
-        const int32_t id = ef[k];
-        const T v = h[id ^ (id >> 31)];
-        acc += id < 0 ? -v : v;
+    const int s = i / kSlice, lane = i % kSlice;      // kBlock is a multiple of kSlice: s is the wave's
+    const int w = sw[s];
+    if (w == 0) return;
+    const int32_t *r = ids + so[s];
+    T acc;
+    switch (w) {
+    case 1: acc = slice_row<T, 1>(r, h, lane); break;
+    case 2: acc = slice_row<T, 2>(r, h, lane); break;
+    case 3: acc = slice_row<T, 3>(r, h, lane); break;
+    case 4: acc = slice_row<T, 4>(r, h, lane); break;
+    case 5: acc = slice_row<T, 5>(r, h, lane); break;
+    case 6: acc = slice_row<T, 6>(r, h, lane); break;
+    case 7: acc = slice_row<T, 7>(r, h, lane); break;
+    case 8: acc = slice_row<T, 8>(r, h, lane); break;
+    default:
+        acc = T(0);
+        for (int k = 0; k < w; ++k) {
+            const int32_t id = r[k * kSlice + lane];
+            const T v = h[id ^ (id >> 31)];
+            acc += id < 0 ? -v : v;
+        }
     }
     e[i] = e[i] + a[i] * acc;
 }
+static_assert(tyee::kBlock % kSlice == 0, "a work-group holds whole slices");
 
 }  // namespace
 }  // namespace tyee
@@ -58,7 +93,7 @@ struct tyee_tet_sim {
     std::vector<double> escale, hscale;   // |e| per edge; d_f per inner face, 1 per wall face
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    tyee::DeviceBuffer e, h, g, a, eab, ebc, eac, off, ef;
+    tyee::DeviceBuffer e, h, g, a, eab, ebc, eac, sw, so, ids;
     int32_t graph_steps = 8;
     hipGraphExec_t graph = nullptr;
     bool timing = false;
@@ -80,7 +115,7 @@ template <typename T>
 int upload_tet(tyee_tet_sim &s, const TetMesh &m) {
     const size_t ts = sizeof(T);
     std::vector<T> g(m.nf), a(m.ne);
-    std::vector<int32_t> eab(m.nf), ebc(m.nf), eac(m.nf), off(m.ne + 1);
+    std::vector<int32_t> eab(m.nf), ebc(m.nf), eac(m.nf);
     for (int64_t f = 0; f < m.nf; ++f) {
         eab[f] = m.face_edge[3 * f];
         ebc[f] = m.face_edge[3 * f + 1];
@@ -88,7 +123,25 @@ int upload_tet(tyee_tet_sim &s, const TetMesh &m) {
         g[f] = m.inner_face[f] ? T(s.dt * m.d[f] / m.farea[f]) : T(0);
     }
     for (int64_t i = 0; i < m.ne; ++i) a[i] = m.inner_edge[i] ? T(s.dt * m.elen[i] / m.dual_area[i]) : T(0);
-    for (int64_t i = 0; i <= m.ne; ++i) off[i] = int32_t(m.ef_off[i]);
+    // sliced rows: width and start of every slice of kSlice edges, entries slot-major, padding
+    // pointing at the zero h[nf]
+    const int64_t ns = (m.ne + kSlice - 1) / kSlice;
+    std::vector<int32_t> sw(ns), so(ns);
+    int64_t slots = 0;
+    for (int64_t q = 0; q < ns; ++q) {
+        int64_t w = 0;
+        for (int64_t i = q * kSlice; i < std::min(m.ne, (q + 1) * kSlice); ++i)
+            w = std::max(w, m.ef_off[i + 1] - m.ef_off[i]);
+        sw[q] = int32_t(w);
+        so[q] = int32_t(slots);
+        slots += w * kSlice;
+        if (slots >= (int64_t(1) << 31)) return fail(TYEE_EINVAL, "too many edge-face entries for one table");
+    }
+    std::vector<int32_t> ids(std::max<int64_t>(slots, 1), int32_t(m.nf));
+    for (int64_t i = 0; i < m.ne; ++i) {
+        const int64_t q = i / kSlice, lane = i % kSlice;
+        for (int64_t k = 0; k < m.ef_off[i + 1] - m.ef_off[i]; ++k) ids[so[q] + k * kSlice + lane] = m.ef[m.ef_off[i] + k];
+    }
     auto put = [&](DeviceBuffer &b, const void *src, size_t bytes) -> int {
         int r = b.alloc(std::max<size_t>(bytes, 16));
         if (r) return r;
@@ -97,11 +150,11 @@ int upload_tet(tyee_tet_sim &s, const TetMesh &m) {
         return TYEE_OK;
     };
     int rc = 0;
-    if ((rc = put(s.e, nullptr, m.ne * ts)) || (rc = put(s.h, nullptr, m.nf * ts)) ||
+    if ((rc = put(s.e, nullptr, m.ne * ts)) || (rc = put(s.h, nullptr, (m.nf + 1) * ts)) ||
         (rc = put(s.g, g.data(), m.nf * ts)) || (rc = put(s.a, a.data(), m.ne * ts)) ||
         (rc = put(s.eab, eab.data(), m.nf * 4)) || (rc = put(s.ebc, ebc.data(), m.nf * 4)) ||
-        (rc = put(s.eac, eac.data(), m.nf * 4)) || (rc = put(s.off, off.data(), (m.ne + 1) * 4)) ||
-        (rc = put(s.ef, m.ef.data(), m.ef.size() * 4)))
+        (rc = put(s.eac, eac.data(), m.nf * 4)) || (rc = put(s.sw, sw.data(), ns * 4)) ||
+        (rc = put(s.so, so.data(), ns * 4)) || (rc = put(s.ids, ids.data(), ids.size() * 4)))
         return rc;
     TYEE_HIP(hipStreamSynchronize(s.stream));
     return TYEE_OK;
@@ -111,7 +164,8 @@ template <typename T>
 void enqueue_edge(tyee_tet_sim &s) {
     const int32_t ne = int32_t(s.ne);
     hipLaunchKernelGGL(k_tet_edge<T>, dim3(unsigned(blocks_for(ne))), dim3(kBlock), 0, s.stream, ne,
-                       s.off.as<int32_t>(), s.ef.as<int32_t>(), s.a.as<T>(), s.h.as<T>(), s.e.as<T>());
+                       s.sw.as<int32_t>(), s.so.as<int32_t>(), s.ids.as<int32_t>(), s.a.as<T>(), s.h.as<T>(),
+                       s.e.as<T>());
 }
 
 template <typename T>
