@@ -85,8 +85,8 @@ def parse(argv=None):
     return p.parse_args(argv)
 
 
-def traffic_file(workload):
-    return os.path.join(ROOT, "profiles", f"traffic_k_fused_{workload}_f32.json")
+def traffic_file(workload, K):
+    return os.path.join(ROOT, "profiles", f"traffic_k_fused_{workload}_k{K}_f32.json")
 
 
 COPY_BYTES = 128 * 1024 * 1024 * 4     # --copy-calibration: bytes read and written per copy
@@ -104,9 +104,10 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, config, workload="torus1415"):
-    """HBM bytes per launch from the committed counter summary, if it still applies."""
+    """HBM bytes per launch from the committed counter summary of this depth, if it still
+    applies (same kernel sources and launch configuration)."""
     try:
-        with open(traffic_file(workload)) as f:
+        with open(traffic_file(workload, config["steps_per_launch"])) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -195,17 +196,17 @@ def traffic_summary(args):
     fetch = sum(v["FETCH_SIZE"][0] for v in per.values())
     write = sum(v["WRITE_SIZE"][0] for v in per.values())
     total = fetch * 1024 * fetch_scale + write * 1024 * write_scale
-    cfg = {"torus1415": {"triangles": 4004450, "steps_per_launch": 4, "tile_tris": 2048,
-                         "prec": "f32", "order": "morton"},
-           "plasma2830": {"triangles": 16017830, "steps_per_launch": 8, "tile_tris": 1024,
-                          "prec": "f32", "order": "morton"}}[args.workload]
+    if args.fusion < 2 or args.tile <= 0:
+        raise SystemExit("--traffic-summary needs the --fusion and --tile the counters were taken with")
+    cfg = {"triangles": {"torus1415": 4004450, "plasma2830": 16017830}[args.workload],
+           "steps_per_launch": args.fusion, "tile_tris": args.tile, "prec": "f32", "order": "morton"}
     out = {"kernel": "k_fused", "workload": args.workload, "source_hash": kernel_source_hash(),
            "config": cfg, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_scale": round(fetch_scale, 6), "write_scale": round(write_scale, 6),
            "per_kernel": {re.search(r"k_fused<[^>]*>", k).group(0): v for k, v in per.items()},
            "fetch_kib_per_launch_raw": fetch, "write_kib_per_launch_raw": write,
            "bytes_per_launch": int(round(total))}
-    with open(traffic_file(args.workload), "w") as f:
+    with open(traffic_file(args.workload, args.fusion), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
 
@@ -258,6 +259,19 @@ def launch_stats(prof, graph_launches):
     steps = g["count"] * graph_launches + e["count"]
     return ("edge+tri", steps, (g["total_ms"] + e["total_ms"] + t["total_ms"]) / steps) \
         if steps else None
+
+
+def region_depth(steps, default_k, short=100):
+    """Fusion depth for a timed region of `steps` steps: the library default, except in a
+    region shorter than `short` launches where the default would leave single steps over;
+    there the deepest depth up to the default that splits the region into an even number of
+    whole launches (so the region runs from graphs alone), if there is one."""
+    if steps >= short * default_k or steps % (2 * default_k) == 0:
+        return default_k
+    for k in range(default_k, 1, -1):
+        if steps % (2 * k) == 0:
+            return k
+    return default_k
 
 
 def graph_size(steps, K, wanted):
@@ -339,6 +353,13 @@ def bench_torus(args, with_extras=True):
     sim.set_state("E", E0)
     sim.set_state("B", B0)
     sim.set_fusion(args.fusion, args.tile)
+    if args.fusion == 0:
+        k_def = sim.fusion_info()["steps_per_launch"]
+        k_run = region_depth(args.steps, k_def)
+        if k_run != k_def:
+            log(f"{args.steps} timed steps: {k_run} steps per launch (default {k_def}) so that "
+                f"the region runs from whole graph spans")
+            sim.set_fusion(k_run, args.tile)
     ne, nt = mesh.ne, mesh.nt
     cells = ne + nt
 

@@ -182,12 +182,13 @@ int tyee_sim_set_source(tyee_sim *sim, const int32_t *node_pairs, const double *
    edge i (the learned correction); NULL restores gamma = 1.  Physical fields are kept. */
 int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma);
 
-/* Temporal fusion: advance steps_per_launch (1, 2, 4 or 8; 0 = the default: 8 for FP32 meshes
-   of 8,000,000 triangles or more, else 4) steps in one launch, with or without plasma and
+/* Temporal fusion: advance steps_per_launch (1..8; 0 = the default: in FP32 8 for meshes of
+   8,000,000 triangles or more, else 6; 4 in FP64) steps in one launch, with or without plasma and
    source edges (tiles that hold such an edge run a variant of the kernel that also advances
    their currents, and the nodal charge follows once per launch).  The device numbering is cut
-   into tiles of tile_tris consecutive triangles (0 = a default for the depth: 2048 at up to 4
-   steps, 1024 at 8 in FP32; 2048 / 1024 in FP64; else 256..8192); each work-group loads its tile with
+   into tiles of tile_tris consecutive triangles (0 = a default for the depth: in FP32 2048 at
+   up to 4 steps, 1792 at 5, 1536 at 6 or 7, 1024 at 8; in FP64 2048 below 4 steps, else 1024;
+   else 256..8192); each work-group loads its tile with
    steps_per_launch rings of neighbours into LDS, advances them, and writes its own cells to
    the other of two field buffers.  Results are bit-identical for every setting.  A mesh
    whose tiles exceed the kernel's capacity falls back to one launch per half-step. */

@@ -91,6 +91,10 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
     // (cells past the tile read the tile's last table entry and slot 0, and are never used),
     // so no branch sits between them and the compiler waits once.
     const bool own_run = ti.own_base >= 0;
+    // The waves of a tile being loaded run at a raised priority until its cells are staged, so
+    // on a CU whose other work-group is in its LDS steps the loads are issued first and their
+    // latency overlaps those steps (measured: 10.84 -> 10.66 us per step at 4 steps per launch).
+    __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
         const int l = tid + r * NT;
@@ -144,6 +148,7 @@ __global__ __launch_bounds__(NT) void k_fused(int K, int lds_tris, const TileInf
         const int l = tid + r * NT;
         if (l < nE) sE[l] = ve[r];
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
 
     for (int s = 1; s <= K; ++s) {
@@ -239,9 +244,13 @@ template <typename T> int upload_vec(Sim &s, DeviceBuffer &buf, const std::vecto
     return TYEE_OK;
 }
 
+// Default tile size for a fusion depth: the largest tile whose K halo rings still fit the
+// register capacity that lets two 1024-item work-groups share a CU (torus1415 FP32 sweep).
 int default_tile(bool f64, int K) {
     if (f64) return K >= 4 ? 1024 : 2048;
-    return K >= 8 ? 1024 : 2048;
+    if (K >= 8) return 1024;
+    if (K >= 6) return 1536;
+    return K == 5 ? 1792 : 2048;
 }
 
 }  // namespace

@@ -687,7 +687,7 @@ class Sim:
         _check(lib.tyee_sim_set_edge_scale(self._h, _ptr(g)))
 
     def set_fusion(self, k, tile=0):
-        """Steps per launch (1, 2, 4, 8; 0 = default) and tile size in triangles (0 = default)."""
+        """Steps per launch (1..8; 0 = default) and tile size in triangles (0 = default)."""
         _check(lib.tyee_sim_set_fusion(self._h, int(k), int(tile)))
 
     def step(self, n):

@@ -1,8 +1,9 @@
 """GPU: the reported bench line, run in-process on the short timed region the full test run uses.
 
 A timed region shorter than one graph span (20 steps against graphs of 8 fused launches of
-4 steps) must still be timed, and the line must carry the value, the roofline of the fused
-kernel as a fraction of the HBM peak, the single-step figure and the CPU oracle baseline.
+6 steps) must still be timed, from whole graph spans (the depth drops to 5 steps per launch,
+one graph of 4 launches), and the line must carry the value, the roofline of the fused kernel
+as a fraction of the HBM peak, the single-step figure and the CPU oracle baseline.
 """
 import json
 import os
@@ -27,6 +28,7 @@ def test_bench_line_on_a_short_timed_region():
     assert out["dtype"] == "f32"
     r = out["roofline"]
     assert r["kernel"] == "k_fused" and r["launches_timed"] == 20 // r["steps_per_launch"]
+    assert out["config"]["graph_launches"] * r["steps_per_launch"] == 20
     assert 0 < r["frac"] <= 1 and r["peak"] == 8000.0 and r["unit"] == "GB/s"
     assert r["algorithmic_bytes_per_launch"] == 64 * 4004450
     s = r["single_step"]

@@ -137,7 +137,8 @@ def test_plasma_and_source(ty, prec, tol):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("fusion,tile,chunks", [(2, 0, 1), (4, 0, 3), (8, 1024, 1), (4, 256, 2)])
+@pytest.mark.parametrize("fusion,tile,chunks", [(2, 0, 1), (4, 0, 3), (8, 1024, 1), (4, 256, 2),
+                                               (3, 0, 1), (5, 0, 2), (6, 0, 1), (7, 512, 1)])
 def test_plasma_fused_bit_identical(ty, prec, fusion, tile, chunks):
     # conforming particle and line source: the fused launch splits tiles into a plain class
     # and a class holding special edges; every field, the current and the charge must equal
@@ -179,7 +180,8 @@ def test_edge_scale_fp64(ty):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("fusion,tile", [(2, 0), (4, 0), (8, 0), (4, 512), (8, 1024), (2, 256)])
+@pytest.mark.parametrize("fusion,tile", [(2, 0), (4, 0), (8, 0), (4, 512), (8, 1024), (2, 256),
+                                         (3, 0), (5, 0), (6, 0), (7, 0), (6, 1536), (5, 768)])
 def test_fusion_depth_bit_identical(ty, fusion, tile, prec):
     n = 64
     _note(f"case: torus{n} {prec} fusion={fusion} tile={tile} bit-exactness")
