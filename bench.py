@@ -74,6 +74,11 @@ def parse(argv=None):
                    help="modes70x101: largest filter degree per iteration (0 = library default)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 512 MiB device copy (for counter calibration)")
+    p.add_argument("--fusion-sweep", default="",
+                   help="torus1415 or plasma2830: comma-separated KxT (steps per launch x tile triangles) "
+                        "configurations of the fused kernel, each timed on the same mesh (graphs "
+                        "of 8 launches, median of 5 regions of about --steps steps); one JSON "
+                        "line per configuration, then exit")
     p.add_argument("--copy-sweep", action="store_true",
                    help="only print device copy rates against buffer size (torch copy and the "
                         "library's non-temporal probe), from 16 MiB to 4 GiB per buffer")
@@ -290,6 +295,9 @@ def main():
     if args.copy_sweep:
         copy_sweep()
         return
+    if args.fusion_sweep:
+        fusion_sweep(args)
+        return
     if args.traffic_summary:
         traffic_summary(args)
         return
@@ -324,6 +332,61 @@ def single_step_rate(sim, bytes_step, steps=2000):
     return {"kernels": "k_edge + k_tri, one launch per half-step, graphs of 8 steps",
             "ms_per_step": round(ms, 6), "achieved": round(ach, 1),
             "frac": round(ach / HBM_PEAK_GBS, 4), "steps_timed": st[1]}
+
+
+def fusion_sweep(args):
+    """Steps per launch and tile size of the fused kernel on the torus1415 (or plasma2830) mesh
+    and start: for
+    each configuration, graphs of 8 launches, a warm-up of 4 graph spans, then the median (and
+    minimum) wall time per step over 5 regions of whole graph spans (about --steps steps)."""
+    import paper_1812_01448_amd as ty
+    from meshgen import lattice_mesh, periodic_wavevector, plane_wave_packet, random_angle, plasma_workload
+    plasma = args.workload == "plasma2830"
+    if plasma:
+        w = plasma_workload()
+        xy, tri, n = w["xy"], w["tri"], w["n"]
+    else:
+        n = args.n
+        xy, tri = lattice_mesh(n, 0.25, 1, periodic=True)
+    mesh = ty.Mesh(xy, tri, periodic=True)
+    mesh.reorder(args.order, 0)
+    lam, _, _ = mesh.cfl(max_iter=20000, rtol=1e-12, seed=0)
+    dt = 0.5 * 2.0 / np.sqrt(lam)
+    view = mesh.view()
+    k, _, _ = periodic_wavevector(random_angle(2), 20.0, 1.0 / n)
+    B0, E0 = plane_wave_packet(view["O"], view["C"], view["evec"] / view["elen"][:, None], k, dt,
+                               sigma=0.1, center=(0.5, 0.5))
+    sim = ty.Sim(mesh, dt, args.prec)
+    sim.set_state("E", E0)
+    sim.set_state("B", B0)
+    if plasma:                  # the plasma particle and the line source: eager fused launches
+        sim.set_media(w["wp2_tri"], w["nu"])
+        sim.set_source(w["src_pairs"], w["src_weights"], w["src_omega"], w["src_cycles"])
+    log(f"fusion sweep on {mesh.nt} triangles")
+    for item in args.fusion_sweep.split(","):
+        K, tile = (int(v) for v in item.lower().split("x"))
+        sim.set_fusion(K, tile)
+        sim.set_graph(8)
+        span = 8 * K
+        steps = span * max(1, round(args.steps / span))
+        sim.step(4 * span)
+        sim.sync()
+        per = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            sim.step(steps)
+            sim.sync()
+            per.append((time.perf_counter() - t0) / steps * 1e6)
+        fi = sim.fusion_info()
+        print(json.dumps({"workload": args.workload, "steps_per_launch": fi["steps_per_launch"], "tile": fi["tile"],
+                          "us_per_step": round(float(np.median(per)), 3), "min_us_per_step": round(min(per), 3),
+                          "cell_updates_per_s": round((mesh.ne + mesh.nt) / (np.median(per) * 1e-6), -8),
+                          "tiles": fi["tiles"], "halo_ratio_tris": round(fi["local_tris"] / mesh.nt, 3),
+                          "halo_ratio_edges": round(fi["local_edges"] / mesh.ne, 3), "steps_timed": steps}),
+              flush=True)
+    d = sim.diagnostics()
+    if d["nonfinite"]:
+        raise SystemExit("non-finite fields after the sweep")
 
 
 def bench_torus(args, with_extras=True):
