@@ -762,8 +762,8 @@ int tyee_sim_set_fusion(tyee_sim *sim, int32_t k, int32_t tile_tris) {
     if (!sim) return fail(TYEE_EINVAL, "null sim");
     // default depth in FP32: 6 steps per launch on 1536-triangle tiles (4M triangles: 9.5
     // against 10.7 us per step at 4 steps); meshes of 8M triangles or more, whose fields no
-    // longer fit the Infinity Cache, take 8 on 1024-triangle tiles (16M triangles: 49.0 us per
-    // step; 6 and 7 steps are within 1 %, 4 steps 61.5).  FP64 keeps 4.
+    // longer fit the Infinity Cache, take 8 on 1024-triangle tiles (16M triangles: 48.8 us per
+    // step; 6 and 7 steps are within 2.3 %, 4 steps 61.2).  FP64 keeps 4.
     if (k == 0) k = sim->s.f64 ? 4 : (sim->s.nt >= 8000000 ? 8 : 6);
     if (k < 1 || k > tyee::kMaxFusion) return fail(TYEE_EINVAL, "steps per launch must be 0 (default) or 1..8");
     if (tile_tris != 0 && (tile_tris < 256 || tile_tris > 8192))
