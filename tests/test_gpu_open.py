@@ -6,7 +6,9 @@ arithmetic differs only in the order of a few additions), FP32 within 1e-5 after
 triangle-mesh solver's FP32 bar). The frame cells' split parts are compared separately. The
 largest eigenvalue of the mixed operator against the oracle's power iteration. At a larger size
 the properties the frame is for: a pulse leaves the box through the PML, stays with a reflecting
-frame, and the leap-frog energy is conserved without damping.
+frame, and the leap-frog energy is conserved without damping. At the bench's size (4.6M
+triangles, graphs of 8 steps) every cell the box's sides cannot reach in 200 steps against the
+closed-box oracle.
 """
 import sys
 
@@ -177,3 +179,63 @@ def test_timing_and_errors(ty):
         sim.set_graph(-1)
     with pytest.raises(ty.TyeeError):
         sim.set_graph(2000)
+
+
+def _reached_from_sides(om, inner, steps):
+    """Edges and triangles that the box's side edges reach in `steps` leap-frog steps: an E
+    update reaches every edge of a reached triangle, a B update every triangle of a reached
+    edge. Advanced by fronts (only the cells reached in the last update can reach new ones)."""
+    te, tt = ~inner, np.zeros(om.nt, bool)
+    fresh_e, fresh_t = np.nonzero(te)[0], np.zeros(0, np.int64)
+    for _ in range(steps):
+        new_e = np.unique(om.A[fresh_t].reshape(-1))
+        new_e = new_e[~te[new_e]]
+        te[new_e] = True
+        cand = np.concatenate([om.R[fresh_e], om.L[fresh_e], om.R[new_e], om.L[new_e]])
+        cand = np.unique(cand[cand >= 0])
+        fresh_t = cand[~tt[cand]]
+        tt[fresh_t] = True
+        fresh_e = np.zeros(0, np.int64)
+    return te, tt
+
+
+def test_open1415_bench_configuration_interior_against_oracle(ty):
+    """The bench's open1415 case at its size (1415 x 1415 triangular-lattice box, jitter 0.1,
+    seed 11: 4.6M triangles, tied to a 16-layer frame, sigma_max 1, cubic grading), FP32, in the
+    bench's launch configuration (graphs of 8 steps): 200 steps from a seeded random state in
+    the box, the frame at rest. The frame is too large for the open-boundary oracle at this size,
+    but away from the box's sides the scheme is the closed box's: the FP64 oracle advances the
+    box with conducting sides, and every edge and triangle the sides cannot reach in 200 steps
+    is compared element by element (the sides' influence is followed exactly through the mesh:
+    a step's E update reaches the edges of a reached triangle, its B update the triangles of a
+    reached edge). FP32 bar 1e-5 (relative L2 per field over the compared cells), as for the
+    frame at small sizes."""
+    _note("case: open1415 (4.6M triangles + 16-layer frame) FP32, graphs of 8 steps, 200 steps, "
+          "interior against the closed-box oracle")
+    xy, tri, Lx, Ly = box_tri_mesh(1415.0, 1415.0, 1.0, 0.1, 11)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    dt = 0.5 * 2 / np.sqrt(om.power()[0])
+    rng = np.random.default_rng(5)
+    inner = (om.R >= 0) & (om.L >= 0)
+    E0 = np.where(inner, rng.standard_normal(om.ne), 0.0)
+    B0 = rng.standard_normal(om.nt)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    sim = ty.Open(m, ty.pml(16, 1.0, 1.0, 3.0), dt, "f32")
+    assert sim.nt == om.nt and sim.ne > om.ne
+    E = np.zeros(sim.ne)
+    E[:om.ne] = E0
+    Bx = np.zeros(sim.ncell)
+    Bx[:om.nt] = B0
+    sim.set_state("E", E)
+    sim.set_state("BX", Bx)
+    sim.set_state("BY", np.zeros(sim.ncell))
+    sim.step(200)
+    e_gpu, b_gpu = sim.get_state("E")[:om.ne], sim.get_state("BX")[:om.nt]
+    del sim
+    ref = om.step(E0, B0, dt, 200)
+    te, tt = _reached_from_sides(om, inner, 200)
+    ce, ct = ~te, ~tt
+    errs = (_rel(e_gpu[ce], ref["E"][ce]), _rel(b_gpu[ct], ref["B"][ct]))
+    _note(f"  {ce.sum()} edges and {ct.sum()} triangles compared: rel L2 E {errs[0]:.2e} B {errs[1]:.2e}")
+    assert ct.sum() > om.nt // 4
+    assert max(errs) <= 1e-5

@@ -15,7 +15,8 @@ comparison a test of conditioning) and a 49k-tetrahedron box (many work-groups a
 last one). Graph replay against eager launches bit for bit; the leap-frog phase of an
 eigenvector start; the energy without damping. At 1.3M tetrahedra, properties that hold at any
 size: the discrete divergence of B in every tetrahedron stays where it started, and the FP32
-energy stays within its rounding.
+energy stays within its rounding. At the bench's size (12M tetrahedra, one graph of 8 steps),
+three balls of the mesh against the oracle on their sub-meshes, every cell the cut cannot reach.
 """
 import sys
 
@@ -211,3 +212,54 @@ def test_timing_and_errors(ty):
         ty.TetSim(T, -1.0, "f32")
     with pytest.raises(ty.TyeeError):
         sim.set_graph(-1)
+
+
+def test_tet100_bench_configuration_sampled_against_oracle(ty):
+    """The bench's tet100 mesh at its size (100^3 BCC box, jitter 0.05 h, seed 0: 12M
+    tetrahedra), FP32, in the bench's launch configuration (graphs of 8 steps): one graph of 8
+    steps from a seeded random state. The oracle cannot build the whole mesh, so it takes three
+    balls of it: the tetrahedra whose centroids lie within 14 h of a centre, with the global node
+    ids (so edges and faces keep their orientation), advanced 8 steps. The ball's cut faces act
+    as walls there, so only the edges and faces the cut cannot reach in 8 steps are compared:
+    the cut's influence is followed exactly through the sub-mesh's incidences (a step's E update
+    reaches every edge of a reached face, its B update every face with a reached edge). FP32
+    bar 1e-5 (relative L2 per field over the compared cells)."""
+    _note("case: tet100 (12M tetrahedra) FP32, one graph of 8 steps, three balls against the oracle")
+    xyz, tets, L = bcc_box(100, 100, 100, 1.0, 0.05, 0)
+    T = ty.Tet(xyz, tets)
+    v = T.view()
+    nv = np.int64(T.nv)
+    ekey = v["edge"][:, 0].astype(np.int64) * nv + v["edge"][:, 1]
+    f64 = v["face"].astype(np.int64)
+    fkey = (f64[:, 0] * nv + f64[:, 1]) * nv + f64[:, 2]
+    assert np.all(np.diff(ekey) > 0) and np.all(np.diff(fkey) > 0)       # canonical order
+    dt = 0.5 * 2 / np.sqrt(65.64)        # CFL 0.5 of this mesh's omega_max^2 (the bench's power iteration)
+    rng = np.random.default_rng(11)
+    E0 = np.where(v["dual_area"] > 0, rng.standard_normal(T.ne), 0.0)
+    B0 = rng.standard_normal(T.nf)
+    sim = ty.TetSim(T, dt, "f32")
+    sim.set_state("E", E0)
+    sim.set_state("B", B0)
+    sim.step(8)
+    e_gpu, b_gpu = sim.get_state("E"), sim.get_state("B")
+    del sim, v
+    cen = xyz[tets].mean(axis=1)
+    for p in ([31.3, 48.6, 57.2], [66.1, 35.4, 40.8], [50.5, 70.2, 28.9]):
+        sub = tets[np.sum((cen - np.array(p)) ** 2, axis=1) < 14.0 ** 2]
+        m = TetMesh(xyz, sub)
+        ie = np.searchsorted(ekey, m.edge[:, 0] * nv + m.edge[:, 1])
+        fk = (m.face[:, 0] * nv + m.face[:, 1]) * nv + m.face[:, 2]       # rows sorted
+        jf = np.searchsorted(fkey, fk)
+        assert np.array_equal(ekey[ie], m.edge[:, 0] * nv + m.edge[:, 1]) and np.array_equal(fkey[jf], fk)
+        Er, Br = m.step(E0[ie], B0[jf], dt, 8)
+        # cells the cut reaches within 8 steps
+        te, tf = ~m.inner_edge, ~m.inner_face
+        for _ in range(8):
+            te[m.face_edge[tf].reshape(-1)] = True
+            tf = tf | np.any(te[m.face_edge], axis=1)
+        ce, cf = ~te, ~tf
+        errs = (_rel(e_gpu[ie][ce], Er[ce]), _rel(b_gpu[jf][cf], Br[cf]))
+        _note(f"  ball at {p}: {len(sub)} tetrahedra, {ce.sum()} edges and {cf.sum()} faces compared, "
+              f"rel L2 E {errs[0]:.2e} B {errs[1]:.2e}")
+        assert ce.sum() > 1000 and cf.sum() > 2000
+        assert max(errs) <= 1e-5
