@@ -211,3 +211,29 @@ def test_repeatable_and_reports_non_convergence(ty):
     assert np.array_equal(a["omega2"], b["omega2"]) and np.array_equal(a["modes"], b["modes"])
     c = m.modes(20, degree=2, tol=1e-14, max_iter=1)
     assert not c["converged"] and c["iters"] == 1 and np.max(c["residual"]) > 1e-14
+
+
+def test_device_omega_max_at_the_bench_size(ty):
+    """eq. 20's omega_max on the device (FP64) at the bench's size: the highest mode of the
+    4M-triangle torus from the block solver against the host power iteration, and (a relaxed
+    mesh has no isolated top mode) of the jello-relaxed 45 x 45 cavity."""
+    n = 1415
+    _note(f"case: torus{n} (4.0M triangles): omega_max^2 from the device's highest mode vs the host power iteration")
+    xy, tri = lattice_mesh(n, 0.25, 1, periodic=True)
+    m = ty.Mesh(xy, tri, True)
+    m.reorder("morton")
+    lam_cfl, it, ok = m.cfl(rtol=1e-14, max_iter=20000)
+    got = m.modes(4, which="highest", tol=1e-11, max_iter=400, want_vectors=False)
+    _note(f"  host {lam_cfl:.15e} ({it} iterations), device {got['omega2'][0]:.15e} "
+          f"(iters {got['iters']}, applies {got['applies']}, {got['total_ms']:.1f} ms)")
+    assert ok and got["converged"]
+    assert abs(got["omega2"][0] - lam_cfl) <= 1e-10 * lam_cfl
+    # a relaxed mesh: no near-cocircular outlier, so the top of the spectrum is a cluster
+    xy, tri = lattice_mesh(45, 0.2, 0, periodic=False)
+    x1, t1, _, _ = ty.Mesh(xy, tri, False).relax(rounds=8, iters=100, step=0.05)
+    mr = ty.Mesh(x1, t1, False)
+    lam_cfl, it, ok = mr.cfl(rtol=1e-14, max_iter=400000)
+    got = mr.modes(8, which="highest", tol=1e-11, max_iter=400, want_vectors=False)
+    _note(f"  relaxed cavity45: host {lam_cfl:.15e} ({it} iterations), device {got['omega2'][0]:.15e}")
+    assert ok and got["converged"]
+    assert abs(got["omega2"][0] - lam_cfl) <= 1e-10 * lam_cfl
