@@ -191,7 +191,8 @@ int tyee_sim_set_edge_scale(tyee_sim *sim, const double *gamma);
    else 256..8192); each work-group loads its tile with
    steps_per_launch rings of neighbours into LDS, advances them, and writes its own cells to
    the other of two field buffers.  Results are bit-identical for every setting.  A mesh
-   whose tiles exceed the kernel's capacity falls back to one launch per half-step. */
+   whose tiles exceed the kernel's capacity falls back to one launch per half-step.  A new
+   simulation advances one launch per half-step (steps_per_launch 1) until this is called. */
 int tyee_sim_set_fusion(tyee_sim *sim, int32_t steps_per_launch, int32_t tile_tris);
 
 /* Enqueue n leap-frog steps on the simulation's stream (asynchronous; n = 0 does nothing).

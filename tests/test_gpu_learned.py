@@ -231,3 +231,21 @@ def test_learned_pieces_at_the_held_out_size(ty):
     ref = OL.timestepped_phase_error(om, g, dt, k, nsteps, samples=10)
     _note(f"  phase error {got:.9e} oracle {ref:.9e} ({nsteps} steps)")
     assert abs(got - ref) < 1e-6
+    # the folded scale in the stepping path the simulations use: default fused launches (6 steps
+    # on 1536-triangle tiles) replayed from graphs of 8, 240 FP32 steps of a packet, element by
+    # element against the oracle's FP64 run with the same scale
+    sim = ty.Sim(m, dt, "f32")
+    sim.set_edge_scale(g)
+    sim.set_fusion(0, 0)
+    sim.set_graph(8)
+    v = m.view()
+    E0, B0 = packet_state(v, dt, n)
+    sim.set_state("E", E0)
+    sim.set_state("B", B0)
+    sim.step(240)
+    ref = om.step(*packet_state(om, dt, n), dt, 240, gamma=g)
+    eE, eB = rel_l2(sim.get_state("E"), ref["E"]), rel_l2(sim.get_state("B"), ref["B"])
+    _note(f"  scaled stepping, {sim.fusion_info()['steps_per_launch']} steps per launch, 240 steps: "
+          f"rel L2 E {eE:.2e} B {eB:.2e}")
+    assert sim.fusion_info()["steps_per_launch"] == 6
+    assert eE < 1e-5 and eB < 1e-5
