@@ -502,13 +502,14 @@ int tyee_batch_sim(tyee_batch *b, tyee_sim **sim);
 
 typedef struct {
     int32_t order;             /* tyee_order */
-    int32_t steps_per_launch;  /* 1, 2, 4 or 8 */
+    int32_t steps_per_launch;  /* 1, 2, 4, 6 or 8 */
     int32_t tile_tris;         /* 0 for one launch per half-step */
     double ms_per_step;        /* HIP-event time of the trial divided by its steps */
 } tyee_tune_result;
 
 /* Autotune: time about steps_per_trial steps for every ordering (Morton, RCM) x steps per
-   launch (1, 2, 4, 8) x tile size (1024, 2048, 3072, 4096), keep the fastest setting and
+   launch (1, 2, 4, 6, 8) x tile size (1024, 1536, 2048, 3072; one trial at 1 step per
+   launch), 34 trials, keep the fastest setting and
    restore the fields and step count.  results: [capacity] trial records (may be NULL when
    capacity is 0); *n_results receives the number of trials. */
 int tyee_batch_tune(tyee_batch *b, int64_t steps_per_trial, tyee_tune_result *results,

@@ -259,8 +259,8 @@ int tyee_batch_tune_progress(tyee_batch *b, int64_t steps_per_trial, tyee_tune_r
                              int64_t capacity, int64_t *n_results, tyee_tune_progress on_trial, void *user) {
     if (!b || steps_per_trial <= 0 || (capacity > 0 && !results)) return fail(TYEE_EINVAL, "bad tune arguments");
     const int32_t orders[] = {TYEE_ORDER_MORTON, TYEE_ORDER_RCM};
-    const int32_t depths[] = {1, 2, 4, 8};
-    const int32_t tiles[] = {1024, 2048, 3072, 4096};
+    const int32_t depths[] = {1, 2, 4, 6, 8};
+    const int32_t tiles[] = {1024, 1536, 2048, 3072};
     std::vector<tyee_tune_result> all;
     // canonical save of the fields and step count
     std::vector<double> E, B;

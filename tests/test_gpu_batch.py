@@ -122,7 +122,7 @@ def test_autotuner_restores_state_and_picks_a_setting(ty):
     before = [batch.get_state(k, "E") for k in range(4)]
     seen = []
     res = batch.tune(16, progress=seen.append)
-    assert len(res) == 2 * (1 + 3 * 4)
+    assert len(res) == 2 * (1 + 4 * 4)
     assert seen == res            # one report per trial, as it ends, with the same record
     assert all(r["ms_per_step"] > 0 for r in res)
     after = [batch.get_state(k, "E") for k in range(4)]
