@@ -733,6 +733,24 @@ int tyee_open_step(tyee_open *o, int64_t nsteps);
 /* Steps per captured graph, 0 .. 1024 (0: every launch eager; default 8).  Waits for the stream
    if a graph exists (it is discarded).  Errors: EINVAL. */
 int tyee_open_set_graph(tyee_open *o, int32_t steps);
+/* Fused stepping of the box (the temporal fusion of tyee_sim_set_fusion carried to the open
+   boundary): steps_per_launch K (1..8; 0 = 6 in FP32, 4 in FP64; 1 = off, the default),
+   tile_tris as in tyee_sim_set_fusion.  mesh must be the triangle mesh the handle was created
+   from (checked: counts and edges).  The library then holds a Morton-numbered copy of the box
+   advanced by the fused kernel, and a band (every frame cell and edge, the box triangles within
+   2K + 3 rings of its sides and their edges) on compact arrays advanced by the single-step
+   kernels; each group of K steps gathers the band's box cells, runs one fused launch over the
+   box and K band steps, and writes the band's cells within K + 2 rings of the sides over the
+   box's (one step carries information one cell, so both parts are exact).  tyee_open_step
+   moves the state into these two parts and back around its whole groups of K steps (the rest
+   run one launch per half-step, as do timed steps); the state stays in canonical order for
+   tyee_open_set_state / _get_state.  Groups run from a captured HIP graph of 8 groups (the
+   band's steps on a second stream of the library's beside the fused launch) when the graph size
+   of tyee_open_set_graph is not 0, else eagerly in order on the handle's stream (bit-identical).
+   Waits for the stream.
+   Errors: EINVAL (bad arguments, another mesh, a box that does not tile at that depth),
+   ENOMEM, EDEVICE. */
+int tyee_open_set_fusion(tyee_open *o, const tyee_mesh *mesh, int32_t steps_per_launch, int32_t tile_tris);
 int tyee_open_sync(tyee_open *o);
 /* With timing on, steps are launched one by one, each with HIP events around its two launches
    (read after every 256 steps, so a timed call waits for its steps; the events add a few us to

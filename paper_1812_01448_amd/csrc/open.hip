@@ -16,8 +16,10 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <set>
 #include <utility>
 #include <vector>
@@ -317,7 +319,25 @@ struct tyee_open {
     std::vector<hipEvent_t> ev;   // timing: three events per step of a chunk of steps
     double ms_edge = 0.0, ms_cell = 0.0;
     int64_t timed = 0;
+    // Fused stepping (tyee_open_set_fusion): the box's triangles are advanced by the fused
+    // K-step kernel of a triangle-mesh simulation `box` (Morton numbering), and a band (the
+    // frame plus the triangles within 2K + 3 rings of the box's sides) by K single steps of the
+    // kernels above on its own compact arrays; see launch_open_fused.
+    int fuse_K = 0;                   // 0: off
+    std::unique_ptr<tyee_sim> box;
+    int64_t bnbe = 0, bnbt = 0, bne = 0, bncell = 0, nw_e = 0, nw_t = 0;
+    tyee::DeviceBuffer bE, bB, bBy, blr, bk, bt0, bt1, bt2, bg, bfe;   // band state and tables
+    tyee::DeviceBuffer slot_e, slot_t;        // canonical box edge / triangle -> box device slot
+    tyee::DeviceBuffer g_e, g_t;              // band box edge / triangle -> box device slot
+    tyee::DeviceBuffer w_from_e, w_to_e, w_from_t, w_to_t;   // band cells written back to the box
+    hipGraphExec_t fgraph = nullptr;  // kFusedGraphGroups fused groups, captured once
+    hipStream_t side = nullptr;       // the band's branch inside the captured graph
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ~tyee_open() {
+        if (fgraph) (void)hipGraphExecDestroy(fgraph);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         if (graph) (void)hipGraphExecDestroy(graph);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -461,6 +481,309 @@ int launch_open(tyee_open &o, int64_t nsteps) {
         for (; nsteps - done >= o.graph_steps; done += o.graph_steps) TYEE_HIP(hipGraphLaunch(o.graph, o.stream));
     }
     for (; done < nsteps; ++done) {
+        enqueue_edge<T>(o);
+        enqueue_cell<T>(o);
+    }
+    TYEE_HIP(hipGetLastError());
+    return TYEE_OK;
+}
+
+// dst[to[i]] = src[from[i]] (a null map is the identity), i < n.
+template <typename T>
+__global__ void k_open_move(int32_t n, const int32_t *__restrict__ from, const int32_t *__restrict__ to,
+                            const T *__restrict__ src, T *__restrict__ dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    dst[to ? to[i] : i] = src[from ? from[i] : i];
+}
+
+// Two such moves in one launch (i < max(n1, n2)).
+template <typename T>
+__global__ void k_open_move2(int32_t n1, const int32_t *__restrict__ f1, const int32_t *__restrict__ t1,
+                             const T *__restrict__ s1, T *__restrict__ d1, int32_t n2, const int32_t *__restrict__ f2,
+                             const int32_t *__restrict__ t2, const T *__restrict__ s2, T *__restrict__ d2) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n1) d1[t1 ? t1[i] : i] = s1[f1 ? f1[i] : i];
+    if (i < n2) d2[t2 ? t2[i] : i] = s2[f2 ? f2[i] : i];
+}
+
+template <typename T>
+void move2(hipStream_t st, int64_t n1, const DeviceBuffer *f1, const DeviceBuffer *t1, const T *s1, T *d1, int64_t n2,
+           const DeviceBuffer *f2, const DeviceBuffer *t2, const T *s2, T *d2) {
+    const int64_t n = std::max(n1, n2);
+    if (n <= 0) return;
+    auto ix = [](const DeviceBuffer *b) { return b ? b->as<int32_t>() : nullptr; };
+    hipLaunchKernelGGL(k_open_move2<T>, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, int32_t(n1),
+                       ix(f1), ix(t1), s1, d1, int32_t(n2), ix(f2), ix(t2), s2, d2);
+}
+
+template <typename T>
+void move(hipStream_t st, int64_t n, const DeviceBuffer *from, const DeviceBuffer *to, const T *src, T *dst) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_open_move<T>, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, int32_t(n),
+                       from ? from->as<int32_t>() : nullptr, to ? to->as<int32_t>() : nullptr, src, dst);
+}
+
+// The band and its tables.  A box triangle's ring is its distance, in triangles, from the box's
+// sides (ring 1 touches a side).  The fused kernel holds the sides' edges fixed, so after K
+// steps it is exact on the triangles of ring > K and on the edges between them; the band
+// (every frame cell and edge, the triangles of ring <= 2K + 3 and their edges) advanced from
+// the same state by K single steps, its inner cut held fixed, is exact on ring <= K + 3.  The
+// band's triangles of ring <= K + 2 and the edges whose triangles all have ring <= K + 2 are
+// written over the fused result.  Band numbering follows the mixed mesh's layout: box edges,
+// then every frame edge in order; box triangles, then every frame cell in order.
+int build_open_fusion(tyee_open &o, const Mesh &mesh, int K, int tile) {
+    const Frame &f = o.f;
+    if (mesh.nt != f.nt || mesh.ne != f.ne_mesh || mesh.nv > f.nv)
+        return fail(TYEE_EINVAL, "the mesh is not the one the open boundary was built from");
+    for (int64_t i = 0; i < mesh.ne; ++i)
+        if (mesh.edge[2 * i] != f.edge[2 * i] || mesh.edge[2 * i + 1] != f.edge[2 * i + 1])
+            return fail(TYEE_EINVAL, "the mesh is not the one the open boundary was built from");
+    std::unique_ptr<tyee_mesh> copy(new tyee_mesh());
+    copy->m = mesh;
+    int rc = reorder_mesh(copy->m, TYEE_ORDER_MORTON, 0);
+    tyee_sim *raw = nullptr;
+    if (!rc) rc = tyee_sim_create(copy.get(), o.f64 ? TYEE_F64 : TYEE_F32, o.dt, o.stream, &raw);
+    if (rc) return rc;
+    std::unique_ptr<tyee_sim> box(raw);
+    copy.reset();
+    Sim &s = box->s;
+    s.fusion = K;
+    s.tile_tris = tile;
+    if ((rc = build_tiling(s, K, tile))) return rc;
+    // rings from the box's sides
+    const int32_t far = 2 * K + 3, keep = K + 2;
+    std::vector<int32_t> ring(mesh.nt, INT32_MAX), front;
+    for (int64_t i = 0; i < mesh.ne; ++i)
+        if (!mesh.interior(i)) {
+            const int32_t j = mesh.R[i] >= 0 ? mesh.R[i] : mesh.L[i];
+            if (j >= 0 && ring[j] > 1) {
+                ring[j] = 1;
+                front.push_back(j);
+            }
+        }
+    for (int32_t r = 1; r < far && !front.empty(); ++r) {
+        std::vector<int32_t> next;
+        for (int32_t j : front)
+            for (int q = 0; q < 3; ++q) {
+                const int32_t i = mesh.A[3 * j + q];
+                const int32_t o2 = mesh.R[i] == j ? mesh.L[i] : mesh.R[i];
+                if (o2 >= 0 && ring[o2] == INT32_MAX) {
+                    ring[o2] = r + 1;
+                    next.push_back(o2);
+                }
+            }
+        front.swap(next);
+    }
+    std::vector<int32_t> tloc(mesh.nt, -1), eloc(mesh.ne, -1), btri, bedge;
+    for (int64_t j = 0; j < mesh.nt; ++j)
+        if (ring[j] <= far) {
+            tloc[j] = int32_t(btri.size());
+            btri.push_back(int32_t(j));
+        }
+    for (int32_t j : btri)
+        for (int q = 0; q < 3; ++q) eloc[mesh.A[3 * j + q]] = 0;
+    for (int64_t i = 0; i < mesh.ne; ++i)
+        if (eloc[i] == 0) {
+            eloc[i] = int32_t(bedge.size());
+            bedge.push_back(int32_t(i));
+        }
+    const int64_t nem = f.ne_mesh, nfe = f.ne - nem;
+    o.bnbe = int64_t(bedge.size());
+    o.bnbt = int64_t(btri.size());
+    o.bne = o.bnbe + nfe;
+    o.bncell = o.bnbt + f.nf;
+    auto cell_of = [&](int32_t c) -> int32_t {   // mixed-mesh cell -> band cell (-1: not in the band)
+        if (c < 0) return -1;
+        return c < f.nt ? tloc[c] : int32_t(o.bnbt + (c - f.nt));
+    };
+    auto edge_of = [&](int32_t i) -> int32_t {   // mixed-mesh edge -> band edge (-1: not in the band)
+        if (i < 0 || i >= f.ne) return -1;
+        return i < nem ? eloc[i] : int32_t(o.bnbe + (i - nem));
+    };
+    const double dt = o.dt;
+    std::vector<int2> lr(o.bne);
+    std::vector<double> kk(o.bne);
+    for (int64_t l = 0; l < o.bne; ++l) {
+        const int64_t i = l < o.bnbe ? bedge[l] : nem + (l - o.bnbe);
+        lr[l] = make_int2(cell_of(f.left[i]), cell_of(f.right[i]));
+        const double sg = 0.5 * f.sigma_e[i] * dt;
+        kk[l] = f.left[i] >= 0 && f.right[i] >= 0 ? f.elen[i] * dt / (1.0 + sg) / f.d[i] : 0.0;
+    }
+    std::vector<int32_t> t0(o.bnbt), t1(o.bnbt), t2(o.bnbt);
+    std::vector<double> gg(o.bnbt);
+    for (int64_t l = 0; l < o.bnbt; ++l) {
+        const int64_t j = btri[l];
+        int32_t id[3];
+        for (int q = 0; q < 3; ++q) {
+            const int32_t e = edge_of(f.cell_edge[4 * j + q]);
+            if (e < 0) return fail(TYEE_EINVAL, "internal: a band triangle's edge is not in the band");
+            id[q] = signed_id(e, f.cell_sl[4 * j + q] > 0.0);
+        }
+        t0[l] = id[0];
+        t1[l] = id[1];
+        t2[l] = id[2];
+        gg[l] = dt / f.S[j];
+    }
+    std::vector<int4> fe(f.nf);
+    for (int64_t q = 0; q < f.nf; ++q) {
+        const int64_t j = f.nt + q;
+        int32_t id[4];
+        for (int c = 0; c < 4; ++c) {
+            const int32_t e = edge_of(f.cell_edge[4 * j + c]);
+            if (e < 0) return fail(TYEE_EINVAL, "internal: a frame cell's edge is not in the band");
+            id[c] = signed_id(e, f.cell_sl[4 * j + c] > 0.0);
+        }
+        fe[q] = make_int4(id[0], id[1], id[2], id[3]);
+    }
+    // device slots of the box simulation, gathers and write-back pairs
+    std::vector<int32_t> ge(o.bnbe), gt(o.bnbt), wfe, wte, wft, wtt;
+    for (int64_t l = 0; l < o.bnbe; ++l) ge[l] = s.slot_e[bedge[l]];
+    for (int64_t l = 0; l < o.bnbt; ++l) gt[l] = s.slot_t[btri[l]];
+    for (int64_t l = 0; l < o.bnbt; ++l)
+        if (ring[btri[l]] <= keep) {
+            wft.push_back(int32_t(l));
+            wtt.push_back(gt[l]);
+        }
+    for (int64_t l = 0; l < o.bnbe; ++l) {
+        const int32_t i = bedge[l], a = mesh.R[i], b = mesh.L[i];
+        if ((a < 0 || ring[a] <= keep) && (b < 0 || ring[b] <= keep)) {
+            wfe.push_back(int32_t(l));
+            wte.push_back(ge[l]);
+        }
+    }
+    // host-side bounds checks of every index the kernels read
+    for (const int2 &c : lr)
+        if (c.x >= o.bncell || c.y >= o.bncell) return fail(TYEE_EINVAL, "internal: band cell out of range");
+    for (int32_t v : ge)
+        if (v < 0 || v >= s.ne) return fail(TYEE_EINVAL, "internal: box edge slot out of range");
+    for (int32_t v : gt)
+        if (v < 0 || v >= s.nt) return fail(TYEE_EINVAL, "internal: box triangle slot out of range");
+    auto put = [&](DeviceBuffer &b, const void *src, size_t bytes) -> int {
+        int r = b.alloc(std::max<size_t>(bytes, 16));
+        if (r) return r;
+        TYEE_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, o.stream));
+        return TYEE_OK;
+    };
+    const size_t ts = o.f64 ? 8 : 4;
+    std::vector<float> kf(kk.begin(), kk.end()), gf(gg.begin(), gg.end());
+    const void *kp = o.f64 ? static_cast<const void *>(kk.data()) : static_cast<const void *>(kf.data());
+    const void *gp = o.f64 ? static_cast<const void *>(gg.data()) : static_cast<const void *>(gf.data());
+    if ((rc = o.bE.alloc(std::max<size_t>(o.bne * ts, 16))) || (rc = o.bB.alloc(std::max<size_t>(o.bncell * ts, 16))) ||
+        (rc = o.bBy.alloc(std::max<size_t>(f.nf * ts, 16))) || (rc = put(o.blr, lr.data(), lr.size() * sizeof(int2))) ||
+        (rc = put(o.bk, kp, o.bne * ts)) || (rc = put(o.bt0, t0.data(), t0.size() * 4)) ||
+        (rc = put(o.bt1, t1.data(), t1.size() * 4)) || (rc = put(o.bt2, t2.data(), t2.size() * 4)) ||
+        (rc = put(o.bg, gp, o.bnbt * ts)) || (rc = put(o.bfe, fe.data(), fe.size() * sizeof(int4))) ||
+        (rc = put(o.slot_e, s.slot_e.data(), s.slot_e.size() * 4)) ||
+        (rc = put(o.slot_t, s.slot_t.data(), s.slot_t.size() * 4)) || (rc = put(o.g_e, ge.data(), ge.size() * 4)) ||
+        (rc = put(o.g_t, gt.data(), gt.size() * 4)) || (rc = put(o.w_from_e, wfe.data(), wfe.size() * 4)) ||
+        (rc = put(o.w_to_e, wte.data(), wte.size() * 4)) || (rc = put(o.w_from_t, wft.data(), wft.size() * 4)) ||
+        (rc = put(o.w_to_t, wtt.data(), wtt.size() * 4)))
+        return rc;
+    if (!o.side) TYEE_HIP(hipStreamCreateWithFlags(&o.side, hipStreamNonBlocking));
+    if (!o.ev_fork) TYEE_HIP(hipEventCreateWithFlags(&o.ev_fork, hipEventDisableTiming));
+    if (!o.ev_join) TYEE_HIP(hipEventCreateWithFlags(&o.ev_join, hipEventDisableTiming));
+    TYEE_HIP(hipStreamSynchronize(o.stream));
+    o.nw_e = int64_t(wfe.size());
+    o.nw_t = int64_t(wft.size());
+    o.box = std::move(box);
+    o.fuse_K = K;
+    return TYEE_OK;
+}
+
+template <typename T>
+void enqueue_band(tyee_open &o, hipStream_t st) {
+    hipLaunchKernelGGL(k_open_edge<T>, dim3(unsigned(blocks_for(o.bne))), dim3(kBlock), 0, st, int32_t(o.bne),
+                       int32_t(o.bnbe), int32_t(o.bnbt), o.blr.as<int2>(), o.bk.as<T>(), o.caf.as<T>(), o.bB.as<T>(),
+                       o.bBy.as<T>(), o.bE.as<T>());
+    hipLaunchKernelGGL(k_open_cell<T>, dim3(unsigned(blocks_for(o.bncell))), dim3(kBlock), 0, st,
+                       int32_t(o.bncell), int32_t(o.bnbt), o.bt0.as<int32_t>(), o.bt1.as<int32_t>(),
+                       o.bt2.as<int32_t>(), o.bg.as<T>(), o.bfe.as<int4>(), o.fc.as<T>(), o.bE.as<T>(), o.bB.as<T>(),
+                       o.bBy.as<T>());
+}
+
+// One fused group of K steps: the band gathers its box cells, one fused launch advances the
+// box, K single steps the band, and the band's exact cells are written over the box's.
+// With `side` (graph capture), the band's K steps run on the side stream beside the fused
+// launch (they touch only the band's arrays, the fused launch only the box's), joined before
+// the write-back; without it everything runs in order on the handle's stream.
+template <typename T>
+int enqueue_fused_group(tyee_open &o, bool side) {
+    Sim &s = o.box->s;
+    const hipStream_t st = o.stream;
+    move2<T>(st, o.bnbe, &o.g_e, nullptr, s.Et().as<T>(), o.bE.as<T>(), o.bnbt, &o.g_t, nullptr, s.B().as<T>(),
+             o.bB.as<T>());
+    if (side) {
+        TYEE_HIP(hipEventRecord(o.ev_fork, st));
+        TYEE_HIP(hipStreamWaitEvent(o.side, o.ev_fork, 0));
+        for (int k = 0; k < o.fuse_K; ++k) enqueue_band<T>(o, o.side);
+        TYEE_HIP(hipEventRecord(o.ev_join, o.side));
+    }
+    int rc = launch_fused<T>(s, o.fuse_K);
+    if (rc) return rc;
+    if (side) TYEE_HIP(hipStreamWaitEvent(st, o.ev_join, 0));
+    else
+        for (int k = 0; k < o.fuse_K; ++k) enqueue_band<T>(o, st);
+    move2<T>(st, o.nw_e, &o.w_from_e, &o.w_to_e, o.bE.as<T>(), s.Et().as<T>(), o.nw_t, &o.w_from_t, &o.w_to_t,
+             o.bB.as<T>(), s.B().as<T>());
+    return TYEE_OK;
+}
+
+constexpr int kFusedGraphGroups = 8;   // fused groups per captured graph (even: the box's two
+                                       // field buffers are back in place after a replay)
+
+// Fused stepping: the state moves into the box simulation and the band, whole groups of K
+// steps run (replayed from a graph of kFusedGraphGroups groups unless graphs are off), and the
+// state moves back; the rest of the steps run one launch per half-step.
+template <typename T>
+int launch_open_fused(tyee_open &o, int64_t nsteps) {
+    const int K = o.fuse_K;
+    const Frame &f = o.f;
+    Sim &s = o.box->s;
+    const hipStream_t st = o.stream;
+    const int64_t cycles = nsteps / K, nem = f.ne_mesh, nfe = f.ne - nem;
+    if (cycles > 0) {
+        move<T>(st, nem, nullptr, &o.slot_e, o.E.as<T>(), s.Et().as<T>());
+        move<T>(st, f.nt, nullptr, &o.slot_t, o.B.as<T>(), s.B().as<T>());
+        move<T>(st, nfe, nullptr, nullptr, o.E.as<T>() + nem, o.bE.as<T>() + o.bnbe);
+        move<T>(st, f.nf, nullptr, nullptr, o.B.as<T>() + f.nt, o.bB.as<T>() + o.bnbt);
+        move<T>(st, f.nf, nullptr, nullptr, o.By.as<T>(), o.bBy.as<T>());
+        int64_t c = 0;
+        if (o.graph_steps > 0 && cycles >= kFusedGraphGroups) {
+            if (!o.fgraph) {
+                TYEE_HIP(hipGetLastError());
+                TYEE_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                int rc = TYEE_OK;
+                for (int g = 0; g < kFusedGraphGroups && !rc; ++g) rc = enqueue_fused_group<T>(o, true);
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &graph);
+                if (rc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc;
+                }
+                if (e != hipSuccess) return fail(TYEE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+                e = hipGraphInstantiate(&o.fgraph, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    o.fgraph = nullptr;
+                    return fail(TYEE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                }
+            }
+            for (; cycles - c >= kFusedGraphGroups; c += kFusedGraphGroups) TYEE_HIP(hipGraphLaunch(o.fgraph, st));
+        }
+        for (; c < cycles; ++c) {
+            int rc = enqueue_fused_group<T>(o, false);
+            if (rc) return rc;
+        }
+        move<T>(st, nem, &o.slot_e, nullptr, s.Et().as<T>(), o.E.as<T>());
+        move<T>(st, f.nt, &o.slot_t, nullptr, s.B().as<T>(), o.B.as<T>());
+        move<T>(st, nfe, nullptr, nullptr, o.bE.as<T>() + o.bnbe, o.E.as<T>() + nem);
+        move<T>(st, f.nf, nullptr, nullptr, o.bB.as<T>() + o.bnbt, o.B.as<T>() + f.nt);
+        move<T>(st, f.nf, nullptr, nullptr, o.bBy.as<T>(), o.By.as<T>());
+        TYEE_HIP(hipGetLastError());
+    }
+    const int64_t rest = nsteps - cycles * K;
+    for (int64_t k = 0; k < rest; ++k) {
         enqueue_edge<T>(o);
         enqueue_cell<T>(o);
     }
@@ -670,16 +993,44 @@ extern "C" int tyee_open_get_state(tyee_open *o, int32_t field, double *values) 
 extern "C" int tyee_open_step(tyee_open *o, int64_t nsteps) {
     using namespace tyee;
     if (!o || nsteps < 0) return fail(TYEE_EINVAL, "null handle or negative step count");
+    if (o->fuse_K > 1 && !o->timing)
+        return o->f64 ? launch_open_fused<double>(*o, nsteps) : launch_open_fused<float>(*o, nsteps);
     return o->f64 ? launch_open<double>(*o, nsteps) : launch_open<float>(*o, nsteps);
+}
+
+extern "C" int tyee_open_set_fusion(tyee_open *o, const tyee_mesh *mesh, int32_t steps_per_launch,
+                                    int32_t tile_tris) {
+    using namespace tyee;
+    if (!o) return fail(TYEE_EINVAL, "null argument");
+    int K = steps_per_launch == 0 ? (o->f64 ? 4 : 6) : steps_per_launch;
+    if (K < 1 || K > kMaxFusion) return fail(TYEE_EINVAL, "steps per launch must be 0 (default) or 1..8");
+    if (tile_tris != 0 && (tile_tris < 256 || tile_tris > 8192))
+        return fail(TYEE_EINVAL, "tile size must be 0 or in [256, 8192] triangles");
+    if (hipStreamSynchronize(o->stream) != hipSuccess) return fail(TYEE_EDEVICE, "hipStreamSynchronize failed");
+    if (o->fgraph) {
+        (void)hipGraphExecDestroy(o->fgraph);
+        o->fgraph = nullptr;
+    }
+    o->fuse_K = 0;
+    o->box.reset();
+    if (K == 1) return TYEE_OK;
+    if (!mesh) return fail(TYEE_EINVAL, "null mesh");
+    try {
+        return build_open_fusion(*o, mesh->m, K, tile_tris);
+    } catch (const std::bad_alloc &) {
+        return fail(TYEE_ENOMEM, "host allocation failed");
+    }
 }
 
 extern "C" int tyee_open_set_graph(tyee_open *o, int32_t steps) {
     if (!o) return tyee::fail(TYEE_EINVAL, "null argument");
     if (steps < 0 || steps > 1024) return tyee::fail(TYEE_EINVAL, "steps per graph must be in 0 .. 1024");
-    if (o->graph) {
+    if (o->graph || o->fgraph) {
         if (hipStreamSynchronize(o->stream) != hipSuccess) return tyee::fail(TYEE_EDEVICE, "hipStreamSynchronize failed");
-        (void)hipGraphExecDestroy(o->graph);
+        if (o->graph) (void)hipGraphExecDestroy(o->graph);
+        if (o->fgraph) (void)hipGraphExecDestroy(o->fgraph);
         o->graph = nullptr;
+        o->fgraph = nullptr;
     }
     o->graph_steps = steps;
     return TYEE_OK;

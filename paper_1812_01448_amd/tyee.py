@@ -121,7 +121,7 @@ EXPORTS = [
     "tyee_sim_current_buffer", "tyee_mesh_modes", "tyee_mesh_spectrum", "tyee_mesh_relax",
     "tyee_mesh_flip", "tyee_open_create", "tyee_open_sizes", "tyee_open_frame", "tyee_open_cfl",
     "tyee_open_set_state", "tyee_open_get_state", "tyee_open_step", "tyee_open_set_graph",
-    "tyee_open_sync",
+    "tyee_open_sync", "tyee_open_set_fusion",
     "tyee_open_set_timing", "tyee_open_kernel_ms", "tyee_open_destroy",
     "tyee_tet_create", "tyee_tet_sizes", "tyee_tet_view", "tyee_tet_cfl", "tyee_tet_destroy",
     "tyee_tet_sim_create", "tyee_tet_sim_set_state", "tyee_tet_sim_get_state", "tyee_tet_sim_step",
@@ -232,6 +232,7 @@ def _load():
         "tyee_open_step": [vp, i64],
         "tyee_open_set_graph": [vp, i32],
         "tyee_open_sync": [vp],
+        "tyee_open_set_fusion": [vp, vp, i32, i32],
         "tyee_open_set_timing": [vp, i32],
         "tyee_open_kernel_ms": [vp, vp, ctypes.POINTER(i64)],
         "tyee_open_destroy": [vp],
@@ -527,6 +528,11 @@ class Open:
     def set_graph(self, steps):
         """Steps per captured HIP graph (0: eager launches; the library's default is 8)."""
         _check(lib.tyee_open_set_graph(self._h, int(steps)))
+
+    def set_fusion(self, mesh, k=0, tile=0):
+        """Fused stepping of the box (tyee_open_set_fusion): k steps per launch (0 = default,
+        1 = off); mesh is the triangle mesh this handle was created from."""
+        _check(lib.tyee_open_set_fusion(self._h, mesh._h, int(k), int(tile)))
 
     def sync(self):
         _check(lib.tyee_open_sync(self._h))

@@ -199,7 +199,8 @@ def _reached_from_sides(om, inner, steps):
     return te, tt
 
 
-def test_open1415_bench_configuration_interior_against_oracle(ty):
+@pytest.mark.parametrize("fusion", [1, 0])
+def test_open1415_bench_configuration_interior_against_oracle(ty, fusion):
     """The bench's open1415 case at its size (1415 x 1415 triangular-lattice box, jitter 0.1,
     seed 11: 4.6M triangles, tied to a 16-layer frame, sigma_max 1, cubic grading), FP32, in the
     bench's launch configuration (graphs of 8 steps): 200 steps from a seeded random state in
@@ -209,9 +210,10 @@ def test_open1415_bench_configuration_interior_against_oracle(ty):
     is compared element by element (the sides' influence is followed exactly through the mesh:
     a step's E update reaches the edges of a reached triangle, its B update the triangles of a
     reached edge). FP32 bar 1e-5 (relative L2 per field over the compared cells), as for the
-    frame at small sizes."""
-    _note("case: open1415 (4.6M triangles + 16-layer frame) FP32, graphs of 8 steps, 200 steps, "
-          "interior against the closed-box oracle")
+    frame at small sizes. Both launch configurations of the bench: graphs of single steps, and
+    the fused box with the frame's band."""
+    _note(f"case: open1415 (4.6M triangles + 16-layer frame) FP32, {'graphs of 8 steps' if fusion == 1 else 'fused box'}, "
+          "200 steps, interior against the closed-box oracle")
     xy, tri, Lx, Ly = box_tri_mesh(1415.0, 1415.0, 1.0, 0.1, 11)
     om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
     dt = 0.5 * 2 / np.sqrt(om.power()[0])
@@ -221,6 +223,8 @@ def test_open1415_bench_configuration_interior_against_oracle(ty):
     B0 = rng.standard_normal(om.nt)
     m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
     sim = ty.Open(m, ty.pml(16, 1.0, 1.0, 3.0), dt, "f32")
+    if fusion != 1:
+        sim.set_fusion(m, fusion)
     assert sim.nt == om.nt and sim.ne > om.ne
     E = np.zeros(sim.ne)
     E[:om.ne] = E0
@@ -239,3 +243,44 @@ def test_open1415_bench_configuration_interior_against_oracle(ty):
     _note(f"  {ce.sum()} edges and {ct.sum()} triangles compared: rel L2 E {errs[0]:.2e} B {errs[1]:.2e}")
     assert ct.sum() > om.nt // 4
     assert max(errs) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", 1e-12)])
+@pytest.mark.parametrize("K,tile", [(6, 256), (3, 512), (0, 0)])
+def test_fused_box_matches_oracle(ty, prec, tol, K, tile):
+    """Fused stepping of the box (tyee_open_set_fusion): a 60 x 50 triangular-lattice box with
+    an 8-layer frame, 203 steps (whole groups of K plus a remainder of single steps) from a
+    random state in the box and the frame, against the open-boundary oracle element by element
+    at the single-step bars, against the single-step launches, and bit for bit between the
+    fused groups replayed from graphs and launched one by one."""
+    _note(f"case: open tri box 60 x 50, 8-layer frame, fused K={K} tile={tile}, {prec}, 203 steps")
+    xy, tri, Lx, Ly = box_tri_mesh(60.0, 50.0, 1.0, 0.1, 3)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    ref = OpenMesh(om, 8, 1.0, 1.0)
+    dt = 0.6 * 2 / ref.omega_max()
+    E, Bx, By = _random_state(ref, 7)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    out = {}
+    for fused, graph in ((False, 8), (True, 8), (True, 0)):
+        sim = ty.Open(m, ty.pml(8, 1.0, 1.0), dt, prec)
+        sim.set_graph(graph)
+        if fused:
+            sim.set_fusion(m, K, tile)
+        sim.set_state("E", E)
+        sim.set_state("BX", Bx)
+        sim.set_state("BY", By)
+        sim.step(203)
+        out[(fused, graph)] = (sim.get_state("E"), sim.get_state("BX"), sim.get_state("BY"))
+    for a, b in zip(out[(True, 8)], out[(True, 0)]):     # graphs of 8 groups replay the eager groups
+        assert np.array_equal(a, b)
+    out = {False: out[(False, 8)], True: out[(True, 8)]}
+    Er, Bxr, Byr = ref.step(E, Bx, By, dt, 203)
+    e, bx, by = out[True]
+    errs = (_rel(e, Er), _rel(bx, Bxr), _rel(by[ref.nt:], Byr[ref.nt:]))
+    _note(f"  fused vs oracle: rel L2 E {errs[0]:.2e} Bx {errs[1]:.2e} By {errs[2]:.2e}")
+    assert max(errs) <= tol
+    e1, bx1, by1 = out[False]
+    d = (_rel(e, e1), _rel(bx, bx1), _rel(by[ref.nt:], by1[ref.nt:]))
+    _note(f"  fused vs single-step: {d[0]:.2e} {d[1]:.2e} {d[2]:.2e}")
+    assert max(d) <= tol
+    assert np.all(e[~ref.inner] == 0.0)
