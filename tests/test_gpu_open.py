@@ -284,3 +284,38 @@ def test_fused_box_matches_oracle(ty, prec, tol, K, tile):
     _note(f"  fused vs single-step: {d[0]:.2e} {d[1]:.2e} {d[2]:.2e}")
     assert max(d) <= tol
     assert np.all(e[~ref.inner] == 0.0)
+
+
+def test_fused_box_arguments_and_switching_off(ty):
+    """tyee_open_set_fusion refuses another mesh and bad depths or tiles; depth 1 switches it
+    off (single steps again, bit for bit); the state carries over either way."""
+    _note("case: open fused box: argument errors, switching on and off mid-run")
+    xy, tri, Lx, Ly = box_tri_mesh(30.0, 24.0, 1.0, 0.1, 2)
+    m = ty.Mesh(xy, tri, False, L=Lx, Ly=Ly)
+    xy2, tri2, Lx2, Ly2 = box_tri_mesh(30.0, 26.0, 1.0, 0.1, 2)
+    other = ty.Mesh(xy2, tri2, False, L=Lx2, Ly=Ly2)
+    om = oracle.OracleMesh(xy, tri, False, Lx, Ly)
+    ref = OpenMesh(om, 4, 0.7, 2.0)
+    dt = 0.6 * 2 / ref.omega_max()
+    E, Bx, By = _random_state(ref, 9)
+    runs = {}
+    for mode in ("single", "switch"):
+        sim = ty.Open(m, ty.pml(4, 0.7, 2.0), dt, "f64")
+        for bad in ((other, 6, 0), (m, 9, 0), (m, -1, 0), (m, 6, 100)):
+            with pytest.raises(ty.TyeeError):
+                sim.set_fusion(*bad)
+        sim.set_state("E", E)
+        sim.set_state("BX", Bx)
+        sim.set_state("BY", By)
+        if mode == "switch":
+            sim.set_fusion(m, 4, 256)
+        sim.step(40)
+        if mode == "switch":
+            sim.set_fusion(m, 1)
+        sim.step(37)
+        runs[mode] = (sim.get_state("E"), sim.get_state("BX"), sim.get_state("BY"))
+    Er, Bxr, Byr = ref.step(E, Bx, By, dt, 77)
+    for got, want in zip(runs["switch"], (Er, Bxr, Byr)):
+        assert _rel(got, want) <= 1e-12
+    for a, b in zip(runs["switch"], runs["single"]):
+        assert _rel(a, b) <= 1e-12
