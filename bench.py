@@ -856,8 +856,8 @@ def bench_open(args):
     dt = 0.5 * 2 / np.sqrt(lam)
     sim = ty.Open(mesh, prm, dt, "f32", stream.cuda_stream)
     # fused stepping of the box (K steps per launch, the frame's band in single steps) unless
-    # --fusion 1; the library's FP32 default depth is 6
-    K = 1 if args.fusion == 1 else (args.fusion or 6)
+    # --fusion 1; the library's FP32 default depth for it is 7
+    K = 1 if args.fusion == 1 else (args.fusion or 7)
     if K > 1:
         sim.set_fusion(mesh, K, args.tile)
     log(f"open1415: mesh, frame and omega_max (lambda {lam:.4g}, {iters} iterations) in "

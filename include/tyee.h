@@ -734,7 +734,7 @@ int tyee_open_step(tyee_open *o, int64_t nsteps);
    if a graph exists (it is discarded).  Errors: EINVAL. */
 int tyee_open_set_graph(tyee_open *o, int32_t steps);
 /* Fused stepping of the box (the temporal fusion of tyee_sim_set_fusion carried to the open
-   boundary): steps_per_launch K (1..8; 0 = 6 in FP32, 4 in FP64; 1 = off, the default),
+   boundary): steps_per_launch K (1..8; 0 = 7 in FP32, 4 in FP64; 1 = off, the default),
    tile_tris as in tyee_sim_set_fusion.  mesh must be the triangle mesh the handle was created
    from (checked: counts and edges).  The library then holds a Morton-numbered copy of the box
    advanced by the fused kernel, and a band (every frame cell and edge, the box triangles within

@@ -1002,7 +1002,9 @@ extern "C" int tyee_open_set_fusion(tyee_open *o, const tyee_mesh *mesh, int32_t
                                     int32_t tile_tris) {
     using namespace tyee;
     if (!o) return fail(TYEE_EINVAL, "null argument");
-    int K = steps_per_launch == 0 ? (o->f64 ? 4 : 6) : steps_per_launch;
+    // default depth: 7 in FP32 (open1415: 18.1 us per step against 19.5 at 6, 19.8 at 8, 20.9 at
+    // 4: deeper groups spread the band's gather and write-back over more steps), 4 in FP64
+    int K = steps_per_launch == 0 ? (o->f64 ? 4 : 7) : steps_per_launch;
     if (K < 1 || K > kMaxFusion) return fail(TYEE_EINVAL, "steps per launch must be 0 (default) or 1..8");
     if (tile_tris != 0 && (tile_tris < 256 || tile_tris > 8192))
         return fail(TYEE_EINVAL, "tile size must be 0 or in [256, 8192] triangles");
