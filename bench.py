@@ -302,7 +302,7 @@ def main():
         traffic_summary(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the method "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (the method "
                                    "shards by contiguous Morton ranges with halo exchange, "
                                    "which is not built)",
                           "n_gpus": args.gpus}), flush=True)
